@@ -1,0 +1,679 @@
+/*
+ * laim_oracle.c -- CPU oracle for the local autonomous inference machine.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library calls, links or
+ * loads this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do. It shares no code with the HIP path: every
+ * routine here (Philox, the FP32 transcendental functions, BP, the feedback
+ * rule, GF(2) elimination) is written separately from the paper and from the
+ * published definitions it names.
+ *
+ * What it computes (the paper's sections are cited per function):
+ *   - i.i.d. Bernoulli(p) Z errors from a counter-based generator
+ *     (Preliminaries; SM "Tanner graphs ..." prior),
+ *   - the syndrome s = H e (SM, syndrome definition),
+ *   - BP in LLR form, Eqs. (BP-LLR1) and (BP-LLR2), either sum-product as
+ *     printed or normalised min-sum (a reading: the paper uses sum-product),
+ *   - the round-discretised check-centric machine of Algorithm 1: BP, then
+ *     every active check whose clock rang this round tests Evidence and
+ *     flips the argmax qubit (LocalMove), then the syndrome update,
+ *   - the decoding-success test (Preliminaries, conditions (1) and (2)) by an
+ *     independent GF(2) rank test,
+ *   - for pins only: the discrete bit-centric machine of the SM ("Setup and
+ *     algorithm"), in double precision.
+ *
+ * Precision: the decoder runs in FP32 because its integer decisions (which
+ * check moves, which qubit flips) are taken from FP32 messages; every float
+ * expression is evaluated left to right, one rounding per operation; the
+ * file must be compiled with -ffp-contract=off and without fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_VERSION 1
+
+int orc_version(void) { return ORC_VERSION; }
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10, as defined by Salmon, Moraes, Dror and Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3" (SC'11): a 4-word counter, 2-word key,
+ * ten rounds; each round multiplies words 0 and 2 by the two round
+ * multipliers, swaps and xors the high halves with the other words and the
+ * round key; the key advances by the two Weyl increments between rounds.
+ * ---------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  const uint32_t MUL0 = 0xD2511F53u, MUL1 = 0xCD9E8D57u;
+  const uint32_t WEYL0 = 0x9E3779B9u, WEYL1 = 0xBB67AE85u;
+  uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += WEYL0;
+      k1 += WEYL1;
+    }
+    uint64_t p0 = (uint64_t)MUL0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)MUL1 * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Bernoulli(p) from one uniform 32-bit word w: the event w < floor(p * 2^32)
+ * (p >= 1: always; p <= 0: never). Returned as a 64-bit bound so p = 1 is
+ * representable. */
+uint64_t orc_bernoulli_bound(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return (uint64_t)1 << 32;
+  return (uint64_t)floor(p * 4294967296.0);
+}
+
+static void philox_for(uint64_t seed, uint64_t shot, uint32_t w2, uint32_t w3, uint32_t out[4]) {
+  uint32_t ctr[4] = {(uint32_t)shot, (uint32_t)(shot >> 32), w2, w3};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------
+ * FP32 evaluation of the sum-product check rule (BP-LLR2).
+ *
+ * 2 atanh(prod tanh(m_i / 2)) is evaluated as the pairwise "box-plus" fold
+ * of the incoming LLRs (Hagenauer, Offer and Papke, IEEE Trans. Inf. Theory
+ * 42 (1996)), using the exact identity
+ *   a [+] b := 2 atanh(tanh(a/2) tanh(b/2))
+ *            = sg(a) sg(b) [min(|a|, |b|) + g(|a| + |b|) - g(||a| - |b||)],
+ *   g(y) := log(1 + e^{-y}),
+ * whose correction terms lie in [0, log 2], so no intermediate saturates
+ * before the clamp (a literal FP32 tanh product rounds to +-1 once |m| > 17
+ * and then jumps to +-CLAMP). +inf is the identity of the fold (an empty
+ * product is 1, whose 2 atanh is +inf).
+ *
+ * g is built from textbook methods with +, -, *, / and exponent-field
+ * manipulation only, so that its result does not depend on the platform:
+ * exp: Cody-Waite argument reduction x = k ln2 + r with ln2 split into a
+ *   16-significant-bit head (k*head exact for |k| < 256) and a tail, the
+ *   degree-7 Taylor polynomial of e^r (coefficients 1/j!) by Horner, then
+ *   scaling by 2^k through the exponent field;
+ * log(1 + u), u in [0, 1]: 2 atanh(s) with s = u / (2 + u) in [0, 1/3], by
+ *   the atanh power series through s^15 (coefficients 1/(2j+1)).
+ * ---------------------------------------------------------------------- */
+static float f32_from_bits(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
+
+/* e^{-a} for a >= 0 (a = +inf allowed). Results below 2^-115 are returned
+ * as 0, which keeps every intermediate a normal number. */
+float orc_exp_neg(float a) {
+  if (!(a <= 80.0f)) return 0.0f; /* also catches +inf */
+  const float LN2_HEAD = f32_from_bits(0x3F317200u); /* ln2 with low 8 mantissa bits cleared */
+  const float LN2_TAIL = (float)(0.69314718055994530942 - 0.693145751953125);
+  const float INV_LN2 = (float)1.44269504088896340736;
+  float x = -a;
+  float kf = floorf(x * INV_LN2 + 0.5f);
+  float r = (x - kf * LN2_HEAD) - kf * LN2_TAIL;
+  float p = 1.0f / 5040.0f;
+  p = p * r + 1.0f / 720.0f;
+  p = p * r + 1.0f / 120.0f;
+  p = p * r + 1.0f / 24.0f;
+  p = p * r + 1.0f / 6.0f;
+  p = p * r + 0.5f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  int k = (int)kf;
+  float scale = f32_from_bits((uint32_t)(k + 127) << 23);
+  return p * scale;
+}
+
+/* log(1 + u) for u in [0, 1]. */
+float orc_log1p_unit(float u) {
+  float s = u / (2.0f + u);
+  float z = s * s;
+  float q = 1.0f / 15.0f;
+  q = q * z + 1.0f / 13.0f;
+  q = q * z + 1.0f / 11.0f;
+  q = q * z + 1.0f / 9.0f;
+  q = q * z + 1.0f / 7.0f;
+  q = q * z + 1.0f / 5.0f;
+  q = q * z + 1.0f / 3.0f;
+  return (s + s) + ((s + s) * z) * q;
+}
+
+/* g(y) = log(1 + e^{-y}) for y >= 0. */
+float orc_softplus_neg(float y) { return orc_log1p_unit(orc_exp_neg(y)); }
+
+/* a [+] b, with sg(x) = -1 if x < 0 else +1, evaluated on magnitudes:
+ *   |a| [+] |b| = min(|a|, |b|) + g(|a| + |b|) - g(||a| - |b||) >= 0,
+ * (a rounding below zero is set to +0), then the sign sg(a) sg(b). This
+ * makes the FP32 result exactly odd in each argument and symmetric. */
+float orc_boxplus(float a, float b) {
+  float aa = fabsf(a), ab = fabsf(b);
+  float mn = (ab < aa) ? ab : aa;
+  float diff = (aa < ab) ? (ab - aa) : (aa - ab);
+  float mag = (mn + orc_softplus_neg(aa + ab)) - orc_softplus_neg(diff);
+  if (mag < 0.0f) mag = 0.0f;
+  int neg = (a < 0.0f) ^ (b < 0.0f);
+  return neg ? -mag : mag;
+}
+
+static float clampf_(float x, float C) {
+  if (x > C) return C;
+  if (x < -C) return -C;
+  return x;
+}
+
+/* ------------------------------------------------------------------------
+ * Tanner graph (SM Definition "Tanner graph"): check c has the qubits
+ * N(c) = row c of H (ascending); qubit v has the checks N(v) (ascending).
+ * Edges are numbered in row order of H: edge rowptr[c] + j is (c, N(c)[j]).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t m, n, E;
+  const int32_t* rowptr; /* [m+1] */
+  const int32_t* col;    /* [E] */
+  int32_t* vptr;         /* [n+1] */
+  int32_t* vedge;        /* [E]: edges of qubit v, ascending check order */
+} tanner;
+
+static int tanner_init(tanner* T, int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col) {
+  T->m = m; T->n = n; T->E = rowptr[m];
+  T->rowptr = rowptr; T->col = col;
+  T->vptr = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  T->vedge = (int32_t*)malloc(sizeof(int32_t) * (size_t)(T->E > 0 ? T->E : 1));
+  if (!T->vptr || !T->vedge) return -2;
+  for (int32_t e = 0; e < T->E; ++e) T->vptr[col[e] + 1]++;
+  for (int32_t v = 0; v < n; ++v) T->vptr[v + 1] += T->vptr[v];
+  int32_t* fill = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!fill) return -2;
+  for (int32_t c = 0; c < m; ++c) /* ascending c, so each qubit's list is ascending */
+    for (int32_t e = rowptr[c]; e < rowptr[c + 1]; ++e) {
+      int32_t v = col[e];
+      T->vedge[T->vptr[v] + fill[v]++] = e;
+    }
+  free(fill);
+  return 0;
+}
+
+static void tanner_free(tanner* T) {
+  free(T->vptr);
+  free(T->vedge);
+}
+
+/* ------------------------------------------------------------------------
+ * Noise and syndrome.
+ * ---------------------------------------------------------------------- */
+
+/* e[v] = 1[w_v < floor(p 2^32)], w_v = word (v mod 4) of
+ * Philox(key = seed, counter = (shot_lo, shot_hi, floor(v/4), 0)). */
+void orc_sample_noise(int32_t n, double p, uint64_t seed, uint64_t shot0, int32_t nshots,
+                      uint8_t* e_out) {
+  uint64_t bound = orc_bernoulli_bound(p);
+  for (int32_t i = 0; i < nshots; ++i) {
+    uint64_t shot = shot0 + (uint64_t)i;
+    for (int32_t v = 0; v < n; ++v) {
+      uint32_t w[4];
+      philox_for(seed, shot, (uint32_t)(v >> 2), 0u, w);
+      e_out[(size_t)i * n + v] = ((uint64_t)w[v & 3] < bound) ? 1 : 0;
+    }
+  }
+}
+
+/* s_c = XOR over v in N(c) of e_v, for nshots rows of e. */
+void orc_syndrome(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                  const uint8_t* e, int32_t nshots, uint8_t* s_out) {
+  for (int32_t i = 0; i < nshots; ++i)
+    for (int32_t c = 0; c < m; ++c) {
+      uint8_t x = 0;
+      for (int32_t k = rowptr[c]; k < rowptr[c + 1]; ++k) x ^= e[(size_t)i * n + col[k]] & 1u;
+      s_out[(size_t)i * m + c] = x;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * BP in LLR form.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t bp;            /* 0: normalised min-sum, 1: sum-product (BP-LLR2) */
+  float alpha;           /* min-sum normalisation */
+  double q;              /* decoder prior; pi = log(q / (1 - q)) */
+  float clamp;           /* every LLR is clamped to [-clamp, clamp] */
+  int32_t iters;         /* BP iterations per round */
+  int32_t rounds;        /* feedback rounds */
+  double mask_density;   /* probability that a check's clock rang in a round */
+  int32_t gauge;         /* 1: negate pi and messages of flipped qubits */
+  int32_t evidence;      /* 1: apply the Evidence test */
+  int32_t retire;        /* 1: stop a shot once its syndrome is clear */
+  uint64_t seed;
+} orc_params;
+
+/* Check-to-qubit rule (BP-LLR2) for edge j of check c:
+ *   m_{c->v} = (-1)^{s_c + d_c} * CN_{w in N(c)\v}(m_{w->c}), then clamped;
+ * sum-product: CN = 2 atanh(prod tanh(m/2)), evaluated as the box-plus fold
+ * ((m_1 [+] m_2) [+] m_3) ... over the other edges in ascending order;
+ * min-sum:     CN = (alpha * min |m|) * prod sg(m), sg(x) = -1 if x < 0
+ *              else +1. An empty product is 1 and an empty minimum is +inf. */
+static float check_rule(const orc_params* P, const float* mvc_row, int32_t dc, int32_t j,
+                        int32_t s_c) {
+  int sigma_neg = (int)((s_c + dc) & 1);
+  float out;
+  if (P->bp == 1) {
+    float acc = INFINITY; /* identity of the fold: (+inf) [+] x == x exactly */
+    for (int32_t i = 0; i < dc; ++i)
+      if (i != j) acc = orc_boxplus(acc, mvc_row[i]);
+    out = sigma_neg ? -acc : acc;
+  } else {
+    float minabs = INFINITY;
+    int neg = sigma_neg;
+    for (int32_t i = 0; i < dc; ++i) {
+      if (i == j) continue;
+      float a = fabsf(mvc_row[i]);
+      if (a < minabs) minabs = a;
+      if (mvc_row[i] < 0.0f) neg ^= 1;
+    }
+    float mag = P->alpha * minabs;
+    out = neg ? -mag : mag;
+  }
+  return clampf_(out, P->clamp);
+}
+
+/* Check phase: every m_{c->v} from the current m_{v->c} and s. */
+static void check_phase(const tanner* T, const orc_params* P, const float* mvc, const uint8_t* s,
+                        float* mcv) {
+  for (int32_t c = 0; c < T->m; ++c) {
+    int32_t b = T->rowptr[c], dc = T->rowptr[c + 1] - b;
+    for (int32_t j = 0; j < dc; ++j) mcv[b + j] = check_rule(P, mvc + b, dc, j, s[c]);
+  }
+}
+
+/* Qubit-to-check rule (BP-LLR1): m_{v->c} = pi_v + sum over c' in N(v)\c of
+ * m_{c'->v}, added left to right in ascending c', then clamped. */
+static void var_phase(const tanner* T, const orc_params* P, const float* pi_v, const float* mcv,
+                      float* mvc) {
+  for (int32_t v = 0; v < T->n; ++v) {
+    int32_t b = T->vptr[v], dv = T->vptr[v + 1] - b;
+    for (int32_t j = 0; j < dv; ++j) {
+      float acc = pi_v[v];
+      for (int32_t i = 0; i < dv; ++i)
+        if (i != j) acc = acc + mcv[T->vedge[b + i]];
+      mvc[T->vedge[b + j]] = clampf_(acc, P->clamp);
+    }
+  }
+}
+
+/* Bit beliefs L_v = pi_v + sum over c in N(v) of m_{c->v} (Preliminaries),
+ * added in ascending c, clamped. */
+static void beliefs(const tanner* T, const orc_params* P, const float* pi_v, const float* mcv,
+                    float* L) {
+  for (int32_t v = 0; v < T->n; ++v) {
+    float acc = pi_v[v];
+    for (int32_t i = T->vptr[v]; i < T->vptr[v + 1]; ++i) acc = acc + mcv[T->vedge[i]];
+    L[v] = clampf_(acc, P->clamp);
+  }
+}
+
+/* One BP sweep (check phase, then qubit phase) on caller-owned arrays, for
+ * the gauge-covariance pin. pi_v has n entries. */
+int32_t orc_bp_sweep(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                     const orc_params* P, const float* pi_v, const uint8_t* s, const float* mvc_in,
+                     float* mcv_out, float* mvc_out) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  check_phase(&T, P, mvc_in, s, mcv_out);
+  var_phase(&T, P, pi_v, mcv_out, mvc_out);
+  tanner_free(&T);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * The round-discretised check-centric machine (Algorithm 1).
+ *
+ * Per shot: z = 0, s = H e0, all messages +0 (the algorithm's m(0) = 0).
+ * Each round r = 0, 1, ...:
+ *   1. `iters` BP sweeps on the current syndrome (messages are never reset);
+ *   2. beliefs L_v;
+ *   3. every check whose clock rang (word 0 of
+ *      Philox(seed, (shot_lo, shot_hi, c, 16 r + 1)) below
+ *      floor(mask_density 2^32)) and which is active (s_c = 1) computes
+ *      Evidence: Lmax = max over v in N(c) of L_v; Pr(e_v = 1 | s) >= 1/d_c
+ *      is sigma(L) >= 1/d_c, i.e. L >= -log(d_c - 1). If it holds, the check
+ *      picks its LocalMove: the qubits with L_v == Lmax (in ascending order)
+ *      are the ties, and word 1 of the same Philox output picks tie number
+ *      floor(w1 * ntie / 2^32). A qubit chosen by several checks flips once;
+ *   4. z ^= f; s = H (e0 ^ z), which equals s ^ H f (the syndrome update);
+ *   5. if s = 0 for the first time, t_clr = r + 1.
+ * t_clr = 0 if H e0 = 0 and -1 if the syndrome never clears.
+ *
+ * Outputs per shot: z [n], s [m], t_clr, and optionally the beliefs of the
+ * final message state L [n]. For a single shot the per-round syndromes and
+ * corrections can be traced (s_trace [rounds][m], z_trace [rounds][n]).
+ * Returns 0, or -3 if the internal syndrome-update identity check fails.
+ * ---------------------------------------------------------------------- */
+static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr,
+                          uint64_t R_bound, float pi, const uint8_t* e0, uint64_t shot,
+                          uint8_t* z, uint8_t* s, int32_t* tclr, float* L_out, uint8_t* s_trace,
+                          uint8_t* z_trace) {
+  const int32_t m = T->m, n = T->n, E = T->E;
+  float* mvc = (float*)calloc((size_t)(E > 0 ? E : 1), sizeof(float));
+  float* mcv = (float*)calloc((size_t)(E > 0 ? E : 1), sizeof(float));
+  float* L = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  float* piv = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  uint8_t* f = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  uint8_t* r_err = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  uint8_t* s_new = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+  int32_t rc = 0;
+  if (!mvc || !mcv || !L || !piv || !f || !r_err || !s_new) {
+    rc = -2;
+    goto done;
+  }
+  for (int32_t v = 0; v < n; ++v) { piv[v] = pi; z[v] = 0; }
+  orc_syndrome(m, n, T->rowptr, T->col, e0, 1, s);
+  int any = 0;
+  for (int32_t c = 0; c < m; ++c) any |= s[c];
+  *tclr = any ? -1 : 0;
+
+  for (int32_t r = 0; r < P->rounds; ++r) {
+    if (P->retire && *tclr >= 0) break;
+    for (int32_t it = 0; it < P->iters; ++it) {
+      check_phase(T, P, mvc, s, mcv);
+      var_phase(T, P, piv, mcv, mvc);
+    }
+    beliefs(T, P, piv, mcv, L);
+    memset(f, 0, (size_t)n);
+    for (int32_t c = 0; c < m; ++c) {
+      if (!s[c]) continue;
+      uint32_t w[4];
+      philox_for(P->seed, shot, (uint32_t)c, ((uint32_t)r << 4) | 1u, w);
+      if (!((uint64_t)w[0] < R_bound)) continue;
+      int32_t b = T->rowptr[c], dc = T->rowptr[c + 1] - b;
+      if (dc == 0) continue;
+      float Lmax = L[T->col[b]];
+      for (int32_t j = 1; j < dc; ++j)
+        if (L[T->col[b + j]] > Lmax) Lmax = L[T->col[b + j]];
+      if (P->evidence && !(Lmax >= thr[dc])) continue;
+      uint32_t ntie = 0;
+      for (int32_t j = 0; j < dc; ++j) ntie += (L[T->col[b + j]] == Lmax) ? 1u : 0u;
+      uint32_t pick = (uint32_t)(((uint64_t)w[1] * (uint64_t)ntie) >> 32);
+      for (int32_t j = 0; j < dc; ++j) {
+        if (L[T->col[b + j]] == Lmax) {
+          if (pick == 0) {
+            f[T->col[b + j]] = 1;
+            break;
+          }
+          pick--;
+        }
+      }
+    }
+    for (int32_t v = 0; v < n; ++v) {
+      z[v] ^= f[v];
+      r_err[v] = (uint8_t)(e0[v] ^ z[v]);
+    }
+    if (P->gauge) {
+      for (int32_t v = 0; v < n; ++v) {
+        if (!f[v]) continue;
+        piv[v] = -piv[v];
+        for (int32_t i = T->vptr[v]; i < T->vptr[v + 1]; ++i) {
+          int32_t e = T->vedge[i];
+          mcv[e] = -mcv[e];
+          mvc[e] = -mvc[e];
+        }
+      }
+    }
+    /* re-measure and check it against the incremental update s ^ H f */
+    orc_syndrome(m, n, T->rowptr, T->col, r_err, 1, s_new);
+    any = 0;
+    for (int32_t c = 0; c < m; ++c) {
+      uint8_t x = s[c];
+      for (int32_t k = T->rowptr[c]; k < T->rowptr[c + 1]; ++k) x ^= f[T->col[k]];
+      if (x != s_new[c]) rc = -3;
+      s[c] = s_new[c];
+      any |= s[c];
+    }
+    if (!any && *tclr < 0) *tclr = r + 1;
+    if (s_trace) memcpy(s_trace + (size_t)r * m, s, (size_t)m);
+    if (z_trace) memcpy(z_trace + (size_t)r * n, z, (size_t)n);
+  }
+  if (L_out) beliefs(T, P, piv, mcv, L_out);
+done:
+  free(mvc); free(mcv); free(L); free(piv); free(f); free(r_err); free(s_new);
+  return rc;
+}
+
+/* thr[d] = -log(d - 1) rounded to float, the Evidence bound for degree d
+ * (thr[1] = +inf: a degree-1 check never has evidence; thr[2] = -0). */
+void orc_evidence_thresholds(int32_t dmax, float* thr) {
+  for (int32_t d = 0; d <= dmax; ++d) thr[d] = (d <= 1) ? INFINITY : (float)(-log((double)(d - 1)));
+}
+
+int32_t orc_decode(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                   const orc_params* P, const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                   uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out, float* L_out,
+                   uint8_t* s_trace, uint8_t* z_trace, int32_t nthreads) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  int32_t dmax = 0;
+  for (int32_t c = 0; c < m; ++c)
+    if (rowptr[c + 1] - rowptr[c] > dmax) dmax = rowptr[c + 1] - rowptr[c];
+  float* thr = (float*)malloc(sizeof(float) * (size_t)(dmax + 1));
+  orc_evidence_thresholds(dmax, thr);
+  const float pi = (float)log(P->q / (1.0 - P->q));
+  const uint64_t R_bound = orc_bernoulli_bound(P->mask_density);
+  int32_t rc = 0;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads) reduction(min : rc)
+  for (int32_t i = 0; i < nshots; ++i) {
+    int32_t r1 = decode_one(&T, P, thr, R_bound, pi, e0 + (size_t)i * n, shot0 + (uint64_t)i,
+                            z_out + (size_t)i * n, s_out + (size_t)i * m, tclr_out + i,
+                            L_out ? L_out + (size_t)i * n : NULL,
+                            (nshots == 1) ? s_trace : NULL, (nshots == 1) ? z_trace : NULL);
+    if (r1 < rc) rc = r1;
+  }
+  free(thr);
+  tanner_free(&T);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * GF(2) linear algebra on bit-packed rows, for the success test.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t rows, words;
+  uint64_t* a;    /* rows x words */
+  int32_t* pivot; /* pivot column of each reduced row */
+  int32_t rank;
+} gf2_basis;
+
+static void pack_rows(int32_t rows, int32_t n, const int32_t* rowptr, const int32_t* col,
+                      int32_t words, uint64_t* a) {
+  memset(a, 0, sizeof(uint64_t) * (size_t)rows * words);
+  for (int32_t r = 0; r < rows; ++r)
+    for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+      a[(size_t)r * words + (col[k] >> 6)] ^= (uint64_t)1 << (col[k] & 63);
+  (void)n;
+}
+
+/* Row-reduce by Gaussian elimination; the reduced rows span the row space. */
+static int gf2_basis_init(gf2_basis* B, int32_t rows, int32_t n, const int32_t* rowptr,
+                          const int32_t* col) {
+  B->rows = rows;
+  B->words = (n + 63) / 64;
+  B->a = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(rows > 0 ? rows : 1) * B->words);
+  B->pivot = (int32_t*)malloc(sizeof(int32_t) * (size_t)(rows > 0 ? rows : 1));
+  if (!B->a || !B->pivot) return -2;
+  pack_rows(rows, n, rowptr, col, B->words, B->a);
+  int32_t rank = 0;
+  for (int32_t c = 0; c < n && rank < rows; ++c) {
+    int32_t w = c >> 6;
+    uint64_t bit = (uint64_t)1 << (c & 63);
+    int32_t piv = -1;
+    for (int32_t r = rank; r < rows; ++r)
+      if (B->a[(size_t)r * B->words + w] & bit) { piv = r; break; }
+    if (piv < 0) continue;
+    if (piv != rank)
+      for (int32_t k = 0; k < B->words; ++k) {
+        uint64_t t = B->a[(size_t)piv * B->words + k];
+        B->a[(size_t)piv * B->words + k] = B->a[(size_t)rank * B->words + k];
+        B->a[(size_t)rank * B->words + k] = t;
+      }
+    for (int32_t r = 0; r < rows; ++r)
+      if (r != rank && (B->a[(size_t)r * B->words + w] & bit))
+        for (int32_t k = 0; k < B->words; ++k)
+          B->a[(size_t)r * B->words + k] ^= B->a[(size_t)rank * B->words + k];
+    B->pivot[rank] = c;
+    rank++;
+  }
+  B->rank = rank;
+  return 0;
+}
+
+static void gf2_basis_free(gf2_basis* B) { free(B->a); free(B->pivot); }
+
+int32_t orc_gf2_rank(int32_t rows, int32_t n, const int32_t* rowptr, const int32_t* col) {
+  gf2_basis B;
+  if (gf2_basis_init(&B, rows, n, rowptr, col)) return -2;
+  int32_t r = B.rank;
+  gf2_basis_free(&B);
+  return r;
+}
+
+/* Is the 0/1 vector x (length n) in the row space of the basis?
+ * Equivalent to rank([G; x]) == rank(G). */
+static int in_row_space(const gf2_basis* B, int32_t n, const uint8_t* x, uint64_t* work) {
+  memset(work, 0, sizeof(uint64_t) * (size_t)B->words);
+  for (int32_t v = 0; v < n; ++v)
+    if (x[v] & 1u) work[v >> 6] ^= (uint64_t)1 << (v & 63);
+  for (int32_t r = 0; r < B->rank; ++r) {
+    int32_t c = B->pivot[r];
+    if (work[c >> 6] & ((uint64_t)1 << (c & 63)))
+      for (int32_t k = 0; k < B->words; ++k) work[k] ^= B->a[(size_t)r * B->words + k];
+  }
+  for (int32_t k = 0; k < B->words; ++k)
+    if (work[k]) return 0;
+  return 1;
+}
+
+/* Decoder failure (Preliminaries): fail unless (1) H (e0 ^ z) = 0 and (2)
+ * e0 ^ z lies in row(G). */
+int32_t orc_logical_failure(int32_t m, int32_t n, const int32_t* h_rowptr, const int32_t* h_col,
+                            int32_t mg, const int32_t* g_rowptr, const int32_t* g_col,
+                            const uint8_t* e0, const uint8_t* z, int32_t nshots, uint8_t* fail_out) {
+  gf2_basis B;
+  if (gf2_basis_init(&B, mg, n, g_rowptr, g_col)) return -2;
+  uint8_t* r = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  uint8_t* s = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+  uint64_t* work = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(B.words > 0 ? B.words : 1));
+  for (int32_t i = 0; i < nshots; ++i) {
+    for (int32_t v = 0; v < n; ++v) r[v] = (uint8_t)((e0[(size_t)i * n + v] ^ z[(size_t)i * n + v]) & 1u);
+    orc_syndrome(m, n, h_rowptr, h_col, r, 1, s);
+    int any = 0;
+    for (int32_t c = 0; c < m; ++c) any |= s[c];
+    fail_out[i] = (uint8_t)(any || !in_row_space(&B, n, r, work));
+  }
+  free(r); free(s); free(work);
+  gf2_basis_free(&B);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Pins only: the discrete bit-centric machine (SM "Setup and algorithm"),
+ * in double precision with libm tanh/atanh.
+ *
+ * Iteration i (from the state of iteration i-1; all updates use old values):
+ *   check-to-bit   m^_{c->v} = 2 (-1)^{s_c + d_c} atanh(prod tanh(m_{w->c}/2))
+ *                  (for d_c = 2 this is (-1)^{s_c} m_{w->c});
+ *   bit-to-check   m^_{v->c} = pi_v + sum_{c' != c} m_{c'->v};
+ *   beliefs        L^_v = pi_v + sum_c m_{c->v};
+ *   feedback       f_v = 1[L^_v > 0]; s_c ^= XOR_{v in N(c)} f_v;
+ *   LLR switch     pi_v, m^_{v->c}, m^_{c->v} multiplied by (-1)^{f_v}.
+ * Messages and pi start at 0 and log(q/(1-q)). Records e^{(i)} = e0 ^ z^{(i)}
+ * for i = 1..iters into e_trace [iters][n] and the beliefs L^ into L_trace.
+ * ---------------------------------------------------------------------- */
+int32_t orc_bitcentric_machine(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                               double q, const uint8_t* e0, int32_t iters, uint8_t* e_trace,
+                               double* L_trace, int32_t* iclr_out) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  const int32_t E = T.E;
+  double* mvc = (double*)calloc((size_t)E + 1, sizeof(double));
+  double* mcv = (double*)calloc((size_t)E + 1, sizeof(double));
+  double* nvc = (double*)calloc((size_t)E + 1, sizeof(double));
+  double* ncv = (double*)calloc((size_t)E + 1, sizeof(double));
+  double* piv = (double*)malloc(sizeof(double) * ((size_t)n + 1));
+  uint8_t* s = (uint8_t*)malloc((size_t)m + 1);
+  uint8_t* z = (uint8_t*)calloc((size_t)n + 1, 1);
+  uint8_t* f = (uint8_t*)calloc((size_t)n + 1, 1);
+  double pi0 = log(q / (1.0 - q));
+  for (int32_t v = 0; v < n; ++v) piv[v] = pi0;
+  orc_syndrome(m, n, rowptr, col, e0, 1, s);
+  int any = 0;
+  for (int32_t c = 0; c < m; ++c) any |= s[c];
+  *iclr_out = any ? -1 : 0;
+  for (int32_t it = 1; it <= iters; ++it) {
+    for (int32_t c = 0; c < m; ++c) {
+      int32_t b = rowptr[c], dc = rowptr[c + 1] - b;
+      double sg = ((s[c] + dc) & 1) ? -1.0 : 1.0;
+      for (int32_t j = 0; j < dc; ++j) {
+        double prod = 1.0;
+        for (int32_t i = 0; i < dc; ++i)
+          if (i != j) prod *= tanh(mvc[b + i] / 2.0);
+        ncv[b + j] = (dc == 2) ? sg * mvc[b + (1 - j)] : sg * 2.0 * atanh(prod);
+      }
+    }
+    for (int32_t v = 0; v < n; ++v) {
+      int32_t b = T.vptr[v], dv = T.vptr[v + 1] - b;
+      double Lh = piv[v];
+      for (int32_t i = 0; i < dv; ++i) Lh += mcv[T.vedge[b + i]];
+      for (int32_t j = 0; j < dv; ++j) {
+        double acc = piv[v];
+        for (int32_t i = 0; i < dv; ++i)
+          if (i != j) acc += mcv[T.vedge[b + i]];
+        nvc[T.vedge[b + j]] = acc;
+      }
+      f[v] = Lh > 0.0;
+      if (L_trace) L_trace[(size_t)(it - 1) * n + v] = Lh;
+    }
+    for (int32_t c = 0; c < m; ++c)
+      for (int32_t k = rowptr[c]; k < rowptr[c + 1]; ++k) s[c] ^= f[col[k]];
+    for (int32_t v = 0; v < n; ++v) {
+      z[v] ^= f[v];
+      double g = f[v] ? -1.0 : 1.0;
+      piv[v] *= g;
+      for (int32_t i = T.vptr[v]; i < T.vptr[v + 1]; ++i) {
+        int32_t e = T.vedge[i];
+        nvc[e] *= g;
+        ncv[e] *= g;
+      }
+      if (e_trace) e_trace[(size_t)(it - 1) * n + v] = (uint8_t)(e0[v] ^ z[v]);
+    }
+    memcpy(mvc, nvc, sizeof(double) * (size_t)E);
+    memcpy(mcv, ncv, sizeof(double) * (size_t)E);
+    any = 0;
+    for (int32_t c = 0; c < m; ++c) any |= s[c];
+    if (!any && *iclr_out < 0) *iclr_out = it;
+  }
+  free(mvc); free(mcv); free(nvc); free(ncv); free(piv); free(s); free(z); free(f);
+  tanner_free(&T);
+  return 0;
+}
+
+/* Elementwise helpers so the tests can pin the FP32 functions on many points. */
+void orc_vec_exp_neg(const float* x, int32_t k, float* y) { for (int32_t i = 0; i < k; ++i) y[i] = orc_exp_neg(x[i]); }
+void orc_vec_log1p_unit(const float* x, int32_t k, float* y) { for (int32_t i = 0; i < k; ++i) y[i] = orc_log1p_unit(x[i]); }
+void orc_vec_boxplus(const float* a, const float* b, int32_t k, float* y) { for (int32_t i = 0; i < k; ++i) y[i] = orc_boxplus(a[i], b[i]); }
+void orc_vec_philox(const uint32_t* ctr, const uint32_t* key, int32_t k, uint32_t* out) {
+  for (int32_t i = 0; i < k; ++i) orc_philox4x32_10(ctr + 4 * (size_t)i, key + 2 * (size_t)i, out + 4 * (size_t)i);
+}

@@ -1,0 +1,261 @@
+"""Python access to the CPU oracle (``laim_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark. The product library never imports it,
+and it never imports the product package: codes are passed in as anything
+with ``H``/``G`` attributes holding ``rows``, ``cols``, ``rowptr``, ``col``.
+
+``build()`` compiles the C file with gcc (FP32 without contraction, OpenMP
+over shots) into ``oracle/liblaim_oracle.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "laim_oracle.c")
+LIB = os.path.join(HERE, "liblaim_oracle.so")
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+          "-fopenmp", "-Wall", "-Wno-unused-function"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (always when ``force``)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+class Params(C.Structure):
+    _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
+                ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
+                ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+@dataclass
+class DecodeParams:
+    """Decoder knobs (defaults: Table S1's q, CLAMP; 20 iterations; rho = 0.5)."""
+
+    bp: str = "minsum"  # "minsum" or "sumproduct"
+    alpha: float = 0.75
+    q: float = 0.05
+    clamp: float = 1000.0
+    iters: int = 20
+    rounds: int = 64
+    mask_density: float = 0.5
+    gauge: bool = False
+    evidence: bool = True
+    retire: bool = True
+    seed: int = 0
+
+    def c(self) -> Params:
+        return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
+                      self.iters, self.rounds, self.mask_density, int(self.gauge),
+                      int(self.evidence), int(self.retire), self.seed)
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        i32p, u8p, f32p, u32p = (C.POINTER(C.c_int32), C.POINTER(C.c_uint8),
+                                 C.POINTER(C.c_float), C.POINTER(C.c_uint32))
+        L.orc_version.restype = C.c_int
+        L.orc_max_threads.restype = C.c_int
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_bernoulli_bound.restype = C.c_uint64
+        L.orc_bernoulli_bound.argtypes = [C.c_double]
+        for nm in ("orc_exp_neg", "orc_log1p_unit", "orc_softplus_neg"):
+            getattr(L, nm).restype = C.c_float
+            getattr(L, nm).argtypes = [C.c_float]
+        L.orc_boxplus.restype = C.c_float
+        L.orc_boxplus.argtypes = [C.c_float, C.c_float]
+        for nm in ("orc_vec_exp_neg", "orc_vec_log1p_unit"):
+            getattr(L, nm).argtypes = [f32p, C.c_int32, f32p]
+        L.orc_vec_boxplus.argtypes = [f32p, f32p, C.c_int32, f32p]
+        L.orc_vec_philox.argtypes = [u32p, u32p, C.c_int32, u32p]
+        L.orc_sample_noise.argtypes = [C.c_int32, C.c_double, C.c_uint64, C.c_uint64, C.c_int32, u8p]
+        L.orc_syndrome.argtypes = [C.c_int32, C.c_int32, i32p, i32p, u8p, C.c_int32, u8p]
+        L.orc_decode.restype = C.c_int32
+        L.orc_decode.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(Params), u8p,
+                                 C.c_uint64, C.c_int32, u8p, u8p, i32p, f32p, u8p, u8p, C.c_int32]
+        L.orc_bp_sweep.restype = C.c_int32
+        L.orc_bp_sweep.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(Params), f32p, u8p,
+                                   f32p, f32p, f32p]
+        L.orc_logical_failure.restype = C.c_int32
+        L.orc_logical_failure.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_int32, i32p, i32p,
+                                          u8p, u8p, C.c_int32, u8p]
+        L.orc_gf2_rank.restype = C.c_int32
+        L.orc_gf2_rank.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
+        L.orc_evidence_thresholds.argtypes = [C.c_int32, f32p]
+        L.orc_bitcentric_machine.restype = C.c_int32
+        L.orc_bitcentric_machine.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_double, u8p,
+                                             C.c_int32, u8p, C.POINTER(C.c_double), i32p]
+        _lib = L
+    return _lib
+
+
+def _csr(M):
+    rp = np.ascontiguousarray(M.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(M.col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    return rp, cl
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 on arrays of counters [k,4] and keys [k,2] (uint32)."""
+    ctr = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
+    key = np.ascontiguousarray(np.atleast_2d(key), dtype=np.uint32)
+    out = np.zeros_like(ctr)
+    lib().orc_vec_philox(_p(ctr, C.c_uint32), _p(key, C.c_uint32), ctr.shape[0], _p(out, C.c_uint32))
+    return out
+
+
+def bernoulli_bound(p: float) -> int:
+    return int(lib().orc_bernoulli_bound(p))
+
+
+def _vec(name, x):
+    x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    y = np.zeros_like(x)
+    getattr(lib(), name)(_p(x, C.c_float), x.size, _p(y, C.c_float))
+    return y
+
+
+def exp_neg(x):
+    return _vec("orc_vec_exp_neg", x)
+
+
+def log1p_unit(x):
+    return _vec("orc_vec_log1p_unit", x)
+
+
+def boxplus(a, b):
+    """a [+] b = 2 atanh(tanh(a/2) tanh(b/2)) in the oracle's FP32 evaluation."""
+    a = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    b = np.ascontiguousarray(b, dtype=np.float32).ravel()
+    y = np.zeros_like(a)
+    lib().orc_vec_boxplus(_p(a, C.c_float), _p(b, C.c_float), a.size, _p(y, C.c_float))
+    return y
+
+
+def evidence_thresholds(dmax: int) -> np.ndarray:
+    t = np.zeros(dmax + 1, dtype=np.float32)
+    lib().orc_evidence_thresholds(dmax, _p(t, C.c_float))
+    return t
+
+
+# ---------------------------------------------------------------- method
+def sample_noise(code, p: float, seed: int, shot0: int, nshots: int) -> np.ndarray:
+    n = code.H.cols
+    e = np.zeros((nshots, n), dtype=np.uint8)
+    lib().orc_sample_noise(n, p, seed, shot0, nshots, _p(e, C.c_uint8))
+    return e
+
+
+def syndrome(code, e) -> np.ndarray:
+    e = np.ascontiguousarray(np.atleast_2d(e), dtype=np.uint8)
+    rp, cl = _csr(code.H)
+    s = np.zeros((e.shape[0], code.H.rows), dtype=np.uint8)
+    lib().orc_syndrome(code.H.rows, code.H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32),
+                       _p(e, C.c_uint8), e.shape[0], _p(s, C.c_uint8))
+    return s
+
+
+def decode(code, params: DecodeParams, e0, shot0: int = 0, nthreads: int = 1,
+           want_beliefs: bool = False, trace: bool = False) -> dict:
+    """Run the round machine on every row of e0 (shot ids shot0, shot0+1, ...)."""
+    e0 = np.ascontiguousarray(np.atleast_2d(e0), dtype=np.uint8)
+    ns, n = e0.shape
+    m = code.H.rows
+    assert n == code.H.cols
+    rp, cl = _csr(code.H)
+    z = np.zeros((ns, n), dtype=np.uint8)
+    s = np.zeros((ns, m), dtype=np.uint8)
+    t = np.zeros(ns, dtype=np.int32)
+    L = np.zeros((ns, n), dtype=np.float32) if want_beliefs else None
+    st = zt = None
+    if trace:
+        assert ns == 1, "traces are per shot"
+        st = np.zeros((params.rounds, m), dtype=np.uint8)
+        zt = np.zeros((params.rounds, n), dtype=np.uint8)
+    P = params.c()
+    rc = lib().orc_decode(m, n, _p(rp, C.c_int32), _p(cl, C.c_int32), C.byref(P), _p(e0, C.c_uint8),
+                          shot0, ns, _p(z, C.c_uint8), _p(s, C.c_uint8), _p(t, C.c_int32),
+                          _p(L, C.c_float) if L is not None else None,
+                          _p(st, C.c_uint8) if st is not None else None,
+                          _p(zt, C.c_uint8) if zt is not None else None, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"oracle decode failed with status {rc}")
+    return {"z": z, "s": s, "tclr": t, "L": L, "s_trace": st, "z_trace": zt}
+
+
+def bp_sweep(code, params: DecodeParams, pi_v, s, mvc):
+    """One check phase then one qubit phase. Returns (m_cv, m_vc)."""
+    rp, cl = _csr(code.H)
+    E = code.H.nnz
+    pi_v = np.ascontiguousarray(pi_v, dtype=np.float32)
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    mvc = np.ascontiguousarray(mvc, dtype=np.float32)
+    mcv_o = np.zeros(E, dtype=np.float32)
+    mvc_o = np.zeros(E, dtype=np.float32)
+    P = params.c()
+    rc = lib().orc_bp_sweep(code.H.rows, code.H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32),
+                            C.byref(P), _p(pi_v, C.c_float), _p(s, C.c_uint8), _p(mvc, C.c_float),
+                            _p(mcv_o, C.c_float), _p(mvc_o, C.c_float))
+    assert rc == 0
+    return mcv_o, mvc_o
+
+
+def logical_failure(code, e0, z) -> np.ndarray:
+    e0 = np.ascontiguousarray(np.atleast_2d(e0), dtype=np.uint8)
+    z = np.ascontiguousarray(np.atleast_2d(z), dtype=np.uint8)
+    hr, hc = _csr(code.H)
+    gr, gc = _csr(code.G)
+    f = np.zeros(e0.shape[0], dtype=np.uint8)
+    rc = lib().orc_logical_failure(code.H.rows, code.H.cols, _p(hr, C.c_int32), _p(hc, C.c_int32),
+                                   code.G.rows, _p(gr, C.c_int32), _p(gc, C.c_int32),
+                                   _p(e0, C.c_uint8), _p(z, C.c_uint8), e0.shape[0], _p(f, C.c_uint8))
+    assert rc == 0
+    return f
+
+
+def gf2_rank(M) -> int:
+    rp, cl = _csr(M)
+    return int(lib().orc_gf2_rank(M.rows, M.cols, _p(rp, C.c_int32), _p(cl, C.c_int32)))
+
+
+def bitcentric_machine(code, q: float, e0, iters: int):
+    """Discrete bit-centric machine (double precision). Returns
+    (e_trace [iters, n], L_trace [iters, n], i_clr)."""
+    rp, cl = _csr(code.H)
+    e0 = np.ascontiguousarray(e0, dtype=np.uint8).ravel()
+    n = code.H.cols
+    et = np.zeros((iters, n), dtype=np.uint8)
+    Lt = np.zeros((iters, n), dtype=np.float64)
+    ic = np.zeros(1, dtype=np.int32)
+    rc = lib().orc_bitcentric_machine(code.H.rows, n, _p(rp, C.c_int32), _p(cl, C.c_int32), q,
+                                      _p(e0, C.c_uint8), iters, _p(et, C.c_uint8),
+                                      Lt.ctypes.data_as(C.POINTER(C.c_double)), _p(ic, C.c_int32))
+    assert rc == 0
+    return et, Lt, int(ic[0])
