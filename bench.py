@@ -1,0 +1,234 @@
+"""Benchmark of the decoder's hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic shots:
+Philox noise -> syndrome, BP rounds with belief-guided moves (one resident
+launch) -> homology-class failure test, for the 2D toric code L = 32 at
+p = 0.05 with 65536 shots per step, 20 BP sweeps per round and 4L = 128
+rounds (normalised min-sum, alpha = 0.75; shots retire once clear). Inputs
+are generated on the device (shot ids advance every step) and every buffer
+is resident in HBM before the timed region starts.
+
+Prints one JSON line. `value` is decoded shots per second; the line also
+carries message updates per second, the roofline of the dominant kernel
+measured with HIP events on its stream, the same workload in the stream
+form, with sum-product and without early retirement, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Device peaks used for roofline fractions (MI355X, published).
+HBM_PEAK_GBS = 8000.0
+CU_COUNT = 256
+CLOCK_GHZ = 2.4
+LANES_PER_CU = 64  # one VALU instruction per lane per clock per CU (4 SIMD x 16 lanes)
+VALU_PEAK_TOPS = CU_COUNT * LANES_PER_CU * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--L", type=int, default=32)
+    ap.add_argument("--p", type=float, default=0.05)
+    ap.add_argument("--shots", type=int, default=65536)
+    ap.add_argument("--rounds", type=int, default=0, help="default 4L")
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--bp", default="minsum", choices=["minsum", "sumproduct"])
+    ap.add_argument("--form", default="resident", choices=["resident", "stream", "auto"])
+    ap.add_argument("--no-retire", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
+    """Runs warmup + steps passes; returns per-step and per-decode times (ms)
+    from HIP events on the stream every kernel is launched on, plus the
+    executed rounds of the last step."""
+    import torch
+    S = args.shots
+    st = torch.cuda.current_stream()
+    e0 = torch.empty((S, code.n), dtype=torch.uint8, device="cuda")
+    out = {"z": torch.empty((S, code.n), dtype=torch.uint8, device="cuda"),
+           "s": torch.empty((S, code.m), dtype=torch.uint8, device="cuda"),
+           "tclr": torch.empty((S,), dtype=torch.int32, device="cuda"), "L": None}
+    ws = torch.empty((max(laim.workspace_bytes(code, P, S, form), 256),), dtype=torch.uint8, device="cuda")
+    fails = torch.zeros((), dtype=torch.int64, device="cuda")
+    rounds_exec = torch.zeros((), dtype=torch.int64, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+
+    def step(i, evs=None):
+        shot0 = shot_base + i * S
+        laim.sample_noise(code, args.p, 0, shot0, S, out=e0)
+        if evs:
+            evs[0].record(st)
+        laim.decode_rounds(code, P, e0, shot0=shot0, form=form, workspace=ws, out=out)
+        if evs:
+            evs[1].record(st)
+        f = laim.logical_failure(code, e0, out["z"])
+        fails.add_(f.sum())
+        t = out["tclr"]
+        rounds_exec.add_(torch.where(t >= 0, t, torch.full_like(t, P.rounds)).sum())
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    fails.zero_()
+    rounds_exec.zero_()
+    t0.record(st)
+    for i in range(steps):
+        step(warmup + i, ev[i])
+    t1.record(st)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    dec_ms = [a.elapsed_time(b) for a, b in ev]
+    return {"ms_per_step": total_ms / steps, "decode_ms": sum(dec_ms) / steps,
+            "failures": int(fails.item()), "rounds_exec": int(rounds_exec.item()),
+            "shots": S * steps}
+
+
+def cpu_baseline(args, spec, P_or, seconds):
+    """The oracle, as it is, on shot ids 0.. of the same workload, in chunks
+    until `seconds` of wall time have passed."""
+    from oracle import oracle as O
+    nthreads = min(16, os.cpu_count() or 1)
+    done = 0
+    rounds = 0
+    t0 = time.perf_counter()
+    chunk = max(nthreads * 2, 16)
+    while time.perf_counter() - t0 < seconds and done < 4096:
+        e0 = O.sample_noise(spec, args.p, 0, done, chunk)
+        r = O.decode(spec, P_or, e0, shot0=done, nthreads=nthreads)
+        O.logical_failure(spec, e0, r["z"])
+        t = r["tclr"]
+        rounds += int(((t >= 0) * t + (t < 0) * P_or.rounds).sum())
+        done += chunk
+    el = time.perf_counter() - t0
+    return done, el, nthreads, rounds
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(shots are independent: N GPUs would each take a disjoint range of shot ids)",
+              file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_2609_38139_amd import codes, laim
+    torch.cuda.set_device(0)
+    L = args.L
+    R = args.rounds or 4 * L
+    spec = codes.toric_2d(L)
+    code = laim.Code(spec, 0)
+    E = code.E
+    P = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire)
+    form = args.form
+    main_run = timed_steps(laim, code, P, args, args.steps, args.warmup, form)
+    S_total = main_run["shots"]
+    sec = main_run["ms_per_step"] * args.steps / 1000.0
+    shots_per_s = S_total / sec
+    msg_updates = 2 * E * args.iters * main_run["rounds_exec"]
+    msg_per_s = msg_updates / sec
+    dec_s = main_run["decode_ms"] / 1000.0
+    msg_per_launch = msg_updates / args.steps
+
+    # roofline of the dominant kernel (the resident decode launch): the
+    # algorithmic work of the BP sweeps is 2E message updates per
+    # shot-sweep; priced in the VALU lane-operations its arithmetic needs
+    # (ops_per_update below) against 256 CU x 64 lanes x 2.4 GHz, and in
+    # the bytes a streaming sweep would move (8 B per update) against HBM.
+    ops_per_update = 11.0 if args.bp == "minsum" else 230.0
+    achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12
+    hbm_equiv_gbs = msg_per_launch * 8.0 / dec_s / 1e9
+    rl = {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 1),
+          "unit": "Tops/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
+          "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
+          "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
+          "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
+          "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
+
+    extras = {}
+    if not args.no_extras:
+        import copy
+        small = copy.copy(args)
+        # stream form (messages in HBM, one launch per sweep): the plain baseline
+        rs = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
+        sec_s = rs["ms_per_step"] / 1000.0
+        upd = 2 * E * args.iters * rs["rounds_exec"]
+        sweeps_bytes = upd * 8.0  # m_{c->v} read by the partner gather + written, 4 B each
+        extras["stream_form"] = {"shots_per_s": round(rs["shots"] / sec_s, 1),
+                                 "msg_updates_per_s": upd / sec_s,
+                                 "decode_ms": round(rs["decode_ms"], 2),
+                                 "algorithmic_hbm_GBs": round(sweeps_bytes / (rs["decode_ms"] / 1000) / 1e9, 1),
+                                 "failures": rs["failures"]}
+        P_fix = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=False)
+        rf = timed_steps(laim, code, P_fix, args, 1, 0, form, shot_base=2 * 10**9)
+        extras["fixed_rounds"] = {"shots_per_s": round(rf["shots"] / (rf["ms_per_step"] / 1000), 1),
+                                  "msg_updates_per_s": 2 * E * args.iters * rf["rounds_exec"] / (rf["ms_per_step"] / 1000),
+                                  "failures": rf["failures"]}
+        other = "sumproduct" if args.bp == "minsum" else "minsum"
+        P_o = laim.DecodeParams(bp=other, rounds=R, iters=args.iters, retire=not args.no_retire)
+        ro = timed_steps(laim, code, P_o, args, 1, 1, form, shot_base=3 * 10**9)
+        extras[other] = {"shots_per_s": round(ro["shots"] / (ro["ms_per_step"] / 1000), 1),
+                         "msg_updates_per_s": 2 * E * args.iters * ro["rounds_exec"] / (ro["ms_per_step"] / 1000),
+                         "decode_ms": round(ro["decode_ms"], 2), "failures": ro["failures"],
+                         "logical_error_rate": ro["failures"] / ro["shots"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        P_or = O.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire)
+        n_done, el, nth, rounds = cpu_baseline(args, spec, P_or, args.cpu_seconds)
+        cpu = {"value": round(n_done / el, 2), "unit": "shots/s", "cores": nth, "kind": "oracle",
+               "msg_updates_per_s": 2 * E * args.iters * rounds / el,
+               "sample": f"shot ids 0..{n_done - 1} of the same workload ({el:.1f} s wall, "
+                         f"{nth} OpenMP threads over shots)"}
+
+    line = {
+        "metric": "shots/s and BP msg-updates/s (2D toric L=32, p=0.05); served p50/p99 latency",
+        "value": round(shots_per_s, 1),
+        "unit": "shots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D toric code L={L}, i.i.d. Z noise p={args.p}, {args.shots} shots per "
+                               f"step (fresh shot ids each step), {args.iters} BP sweeps x {R} rounds, "
+                               f"{args.bp}{' alpha=0.75' if args.bp == 'minsum' else ''}, clocks at "
+                               f"density 0.5, {'retire on clear' if not args.no_retire else 'fixed rounds'}, "
+                               f"{form} form",
+                   "code": f"toric2d:{L}", "p": args.p, "shots_per_step": args.shots, "rounds": R,
+                   "iters": args.iters, "bp": args.bp, "form": form, "retire": not args.no_retire},
+        "msg_updates_per_s": msg_per_s,
+        "logical_error_rate": main_run["failures"] / S_total,
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,281 @@
+/*
+ * laim.h -- C ABI of the MI355X local autonomous inference machine decoder.
+ *
+ * The library decodes quantum CSS codes with the local machine of
+ * "Local autonomous inference machines for quantum LDPC codes": many
+ * Monte-Carlo shots run belief propagation (BP) on the Tanner graph of the
+ * X-check matrix H (Preliminaries; SM Definition "Tanner graph"),
+ * interleaved with belief-guided local moves of the active checks
+ * (Algorithm 1: Evidence test and LocalMove), until the syndrome clears.
+ *
+ * Conventions for every call:
+ *  - Pointers named *_host are host memory; every other buffer is device
+ *    memory on the code's device. All arrays are dense, row-major, C order.
+ *  - The caller owns every input, output and workspace buffer. The library
+ *    owns laim_code, laim_batch_plan and laim_server objects and keeps no
+ *    caller pointer after the call's work has completed on its stream.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *    and is asynchronous unless stated otherwise.
+ *  - A non-zero status means nothing was enqueued; argument and shape errors
+ *    are detected before any work is launched. laim_last_error() returns a
+ *    text for the last failing call on the calling thread. No C++ exception
+ *    crosses this interface.
+ *  - Results depend only on (H, parameters, seed, shot ids, e0): never on
+ *    the stream, the batch a shot is in, its position, the launch shape or
+ *    the form used.
+ */
+#ifndef LAIM_H
+#define LAIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t laim_status;
+#define LAIM_OK 0
+#define LAIM_EINVAL (-1) /* bad argument or shape */
+#define LAIM_ENOMEM (-2) /* allocation failed or workspace too small */
+#define LAIM_EHIP (-3)   /* a HIP runtime call failed */
+#define LAIM_EUNSUP (-4) /* valid, but not supported by this build */
+#define LAIM_EBUSY (-5)  /* resource exhausted (server slots, budget) */
+
+typedef void* laim_stream; /* hipStream_t */
+
+/* Text of the last failure on this thread ("" if none). */
+const char* laim_last_error(void);
+/* ABI version of this library (increments on incompatible change). */
+int32_t laim_version(void);
+
+/* ------------------------------------------------------------------ codes
+ * laim_build_tanner -- the Tanner graph of H (SM Definition "Tanner
+ * graph": an edge {v, c} for every H[c][v] = 1) laid out for the device, and
+ * the logical basis used by the success test (Preliminaries, conditions (1)
+ * and (2)).
+ *   m, n             H is m x n (checks x qubits), m, n >= 1.
+ *   h_rowptr_host    [m+1] CSR row pointers of H, h_rowptr[0] = 0.
+ *   h_col_host       [nnz] column indices; strictly ascending within a row,
+ *                    0 <= col < n. Every qubit must lie in >= 1 check.
+ *   mg, g_*_host     G (mg x n): the commuting stabilisers whose row space is
+ *                    the trivial class (H_Z for Z noise). mg may be 0.
+ *                    H G^T = 0 is required (checked).
+ *   device           HIP device index that will hold the code.
+ *   out              receives the code object (free with laim_free_code).
+ * The logical basis (k rows spanning ker(G) modulo row(H)) is computed by
+ * GF(2) elimination, which is done for n <= 20480; larger codes must pass
+ * their logicals through laim_build_tanner_ex. Check degree <= 32 and qubit
+ * degree <= 16 are supported.
+ */
+typedef struct laim_code laim_code;
+
+laim_status laim_build_tanner(int32_t m, int32_t n, const int32_t* h_rowptr_host,
+                              const int32_t* h_col_host, int32_t mg,
+                              const int32_t* g_rowptr_host, const int32_t* g_col_host,
+                              int32_t device, laim_code** out);
+
+/* As laim_build_tanner, with the logical basis given by the caller: kl rows
+ * (CSR, ascending columns), each of even overlap with every row of G
+ * (checked) and independent modulo row(H) (not checked). kl = -1 asks for
+ * the elimination. */
+laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr_host,
+                                 const int32_t* h_col_host, int32_t mg,
+                                 const int32_t* g_rowptr_host, const int32_t* g_col_host,
+                                 int32_t kl, const int32_t* l_rowptr_host,
+                                 const int32_t* l_col_host, int32_t device, laim_code** out);
+
+void laim_free_code(laim_code* code);
+
+/* Sizes: m checks, n qubits, E edges, k logicals, largest check and qubit
+ * degree. Any output pointer may be NULL. */
+laim_status laim_code_info(const laim_code* code, int32_t* m, int32_t* n, int32_t* E, int32_t* k,
+                           int32_t* dc_max, int32_t* dv_max);
+
+/* The logical basis as a dense k x n 0/1 host matrix (out_host [k][n]). */
+laim_status laim_code_logicals(const laim_code* code, uint8_t* out_host);
+
+/* Host-only GF(2) elimination (no device involved): writes up to kmax rows
+ * of a basis of ker(G) modulo row(H) to out_host [kmax][n] and its size to
+ * *k_out. Same limits as laim_build_tanner. */
+laim_status laim_host_logicals(int32_t m, int32_t n, const int32_t* h_rowptr_host,
+                               const int32_t* h_col_host, int32_t mg, const int32_t* g_rowptr_host,
+                               const int32_t* g_col_host, int32_t kmax, uint8_t* out_host,
+                               int32_t* k_out);
+
+/* ------------------------------------------------------------------ noise
+ * laim_sample_noise -- i.i.d. Bernoulli(p) Z errors (Preliminaries; SM
+ * prior). e_out[i][v] = 1 iff w < floor(p 2^32) (p >= 1: always), where w is
+ * word (v mod 4) of Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ * counter = (shot_lo, shot_hi, floor(v / 4), 0), shot = shot0 + i.
+ *   e_out   device [nshots][n] uint8, written with 0/1.
+ * nshots >= 0; p in [0, 1] (values outside are clamped to it).
+ */
+laim_status laim_sample_noise(const laim_code* code, double p, uint64_t seed, uint64_t shot0,
+                              int32_t nshots, uint8_t* e_out, laim_stream stream);
+
+/* laim_syndrome -- s = H e mod 2 (SM, syndrome of an error).
+ *   e      device [nshots][n] uint8 (only bit 0 is read)
+ *   s_out  device [nshots][m] uint8 */
+laim_status laim_syndrome(const laim_code* code, const uint8_t* e, int32_t nshots, uint8_t* s_out,
+                          laim_stream stream);
+
+/* ----------------------------------------------------------------- decode
+ * Parameters of the round-discretised machine (Algorithm 1 run in rounds):
+ * each round runs `iters` BP sweeps (check phase, then qubit phase; BP-LLR2
+ * then BP-LLR1; messages start at 0 and are never reset), then every
+ * active check whose Poisson clock rang in the round (probability
+ * mask_density, word 0 of Philox(key = seed, counter = (shot_lo, shot_hi, c,
+ * 16 r + 1)) below floor(mask_density 2^32)) and whose Evidence holds
+ * (max over v in N(c) of L_v >= -log(d_c - 1), i.e. Pr_BP >= 1/d_c) flips its
+ * LocalMove qubit (the largest belief; ties, compared with ==, broken by
+ * word 1 of the same Philox output as tie number floor(w1 ntie / 2^32) in
+ * ascending qubit order). A qubit chosen by several checks flips once. The
+ * syndrome is then updated (s ^= H f). All arithmetic is FP32 without
+ * contraction: every LLR (messages and beliefs) is clamped to [-clamp,
+ * clamp] (SM numerical details: CLAMP).
+ */
+typedef struct {
+  int32_t bp;           /* 0: normalised min-sum (alpha * min, sign product); 1: sum-product
+                           (BP-LLR2, evaluated as an ascending box-plus fold) */
+  float alpha;          /* min-sum scale, > 0 (0.75) */
+  double q;             /* decoder prior in (0, 1): pi = log(q / (1 - q)) (Table S1: 0.05) */
+  float clamp;          /* CLAMP > 0 (Table S1: 1000) */
+  int32_t iters;        /* BP sweeps per round, >= 0 (20) */
+  int32_t rounds;       /* feedback rounds R, >= 0; a shot not clear after R rounds fails */
+  double mask_density;  /* probability that a check's clock rings in a round (0.5) */
+  int32_t gauge;        /* must be 0 (the LLR switch of the bit-centric machine is not
+                           part of the check-centric machine) */
+  int32_t evidence;     /* 1: apply the Evidence test; 0: ablation without it */
+  int32_t retire;       /* 1: stop a shot at its first clear syndrome (same z, s, t_clr) */
+  uint64_t seed;        /* Philox key for the clocks and tie-breaks */
+} laim_decode_params;
+
+/* Execution forms of laim_decode_rounds; all give identical results. */
+#define LAIM_FORM_AUTO 0     /* resident if the code fits in LDS, else stream */
+#define LAIM_FORM_RESIDENT 1 /* one persistent launch, per-shot state in LDS/registers */
+#define LAIM_FORM_STREAM 2   /* messages in HBM, one launch per BP sweep and per phase */
+
+/* Workspace needed by laim_decode_rounds for nshots shots in `form`. */
+size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* params,
+                            int32_t nshots, int32_t form);
+
+/* laim_decode_rounds -- run the machine on nshots shots (ids shot0 + i).
+ *   e0         device [nshots][n] uint8: the initial errors (bit 0 read)
+ *   workspace  device, >= laim_workspace_bytes(...) bytes, 256-byte aligned;
+ *              scratch owned by the caller, contents undefined afterwards
+ *   z_out      device [nshots][n] uint8: cumulative correction z
+ *   s_out      device [nshots][m] uint8: final syndrome H (e0 ^ z)
+ *   tclr_out   device [nshots] int32: rounds completed when the syndrome first
+ *              became 0 (0 if H e0 = 0), or -1 if it never did within R
+ *   L_out      device [nshots][n] float or NULL: beliefs of the final message
+ *              state, clamp(pi + sum over N(v) of m_{c->v}) (for a retired
+ *              shot, the state at retirement)
+ * Concurrent calls on different streams may share a laim_code but not a
+ * workspace.
+ */
+laim_status laim_decode_rounds(const laim_code* code, const laim_decode_params* params,
+                               const uint8_t* e0, uint64_t shot0, int32_t nshots, void* workspace,
+                               size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
+                               float* L_out, int32_t form, laim_stream stream);
+
+/* Launch shape of the resident form (0 in a field means: choose). */
+typedef struct {
+  int32_t threads_per_shot; /* threads cooperating on one shot */
+  int32_t checks_per_thread;
+  int32_t shots_per_block;
+} laim_resident_cfg;
+
+/* As laim_decode_rounds in the resident form with an explicit launch shape
+ * (used by the autotuner; results do not depend on the shape). */
+laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_params* params,
+                                   const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                                   void* workspace, size_t ws_bytes, uint8_t* z_out,
+                                   uint8_t* s_out, int32_t* tclr_out, float* L_out,
+                                   const laim_resident_cfg* cfg, laim_stream stream);
+
+/* Sets the resident launch shape used from now on for this code and BP
+ * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */
+laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg);
+/* The launch shape that would be used (after the built-in rule). */
+laim_status laim_get_resident_cfg(const laim_code* code, int32_t bp, laim_resident_cfg* cfg);
+
+/* laim_logical_failure -- decoder failure (Preliminaries): with r = e0 ^ z,
+ * fail = [H r != 0] or [r not in row(G)], the latter tested as any odd
+ * overlap of r with a row of the logical basis.
+ *   e0, z     device [nshots][n] uint8
+ *   fail_out  device [nshots] uint8 (0/1) */
+laim_status laim_logical_failure(const laim_code* code, const uint8_t* e0, const uint8_t* z,
+                                 int32_t nshots, uint8_t* fail_out, laim_stream stream);
+
+/* ----------------------------------------------------------- batched form
+ * One persistent launch over shots of several codes and sizes (each item a
+ * contiguous range of shot ids of one code with its own parameters and
+ * outputs, laid out as in laim_decode_rounds). The plan precomputes the work
+ * list, owns its device workspace and records the launch sequence in a HIP
+ * graph that laim_batch_plan_launch replays. Inputs and outputs are read and
+ * written at the addresses given at creation.
+ */
+typedef struct {
+  const laim_code* code;
+  laim_decode_params params;
+  const uint8_t* e0;  /* device [nshots][n] */
+  uint64_t shot0;
+  int32_t nshots;
+  uint8_t* z_out;     /* device [nshots][n] */
+  uint8_t* s_out;     /* device [nshots][m] */
+  int32_t* tclr_out;  /* device [nshots] */
+  uint8_t* fail_out;  /* device [nshots] or NULL: logical failure of each shot */
+} laim_batch_item;
+
+typedef struct laim_batch_plan laim_batch_plan;
+
+laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
+                                   laim_stream stream, laim_batch_plan** out);
+laim_status laim_batch_plan_launch(laim_batch_plan* plan, laim_stream stream);
+void laim_batch_plan_destroy(laim_batch_plan* plan);
+
+/* --------------------------------------------------------------- serving
+ * A continuous-batching server: requests (one shot of one code each, with
+ * its own rounds budget) are admitted while device memory and slots allow,
+ * keep their BP messages and syndrome state resident in device memory
+ * across rounds, and advance one round per laim_server_step together with
+ * every other resident request. Requests that do not fit wait in FIFO order.
+ * Calls on one server must not overlap; the server uses its own stream.
+ */
+typedef struct laim_server laim_server;
+
+typedef struct {
+  uint64_t ticket;   /* from laim_server_submit */
+  int32_t round;     /* rounds completed by this request after this step */
+  int32_t done;      /* 1 when the request finished (cleared or rounds exhausted) */
+  int32_t tclr;      /* as in laim_decode_rounds, valid when done */
+  int32_t flips;     /* qubits flipped in this round */
+  int32_t defects;   /* syndrome weight after this round */
+} laim_server_event;
+
+laim_status laim_server_create(int32_t device, size_t mem_budget_bytes, int32_t max_slots,
+                               laim_server** out);
+/* Queues one request; e0_host [n] (0/1) is copied. Returns a ticket. */
+laim_status laim_server_submit(laim_server* srv, const laim_code* code,
+                               const laim_decode_params* params, uint64_t shot_id,
+                               const uint8_t* e0_host, uint64_t* ticket);
+/* Admits waiting requests that fit, advances every resident request by one
+ * round, and returns one event per advanced request (blocking until the
+ * round's results are on the host). events_host has room for max_events. */
+laim_status laim_server_step(laim_server* srv, laim_server_event* events_host, int32_t max_events,
+                             int32_t* n_events);
+/* Final z [n], s [m] and t_clr of a finished request (host copies); the
+ * request's storage is released afterwards. */
+laim_status laim_server_result(laim_server* srv, uint64_t ticket, uint8_t* z_host, uint8_t* s_host,
+                               int32_t* tclr);
+/* Resident requests, waiting requests, bytes in use. */
+laim_status laim_server_stats(const laim_server* srv, int32_t* resident, int32_t* waiting,
+                              size_t* bytes_in_use);
+void laim_server_destroy(laim_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAIM_H */

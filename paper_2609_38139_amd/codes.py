@@ -86,13 +86,19 @@ class CSR:
 
 @dataclass
 class Code:
-    """A CSS code seen from the decoder: X checks ``H`` and Z stabilisers ``G``."""
+    """A CSS code seen from the decoder: X checks ``H`` and Z stabilisers ``G``.
+
+    ``logicals`` optionally lists a basis of ker(G) modulo row(H) (one row
+    per logical qubit) in closed form; without it the library finds one by
+    GF(2) elimination.
+    """
 
     name: str
     H: CSR
     G: CSR
     # sizes used in the literature's notation, kept for reporting only
     meta: dict = field(default_factory=dict)
+    logicals: CSR | None = None
 
     @property
     def n(self) -> int:
@@ -143,6 +149,10 @@ def toric_2d(L: int) -> Code:
     """2D toric code, ``A = 1 + x``, ``B = 1 + y``: n = 2L^2, m = L^2."""
     c = group_algebra_code(L, L, [(0, 0), (1, 0)], [(0, 0), (0, 1)], f"toric2d_L{L}")
     c.meta = {"L": L, "family": "toric2d"}
+    # a row of A-block edges (a = 0, every b) and a column of B-block edges
+    # (every a, b = 0): each meets every plaquette an even number of times
+    c.logicals = CSR.from_rows(2, 2 * L * L, [[b for b in range(L)],
+                                              [L * L + a * L for a in range(L)]])
     return c
 
 
@@ -190,16 +200,37 @@ def toric_3d_point(L: int) -> Code:
     """3D toric code, point-like sector: vertex checks (weight 6), face stabilisers."""
     vr, fr = _toric3d_parts(L)
     L3 = L ** 3
+    # edges of direction a crossing the plane v_a = 0 (L^2 each)
+    logi = []
+    for a in range(3):
+        row = []
+        for z in range(L):
+            for y in range(L):
+                for x in range(L):
+                    if (x, y, z)[a] == 0:
+                        row.append(a * L3 + _v3(L, x, y, z))
+        logi.append(row)
     return Code(f"toric3d_point_L{L}", CSR.from_rows(L3, 3 * L3, vr),
-                CSR.from_rows(3 * L3, 3 * L3, fr), {"L": L, "family": "toric3d_point"})
+                CSR.from_rows(3 * L3, 3 * L3, fr), {"L": L, "family": "toric3d_point"},
+                CSR.from_rows(3, 3 * L3, logi))
 
 
 def toric_3d_membrane(L: int) -> Code:
     """3D toric code, membrane-like sector: face checks (weight 4), vertex stabilisers."""
     vr, fr = _toric3d_parts(L)
     L3 = L ** 3
+    # straight lines of direction a through the origin (L edges each)
+    logi = []
+    for a in range(3):
+        row = []
+        for t in range(L):
+            xyz = [0, 0, 0]
+            xyz[a] = t
+            row.append(a * L3 + _v3(L, *xyz))
+        logi.append(row)
     return Code(f"toric3d_membrane_L{L}", CSR.from_rows(3 * L3, 3 * L3, fr),
-                CSR.from_rows(L3, 3 * L3, vr), {"L": L, "family": "toric3d_membrane"})
+                CSR.from_rows(L3, 3 * L3, vr), {"L": L, "family": "toric3d_membrane"},
+                CSR.from_rows(3, 3 * L3, logi))
 
 
 def repetition(d: int, periodic: bool = True) -> Code:

@@ -1,0 +1,106 @@
+// device_math.h -- device-side primitives of the decoder: the counter-based
+// generator behind every random draw, and the FP32 arithmetic of the BP
+// check rule (BP-LLR2). Compiled with -ffp-contract=off: every expression
+// below is one IEEE operation per arithmetic operator, evaluated in the
+// order written, so results are reproducible bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace laim {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11). Ten rounds of the 4x32 S-box: the products of
+// words 0 and 2 with the two round multipliers are split into halves; the
+// high halves are mixed into words 1 and 3 together with the round key;
+// the round key advances by the two Weyl constants after each round.
+struct Philox4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t a = 0xD2511F53u * c0;                  // low half of M0 * c0
+    const uint32_t ah = __umulhi(0xD2511F53u, c0);        // high half
+    const uint32_t b = 0xCD9E8D57u * c2;
+    const uint32_t bh = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = bh ^ c1 ^ k0;
+    const uint32_t n2 = ah ^ c3 ^ k1;
+    c0 = n0;
+    c1 = b;
+    c2 = n2;
+    c3 = a;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Philox4{c0, c1, c2, c3};
+}
+
+// Bernoulli event "w < bound" with a 64-bit bound (bound = 2^32 means always).
+__device__ __forceinline__ bool below(uint32_t w, uint64_t bound) { return (uint64_t)w < bound; }
+
+__device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
+
+// e^{-a} for a >= 0, by Cody-Waite reduction -a = k ln2 + r (ln2 split into
+// a head with 16 significant bits, so k*head is exact, and a tail), the
+// degree-7 Taylor polynomial of e^r in Horner form, and a 2^k scale built in
+// the exponent field. Arguments above 80 (and +inf) give 0.
+__device__ __forceinline__ float exp_neg(float a) {
+  if (!(a <= 80.0f)) return 0.0f;
+  const float ln2_hi = __uint_as_float(0x3F317200u);
+  const float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
+  const float log2e = (float)1.44269504088896340736;
+  const float x = -a;
+  const float kf = floorf(x * log2e + 0.5f);
+  const float r = (x - kf * ln2_hi) - kf * ln2_lo;
+  float p = 1.0f / 5040.0f;
+  p = p * r + 1.0f / 720.0f;
+  p = p * r + 1.0f / 120.0f;
+  p = p * r + 1.0f / 24.0f;
+  p = p * r + 1.0f / 6.0f;
+  p = p * r + 0.5f;
+  p = p * r + 1.0f;
+  p = p * r + 1.0f;
+  const int k = (int)kf;
+  return p * __uint_as_float((uint32_t)(k + 127) << 23);
+}
+
+// log(1 + u) for u in [0, 1]: 2 atanh(s), s = u / (2 + u) <= 1/3, from the
+// atanh series s + s^3/3 + ... + s^15/15 (Horner in s^2).
+__device__ __forceinline__ float log1p_unit(float u) {
+  const float s = u / (2.0f + u);
+  const float z = s * s;
+  float q = 1.0f / 15.0f;
+  q = q * z + 1.0f / 13.0f;
+  q = q * z + 1.0f / 11.0f;
+  q = q * z + 1.0f / 9.0f;
+  q = q * z + 1.0f / 7.0f;
+  q = q * z + 1.0f / 5.0f;
+  q = q * z + 1.0f / 3.0f;
+  const float s2 = s + s;
+  return s2 + (s2 * z) * q;
+}
+
+// log(1 + e^{-y}), y >= 0.
+__device__ __forceinline__ float softplus_neg(float y) { return log1p_unit(exp_neg(y)); }
+
+// a [+] b = 2 atanh(tanh(a/2) tanh(b/2)) (the two-input sum-product check
+// rule; Hagenauer, Offer, Papke 1996), through its exact rewriting on the
+// magnitudes |a| [+] |b| = min + log(1 + e^{-(|a|+|b|)}) - log(1 + e^{-||a|-|b||}),
+// a negative rounding set to +0, and the sign sg(a) sg(b) with sg(x) = -1
+// iff x < 0.
+__device__ __forceinline__ float boxplus(float a, float b) {
+  const float aa = fabsf(a);
+  const float ab = fabsf(b);
+  const float mn = (ab < aa) ? ab : aa;
+  const float d = (aa < ab) ? (ab - aa) : (aa - ab);
+  float mag = (mn + softplus_neg(aa + ab)) - softplus_neg(d);
+  if (mag < 0.0f) mag = 0.0f;
+  const bool neg = (a < 0.0f) != (b < 0.0f);
+  return neg ? -mag : mag;
+}
+
+}  // namespace laim

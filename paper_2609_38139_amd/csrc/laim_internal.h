@@ -1,0 +1,104 @@
+// laim_internal.h -- shared declarations of the library's host code and
+// kernel launchers (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "laim.h"
+
+namespace laim {
+
+// Limits of the device layout.
+constexpr int kMaxCheckDegree = 32;
+constexpr int kMaxQubitDegree = 16;
+constexpr int kStreamTile = 64;  // shots per tile in the stream form (one wavefront)
+
+// Edge reference (c, j): the j-th qubit of check c, packed as (c << 5) | j.
+__host__ __device__ inline int32_t pack_edge(int32_t c, int32_t j) { return (c << 5) | j; }
+__host__ __device__ inline int32_t edge_check(int32_t e) { return e >> 5; }
+__host__ __device__ inline int32_t edge_slot(int32_t e) { return e & 31; }
+
+// Device-side view of a code. Tables are ELL-padded with -1.
+struct DevCode {
+  int32_t m, n, E, dcmax, dvmax, k, kw, regular;
+  const int32_t* chk_var;   // [m][dcmax] qubits of check c, ascending
+  const int32_t* chk_deg;   // [m]
+  const int32_t* var_deg;   // [n]
+  const int32_t* var_edge;  // [n][dvmax] packed edges of qubit v, ascending check
+  const int32_t* partner;   // [m][dcmax][dvmax-1] packed edges of qubit chk_var[c][j]
+                            // other than (c, j), ascending check
+  const uint32_t* lcol;     // [n][kw] bit i of word w: qubit v in logical 32w + i
+  const float* thr;         // [dcmax + 1] Evidence bound per check degree
+};
+
+void set_error(const char* fmt, ...);
+laim_status hip_fail(hipError_t e, const char* what);
+
+// Parameters resolved on the host for the kernels.
+struct KParams {
+  int32_t bp;
+  float alpha;
+  float pi;       // (float) log(q / (1 - q))
+  float clamp;
+  int32_t iters;
+  int32_t rounds;
+  uint64_t mask_bound;  // floor(mask_density 2^32), 2^32 = always
+  int32_t evidence;
+  int32_t retire;
+  uint64_t seed;
+};
+
+laim_status resolve_params(const laim_decode_params* p, KParams* kp);
+uint64_t bernoulli_bound(double p);
+
+// ---- kernel launchers (laim_kernels.hip) ----
+hipError_t launch_noise(const DevCode& c, uint64_t bound, uint64_t seed, uint64_t shot0,
+                        int32_t nshots, uint8_t* e, hipStream_t st);
+hipError_t launch_syndrome(const DevCode& c, const uint8_t* e, int32_t nshots, uint8_t* s,
+                           hipStream_t st);
+hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z, int32_t nshots,
+                          uint8_t* fail, hipStream_t st);
+
+struct ResidentShape {
+  int32_t nt;    // threads per shot
+  int32_t cpt;   // checks per thread
+  int32_t vpt;   // qubits per thread
+  int32_t spb;   // shots per block
+  int32_t mpad;  // LDS stride of one edge slot (>= nt * cpt)
+  size_t lds;    // dynamic LDS bytes per block
+};
+
+// Picks / validates the resident launch shape; returns false (with an
+// error text) if the code cannot run resident with it.
+bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
+                    int device);
+size_t resident_workspace_bytes();
+hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                           const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
+                           uint8_t* z, uint8_t* s, int32_t* tclr, float* L, hipStream_t st);
+
+size_t stream_workspace_bytes(const DevCode& c, int32_t nshots);
+hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
+                         int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
+                         hipStream_t st);
+
+// Batched persistent launch over several codes (laim_batch.hip).
+struct BatchUnit;  // opaque here
+
+}  // namespace laim
+
+// The code object behind the opaque ABI handle.
+struct laim_code {
+  int32_t device;
+  int32_t m, n, E, dcmax, dvmax, k;
+  std::vector<int32_t> h_rowptr, h_col;  // H (host copy)
+  std::vector<uint8_t> logicals;         // [k][n] dense host copy
+  void* dev_mem;                         // one allocation holding every table
+  laim::DevCode dev;
+  bool has_cfg[2];
+  laim_resident_cfg cfg[2];
+};

@@ -1,0 +1,1020 @@
+// laim_kernels.hip -- gfx950 kernels of the decoder and their launchers.
+//
+// Notation: m checks, n qubits, an edge (c, j) is the j-th qubit of check c
+// (SM Definition "Tanner graph"); m_{c->v} / m_{v->c} are the LLR messages
+// of Eqs. (BP-LLR1), (BP-LLR2); pi = log(q / (1 - q)).
+//
+// Both decode forms keep only the check-to-qubit messages m_{c->v} as
+// state: a sweep's qubit phase m_{v->c} = clamp(pi + sum_{c' != c} m_{c'->v})
+// is recomputed, in ascending check order, where the next check phase reads
+// it. This is the same arithmetic as a stored two-phase sweep (check phase
+// from m_{v->c}, then qubit phase), with the very first check phase of a
+// shot reading m_{v->c} = 0.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "laim_internal.h"
+
+namespace laim {
+
+// ---------------------------------------------------------------- noise
+// One thread per (shot, block of 4 qubits): one Philox call gives the four
+// uniform words of qubits 4b .. 4b+3.
+__global__ void __launch_bounds__(256) noise_kernel(int32_t n, int32_t nb4, uint64_t bound,
+                                                    uint64_t seed, uint64_t shot0, int64_t total,
+                                                    uint8_t* __restrict__ e) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t i = idx / nb4;
+  const int32_t b = (int32_t)(idx - i * nb4);
+  const uint64_t shot = shot0 + (uint64_t)i;
+  const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)b, 0u,
+                                  (uint32_t)seed, (uint32_t)(seed >> 32));
+  uint8_t* row = e + i * (int64_t)n;
+  const int32_t v = 4 * b;
+  if (v + 0 < n) row[v + 0] = below(w.w0, bound) ? 1 : 0;
+  if (v + 1 < n) row[v + 1] = below(w.w1, bound) ? 1 : 0;
+  if (v + 2 < n) row[v + 2] = below(w.w2, bound) ? 1 : 0;
+  if (v + 3 < n) row[v + 3] = below(w.w3, bound) ? 1 : 0;
+}
+
+hipError_t launch_noise(const DevCode& c, uint64_t bound, uint64_t seed, uint64_t shot0,
+                        int32_t nshots, uint8_t* e, hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  const int32_t nb4 = (c.n + 3) / 4;
+  const int64_t total = (int64_t)nb4 * nshots;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(noise_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.n, nb4, bound, seed,
+                     shot0, total, e);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- syndrome
+__global__ void __launch_bounds__(256) syndrome_kernel(DevCode c, const uint8_t* __restrict__ e,
+                                                       int64_t total, uint8_t* __restrict__ s) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t i = idx / c.m;
+  const int32_t ch = (int32_t)(idx - i * c.m);
+  const uint8_t* row = e + i * (int64_t)c.n;
+  const int32_t d = c.chk_deg[ch];
+  uint32_t x = 0;
+  for (int32_t j = 0; j < d; ++j) x ^= row[c.chk_var[(int64_t)ch * c.dcmax + j]];
+  s[idx] = (uint8_t)(x & 1u);
+}
+
+hipError_t launch_syndrome(const DevCode& c, const uint8_t* e, int32_t nshots, uint8_t* s,
+                           hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  const int64_t total = (int64_t)c.m * nshots;
+  hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, c,
+                     e, total, s);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- failure
+// One block per shot: r = e0 ^ z; fail = any(H r) or any odd overlap of r
+// with a logical (the logical parities are folded into LDS words).
+constexpr int kFailMaxWords = 64;
+
+__global__ void __launch_bounds__(256) failure_kernel(DevCode c, const uint8_t* __restrict__ e0,
+                                                      const uint8_t* __restrict__ z,
+                                                      uint8_t* __restrict__ fail) {
+  __shared__ uint32_t par[kFailMaxWords];
+  __shared__ int32_t anys;
+  const int64_t i = blockIdx.x;
+  const uint8_t* a = e0 + i * (int64_t)c.n;
+  const uint8_t* b = z + i * (int64_t)c.n;
+  for (int w = threadIdx.x; w < kFailMaxWords; w += blockDim.x) par[w] = 0u;
+  if (threadIdx.x == 0) anys = 0;
+  __syncthreads();
+  uint32_t local[4] = {0u, 0u, 0u, 0u};
+  for (int32_t v = threadIdx.x; v < c.n; v += blockDim.x) {
+    if ((a[v] ^ b[v]) & 1u) {
+      for (int32_t w = 0; w < c.kw; ++w) {
+        const uint32_t bits = c.lcol[(int64_t)v * c.kw + w];
+        if (w < 4)
+          local[w] ^= bits;
+        else if (bits)
+          atomicXor(&par[w], bits);
+      }
+    }
+  }
+  for (int32_t w = 0; w < c.kw && w < 4; ++w)
+    if (local[w]) atomicXor(&par[w], local[w]);
+  int32_t mine = 0;
+  for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+    const int32_t d = c.chk_deg[ch];
+    uint32_t x = 0;
+    for (int32_t j = 0; j < d; ++j) {
+      const int32_t v = c.chk_var[(int64_t)ch * c.dcmax + j];
+      x ^= (uint32_t)(a[v] ^ b[v]);
+    }
+    mine |= (int32_t)(x & 1u);
+  }
+  if (mine) anys = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t f = (uint32_t)anys;
+    for (int32_t w = 0; w < c.kw; ++w) f |= par[w];
+    fail[i] = f ? 1 : 0;
+  }
+}
+
+hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z, int32_t nshots,
+                          uint8_t* fail, hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  if (c.kw > kFailMaxWords) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(failure_kernel, dim3((unsigned)nshots), dim3(256), 0, st, c, e0, z, fail);
+  return hipGetLastError();
+}
+
+// ====================================================================
+// Resident form: one persistent launch. A block holds `spb` shot groups of
+// `nt` threads; thread t of a group owns checks t + k nt (k < CPT) and qubits
+// t + k nt (k < vpt). Per group, LDS holds the current m_{c->v} in
+// slot-major order msg[j * mpad + c] (consecutive lanes touch consecutive
+// words) plus one word holding -0.0 that padded qubit-side partners point
+// at (x + (-0.0) == x for every x), and one byte per qubit for the flip
+// requests of the feedback step. A block takes `spb` consecutive shots from
+// a queue, runs them in lockstep for up to R rounds, writes their results,
+// and takes the next ones until the queue is empty.
+// ====================================================================
+struct ResArgs {
+  int32_t nt, vpt, spb, mpad;
+  int32_t group_bytes;
+  const uint8_t* e0;
+  uint64_t shot0;
+  int32_t nshots;
+  uint32_t* counter;  // queue head, zeroed before the launch
+  uint8_t* z;
+  uint8_t* s;
+  int32_t* tclr;
+  float* L;
+};
+
+// LDS control words at the start of the block's LDS.
+constexpr int kCtrlWords = 128;  // [0] queue base; flags per group follow
+constexpr int kMaxShotsPerBlock = 31;
+
+template <int DC, int DV, int CPT, int BP, bool REG>
+__global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, ResArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+  // ctrl layout: [0] base, [1 + g] init flag, [1 + spb + g] round-parity-0 flag,
+  // [1 + 2 spb + g] round-parity-1 flag, [1 + 3 spb + g] group still working.
+  const int32_t spb = a.spb;
+  const int32_t tid = threadIdx.x;
+  const int32_t g = tid / a.nt;
+  const int32_t t = tid - g * a.nt;
+  float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)g * a.group_bytes);
+  const int32_t zslot = DC * a.mpad;
+  uint8_t* fl = reinterpret_cast<uint8_t*>(msg + zslot + 4);
+  const float C = kp.clamp;
+  const float pi = kp.pi;
+
+  // ---- per-thread graph tables, loaded once
+  int32_t cidx[CPT];
+  int32_t deg[CPT];
+  int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int32_t ch = t + k * a.nt;
+    const bool valid = ch < c.m;
+    cidx[k] = valid ? ch : -1;
+    deg[k] = valid ? c.chk_deg[ch] : 0;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+#pragma unroll
+      for (int p = 0; p < DV - 1; ++p) {
+        int32_t e = -1;
+        if (valid && j < c.dcmax && p < c.dvmax - 1)
+          e = c.partner[((int64_t)ch * c.dcmax + j) * (c.dvmax - 1) + p];
+        pidx[k][j][p] = (e >= 0) ? edge_slot(e) * a.mpad + edge_check(e) : zslot;
+      }
+    }
+  }
+  if (t == 0) msg[zslot] = -0.0f;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) ctrl[0] = (int32_t)atomicAdd(a.counter, (uint32_t)spb);
+    __syncthreads();
+    const int32_t base = ctrl[0];
+    if (base >= a.nshots) break;
+    const int32_t idx = base + g;
+    const bool alive = idx < a.nshots;
+    const uint64_t shot = a.shot0 + (uint64_t)(alive ? idx : 0);
+    const uint8_t* e0row = a.e0 + (int64_t)(alive ? idx : 0) * c.n;
+
+    // ---- shot start: e0, z = 0, s = H e0, messages 0, no flip requests
+    uint32_t zb = 0, sb = 0;
+#pragma unroll 1
+    for (int k = 0; k < a.vpt; ++k) {
+      const int32_t v = t + k * a.nt;
+      if (v < c.n) fl[v] = 0;
+    }
+#pragma unroll 1
+    for (int k = 0; k < CPT; ++k) {
+      const int32_t ch = t + k * a.nt;
+      if (ch >= c.m) continue;
+      for (int j = 0; j < DC; ++j) msg[j * a.mpad + ch] = 0.0f;
+      uint32_t x = 0;
+      if (alive) {
+        const int32_t d = c.chk_deg[ch];
+        for (int32_t j = 0; j < d; ++j) x ^= e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
+      }
+      sb |= (x & 1u) << k;
+    }
+    if (t == 0) {
+      ctrl[1 + g] = 0;
+      ctrl[1 + spb + g] = 0;
+    }
+    __syncthreads();
+    if (sb) ctrl[1 + g] = 1;
+    __syncthreads();
+    int32_t tclr = ctrl[1 + g] ? -1 : 0;
+    bool working = alive && !(kp.retire && tclr >= 0);
+    bool fresh = true;
+
+    for (int32_t r = 0; r < kp.rounds; ++r) {
+      __syncthreads();
+      if (t == 0) {
+        ctrl[1 + 3 * spb + g] = working ? 1 : 0;
+        ctrl[1 + (((r + 1) & 1) ? 2 : 1) * spb + g] = 0;
+      }
+      __syncthreads();
+      int32_t anyw = 0;
+      for (int32_t h = 0; h < spb; ++h) anyw |= ctrl[1 + 3 * spb + h];
+      if (!anyw) break;
+
+      // ---- BP sweeps
+      for (int32_t it = 0; it < kp.iters; ++it) {
+        float x[CPT][DC];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            float acc = pi;
+#pragma unroll
+            for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
+            acc = clampf(acc, C);
+            if (fresh) acc = 0.0f;
+            if (!REG && j >= deg[k]) acc = __builtin_inff();
+            x[k][j] = acc;
+          }
+        }
+        __syncthreads();
+        if (working) {
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            if (cidx[k] < 0) continue;
+            const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)deg[k]) & 1u;
+            float out[DC];
+            if (BP == 0) {
+              // normalised min-sum: alpha * (smallest other |m|), sign product
+              float mn1 = __builtin_inff(), mn2 = __builtin_inff();
+              uint32_t par = sigma_neg, negm = 0;
+#pragma unroll
+              for (int j = 0; j < DC; ++j) {
+                const float av = fabsf(x[k][j]);
+                const uint32_t ng = (x[k][j] < 0.0f) ? 1u : 0u;
+                negm |= ng << j;
+                par ^= ng;
+                mn2 = fminf(mn2, fmaxf(mn1, av));
+                mn1 = fminf(mn1, av);
+              }
+              const float m1 = clampf(kp.alpha * mn1, C);
+              const float m2 = clampf(kp.alpha * mn2, C);
+#pragma unroll
+              for (int j = 0; j < DC; ++j) {
+                const float mag = (fabsf(x[k][j]) == mn1) ? m2 : m1;
+                out[j] = ((par ^ (negm >> j)) & 1u) ? -mag : mag;
+              }
+            } else {
+              // sum-product: box-plus fold of the other inputs, ascending
+#pragma unroll
+              for (int j = 0; j < DC; ++j) {
+                float acc = __builtin_inff();
+                bool first = true;
+#pragma unroll
+                for (int i = 0; i < DC; ++i) {
+                  if (i == j) continue;
+                  if (!REG && i >= deg[k]) continue;
+                  if (first) {
+                    acc = x[k][i] + 0.0f;  // (+inf) [+] x == x + 0
+                    first = false;
+                  } else {
+                    acc = boxplus(acc, x[k][i]);
+                  }
+                }
+                out[j] = clampf(sigma_neg ? -acc : acc, C);
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < DC; ++j) msg[j * a.mpad + cidx[k]] = out[j];
+          }
+        }
+        fresh = false;
+        __syncthreads();
+      }
+
+      // ---- feedback: every active check whose clock rang tests Evidence
+      // and requests a flip of its LocalMove qubit
+      if (working) {
+#pragma unroll 1
+        for (int k = 0; k < CPT; ++k) {
+          const int32_t ch = t + k * a.nt;
+          if (ch >= c.m || !((sb >> k) & 1u)) continue;
+          const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                          ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                          (uint32_t)(kp.seed >> 32));
+          if (!below(w.w0, kp.mask_bound)) continue;
+          const int32_t d = c.chk_deg[ch];
+          const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+          float Lv[DC];
+          float Lmax = -__builtin_inff();
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            if (j >= d) continue;
+            const int32_t v = nb[j];
+            const int32_t dv = c.var_deg[v];
+            float acc = pi;
+            if (!fresh)
+              for (int32_t q = 0; q < dv; ++q) {
+                const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+                acc = acc + msg[edge_slot(e) * a.mpad + edge_check(e)];
+              }
+            else
+              for (int32_t q = 0; q < dv; ++q) acc = acc + 0.0f;
+            acc = clampf(acc, C);
+            Lv[j] = acc;
+            if (j == 0 || acc > Lmax) Lmax = acc;
+          }
+          if (d == 0) continue;
+          if (kp.evidence && !(Lmax >= c.thr[d])) continue;
+          uint32_t ntie = 0;
+#pragma unroll
+          for (int j = 0; j < DC; ++j)
+            if (j < d && Lv[j] == Lmax) ++ntie;
+          uint32_t pick = (uint32_t)(((uint64_t)w.w1 * (uint64_t)ntie) >> 32);
+          int32_t chosen = -1;
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            if (j < d && Lv[j] == Lmax && chosen < 0) {
+              if (pick == 0)
+                chosen = nb[j];
+              else
+                --pick;
+            }
+          }
+          if (chosen >= 0) fl[chosen] = 1;
+        }
+      }
+      __syncthreads();
+      // ---- syndrome update s ^= H f and correction z ^= f
+      if (working) {
+#pragma unroll 1
+        for (int k = 0; k < CPT; ++k) {
+          const int32_t ch = t + k * a.nt;
+          if (ch >= c.m) continue;
+          uint32_t x = 0;
+          const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+          const int32_t d = c.chk_deg[ch];
+          for (int32_t j = 0; j < d; ++j) x ^= fl[nb[j]];
+          sb ^= (x & 1u) << k;
+        }
+        for (int k = 0; k < a.vpt; ++k) {
+          const int32_t v = t + k * a.nt;
+          if (v < c.n && fl[v]) zb ^= 1u << k;
+        }
+        if (sb) ctrl[1 + ((r & 1) ? 2 : 1) * spb + g] = 1;
+      }
+      __syncthreads();
+      if (working) {
+        for (int k = 0; k < a.vpt; ++k) {
+          const int32_t v = t + k * a.nt;
+          if (v < c.n) fl[v] = 0;
+        }
+        const bool any = ctrl[1 + ((r & 1) ? 2 : 1) * spb + g] != 0;
+        if (!any && tclr < 0) tclr = r + 1;
+        if (kp.retire && tclr >= 0) working = false;
+      }
+    }
+
+    // ---- results of this group's shot
+    if (alive) {
+      uint8_t* zrow = a.z + (int64_t)idx * c.n;
+      for (int k = 0; k < a.vpt; ++k) {
+        const int32_t v = t + k * a.nt;
+        if (v < c.n) zrow[v] = (uint8_t)((zb >> k) & 1u);
+      }
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * a.nt;
+        if (ch < c.m) a.s[(int64_t)idx * c.m + ch] = (uint8_t)((sb >> k) & 1u);
+      }
+      if (t == 0) a.tclr[idx] = tclr;
+      if (a.L) {
+        for (int k = 0; k < a.vpt; ++k) {
+          const int32_t v = t + k * a.nt;
+          if (v >= c.n) continue;
+          const int32_t dv = c.var_deg[v];
+          float acc = pi;
+          for (int32_t q = 0; q < dv; ++q) {
+            const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+            acc = acc + msg[edge_slot(e) * a.mpad + edge_check(e)];
+          }
+          a.L[(int64_t)idx * c.n + v] = clampf(acc, C);
+        }
+      }
+    }
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) p[i] = 0u;
+}
+
+// ---- instantiation table
+typedef void (*ResKernel)(DevCode, KParams, ResArgs);
+
+struct ResVariant {
+  int dc, dv, cpt, bp, reg;
+  ResKernel fn;
+};
+
+#define LAIM_RES(DC, DV, CPT)                                                     \
+  {DC, DV, CPT, 0, 1, resident_kernel<DC, DV, CPT, 0, true>},                    \
+      {DC, DV, CPT, 1, 1, resident_kernel<DC, DV, CPT, 1, true>}
+#define LAIM_RES_IRR(DC, DV, CPT)                                                 \
+  {DC, DV, CPT, 0, 0, resident_kernel<DC, DV, CPT, 0, false>},                   \
+      {DC, DV, CPT, 1, 0, resident_kernel<DC, DV, CPT, 1, false>}
+
+static const ResVariant kResVariants[] = {
+    LAIM_RES(2, 2, 1), LAIM_RES(2, 2, 2), LAIM_RES(2, 2, 4), LAIM_RES(2, 2, 8),
+    LAIM_RES(4, 2, 1), LAIM_RES(4, 2, 2), LAIM_RES(4, 2, 4), LAIM_RES(4, 2, 8),
+    LAIM_RES(6, 2, 1), LAIM_RES(6, 2, 2), LAIM_RES(6, 2, 4), LAIM_RES(6, 2, 8),
+    LAIM_RES(4, 4, 1), LAIM_RES(4, 4, 2), LAIM_RES(4, 4, 4),
+    LAIM_RES(6, 3, 1), LAIM_RES(6, 3, 2), LAIM_RES(6, 3, 4),
+    LAIM_RES_IRR(8, 4, 1), LAIM_RES_IRR(8, 4, 2), LAIM_RES_IRR(8, 4, 4),
+};
+
+// Template degrees for a code: exact ones for the regular families, the
+// padded (8, 4) variant otherwise.
+static bool pick_degrees(const DevCode& c, int* dc, int* dv, int* reg) {
+  static const int exact[][2] = {{2, 2}, {4, 2}, {6, 2}, {4, 4}, {6, 3}};
+  if (c.regular) {
+    for (auto& e : exact)
+      if (e[0] == c.dcmax && e[1] == c.dvmax) {
+        *dc = e[0];
+        *dv = e[1];
+        *reg = 1;
+        return true;
+      }
+  }
+  if (c.dcmax <= 8 && c.dvmax <= 4) {
+    *dc = 8;
+    *dv = 4;
+    *reg = 0;
+    return true;
+  }
+  return false;
+}
+
+static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) {
+  for (const auto& v : kResVariants)
+    if (v.dc == dc && v.dv == dv && v.cpt == cpt && v.bp == bp && v.reg == reg) return &v;
+  return nullptr;
+}
+
+static size_t group_bytes_for(int dc, int mpad, int n) {
+  size_t b = (size_t)(dc * mpad + 4) * 4 + (size_t)((n + 15) / 16) * 16;
+  return (b + 15) / 16 * 16;
+}
+
+bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
+                    int device) {
+  int dc, dv, reg;
+  if (!pick_degrees(c, &dc, &dv, &reg)) {
+    set_error("resident form needs check degree <= 8 and qubit degree <= 4 (have %d, %d)", c.dcmax,
+              c.dvmax);
+    return false;
+  }
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess ||
+      lds_max <= 0)
+    lds_max = 64 * 1024;
+  int cpt = want ? want->checks_per_thread : 0;
+  int nt = want ? want->threads_per_shot : 0;
+  int spb = want ? want->shots_per_block : 0;
+  if (cpt <= 0) {
+    if (nt > 0)
+      cpt = (c.m + nt - 1) / nt;
+    else
+      cpt = (c.m <= 256) ? 1 : (c.m <= 512 ? 2 : (c.m <= 1024 ? 4 : 8));
+    int allowed[] = {1, 2, 4, 8};
+    int pick = -1;
+    for (int a : allowed)
+      if (a >= cpt && find_variant(dc, dv, a, bp, reg)) {
+        pick = a;
+        break;
+      }
+    if (pick < 0)
+      for (int i = 3; i >= 0; --i)
+        if (find_variant(dc, dv, allowed[i], bp, reg)) {
+          pick = allowed[i];
+          break;
+        }
+    cpt = pick;
+  }
+  if (!find_variant(dc, dv, cpt, bp, reg)) {
+    set_error("no resident kernel for checks_per_thread = %d (degrees %d/%d)", cpt, dc, dv);
+    return false;
+  }
+  if (nt <= 0) nt = (c.m + cpt - 1) / cpt;
+  if (nt * cpt < c.m) {
+    set_error("threads_per_shot * checks_per_thread = %d < m = %d", nt * cpt, c.m);
+    return false;
+  }
+  const int vpt = (c.n + nt - 1) / nt;
+  if (vpt > 32) {
+    set_error("more than 32 qubits per thread (n = %d, threads_per_shot = %d)", c.n, nt);
+    return false;
+  }
+  if (spb <= 0) spb = (nt >= 256) ? 1 : 256 / nt;
+  if (spb > kMaxShotsPerBlock) spb = kMaxShotsPerBlock;
+  if (nt * spb > 1024) {
+    set_error("block of %d threads exceeds 1024", nt * spb);
+    return false;
+  }
+  const int mpad = nt * cpt;
+  const size_t gb = group_bytes_for(dc, mpad, c.n);
+  const size_t lds = kCtrlWords * 4 + gb * (size_t)spb;
+  if (lds > (size_t)lds_max) {
+    set_error("resident form needs %zu bytes of LDS per block (device limit %d)", lds, lds_max);
+    return false;
+  }
+  out->nt = nt;
+  out->cpt = cpt;
+  out->vpt = vpt;
+  out->spb = spb;
+  out->mpad = mpad;
+  out->lds = lds;
+  return true;
+}
+
+size_t resident_workspace_bytes() { return 256; }
+
+hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                           const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
+                           uint8_t* s, int32_t* tclr, float* L, hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  int dc, dv, reg;
+  if (!pick_degrees(c, &dc, &dv, &reg)) return hipErrorInvalidValue;
+  const ResVariant* var = find_variant(dc, dv, sh.cpt, kp.bp, reg);
+  if (!var) return hipErrorInvalidValue;
+  ResArgs a;
+  a.nt = sh.nt;
+  a.vpt = sh.vpt;
+  a.spb = sh.spb;
+  a.mpad = sh.mpad;
+  a.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  a.e0 = e0;
+  a.shot0 = shot0;
+  a.nshots = nshots;
+  a.counter = reinterpret_cast<uint32_t*>(ws);
+  a.z = z;
+  a.s = s;
+  a.tclr = tclr;
+  a.L = L;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, a.counter, 1);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (sh.lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(var->fn),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+    (void)hipGetLastError();
+  }
+  int per_cu = 0;
+  err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(var->fn),
+                                                     sh.nt * sh.spb, sh.lds);
+  if (err != hipSuccess) return err;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (cus <= 0) cus = 256;
+  const int64_t groups = ((int64_t)nshots + sh.spb - 1) / sh.spb;
+  int64_t blocks = (int64_t)per_cu * cus;
+  if (blocks > groups) blocks = groups;
+  hipLaunchKernelGGL(var->fn, dim3((unsigned)blocks), dim3(sh.nt * sh.spb), sh.lds, st, c, kp, a);
+  return hipGetLastError();
+}
+
+// ====================================================================
+// Stream form: messages live in HBM in 64-shot tiles, msg[tile][edge][lane]
+// with edges in ELL order (c * dcmax + j); every graph lookup is uniform
+// across a wavefront (one check, 64 shots) and every data access is a
+// contiguous 256-byte row. One launch per BP sweep (double-buffered
+// m_{c->v}) and a few small launches per round for the feedback step.
+// ====================================================================
+struct StreamWS {
+  float* msg[2];     // [ntile][m * dcmax][64]
+  uint8_t* s;        // [ntile][m][64]
+  uint8_t* z;        // [ntile][n][64]
+  uint8_t* fl;       // [ntile][n][64]
+  uint32_t* anys;    // [nshots]
+  int32_t* tclr;     // [nshots]
+  uint8_t* done;     // [nshots]
+  uint8_t* newdone;  // [nshots]
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t* total) {
+  const int64_t ntile = ((int64_t)nshots + kStreamTile - 1) / kStreamTile;
+  const size_t msg_b = align256((size_t)ntile * c.m * c.dcmax * kStreamTile * 4);
+  const size_t s_b = align256((size_t)ntile * c.m * kStreamTile);
+  const size_t z_b = align256((size_t)ntile * c.n * kStreamTile);
+  const size_t sh4 = align256((size_t)nshots * 4);
+  const size_t sh1 = align256((size_t)nshots);
+  StreamWS w;
+  char* p = reinterpret_cast<char*>(ws);
+  size_t off = 0;
+  w.msg[0] = reinterpret_cast<float*>(p + off);
+  off += msg_b;
+  w.msg[1] = reinterpret_cast<float*>(p + off);
+  off += msg_b;
+  w.s = reinterpret_cast<uint8_t*>(p + off);
+  off += s_b;
+  w.z = reinterpret_cast<uint8_t*>(p + off);
+  off += z_b;
+  w.fl = reinterpret_cast<uint8_t*>(p + off);
+  off += z_b;
+  w.anys = reinterpret_cast<uint32_t*>(p + off);
+  off += sh4;
+  w.tclr = reinterpret_cast<int32_t*>(p + off);
+  off += sh4;
+  w.done = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  w.newdone = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  if (total) *total = off;
+  return w;
+}
+
+size_t stream_workspace_bytes(const DevCode& c, int32_t nshots) {
+  size_t t = 0;
+  stream_carve(c, nshots, nullptr, &t);
+  return t;
+}
+
+constexpr int kStreamChecksPerBlock = 4;
+
+// Shot start: z = 0, no flip requests (one thread per (tile, qubit, lane)).
+__global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  if (v >= c.n) return;
+  const int64_t o = (tile * c.n + v) * kStreamTile + lane;
+  w.z[o] = 0;
+  w.fl[o] = 0;
+}
+
+// Shot start: s = H e0 and messages 0 (one thread per (tile, check, lane)).
+__global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, const uint8_t* e0,
+                                                       int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (ch >= c.m) return;
+  uint32_t x = 0;
+  const int32_t d = c.chk_deg[ch];
+  if (i < nshots)
+    for (int32_t j = 0; j < d; ++j) x ^= e0[i * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]];
+  x &= 1u;
+  w.s[(tile * c.m + ch) * kStreamTile + lane] = (uint8_t)x;
+  for (int32_t j = 0; j < c.dcmax; ++j)
+    w.msg[0][((tile * c.m + ch) * c.dcmax + j) * kStreamTile + lane] = 0.0f;
+  if (x && i < nshots) w.anys[i] = 1u;
+}
+
+// One BP sweep: m_{c->v} (src) -> m_{c->v} (dst), one thread per (tile,
+// check, lane). `fresh` marks the first sweep of every shot (m_{v->c} = 0).
+template <int DCT>
+__global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
+                                                    const float* __restrict__ src,
+                                                    float* __restrict__ dst, int32_t fresh,
+                                                    int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (ch >= c.m || i >= nshots) return;
+  if (w.done[i]) return;
+  const float C = kp.clamp;
+  const int32_t d = c.chk_deg[ch];
+  const int32_t pw = c.dvmax - 1;
+  float x[DCT];
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    float acc = kp.pi;
+    for (int32_t p = 0; p < pw; ++p) {
+      const int32_t e = c.partner[((int64_t)ch * c.dcmax + j) * pw + p];
+      if (e < 0) break;
+      acc = acc + src[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + lane];
+    }
+    acc = clampf(acc, C);
+    x[j] = fresh ? 0.0f : acc;
+  }
+  const uint32_t sigma_neg =
+      ((uint32_t)w.s[(tile * c.m + ch) * kStreamTile + lane] ^ (uint32_t)d) & 1u;
+  float* out = dst + ((tile * c.m + ch) * c.dcmax) * kStreamTile + lane;
+  if (kp.bp == 0) {
+    float mn1 = __builtin_inff(), mn2 = __builtin_inff();
+    uint32_t par = sigma_neg;
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      const float av = fabsf(x[j]);
+      par ^= (x[j] < 0.0f) ? 1u : 0u;
+      mn2 = fminf(mn2, fmaxf(mn1, av));
+      mn1 = fminf(mn1, av);
+    }
+    const float m1 = clampf(kp.alpha * mn1, C);
+    const float m2 = clampf(kp.alpha * mn2, C);
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      const float mag = (fabsf(x[j]) == mn1) ? m2 : m1;
+      const uint32_t ng = par ^ ((x[j] < 0.0f) ? 1u : 0u);
+      out[(int64_t)j * kStreamTile] = ng ? -mag : mag;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      float acc = __builtin_inff();
+      bool first = true;
+#pragma unroll
+      for (int i2 = 0; i2 < DCT; ++i2) {
+        if (i2 == j || i2 >= d) continue;
+        if (first) {
+          acc = x[i2] + 0.0f;
+          first = false;
+        } else {
+          acc = boxplus(acc, x[i2]);
+        }
+      }
+      out[(int64_t)j * kStreamTile] = clampf(sigma_neg ? -acc : acc, C);
+    }
+  }
+}
+
+__device__ __forceinline__ float stream_belief(const DevCode& c, const float* msg, int64_t tile,
+                                               int32_t lane, int32_t v, float pi, float C) {
+  float acc = pi;
+  const int32_t dv = c.var_deg[v];
+  for (int32_t q = 0; q < dv; ++q) {
+    const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+    acc = acc + msg[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + lane];
+  }
+  return clampf(acc, C);
+}
+
+// Feedback: active checks whose clock rang and whose Evidence holds
+// request a flip of their LocalMove qubit.
+template <int DCT>
+__global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, StreamWS w,
+                                                    const float* __restrict__ msg, int32_t r,
+                                                    int32_t fresh, uint64_t shot0, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (ch >= c.m || i >= nshots) return;
+  if (w.done[i] || !w.s[(tile * c.m + ch) * kStreamTile + lane]) return;
+  const uint64_t shot = shot0 + (uint64_t)i;
+  const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                   ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                   (uint32_t)(kp.seed >> 32));
+  if (!below(rw.w0, kp.mask_bound)) return;
+  const int32_t d = c.chk_deg[ch];
+  if (d == 0) return;
+  const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+  float Lv[DCT];
+  float Lmax = 0.0f;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    float L;
+    if (fresh) {
+      L = kp.pi;
+      for (int32_t q = 0; q < c.var_deg[nb[j]]; ++q) L = L + 0.0f;
+      L = clampf(L, kp.clamp);
+    } else {
+      L = stream_belief(c, msg, tile, lane, nb[j], kp.pi, kp.clamp);
+    }
+    Lv[j] = L;
+    if (j == 0 || L > Lmax) Lmax = L;
+  }
+  if (kp.evidence && !(Lmax >= c.thr[d])) return;
+  uint32_t ntie = 0;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j)
+    if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
+  uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
+  int32_t chosen = -1;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j < d && Lv[j] == Lmax && chosen < 0) {
+      if (pick == 0)
+        chosen = nb[j];
+      else
+        --pick;
+    }
+  }
+  if (chosen >= 0) w.fl[(tile * c.n + chosen) * kStreamTile + lane] = 1;
+}
+
+// s ^= H f (one thread per (tile, check, lane)); flags shots with s != 0.
+__global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (ch >= c.m || i >= nshots) return;
+  if (w.done[i]) return;
+  const int32_t d = c.chk_deg[ch];
+  uint32_t x = 0;
+  for (int32_t j = 0; j < d; ++j)
+    x ^= w.fl[(tile * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]) * kStreamTile + lane];
+  const int64_t so = (tile * c.m + ch) * kStreamTile + lane;
+  const uint32_t s = (w.s[so] ^ x) & 1u;
+  w.s[so] = (uint8_t)s;
+  if (s) w.anys[i] = 1u;
+}
+
+// z ^= f and clear the requests (one thread per (tile, qubit, lane)).
+__global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (v >= c.n || i >= nshots) return;
+  if (w.done[i]) return;
+  const int64_t o = (tile * c.n + v) * kStreamTile + lane;
+  w.z[o] ^= w.fl[o];
+  w.fl[o] = 0;
+}
+
+// Per shot: t_clr at the first clear syndrome, retirement.
+__global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int32_t r,
+                                                     int32_t nshots) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nshots) return;
+  w.newdone[i] = 0;
+  if (w.done[i]) return;
+  const bool any = w.anys[i] != 0u;
+  w.anys[i] = 0u;
+  if (r < 0) w.tclr[i] = any ? -1 : 0;
+  else if (!any && w.tclr[i] < 0) w.tclr[i] = r + 1;
+  if (kp.retire && w.tclr[i] >= 0) {
+    w.done[i] = 1;
+    w.newdone[i] = 1;
+  }
+}
+
+__global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nshots) return;
+  w.anys[i] = 0u;
+  w.done[i] = 0;
+  w.newdone[i] = 0;
+  w.tclr[i] = -1;
+}
+
+// Beliefs of the current message state for shots that just retired
+// (only_new) or for every shot not retired before (!only_new).
+__global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp, StreamWS w,
+                                                          const float* __restrict__ msg,
+                                                          int32_t only_new, int32_t fresh,
+                                                          float* __restrict__ L, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t tile = blockIdx.y;
+  const int64_t i = tile * kStreamTile + lane;
+  if (v >= c.n || i >= nshots) return;
+  if (only_new ? !w.newdone[i] : (w.done[i] && !w.newdone[i])) return;
+  float val;
+  if (fresh) {
+    val = kp.pi;
+    for (int32_t q = 0; q < c.var_deg[v]; ++q) val = val + 0.0f;
+    val = clampf(val, kp.clamp);
+  } else {
+    val = stream_belief(c, msg, tile, lane, v, kp.pi, kp.clamp);
+  }
+  L[i * c.n + v] = val;
+}
+
+// Interleaved state -> caller's row-major outputs.
+__global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t* z, uint8_t* s,
+                                                  int32_t* tclr, int32_t nshots) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tz = (int64_t)nshots * c.n;
+  const int64_t ts = (int64_t)nshots * c.m;
+  if (idx < tz) {
+    const int64_t i = idx / c.n;
+    const int32_t v = (int32_t)(idx - i * c.n);
+    z[idx] = w.z[((i / kStreamTile) * c.n + v) * kStreamTile + (i % kStreamTile)];
+  } else if (idx < tz + ts) {
+    const int64_t k = idx - tz;
+    const int64_t i = k / c.m;
+    const int32_t ch = (int32_t)(k - i * c.m);
+    s[k] = w.s[((i / kStreamTile) * c.m + ch) * kStreamTile + (i % kStreamTile)];
+  } else if (idx < tz + ts + nshots) {
+    const int64_t i = idx - tz - ts;
+    tclr[i] = w.tclr[i];
+  }
+}
+
+typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t, int32_t);
+typedef void (*MovesFn)(DevCode, KParams, StreamWS, const float*, int32_t, int32_t, uint64_t,
+                        int32_t);
+
+static void stream_fns(int dcmax, SweepFn* sw, MovesFn* mv) {
+  if (dcmax <= 2) {
+    *sw = stream_sweep<2>;
+    *mv = stream_moves<2>;
+  } else if (dcmax <= 4) {
+    *sw = stream_sweep<4>;
+    *mv = stream_moves<4>;
+  } else if (dcmax <= 6) {
+    *sw = stream_sweep<6>;
+    *mv = stream_moves<6>;
+  } else if (dcmax <= 8) {
+    *sw = stream_sweep<8>;
+    *mv = stream_moves<8>;
+  } else if (dcmax <= 16) {
+    *sw = stream_sweep<16>;
+    *mv = stream_moves<16>;
+  } else {
+    *sw = stream_sweep<32>;
+    *mv = stream_moves<32>;
+  }
+}
+
+hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
+                         int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
+                         hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  SweepFn sweep_fn;
+  MovesFn moves_fn;
+  stream_fns(c.dcmax, &sweep_fn, &moves_fn);
+  StreamWS w = stream_carve(c, nshots, ws, nullptr);
+  const unsigned ntile = (unsigned)((nshots + kStreamTile - 1) / kStreamTile);
+  const dim3 gchk((unsigned)((c.m + kStreamChecksPerBlock - 1) / kStreamChecksPerBlock), ntile);
+  const dim3 gvar((unsigned)((c.n + 3) / 4), ntile);
+  const dim3 blk(256);
+  const unsigned gshot = (unsigned)((nshots + 255) / 256);
+  hipLaunchKernelGGL(stream_clear_shots, dim3(gshot), blk, 0, st, w, nshots);
+  hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w, nshots);
+  hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, nshots);
+  hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, -1, nshots);
+  int cur = 0;
+  bool fresh = true;
+  if (L) hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1, 1, L,
+                            nshots);
+  for (int32_t r = 0; r < kp.rounds; ++r) {
+    for (int32_t it = 0; it < kp.iters; ++it) {
+      hipLaunchKernelGGL(sweep_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], w.msg[cur ^ 1],
+                         fresh ? 1 : 0, nshots);
+      cur ^= 1;
+      fresh = false;
+    }
+    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0,
+                       nshots);
+    hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w, nshots);
+    hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w, nshots);
+    hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, r, nshots);
+    if (L)
+      hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1,
+                         fresh ? 1 : 0, L, nshots);
+  }
+  if (L)
+    hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 0, fresh ? 1 : 0,
+                       L, nshots);
+  const int64_t tot = (int64_t)nshots * (c.n + c.m + 1);
+  hipLaunchKernelGGL(stream_out, dim3((unsigned)((tot + 255) / 256)), blk, 0, st, c, w, z, s, tclr,
+                     nshots);
+  return hipGetLastError();
+}
+
+}  // namespace laim

@@ -1,0 +1,301 @@
+"""Python binding of the C ABI declared in ``include/laim.h``.
+
+Argument marshalling only: every step of the decoder runs in the HIP
+library ``liblaim.so`` built next to this file. PyTorch provides device
+memory and the stream each call is enqueued on. Importing this module does
+not need a GPU; the calls do, and there is no CPU fallback: without the
+built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblaim.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUP, EBUSY = 0, -1, -2, -3, -4, -5
+FORM_AUTO, FORM_RESIDENT, FORM_STREAM = 0, 1, 2
+FORMS = {"auto": FORM_AUTO, "resident": FORM_RESIDENT, "stream": FORM_STREAM}
+
+# Every symbol the header declares (checked by the tests).
+SYMBOLS = [
+    "laim_last_error", "laim_version", "laim_build_tanner", "laim_build_tanner_ex",
+    "laim_free_code", "laim_code_info", "laim_code_logicals", "laim_host_logicals",
+    "laim_sample_noise", "laim_syndrome", "laim_workspace_bytes", "laim_decode_rounds",
+    "laim_decode_rounds_cfg", "laim_set_resident_cfg", "laim_get_resident_cfg",
+    "laim_logical_failure", "laim_batch_plan_create", "laim_batch_plan_launch",
+    "laim_batch_plan_destroy", "laim_server_create", "laim_server_submit", "laim_server_step",
+    "laim_server_result", "laim_server_stats", "laim_server_destroy",
+]
+
+
+class LaimError(RuntimeError):
+    def __init__(self, status: int, where: str, text: str):
+        super().__init__(f"{where} failed with status {status}: {text}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
+                ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
+                ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class ResidentCfg(C.Structure):
+    _fields_ = [("threads_per_shot", C.c_int32), ("checks_per_thread", C.c_int32),
+                ("shots_per_block", C.c_int32)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("code", C.c_void_p), ("params", Params), ("e0", C.c_void_p), ("shot0", C.c_uint64),
+                ("nshots", C.c_int32), ("z_out", C.c_void_p), ("s_out", C.c_void_p),
+                ("tclr_out", C.c_void_p), ("fail_out", C.c_void_p)]
+
+
+class ServerEvent(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("round", C.c_int32), ("done", C.c_int32),
+                ("tclr", C.c_int32), ("flips", C.c_int32), ("defects", C.c_int32)]
+
+
+@dataclass
+class DecodeParams:
+    """Knobs of the round machine (defaults: Table S1's q and CLAMP for the
+    2D toric code; 20 BP sweeps per round; clocks ring with probability 0.5)."""
+
+    bp: str = "minsum"
+    alpha: float = 0.75
+    q: float = 0.05
+    clamp: float = 1000.0
+    iters: int = 20
+    rounds: int = 64
+    mask_density: float = 0.5
+    gauge: bool = False
+    evidence: bool = True
+    retire: bool = True
+    seed: int = 0
+
+    def c(self) -> Params:
+        if self.bp not in ("minsum", "sumproduct"):
+            raise ValueError("bp must be 'minsum' or 'sumproduct'")
+        return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
+                      self.iters, self.rounds, self.mask_density, int(self.gauge),
+                      int(self.evidence), int(self.retire), self.seed)
+
+
+_lib = None
+
+
+def lib():
+    """Loads ``liblaim.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                               "python paper_2609_38139_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64, sz = C.c_void_p, C.c_int32, C.c_uint64, C.c_size_t
+        i32p = C.POINTER(C.c_int32)
+        L.laim_last_error.restype = C.c_char_p
+        L.laim_version.restype = i32
+        L.laim_build_tanner_ex.argtypes = [i32, i32, i32p, i32p, i32, i32p, i32p, i32, i32p, i32p,
+                                           i32, C.POINTER(vp)]
+        L.laim_build_tanner.argtypes = [i32, i32, i32p, i32p, i32, i32p, i32p, i32, C.POINTER(vp)]
+        L.laim_free_code.argtypes = [vp]
+        L.laim_free_code.restype = None
+        L.laim_code_info.argtypes = [vp] + [i32p] * 6
+        L.laim_code_logicals.argtypes = [vp, vp]
+        L.laim_host_logicals.argtypes = [i32, i32, i32p, i32p, i32, i32p, i32p, i32, vp, i32p]
+        L.laim_sample_noise.argtypes = [vp, C.c_double, u64, u64, i32, vp, vp]
+        L.laim_syndrome.argtypes = [vp, vp, i32, vp, vp]
+        L.laim_workspace_bytes.argtypes = [vp, C.POINTER(Params), i32, i32]
+        L.laim_workspace_bytes.restype = sz
+        L.laim_decode_rounds.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp, vp,
+                                         i32, vp]
+        L.laim_decode_rounds_cfg.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp,
+                                             vp, C.POINTER(ResidentCfg), vp]
+        L.laim_set_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
+        L.laim_get_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
+        L.laim_logical_failure.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.laim_batch_plan_create.argtypes = [C.POINTER(BatchItem), i32, vp, C.POINTER(vp)]
+        L.laim_batch_plan_launch.argtypes = [vp, vp]
+        L.laim_batch_plan_destroy.argtypes = [vp]
+        L.laim_batch_plan_destroy.restype = None
+        L.laim_server_create.argtypes = [i32, sz, i32, C.POINTER(vp)]
+        L.laim_server_submit.argtypes = [vp, vp, C.POINTER(Params), u64, vp, C.POINTER(u64)]
+        L.laim_server_step.argtypes = [vp, C.POINTER(ServerEvent), i32, i32p]
+        L.laim_server_result.argtypes = [vp, u64, vp, vp, i32p]
+        L.laim_server_stats.argtypes = [vp, i32p, i32p, C.POINTER(sz)]
+        L.laim_server_destroy.argtypes = [vp]
+        L.laim_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str):
+    if status != OK:
+        raise LaimError(status, where, lib().laim_last_error().decode(errors="replace"))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Code:
+    """A code on a device (``laim_build_tanner``)."""
+
+    def __init__(self, code, device: int | None = None, logicals: str = "auto"):
+        import torch
+        self.spec = code
+        self.device = torch.cuda.current_device() if device is None else device
+        H, G = code.H, code.G
+        hr, hrp = _i32(H.rowptr)
+        hc, hcp = _i32(H.col if H.col.size else np.zeros(1))
+        gr, grp = _i32(G.rowptr)
+        gc, gcp = _i32(G.col if G.col.size else np.zeros(1))
+        h = C.c_void_p()
+        Lg = getattr(code, "logicals", None)
+        if logicals == "auto" and Lg is not None:
+            lr, lrp = _i32(Lg.rowptr)
+            lc, lcp = _i32(Lg.col if Lg.col.size else np.zeros(1))
+            st = lib().laim_build_tanner_ex(H.rows, H.cols, hrp, hcp, G.rows, grp, gcp, Lg.rows, lrp,
+                                            lcp, self.device, C.byref(h))
+        else:
+            st = lib().laim_build_tanner(H.rows, H.cols, hrp, hcp, G.rows, grp, gcp, self.device,
+                                         C.byref(h))
+        check(st, "laim_build_tanner")
+        self.handle = h
+        vals = [C.c_int32() for _ in range(6)]
+        check(lib().laim_code_info(h, *[C.byref(v) for v in vals]), "laim_code_info")
+        self.m, self.n, self.E, self.k, self.dc_max, self.dv_max = [v.value for v in vals]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.laim_free_code(h)
+            self.handle = None
+
+    def logical_matrix(self) -> np.ndarray:
+        out = np.zeros((self.k, self.n), dtype=np.uint8)
+        check(lib().laim_code_logicals(self.handle, out.ctypes.data_as(C.c_void_p)), "laim_code_logicals")
+        return out
+
+    def resident_cfg(self, bp: str = "minsum") -> dict:
+        cfg = ResidentCfg()
+        check(lib().laim_get_resident_cfg(self.handle, 1 if bp == "sumproduct" else 0, C.byref(cfg)),
+              "laim_get_resident_cfg")
+        return {"threads_per_shot": cfg.threads_per_shot, "checks_per_thread": cfg.checks_per_thread,
+                "shots_per_block": cfg.shots_per_block}
+
+    def set_resident_cfg(self, bp: str, cfg: dict | None):
+        c = None
+        if cfg is not None:
+            c = ResidentCfg(cfg.get("threads_per_shot", 0), cfg.get("checks_per_thread", 0),
+                            cfg.get("shots_per_block", 0))
+        check(lib().laim_set_resident_cfg(self.handle, 1 if bp == "sumproduct" else 0,
+                                          C.byref(c) if c is not None else None), "laim_set_resident_cfg")
+
+
+def host_logicals(code, kmax: int = 4096) -> np.ndarray:
+    """GF(2) logical basis computed by the library's host code (no device)."""
+    H, G = code.H, code.G
+    hr, hrp = _i32(H.rowptr)
+    hc, hcp = _i32(H.col if H.col.size else np.zeros(1))
+    gr, grp = _i32(G.rowptr)
+    gc, gcp = _i32(G.col if G.col.size else np.zeros(1))
+    out = np.zeros((kmax, H.cols), dtype=np.uint8)
+    k = C.c_int32()
+    check(lib().laim_host_logicals(H.rows, H.cols, hrp, hcp, G.rows, grp, gcp, kmax,
+                                   out.ctypes.data_as(C.c_void_p), C.byref(k)), "laim_host_logicals")
+    return out[:k.value]
+
+
+def sample_noise(code: Code, p: float, seed: int, shot0: int, nshots: int, out=None, stream=None):
+    import torch
+    e = out if out is not None else torch.empty((nshots, code.n), dtype=torch.uint8,
+                                                device=f"cuda:{code.device}")
+    _dev(e, torch.uint8, (nshots, code.n), "e_out")
+    check(lib().laim_sample_noise(code.handle, p, seed, shot0, nshots, _ptr(e), _stream(stream)),
+          "laim_sample_noise")
+    return e
+
+
+def syndrome(code: Code, e, stream=None):
+    import torch
+    _dev(e, torch.uint8, (e.shape[0], code.n), "e")
+    s = torch.empty((e.shape[0], code.m), dtype=torch.uint8, device=e.device)
+    check(lib().laim_syndrome(code.handle, _ptr(e), e.shape[0], _ptr(s), _stream(stream)), "laim_syndrome")
+    return s
+
+
+def workspace_bytes(code: Code, params: DecodeParams, nshots: int, form: str = "auto") -> int:
+    P = params.c()
+    return int(lib().laim_workspace_bytes(code.handle, C.byref(P), nshots, FORMS[form]))
+
+
+def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: str = "auto",
+                  want_beliefs: bool = False, cfg: dict | None = None, workspace=None, out=None,
+                  stream=None) -> dict:
+    """``laim_decode_rounds``: returns device tensors z, s, tclr (and L)."""
+    import torch
+    ns = e0.shape[0]
+    _dev(e0, torch.uint8, (ns, code.n), "e0")
+    P = params.c()
+    dev = e0.device
+    if out is None:
+        out = {"z": torch.empty((ns, code.n), dtype=torch.uint8, device=dev),
+               "s": torch.empty((ns, code.m), dtype=torch.uint8, device=dev),
+               "tclr": torch.empty((ns,), dtype=torch.int32, device=dev),
+               "L": torch.empty((ns, code.n), dtype=torch.float32, device=dev) if want_beliefs else None}
+    f = FORM_RESIDENT if cfg is not None else FORMS[form]
+    need = int(lib().laim_workspace_bytes(code.handle, C.byref(P), ns, f))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty((max(need, 256),), dtype=torch.uint8, device=dev)
+    if cfg is None:
+        st = lib().laim_decode_rounds(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
+                                      workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
+                                      _ptr(out["tclr"]), _ptr(out.get("L")), f, _stream(stream))
+    else:
+        rc = ResidentCfg(cfg.get("threads_per_shot", 0), cfg.get("checks_per_thread", 0),
+                         cfg.get("shots_per_block", 0))
+        st = lib().laim_decode_rounds_cfg(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
+                                          workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
+                                          _ptr(out["tclr"]), _ptr(out.get("L")), C.byref(rc),
+                                          _stream(stream))
+    check(st, "laim_decode_rounds")
+    out["workspace"] = workspace
+    return out
+
+
+def logical_failure(code: Code, e0, z, stream=None):
+    import torch
+    ns = e0.shape[0]
+    _dev(e0, torch.uint8, (ns, code.n), "e0")
+    _dev(z, torch.uint8, (ns, code.n), "z")
+    f = torch.empty((ns,), dtype=torch.uint8, device=e0.device)
+    check(lib().laim_logical_failure(code.handle, _ptr(e0), _ptr(z), ns, _ptr(f), _stream(stream)),
+          "laim_logical_failure")
+    return f

@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+try:  # the first import of torch on a fresh machine is slow; pay it at collection
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

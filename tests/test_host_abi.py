@@ -1,0 +1,91 @@
+"""CPU-side checks of the library: it loads, exports every symbol the header
+declares, rejects malformed input before touching a device, and its host
+GF(2) code finds a correct logical basis."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2609_38139_amd import codes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def laim():
+    from paper_2609_38139_amd import laim as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("liblaim.so is not built: run __graft_entry__.build()")
+    L.lib()
+    return L
+
+
+def test_exports_every_declared_symbol(laim):
+    hdr = open(os.path.join(ROOT, "include", "laim.h")).read()
+    declared = set(re.findall(r"\b(laim_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(laim.SYMBOLS)
+    lib = laim.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_rejects_malformed_csr_without_a_device(laim):
+    import ctypes as C
+    lib = laim.lib()
+    rp = np.array([0, 2, 4], dtype=np.int32)
+    bad = np.array([1, 0, 2, 3], dtype=np.int32)  # not ascending
+    out = C.c_void_p()
+    st = lib.laim_build_tanner(2, 4, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                               bad.ctypes.data_as(C.POINTER(C.c_int32)), 0, None, None, 0, C.byref(out))
+    assert st == laim.EINVAL and b"ascending" in lib.laim_last_error()
+    col = np.array([0, 1, 2, 7], dtype=np.int32)  # out of range
+    st = lib.laim_build_tanner(2, 4, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                               col.ctypes.data_as(C.POINTER(C.c_int32)), 0, None, None, 0, C.byref(out))
+    assert st == laim.EINVAL
+    # G that does not commute with H
+    col = np.array([0, 1, 2, 3], dtype=np.int32)
+    grp = np.array([0, 1], dtype=np.int32)
+    gcol = np.array([0], dtype=np.int32)
+    st = lib.laim_build_tanner(2, 4, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                               col.ctypes.data_as(C.POINTER(C.c_int32)), 1,
+                               grp.ctypes.data_as(C.POINTER(C.c_int32)),
+                               gcol.ctypes.data_as(C.POINTER(C.c_int32)), 0, C.byref(out))
+    assert st == laim.EINVAL and b"commute" in lib.laim_last_error()
+
+
+def _check_logicals(orc, code, L):
+    """L spans ker(G) modulo row(H): right size, commutes with G, and is
+    independent modulo row(H) -- checked with the oracle's rank routine."""
+    k = code.n - orc.gf2_rank(code.H) - orc.gf2_rank(code.G)
+    assert L.shape == (k, code.n)
+    if code.G.rows:
+        assert not ((code.G.to_dense().astype(np.int64) @ L.T) % 2).any()
+    stacked = codes.CSR.from_dense(np.vstack([code.H.to_dense(), L]))
+    assert orc.gf2_rank(stacked) == orc.gf2_rank(code.H) + k
+
+
+@pytest.mark.parametrize("name", ["toric2d:3", "toric2d:6", "bb:6x6", "bb:12x6", "toric3d_point:3",
+                                  "toric3d_membrane:3", "rep:7"])
+def test_host_logical_basis(laim, orc, name):
+    c = codes.by_name(name)
+    _check_logicals(orc, c, laim.host_logicals(c))
+
+
+@pytest.mark.parametrize("name", ["toric2d:5", "toric3d_point:3", "toric3d_point:4",
+                                  "toric3d_membrane:3", "toric3d_membrane:4"])
+def test_closed_form_logicals(orc, name):
+    c = codes.by_name(name)
+    _check_logicals(orc, c, c.logicals.to_dense())
+
+
+def test_homology_test_by_logicals_matches_rank_test(laim, orc):
+    """On the L = 3 toric code, 'odd overlap with a logical' decides exactly
+    the same shots as the oracle's rank test, over all of ker H plus noise."""
+    c = codes.toric_2d(3)
+    L = laim.host_logicals(c)
+    rng = np.random.default_rng(0)
+    r = (rng.random((3000, c.n)) < 0.3).astype(np.uint8)
+    s = (r @ c.H.to_dense().T) % 2
+    by_logicals = (s.any(1) | ((r @ L.T) % 2).any(1)).astype(np.uint8)
+    assert np.array_equal(by_logicals, orc.logical_failure(c, r, np.zeros_like(r)))
