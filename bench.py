@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true", help="built-in resident launch shape")
+    ap.add_argument("--cfg", default="", help="resident shape 'checks_per_thread,shots_per_block'")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="copy this many MiB device-to-device first (counter calibration)")
     return ap.parse_args()
 
 
@@ -140,6 +144,22 @@ def main():
     E = code.E
     P = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire)
     form = args.form
+    if args.calibrate_copy_mb:
+        src = torch.ones((args.calibrate_copy_mb << 20,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    tuned = None
+    if args.cfg:
+        cpt, spb = (int(v) for v in args.cfg.split(","))
+        code.set_resident_cfg(args.bp, {"checks_per_thread": cpt, "shots_per_block": spb})
+    elif not args.no_tune and form != "stream":
+        from paper_2609_38139_amd import autotune
+        for bp in ("minsum", "sumproduct"):
+            t = autotune.tune(code, bp, use_cache=False)
+            if bp == args.bp:
+                tuned = t
     main_run = timed_steps(laim, code, P, args, args.steps, args.warmup, form)
     S_total = main_run["shots"]
     sec = main_run["ms_per_step"] * args.steps / 1000.0
@@ -149,18 +169,30 @@ def main():
     dec_s = main_run["decode_ms"] / 1000.0
     msg_per_launch = msg_updates / args.steps
 
-    # roofline of the dominant kernel (the resident decode launch): the
-    # algorithmic work of the BP sweeps is 2E message updates per
-    # shot-sweep; priced in the VALU lane-operations its arithmetic needs
-    # (ops_per_update below) against 256 CU x 64 lanes x 2.4 GHz, and in
-    # the bytes a streaming sweep would move (8 B per update) against HBM.
-    ops_per_update = 11.0 if args.bp == "minsum" else 230.0
+    # Roofline of the dominant kernel (the resident decode launch). It keeps
+    # every message on chip, so HBM carries only e0 in and z, s, t_clr out;
+    # its bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is
+    # the algorithmic operation count of the sweeps: per check and sweep,
+    # d_c d_v for the qubit-side sums and clamps, then for min-sum
+    # 2(d_c - 1) for the smallest and second-smallest |m|, d_c - 1 sign
+    # parities, 2 scalings and 2 per output (pick, sign) = d_c (d_v + 5) - 1;
+    # for sum-product d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus
+    # d_c clamps. The bytes a streaming sweep would move (8 B per update)
+    # are reported beside it as the HBM-equivalent rate.
+    dc, dv = code.dc_max, code.dv_max
+    BOXPLUS_OPS = 100
+    if args.bp == "minsum":
+        ops_check = dc * (dv + 5) - 1
+    else:
+        ops_check = dc * dv + BOXPLUS_OPS * dc * (dc - 2) + dc
+    ops_per_update = ops_check / (2.0 * dc)
     achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12
     hbm_equiv_gbs = msg_per_launch * 8.0 / dec_s / 1e9
     rl = {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 1),
           "unit": "Tops/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
           "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
           "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
+          "msg_updates_per_launch": msg_per_launch,
           "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
           "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
 
@@ -219,7 +251,9 @@ def main():
                                f"density 0.5, {'retire on clear' if not args.no_retire else 'fixed rounds'}, "
                                f"{form} form",
                    "code": f"toric2d:{L}", "p": args.p, "shots_per_step": args.shots, "rounds": R,
-                   "iters": args.iters, "bp": args.bp, "form": form, "retire": not args.no_retire},
+                   "iters": args.iters, "bp": args.bp, "form": form, "retire": not args.no_retire,
+                   "resident_shape": code.resident_cfg(args.bp) if form != "stream" else None,
+                   "autotuned": tuned is not None},
         "msg_updates_per_s": msg_per_s,
         "logical_error_rate": main_run["failures"] / S_total,
         "roofline": rl,

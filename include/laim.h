@@ -152,7 +152,8 @@ typedef struct {
 } laim_decode_params;
 
 /* Execution forms of laim_decode_rounds; all give identical results. */
-#define LAIM_FORM_AUTO 0     /* resident if the code fits in LDS, else stream */
+#define LAIM_FORM_AUTO 0     /* resident if the code fits in LDS (and, for min-sum,
+                                alpha <= 1), else stream */
 #define LAIM_FORM_RESIDENT 1 /* one persistent launch, per-shot state in LDS/registers */
 #define LAIM_FORM_STREAM 2   /* messages in HBM, one launch per BP sweep and per phase */
 

@@ -25,6 +25,9 @@ ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
+    # No value on the decoder's path is ever NaN; with IEEE mode off the
+    # min/max instructions need no canonicalising copies of their inputs.
+    "-fno-honor-nans", "-mno-amdgpu-ieee",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",

@@ -44,6 +44,9 @@ __device__ __forceinline__ bool below(uint32_t w, uint64_t bound) { return (uint
 
 __device__ __forceinline__ float clampf(float x, float c) { return fminf(fmaxf(x, -c), c); }
 
+// Smallest of three (exact; the compiler forms one v_min3_f32).
+__device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
+
 // e^{-a} for a >= 0, by Cody-Waite reduction -a = k ln2 + r (ln2 split into
 // a head with 16 significant bits, so k*head is exact, and a tail), the
 // degree-7 Taylor polynomial of e^r in Horner form, and a 2^k scale built in

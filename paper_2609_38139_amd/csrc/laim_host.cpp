@@ -546,7 +546,8 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
                             int32_t nshots, int32_t form) {
   if (!code || !params || nshots < 0) return 0;
   ResidentShape sh;
-  const int f = resolve_form(code, params->bp == 1 ? 1 : 0, form, &sh);
+  int f = resolve_form(code, params->bp == 1 ? 1 : 0, form, &sh);
+  if (params->bp == 0 && params->alpha > 1.0f) f = (form == LAIM_FORM_RESIDENT) ? -1 : LAIM_FORM_STREAM;
   if (f == LAIM_FORM_RESIDENT) return resident_workspace_bytes();
   if (f == LAIM_FORM_STREAM) return stream_workspace_bytes(code->dev, nshots);
   return 0;
@@ -571,9 +572,22 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
   if (nshots == 0) return LAIM_OK;
   ResidentShape sh;
   int f;
+  // The resident min-sum kernel relies on alpha <= 1 (its outputs cannot
+  // reach the clamp); other scales run in the stream form.
+  const bool resident_ok = !(kp.bp == 0 && kp.alpha > 1.0f);
   if (cfg) {
+    if (!resident_ok) {
+      set_error("the resident min-sum form needs alpha <= 1");
+      return LAIM_EUNSUP;
+    }
     if (!resident_shape(code->dev, kp.bp, cfg, &sh, code->device)) return LAIM_EINVAL;
     f = LAIM_FORM_RESIDENT;
+  } else if (!resident_ok) {
+    if (form == LAIM_FORM_RESIDENT) {
+      set_error("the resident min-sum form needs alpha <= 1");
+      return LAIM_EUNSUP;
+    }
+    f = LAIM_FORM_STREAM;
   } else {
     f = resolve_form(code, kp.bp, form, &sh);
     if (f < 0) return LAIM_EUNSUP;

@@ -250,19 +250,42 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
       if (!anyw) break;
 
       // ---- BP sweeps
-      for (int32_t it = 0; it < kp.iters; ++it) {
+      int32_t it0 = 0;
+      if (fresh && REG && kp.iters > 0) {
+        // First sweep of a shot: every m_{v->c} is 0, so each check sends
+        // (-1)^{s_c + d_c} * 0 (min-sum: alpha * 0; sum-product: 0 [+] 0 = +0).
+        if (working) {
+#pragma unroll
+          for (int k = 0; k < CPT; ++k) {
+            if (cidx[k] < 0) continue;
+            const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
+#pragma unroll
+            for (int j = 0; j < DC; ++j) msg[j * a.mpad + cidx[k]] = z0;
+          }
+        }
+        fresh = false;
+        it0 = 1;
+        __syncthreads();
+      }
+      for (int32_t it = it0; it < kp.iters; ++it) {
         float x[CPT][DC];
+        if (!REG && fresh) {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
+          for (int k = 0; k < CPT; ++k)
 #pragma unroll
-          for (int j = 0; j < DC; ++j) {
-            float acc = pi;
+            for (int j = 0; j < DC; ++j) x[k][j] = (j >= deg[k]) ? __builtin_inff() : 0.0f;
+        } else {
 #pragma unroll
-            for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
-            acc = clampf(acc, C);
-            if (fresh) acc = 0.0f;
-            if (!REG && j >= deg[k]) acc = __builtin_inff();
-            x[k][j] = acc;
+          for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+              float acc = pi;
+#pragma unroll
+              for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
+              acc = __builtin_amdgcn_fmed3f(acc, -C, C);
+              if (!REG && j >= deg[k]) acc = __builtin_inff();
+              x[k][j] = acc;
+            }
           }
         }
         __syncthreads();
@@ -273,24 +296,48 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
             const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)deg[k]) & 1u;
             float out[DC];
             if (BP == 0) {
-              // normalised min-sum: alpha * (smallest other |m|), sign product
-              float mn1 = __builtin_inff(), mn2 = __builtin_inff();
-              uint32_t par = sigma_neg, negm = 0;
+              // normalised min-sum: alpha * (smallest other |m|) with the
+              // sign product. No input is -0 (pi + messages with pi != -0,
+              // or +0 on a fresh sweep), so the sign bit is sg(). The sign
+              // product of all inputs goes into the scale (alpha * min
+              // rounds the same for either sign); each output then removes
+              // its own input's sign with one bit operation.
+              uint32_t par = sigma_neg << 31;
 #pragma unroll
-              for (int j = 0; j < DC; ++j) {
-                const float av = fabsf(x[k][j]);
-                const uint32_t ng = (x[k][j] < 0.0f) ? 1u : 0u;
-                negm |= ng << j;
-                par ^= ng;
-                mn2 = fminf(mn2, fmaxf(mn1, av));
-                mn1 = fminf(mn1, av);
+              for (int j = 0; j < DC; ++j) par ^= __float_as_uint(x[k][j]);
+              const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
+              float ex[DC];  // smallest |m| over the other inputs
+              if (DC == 2) {
+                ex[0] = fabsf(x[k][1]);
+                ex[1] = fabsf(x[k][0]);
+              } else if (DC == 4) {
+                ex[0] = min3f(fabsf(x[k][1]), fabsf(x[k][2]), fabsf(x[k][3]));
+                ex[1] = min3f(fabsf(x[k][0]), fabsf(x[k][2]), fabsf(x[k][3]));
+                ex[2] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][3]));
+                ex[3] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][2]));
+              } else {
+                float pre[DC], suf[DC];
+                pre[1] = fabsf(x[k][0]);
+#pragma unroll
+                for (int j = 2; j < DC; ++j) pre[j] = fminf(pre[j - 1], fabsf(x[k][j - 1]));
+                suf[DC - 2] = fabsf(x[k][DC - 1]);
+#pragma unroll
+                for (int j = DC - 3; j >= 0; --j) suf[j] = fminf(suf[j + 1], fabsf(x[k][j + 1]));
+                ex[0] = suf[0];
+                ex[DC - 1] = pre[DC - 1];
+#pragma unroll
+                for (int j = 1; j < DC - 1; ++j) ex[j] = fminf(pre[j], suf[j]);
               }
-              const float m1 = clampf(kp.alpha * mn1, C);
-              const float m2 = clampf(kp.alpha * mn2, C);
 #pragma unroll
               for (int j = 0; j < DC; ++j) {
-                const float mag = (fabsf(x[k][j]) == mn1) ? m2 : m1;
-                out[j] = ((par ^ (negm >> j)) & 1u) ? -mag : mag;
+                // With degree >= 2 there is an input to take the minimum of,
+                // so |v| <= alpha * clamp <= clamp (the resident min-sum path
+                // runs only with alpha <= 1) and the output clamp cannot bind;
+                // a degree-1 check of an irregular code has an empty minimum
+                // (+inf) and is clamped.
+                float v = alpha_s * ex[j];
+                if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
+                out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
               }
             } else {
               // sum-product: box-plus fold of the other inputs, ascending
@@ -309,7 +356,7 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
                     acc = boxplus(acc, x[k][i]);
                   }
                 }
-                out[j] = clampf(sigma_neg ? -acc : acc, C);
+                out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
               }
             }
 #pragma unroll
