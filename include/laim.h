@@ -247,14 +247,22 @@ void laim_batch_plan_destroy(laim_batch_plan* plan);
 typedef struct laim_server laim_server;
 
 typedef struct {
-  uint64_t ticket;   /* from laim_server_submit */
-  int32_t round;     /* rounds completed by this request after this step */
-  int32_t done;      /* 1 when the request finished (cleared or rounds exhausted) */
-  int32_t tclr;      /* as in laim_decode_rounds, valid when done */
-  int32_t flips;     /* qubits flipped in this round */
-  int32_t defects;   /* syndrome weight after this round */
+  uint64_t ticket;     /* from laim_server_submit */
+  int32_t round;       /* rounds completed by this request after this step */
+  int32_t done;        /* 1 when the request finished (cleared and retired, or rounds exhausted) */
+  int32_t tclr;        /* as in laim_decode_rounds (-1 while not cleared) */
+  int32_t flips;       /* qubits flipped in this round */
+  int32_t defects;     /* syndrome weight after this round */
+  int32_t fail;        /* decoder failure of the current state (final when done) */
+  int64_t latency_ns;  /* this round: from its input being ready (submission for round 0,
+                          the previous round's completion otherwise) to its results on the host */
 } laim_server_event;
 
+/* Creates a server on `device` with a device-memory budget for request
+ * state (per request about n + 4 m d_c + n + m + 256 bytes, 256-aligned
+ * parts) and at most max_slots requests advanced per step. Requests must
+ * use codes with check degree <= 8 and qubit degree <= 4 (min-sum with
+ * alpha <= 1). */
 laim_status laim_server_create(int32_t device, size_t mem_budget_bytes, int32_t max_slots,
                                laim_server** out);
 /* Queues one request; e0_host [n] (0/1) is copied. Returns a ticket. */

@@ -1,29 +1,595 @@
-// laim_batch.cpp -- batched persistent launch and serving loop (placeholder
-// entry points until the implementations land).
+// laim_batch.cpp -- batched plans (one persistent launch over shots of
+// several codes, replayed from a HIP graph) and the continuous-batching
+// server (requests resident in device memory, one round per step).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
 #include "laim_internal.h"
 
 using namespace laim;
 
+namespace {
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+int cu_count(int device) {
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  return cus > 0 ? cus : 256;
+}
+
+// Resolves one code + parameters into the device record of the multi-code
+// kernels (shape, variant) and its LDS/block needs.
+laim_status make_item(const laim_code* code, const laim_decode_params* params, BatchItemDev* it,
+                      size_t* lds, int* block) {
+  KParams kp;
+  laim_status st = resolve_params(params, &kp);
+  if (st != LAIM_OK) return st;
+  if (kp.bp == 0 && kp.alpha > 1.0f) {
+    set_error("the batched form runs min-sum with alpha <= 1 only");
+    return LAIM_EUNSUP;
+  }
+  memset(it, 0, sizeof(*it));
+  it->c = code->dev;
+  it->kp = kp;
+  const laim_resident_cfg* want = code->has_cfg[kp.bp] ? &code->cfg[kp.bp] : nullptr;
+  if (!batch_variant(code->dev, kp.bp, want, code->device, &it->u, &it->variant, lds, block))
+    return LAIM_EUNSUP;
+  it->u.rounds = kp.rounds;
+  return LAIM_OK;
+}
+
+}  // namespace
+
+// ===================================================================== plan
+struct laim_batch_plan {
+  int device = 0;
+  hipStream_t cap = nullptr;
+  void* dev_mem = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 extern "C" {
-laim_status laim_batch_plan_create(const laim_batch_item*, int32_t, laim_stream, laim_batch_plan** out) {
-  if (out) *out = nullptr;
-  set_error("batched plans are not available in this build");
-  return LAIM_EUNSUP;
+
+laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems, laim_stream stream,
+                                   laim_batch_plan** out) {
+  (void)stream;
+  if (!out || nitems < 1 || !items) {
+    set_error("laim_batch_plan_create: bad arguments");
+    return LAIM_EINVAL;
+  }
+  *out = nullptr;
+  const int device = items[0].code ? items[0].code->device : 0;
+  struct PerBp {
+    std::vector<BatchItemDev> items;
+    std::vector<BatchUnitDev> units;
+    std::vector<double> cost;
+    size_t lds = 0;
+    int block = 0;
+  } per[2];
+  std::vector<int> fallback_fail;  // items whose failure test runs in its own kernel
+  for (int32_t i = 0; i < nitems; ++i) {
+    const laim_batch_item& b = items[i];
+    if (!b.code || b.nshots < 0 ||
+        (b.nshots > 0 && (!b.e0 || !b.z_out || !b.s_out || !b.tclr_out))) {
+      set_error("batch item %d: bad arguments", i);
+      return LAIM_EINVAL;
+    }
+    if (b.code->device != device) {
+      set_error("batch item %d: every code must live on the same device", i);
+      return LAIM_EINVAL;
+    }
+    BatchItemDev it;
+    size_t lds = 0;
+    int block = 0;
+    laim_status st = make_item(b.code, &b.params, &it, &lds, &block);
+    if (st != LAIM_OK) return st;
+    it.e0 = b.e0;
+    it.shot0 = b.shot0;
+    it.nshots = b.nshots;
+    it.z = b.z_out;
+    it.s = b.s_out;
+    it.tclr = b.tclr_out;
+    it.fail = (b.fail_out && b.code->dev.kw <= 4) ? b.fail_out : nullptr;
+    if (b.fail_out && !it.fail) fallback_fail.push_back(i);
+    PerBp& P = per[it.kp.bp];
+    const int32_t idx = (int32_t)P.items.size();
+    P.items.push_back(it);
+    P.lds = std::max(P.lds, lds);
+    P.block = std::max(P.block, block);
+    // cost of a unit ~ the work of one of its threads
+    const double cost = (double)it.kp.rounds * std::max(it.kp.iters, 1) *
+                        ((double)b.code->E / std::max(it.u.nt, 1));
+    for (int32_t base = 0; base < b.nshots; base += it.u.spb) {
+      P.units.push_back(BatchUnitDev{idx, base});
+      P.cost.push_back(cost);
+    }
+  }
+  // longest work first
+  for (auto& P : per) {
+    std::vector<size_t> ord(P.units.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return P.cost[a] > P.cost[b]; });
+    std::vector<BatchUnitDev> u2;
+    for (size_t k : ord) u2.push_back(P.units[k]);
+    P.units.swap(u2);
+  }
+  laim_batch_plan* plan = new (std::nothrow) laim_batch_plan();
+  if (!plan) {
+    set_error("out of host memory");
+    return LAIM_ENOMEM;
+  }
+  plan->device = device;
+  DeviceGuard g(device);
+  size_t off[2][3];
+  size_t total = 0;
+  for (int bp = 0; bp < 2; ++bp) {
+    off[bp][0] = total;
+    total += al256(per[bp].items.size() * sizeof(BatchItemDev));
+    off[bp][1] = total;
+    total += al256(per[bp].units.size() * sizeof(BatchUnitDev));
+    off[bp][2] = total;
+    total += 256;
+  }
+  hipError_t e = hipMalloc(&plan->dev_mem, total);
+  if (e != hipSuccess) {
+    delete plan;
+    set_error("hipMalloc of %zu bytes for the plan failed", total);
+    return LAIM_ENOMEM;
+  }
+  char* base = (char*)plan->dev_mem;
+  for (int bp = 0; bp < 2 && e == hipSuccess; ++bp) {
+    if (!per[bp].items.empty())
+      e = hipMemcpy(base + off[bp][0], per[bp].items.data(), per[bp].items.size() * sizeof(BatchItemDev),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess && !per[bp].units.empty())
+      e = hipMemcpy(base + off[bp][1], per[bp].units.data(), per[bp].units.size() * sizeof(BatchUnitDev),
+                    hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipStreamCreate(&plan->cap);
+  if (e == hipSuccess) e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+  for (int bp = 0; bp < 2 && e == hipSuccess; ++bp) {
+    PerBp& P = per[bp];
+    if (P.units.empty()) continue;
+    const int per_cu = batch_blocks_per_cu(bp, P.block, P.lds);
+    if (per_cu < 1) {
+      e = hipErrorInvalidConfiguration;
+      break;
+    }
+    const int grid = (int)std::min<size_t>(P.units.size(), (size_t)per_cu * cu_count(device));
+    e = launch_batch(bp, (const BatchItemDev*)(base + off[bp][0]),
+                     (const BatchUnitDev*)(base + off[bp][1]), (int32_t)P.units.size(),
+                     (uint32_t*)(base + off[bp][2]), P.lds, P.block, grid, plan->cap);
+  }
+  for (int i : fallback_fail) {
+    if (e != hipSuccess) break;
+    const laim_batch_item& b = items[i];
+    e = launch_failure(b.code->dev, b.e0, b.z_out, b.nshots, b.fail_out, plan->cap);
+  }
+  if (plan->cap) {
+    hipGraph_t gph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(plan->cap, &gph);
+    if (e == hipSuccess) e = e2;
+    plan->graph = gph;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    laim_status st = hip_fail(e, "building the batched plan");
+    laim_batch_plan_destroy(plan);
+    return st;
+  }
+  *out = plan;
+  return LAIM_OK;
 }
-laim_status laim_batch_plan_launch(laim_batch_plan*, laim_stream) {
-  set_error("batched plans are not available in this build");
-  return LAIM_EUNSUP;
+
+laim_status laim_batch_plan_launch(laim_batch_plan* plan, laim_stream stream) {
+  if (!plan || !plan->exec) {
+    set_error("plan is NULL");
+    return LAIM_EINVAL;
+  }
+  DeviceGuard g(plan->device);
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  return e == hipSuccess ? LAIM_OK : hip_fail(e, "hipGraphLaunch");
 }
-void laim_batch_plan_destroy(laim_batch_plan*) {}
-laim_status laim_server_create(int32_t, size_t, int32_t, laim_server** out) {
-  if (out) *out = nullptr;
-  set_error("the server is not available in this build");
-  return LAIM_EUNSUP;
+
+void laim_batch_plan_destroy(laim_batch_plan* plan) {
+  if (!plan) return;
+  DeviceGuard g(plan->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->cap) (void)hipStreamDestroy(plan->cap);
+  if (plan->dev_mem) (void)hipFree(plan->dev_mem);
+  delete plan;
 }
-laim_status laim_server_submit(laim_server*, const laim_code*, const laim_decode_params*, uint64_t,
-                               const uint8_t*, uint64_t*) { return LAIM_EUNSUP; }
-laim_status laim_server_step(laim_server*, laim_server_event*, int32_t, int32_t*) { return LAIM_EUNSUP; }
-laim_status laim_server_result(laim_server*, uint64_t, uint8_t*, uint8_t*, int32_t*) { return LAIM_EUNSUP; }
-laim_status laim_server_stats(const laim_server*, int32_t*, int32_t*, size_t*) { return LAIM_EUNSUP; }
-void laim_server_destroy(laim_server*) {}
+
+}  // extern "C"
+
+// =================================================================== server
+namespace {
+
+// First-fit allocator over one device arena (offsets, 256-byte granules).
+struct Arena {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  size_t used = 0;
+  void init(size_t s) {
+    size = s;
+    free_.clear();
+    if (s) free_[0] = s;
+    used = 0;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = al256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n;
+        const size_t roff = it->first + n;
+        free_.erase(it);
+        if (rest) free_[roff] = rest;
+        used += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = al256(n);
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Request {
+  uint64_t ticket;
+  const laim_code* code;
+  int item;  // index into the server's item table
+  int bp;
+  uint64_t shot;
+  int32_t rounds_total;
+  int32_t round = 0;
+  int32_t retire = 1;
+  std::vector<uint8_t> e0;
+  bool resident = false, done = false;
+  size_t off = 0, bytes = 0;  // arena block
+  size_t o_e0, o_msg, o_z, o_s, o_hdr;
+  int32_t tclr = -1, fail = 0;
+  int64_t t_ready = 0;
+};
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
 }
+
+}  // namespace
+
+struct laim_server {
+  int device = 0;
+  int max_slots = 0;
+  hipStream_t st = nullptr;
+  void* arena_mem = nullptr;
+  Arena arena;
+  // item table (one record per distinct code + parameters), on host and device
+  std::vector<BatchItemDev> items;
+  std::vector<std::vector<char>> item_keys;
+  std::vector<size_t> item_lds;
+  std::vector<int> item_block;
+  BatchItemDev* items_dev = nullptr;
+  size_t items_dev_cap = 0;
+  bool items_dirty = false;
+  // per-step tables (pinned host, device)
+  ServerReqDev* reqs_h = nullptr;
+  ServerUnitDev* units_h = nullptr;
+  int32_t* ev_h = nullptr;
+  ServerReqDev* reqs_d = nullptr;
+  ServerUnitDev* units_d = nullptr;
+  int32_t* ev_d = nullptr;
+  std::map<uint64_t, Request> reqs;
+  std::deque<uint64_t> waiting;
+  uint64_t next_ticket = 1;
+};
+
+extern "C" {
+
+laim_status laim_server_create(int32_t device, size_t mem_budget_bytes, int32_t max_slots,
+                               laim_server** out) {
+  if (!out || max_slots < 1 || mem_budget_bytes < 4096) {
+    set_error("laim_server_create: bad arguments");
+    return LAIM_EINVAL;
+  }
+  *out = nullptr;
+  laim_server* s = new (std::nothrow) laim_server();
+  if (!s) {
+    set_error("out of host memory");
+    return LAIM_ENOMEM;
+  }
+  s->device = device;
+  s->max_slots = max_slots;
+  DeviceGuard g(device);
+  hipError_t e = hipStreamCreate(&s->st);
+  if (e == hipSuccess) e = hipMalloc(&s->arena_mem, mem_budget_bytes);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->reqs_h, sizeof(ServerReqDev) * max_slots, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->units_h, sizeof(ServerUnitDev) * max_slots, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->ev_h, sizeof(int32_t) * 4 * max_slots, 0);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->reqs_d, sizeof(ServerReqDev) * max_slots);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->units_d, sizeof(ServerUnitDev) * max_slots);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->ev_d, sizeof(int32_t) * 4 * max_slots);
+  if (e != hipSuccess) {
+    laim_status st = hip_fail(e, "creating the server");
+    laim_server_destroy(s);
+    return st == LAIM_EHIP ? LAIM_ENOMEM : st;
+  }
+  s->arena.init(mem_budget_bytes);
+  *out = s;
+  return LAIM_OK;
+}
+
+void laim_server_destroy(laim_server* s) {
+  if (!s) return;
+  DeviceGuard g(s->device);
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  if (s->reqs_h) (void)hipHostFree(s->reqs_h);
+  if (s->units_h) (void)hipHostFree(s->units_h);
+  if (s->ev_h) (void)hipHostFree(s->ev_h);
+  if (s->reqs_d) (void)hipFree(s->reqs_d);
+  if (s->units_d) (void)hipFree(s->units_d);
+  if (s->ev_d) (void)hipFree(s->ev_d);
+  if (s->items_dev) (void)hipFree(s->items_dev);
+  if (s->arena_mem) (void)hipFree(s->arena_mem);
+  if (s->st) (void)hipStreamDestroy(s->st);
+  delete s;
+}
+
+laim_status laim_server_submit(laim_server* s, const laim_code* code,
+                               const laim_decode_params* params, uint64_t shot_id,
+                               const uint8_t* e0_host, uint64_t* ticket) {
+  if (!s || !code || !params || !e0_host || !ticket) {
+    set_error("laim_server_submit: bad arguments");
+    return LAIM_EINVAL;
+  }
+  if (code->device != s->device) {
+    set_error("the code lives on another device than the server");
+    return LAIM_EINVAL;
+  }
+  // one item per distinct (code, parameters)
+  std::vector<char> key(sizeof(void*) + sizeof(laim_decode_params));
+  memcpy(key.data(), &code, sizeof(void*));
+  memcpy(key.data() + sizeof(void*), params, sizeof(laim_decode_params));
+  int item = -1;
+  for (size_t i = 0; i < s->item_keys.size(); ++i)
+    if (s->item_keys[i] == key) item = (int)i;
+  if (item < 0) {
+    BatchItemDev it;
+    size_t lds = 0;
+    int block = 0;
+    laim_status st = make_item(code, params, &it, &lds, &block);
+    if (st != LAIM_OK) return st;
+    item = (int)s->items.size();
+    s->items.push_back(it);
+    s->item_keys.push_back(key);
+    s->item_lds.push_back(lds);
+    s->item_block.push_back(block);
+    s->items_dirty = true;
+  }
+  Request r;
+  r.ticket = s->next_ticket++;
+  r.code = code;
+  r.item = item;
+  r.bp = s->items[item].kp.bp;
+  r.shot = shot_id;
+  r.rounds_total = params->rounds;
+  r.retire = params->retire ? 1 : 0;
+  r.e0.assign(e0_host, e0_host + code->n);
+  for (auto& b : r.e0) b &= 1u;
+  r.t_ready = now_ns();
+  *ticket = r.ticket;
+  s->waiting.push_back(r.ticket);
+  s->reqs.emplace(r.ticket, std::move(r));
+  return LAIM_OK;
+}
+
+laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t max_events,
+                             int32_t* n_events) {
+  if (!s || !n_events || (max_events > 0 && !events)) {
+    set_error("laim_server_step: bad arguments");
+    return LAIM_EINVAL;
+  }
+  *n_events = 0;
+  DeviceGuard g(s->device);
+  hipError_t e = hipSuccess;
+  // ---- admission, FIFO, while slots and memory allow
+  int resident = 0;
+  for (auto& kv : s->reqs)
+    if (kv.second.resident && !kv.second.done) ++resident;
+  while (!s->waiting.empty() && resident < s->max_slots) {
+    Request& r = s->reqs.at(s->waiting.front());
+    const laim_code* c = r.code;
+    const size_t b_e0 = al256(c->n), b_msg = al256((size_t)c->m * c->dcmax * 4),
+                 b_z = al256(c->n), b_s = al256(c->m), b_hdr = 256;
+    const size_t bytes = b_e0 + b_msg + b_z + b_s + b_hdr;
+    size_t off;
+    if (!s->arena.alloc(bytes, &off)) break;
+    r.off = off;
+    r.bytes = bytes;
+    r.o_e0 = off;
+    r.o_msg = r.o_e0 + b_e0;
+    r.o_z = r.o_msg + b_msg;
+    r.o_s = r.o_z + b_z;
+    r.o_hdr = r.o_s + b_s;
+    e = hipMemcpyAsync((char*)s->arena_mem + r.o_e0, r.e0.data(), c->n, hipMemcpyHostToDevice, s->st);
+    if (e != hipSuccess) return hip_fail(e, "admitting a request");
+    r.resident = true;
+    s->waiting.pop_front();
+    ++resident;
+  }
+  if (s->items_dirty) {
+    if (s->items.size() > s->items_dev_cap) {
+      if (s->items_dev) {
+        (void)hipStreamSynchronize(s->st);
+        (void)hipFree(s->items_dev);
+      }
+      s->items_dev_cap = std::max<size_t>(16, s->items.size() * 2);
+      e = hipMalloc((void**)&s->items_dev, s->items_dev_cap * sizeof(BatchItemDev));
+      if (e != hipSuccess) return hip_fail(e, "server item table");
+    }
+    e = hipMemcpyAsync(s->items_dev, s->items.data(), s->items.size() * sizeof(BatchItemDev),
+                       hipMemcpyHostToDevice, s->st);
+    if (e != hipSuccess) return hip_fail(e, "server item table");
+    s->items_dirty = false;
+  }
+  // ---- units: resident requests grouped by (BP, item, first round or not)
+  std::vector<uint64_t> order;
+  for (auto& kv : s->reqs)
+    if (kv.second.resident && !kv.second.done) order.push_back(kv.first);
+  if (order.empty()) return LAIM_OK;
+  std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+    const Request &x = s->reqs.at(a), &y = s->reqs.at(b);
+    const int kx = x.bp * 1000000 + x.item * 2 + (x.round > 0);
+    const int ky = y.bp * 1000000 + y.item * 2 + (y.round > 0);
+    return kx < ky;
+  });
+  int nreq = 0, nunit = 0;
+  int unit_first[2] = {-1, -1}, unit_count[2] = {0, 0};
+  size_t lds[2] = {0, 0};
+  int block[2] = {0, 0};
+  for (size_t k = 0; k < order.size(); ++k) {
+    Request& r = s->reqs.at(order[k]);
+    char* A = (char*)s->arena_mem;
+    ServerReqDev q;
+    q.shot = r.shot;
+    q.round = r.round;
+    q.pad = 0;
+    q.e0 = (const uint8_t*)(A + r.o_e0);
+    q.msg = (float*)(A + r.o_msg);
+    q.z = (uint8_t*)(A + r.o_z);
+    q.s = (uint8_t*)(A + r.o_s);
+    q.hdr = (int32_t*)(A + r.o_hdr);
+    q.fail = (uint8_t*)(A + r.o_hdr + 16);
+    q.ev = s->ev_d + 4 * nreq;
+    s->reqs_h[nreq] = q;
+    const BatchItemDev& it = s->items[r.item];
+    const bool resume = r.round > 0;
+    const bool new_unit = nunit == 0 || s->units_h[nunit - 1].item != r.item ||
+                          s->units_h[nunit - 1].resume != (resume ? 1 : 0) ||
+                          s->units_h[nunit - 1].count >= it.u.spb;
+    if (new_unit) {
+      if (unit_first[r.bp] < 0) unit_first[r.bp] = nunit;
+      ++unit_count[r.bp];
+      s->units_h[nunit++] = ServerUnitDev{r.item, nreq, 0, resume ? 1 : 0};
+      lds[r.bp] = std::max(lds[r.bp], s->item_lds[r.item]);
+      block[r.bp] = std::max(block[r.bp], s->item_block[r.item]);
+    }
+    s->units_h[nunit - 1].count++;
+    ++nreq;
+  }
+  e = hipMemcpyAsync(s->reqs_d, s->reqs_h, sizeof(ServerReqDev) * nreq, hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->units_d, s->units_h, sizeof(ServerUnitDev) * nunit, hipMemcpyHostToDevice, s->st);
+  for (int bp = 0; bp < 2 && e == hipSuccess; ++bp)
+    if (unit_count[bp])
+      e = launch_server(bp, s->items_dev, s->units_d + unit_first[bp], unit_count[bp], s->reqs_d,
+                        lds[bp], block[bp], s->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ev_h, s->ev_d, sizeof(int32_t) * 4 * nreq, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(e, "server step");
+  const int64_t t = now_ns();
+  int32_t ne = 0;
+  for (int i = 0; i < nreq; ++i) {
+    Request& r = s->reqs.at(order[i]);
+    r.round += 1;
+    r.tclr = s->ev_h[4 * i + 2];
+    r.fail = s->ev_h[4 * i + 3];
+    r.done = (r.retire && r.tclr >= 0) || r.round >= r.rounds_total;
+    if (ne < max_events) {
+      laim_server_event& ev = events[ne++];
+      ev.ticket = r.ticket;
+      ev.round = r.round;
+      ev.done = r.done ? 1 : 0;
+      ev.tclr = r.tclr;
+      ev.flips = s->ev_h[4 * i + 0];
+      ev.defects = s->ev_h[4 * i + 1];
+      ev.fail = r.fail;
+      ev.latency_ns = t - r.t_ready;
+    }
+    r.t_ready = t;
+  }
+  *n_events = ne;
+  return LAIM_OK;
+}
+
+laim_status laim_server_result(laim_server* s, uint64_t ticket, uint8_t* z_host, uint8_t* s_host,
+                               int32_t* tclr) {
+  if (!s) {
+    set_error("server is NULL");
+    return LAIM_EINVAL;
+  }
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) {
+    set_error("unknown ticket");
+    return LAIM_EINVAL;
+  }
+  Request& r = it->second;
+  if (!r.done) {
+    set_error("request %llu is not finished", (unsigned long long)ticket);
+    return LAIM_EBUSY;
+  }
+  DeviceGuard g(s->device);
+  hipError_t e = hipSuccess;
+  char* A = (char*)s->arena_mem;
+  if (z_host) e = hipMemcpy(z_host, A + r.o_z, r.code->n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && s_host) e = hipMemcpy(s_host, A + r.o_s, r.code->m, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading a result");
+  if (tclr) *tclr = r.tclr;
+  s->arena.release(r.off, r.bytes);
+  s->reqs.erase(it);
+  return LAIM_OK;
+}
+
+laim_status laim_server_stats(const laim_server* s, int32_t* resident, int32_t* waiting,
+                              size_t* bytes_in_use) {
+  if (!s) {
+    set_error("server is NULL");
+    return LAIM_EINVAL;
+  }
+  int32_t res = 0;
+  for (auto& kv : s->reqs)
+    if (kv.second.resident && !kv.second.done) ++res;
+  if (resident) *resident = res;
+  if (waiting) *waiting = (int32_t)s->waiting.size();
+  if (bytes_in_use) *bytes_in_use = s->arena.used;
+  return LAIM_OK;
+}
+
+}  // extern "C"

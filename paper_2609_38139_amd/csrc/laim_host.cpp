@@ -606,7 +606,7 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
   hipError_t er;
   if (f == LAIM_FORM_RESIDENT)
     er = launch_resident(code->dev, kp, sh, e0, shot0, nshots, ws, z_out, s_out, tclr_out, L_out,
-                         (hipStream_t)stream);
+                         nullptr, (hipStream_t)stream);
   else
     er = launch_stream(code->dev, kp, e0, shot0, nshots, ws, z_out, s_out, tclr_out, L_out,
                        (hipStream_t)stream);

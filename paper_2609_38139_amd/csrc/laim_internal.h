@@ -79,15 +79,72 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
 size_t resident_workspace_bytes();
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
-                           uint8_t* z, uint8_t* s, int32_t* tclr, float* L, hipStream_t st);
+                           uint8_t* z, uint8_t* s, int32_t* tclr, float* L, uint8_t* fail,
+                           hipStream_t st);
 
 size_t stream_workspace_bytes(const DevCode& c, int32_t nshots);
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
                          int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
                          hipStream_t st);
 
-// Batched persistent launch over several codes (laim_batch.hip).
-struct BatchUnit;  // opaque here
+// ---- multi-code kernels (batched plans and the serving loop)
+// Block-uniform description of a unit: the launch shape of one code, the
+// rounds to run, and whether groups resume from saved state.
+struct UnitCtx {
+  int32_t nt, vpt, spb, mpad, group_bytes;
+  int32_t rounds;  // rounds run in this unit
+  int32_t resume;  // 1: every group continues from its saved state
+  int32_t events;  // 1: count flips and defects for the groups' ev_out
+};
+
+struct BatchItemDev {
+  DevCode c;
+  KParams kp;
+  UnitCtx u;
+  int32_t variant;
+  const uint8_t* e0;
+  uint64_t shot0;
+  int32_t nshots;
+  uint8_t* z;
+  uint8_t* s;
+  int32_t* tclr;
+  uint8_t* fail;
+};
+
+struct BatchUnitDev {
+  int32_t item;
+  int32_t base;  // first shot index of the unit within the item
+};
+
+struct ServerUnitDev {
+  int32_t item;    // code and parameters
+  int32_t first;   // first request of the unit in the request table
+  int32_t count;   // requests in the unit (<= spb)
+  int32_t resume;  // 0 on a request's first round
+};
+
+struct ServerReqDev {
+  uint64_t shot;
+  int32_t round;  // rounds already run
+  int32_t pad;
+  const uint8_t* e0;  // [n]
+  float* msg;         // [m * dcmax]
+  uint8_t* z;         // [n]
+  uint8_t* s;         // [m]
+  int32_t* hdr;       // [4]: t_clr
+  int32_t* ev;        // [2]: flips, syndrome weight
+  uint8_t* fail;      // [1]
+};
+
+bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, UnitCtx* u,
+                   int* variant, size_t* lds, int* block);
+hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
+                        int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
+                        hipStream_t st);
+int batch_blocks_per_cu(int bp, int block, size_t lds);
+hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev* units,
+                         int32_t nunits, const ServerReqDev* reqs, size_t lds, int block,
+                         hipStream_t st);
 
 }  // namespace laim
 

@@ -131,19 +131,469 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 }
 
 // ====================================================================
-// Resident form: one persistent launch. A block holds `spb` shot groups of
-// `nt` threads; thread t of a group owns checks t + k nt (k < CPT) and qubits
+// Resident form. A block runs "units": up to `spb` shots of one code at
+// once, one shot per group of `nt` threads, in lockstep through the same
+// rounds. Thread t of a group owns checks t + k nt (k < CPT) and qubits
 // t + k nt (k < vpt). Per group, LDS holds the current m_{c->v} in
 // slot-major order msg[j * mpad + c] (consecutive lanes touch consecutive
-// words) plus one word holding -0.0 that padded qubit-side partners point
-// at (x + (-0.0) == x for every x), and one byte per qubit for the flip
-// requests of the feedback step. A block takes `spb` consecutive shots from
-// a queue, runs them in lockstep for up to R rounds, writes their results,
-// and takes the next ones until the queue is empty.
+// words), a few scratch words -- the first holds -0.0, which padded
+// qubit-side partners point at (x + (-0.0) == x for every x) -- and one byte
+// per qubit for the flip requests of the feedback step. A shot either
+// starts fresh from its initial error or resumes from state saved in device
+// memory (used by the serving loop, which runs one round per launch).
 // ====================================================================
+
+// What one group of a unit works on.
+struct GroupJob {
+  int32_t alive;
+  int32_t r0;            // number of the first round run here (Philox counter)
+  uint64_t shot;         // logical shot id
+  const uint8_t* e0row;  // [n] initial error
+  float* st_msg;         // resumable state or null: [m * dcmax] m_{c->v} in ELL order,
+  uint8_t* st_z;         //   [n] correction, [m] syndrome,
+  uint8_t* st_s;
+  int32_t* st_hdr;       //   [0] t_clr
+  uint8_t* z_out;        // results or null: [n] z, [m] s, t_clr, [n] beliefs,
+  uint8_t* s_out;
+  int32_t* t_out;
+  float* L_out;
+  uint8_t* f_out;        //   logical failure (0/1)
+  int32_t* ev_out;       //   [4] flips and syndrome weight of the last round run, t_clr, failure
+};
+
+constexpr int kCtrlWords = 64;  // [0] queue value, [1 + g] group still working
+constexpr int kMaxShotsPerBlock = 31;
+constexpr int kGroupWords = 16;  // per-group scratch words after msg
+// scratch word indices
+constexpr int kGwZero = 0, kGwLpar = 1 /* 4 words */, kGwFlips = 5, kGwDefects = 6, kGwInit = 7,
+              kGwAct0 = 8, kGwAct1 = 9;
+constexpr int kFusedMaxWords = 4;  // logicals folded in LDS by the fused failure test
+
+__device__ __forceinline__ GroupJob dead_job() {
+  GroupJob j;
+  j.alive = 0;
+  j.r0 = 0;
+  j.shot = 0;
+  j.e0row = nullptr;
+  j.st_msg = nullptr;
+  j.st_z = j.st_s = nullptr;
+  j.st_hdr = nullptr;
+  j.z_out = j.s_out = nullptr;
+  j.t_out = nullptr;
+  j.L_out = nullptr;
+  j.f_out = nullptr;
+  j.ev_out = nullptr;
+  return j;
+}
+
+// Runs one unit; every thread of the block calls it (threads beyond
+// spb * nt only take part in the barriers).
+template <int DC, int DV, int CPT, int BP, bool REG, class JobAt>
+__device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, const JobAt& job_at,
+                         unsigned char* smem) {
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+  const int32_t spb = u.spb;
+  const int32_t tid = threadIdx.x;
+  const int32_t g = tid / u.nt;
+  const bool member = g < spb;
+  const int32_t t = member ? tid - g * u.nt : 0;
+  // The job is read twice (here and for the results) rather than kept in
+  // registers through the rounds: only the shot id and first round live on.
+  bool alive;
+  uint64_t shot;
+  int32_t r0;
+  {
+    const GroupJob job = member ? job_at(g) : dead_job();
+    alive = member && job.alive;
+    shot = job.shot;
+    r0 = job.r0;
+  }
+  float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)(member ? g : 0) * u.group_bytes);
+  const int32_t zslot = DC * u.mpad;
+  int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
+  uint8_t* fl = reinterpret_cast<uint8_t*>(gw + kGroupWords);
+  const float C = kp.clamp;
+  const float pi = kp.pi;
+
+  // ---- per-thread graph tables
+  int32_t cidx[CPT];
+  int32_t deg[CPT];
+  int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int32_t ch = t + k * u.nt;
+    const bool valid = member && ch < c.m;
+    cidx[k] = valid ? ch : -1;
+    deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+#pragma unroll
+      for (int p = 0; p < DV - 1; ++p) {
+        int32_t e = -1;
+        if (valid && j < c.dcmax && p < c.dvmax - 1)
+          e = c.partner[((int64_t)ch * c.dcmax + j) * (c.dvmax - 1) + p];
+        pidx[k][j][p] = (e >= 0) ? edge_slot(e) * u.mpad + edge_check(e) : zslot;
+      }
+    }
+  }
+
+  // ---- start: e0 bits, z, s, messages, flip requests, scratch words
+  uint32_t zb = 0, sb = 0, eb = 0;
+  int32_t tclr = -1;
+  if (member) {
+    const GroupJob job = job_at(g);
+    if (t == 0) {
+      gw[kGwZero] = (int32_t)0x80000000u;  // -0.0f
+      for (int w = 1; w < kGroupWords; ++w) gw[w] = 0;
+    }
+#pragma unroll 1
+    for (int k = 0; k < u.vpt; ++k) {
+      const int32_t v = t + k * u.nt;
+      if (v >= c.n) continue;
+      fl[v] = 0;
+      if (alive) {
+        eb |= (uint32_t)(job.e0row[v] & 1u) << k;
+        if (u.resume) zb |= (uint32_t)(job.st_z[v] & 1u) << k;
+      }
+    }
+#pragma unroll 1
+    for (int k = 0; k < CPT; ++k) {
+      const int32_t ch = t + k * u.nt;
+      if (ch >= c.m) continue;
+      uint32_t x = 0;
+      if (u.resume) {
+        for (int j = 0; j < DC; ++j)
+          msg[j * u.mpad + ch] = (alive && j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
+        if (alive) x = job.st_s[ch] & 1u;
+      } else {
+        for (int j = 0; j < DC; ++j) msg[j * u.mpad + ch] = 0.0f;
+        if (alive) {
+          const int32_t d = c.chk_deg[ch];
+          for (int32_t j = 0; j < d; ++j) x ^= job.e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
+        }
+      }
+      sb |= (x & 1u) << k;
+    }
+  }
+  __syncthreads();
+  if (member && sb) gw[kGwInit] = 1;
+  __syncthreads();
+  if (member) {
+    if (u.resume)
+      tclr = alive ? job_at(g).st_hdr[0] : -1;
+    else
+      tclr = gw[kGwInit] ? -1 : 0;
+  }
+  bool working = alive && !(kp.retire && tclr >= 0);
+  bool fresh = !u.resume;
+  int32_t flips_last = 0;
+
+  for (int32_t rr = 0; rr < u.rounds; ++rr) {
+    const int32_t r = r0 + rr;
+    __syncthreads();
+    if (member && t == 0) {
+      ctrl[1 + g] = working ? 1 : 0;
+      gw[((rr + 1) & 1) ? kGwAct1 : kGwAct0] = 0;
+      gw[kGwFlips] = 0;
+    }
+    __syncthreads();
+    int32_t anyw = 0;
+    for (int32_t h = 0; h < spb; ++h) anyw |= ctrl[1 + h];
+    if (!anyw) break;
+
+    // ---- BP sweeps
+    int32_t it0 = 0;
+    if (fresh && REG && kp.iters > 0) {
+      // First sweep of a shot: every m_{v->c} is 0, so each check sends
+      // (-1)^{s_c + d_c} * 0 (min-sum: alpha * 0; sum-product: 0 [+] 0 = +0).
+      if (working) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          if (cidx[k] < 0) continue;
+          const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
+#pragma unroll
+          for (int j = 0; j < DC; ++j) msg[j * u.mpad + cidx[k]] = z0;
+        }
+      }
+      fresh = false;
+      it0 = 1;
+      __syncthreads();
+    }
+    for (int32_t it = it0; it < kp.iters; ++it) {
+      float x[CPT][DC];
+      if (!REG && fresh) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+#pragma unroll
+          for (int j = 0; j < DC; ++j) x[k][j] = (j >= deg[k]) ? __builtin_inff() : 0.0f;
+      } else {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            float acc = pi;
+#pragma unroll
+            for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
+            acc = __builtin_amdgcn_fmed3f(acc, -C, C);
+            if (!REG && j >= deg[k]) acc = __builtin_inff();
+            x[k][j] = acc;
+          }
+        }
+      }
+      __syncthreads();
+      if (working) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+          if (cidx[k] < 0) continue;
+          const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
+          float out[DC];
+          if (BP == 0) {
+            // normalised min-sum: alpha * (smallest other |m|) with the
+            // sign product. No input is -0 (pi + messages with pi != -0,
+            // or +0 on a fresh sweep), so the sign bit is sg(). The sign
+            // product of all inputs goes into the scale (alpha * min
+            // rounds the same for either sign); each output then removes
+            // its own input's sign with one bit operation.
+            uint32_t par = sigma_neg << 31;
+#pragma unroll
+            for (int j = 0; j < DC; ++j) par ^= __float_as_uint(x[k][j]);
+            const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
+            float ex[DC];  // smallest |m| over the other inputs
+            if (DC == 2) {
+              ex[0] = fabsf(x[k][1]);
+              ex[1] = fabsf(x[k][0]);
+            } else if (DC == 4) {
+              ex[0] = min3f(fabsf(x[k][1]), fabsf(x[k][2]), fabsf(x[k][3]));
+              ex[1] = min3f(fabsf(x[k][0]), fabsf(x[k][2]), fabsf(x[k][3]));
+              ex[2] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][3]));
+              ex[3] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][2]));
+            } else {
+              float pre[DC], suf[DC];
+              pre[1] = fabsf(x[k][0]);
+#pragma unroll
+              for (int j = 2; j < DC; ++j) pre[j] = fminf(pre[j - 1], fabsf(x[k][j - 1]));
+              suf[DC - 2] = fabsf(x[k][DC - 1]);
+#pragma unroll
+              for (int j = DC - 3; j >= 0; --j) suf[j] = fminf(suf[j + 1], fabsf(x[k][j + 1]));
+              ex[0] = suf[0];
+              ex[DC - 1] = pre[DC - 1];
+#pragma unroll
+              for (int j = 1; j < DC - 1; ++j) ex[j] = fminf(pre[j], suf[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+              // With degree >= 2 there is an input to take the minimum of,
+              // so |v| <= alpha * clamp <= clamp (the resident min-sum path
+              // runs only with alpha <= 1) and the output clamp cannot bind;
+              // a degree-1 check of an irregular code has an empty minimum
+              // (+inf) and is clamped.
+              float v = alpha_s * ex[j];
+              if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
+              out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
+            }
+          } else {
+            // sum-product: box-plus fold of the other inputs, ascending
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+              float acc = __builtin_inff();
+              bool first = true;
+#pragma unroll
+              for (int i = 0; i < DC; ++i) {
+                if (i == j) continue;
+                if (!REG && i >= deg[k]) continue;
+                if (first) {
+                  acc = x[k][i] + 0.0f;  // (+inf) [+] x == x + 0
+                  first = false;
+                } else {
+                  acc = boxplus(acc, x[k][i]);
+                }
+              }
+              out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < DC; ++j) msg[j * u.mpad + cidx[k]] = out[j];
+        }
+      }
+      fresh = false;
+      __syncthreads();
+    }
+
+    // ---- feedback: every active check whose clock rang tests Evidence
+    // and requests a flip of its LocalMove qubit
+    if (working) {
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * u.nt;
+        if (ch >= c.m || !((sb >> k) & 1u)) continue;
+        const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                        ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                        (uint32_t)(kp.seed >> 32));
+        if (!below(w.w0, kp.mask_bound)) continue;
+        const int32_t d = c.chk_deg[ch];
+        const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+        float Lv[DC];
+        float Lmax = -__builtin_inff();
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          if (j >= d) continue;
+          const int32_t v = nb[j];
+          const int32_t dv = c.var_deg[v];
+          float acc = pi;
+          for (int32_t q = 0; q < dv; ++q) {
+            const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+            acc = acc + msg[edge_slot(e) * u.mpad + edge_check(e)];
+          }
+          acc = clampf(acc, C);
+          Lv[j] = acc;
+          if (j == 0 || acc > Lmax) Lmax = acc;
+        }
+        if (d == 0) continue;
+        if (kp.evidence && !(Lmax >= c.thr[d])) continue;
+        uint32_t ntie = 0;
+#pragma unroll
+        for (int j = 0; j < DC; ++j)
+          if (j < d && Lv[j] == Lmax) ++ntie;
+        uint32_t pick = (uint32_t)(((uint64_t)w.w1 * (uint64_t)ntie) >> 32);
+        int32_t chosen = -1;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          if (j < d && Lv[j] == Lmax && chosen < 0) {
+            if (pick == 0)
+              chosen = nb[j];
+            else
+              --pick;
+          }
+        }
+        if (chosen >= 0) fl[chosen] = 1;
+      }
+    }
+    __syncthreads();
+    // ---- syndrome update s ^= H f and correction z ^= f
+    if (working) {
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * u.nt;
+        if (ch >= c.m) continue;
+        uint32_t x = 0;
+        const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+        const int32_t d = c.chk_deg[ch];
+        for (int32_t j = 0; j < d; ++j) x ^= fl[nb[j]];
+        sb ^= (x & 1u) << k;
+      }
+      int32_t nflip = 0;
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v < c.n && fl[v]) {
+          zb ^= 1u << k;
+          ++nflip;
+        }
+      }
+      if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
+      if (u.events && nflip) atomicAdd(&gw[kGwFlips], nflip);
+    }
+    __syncthreads();
+    if (working) {
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v < c.n) fl[v] = 0;
+      }
+      const bool any = gw[(rr & 1) ? kGwAct1 : kGwAct0] != 0;
+      if (!any && tclr < 0) tclr = r + 1;
+      flips_last = gw[kGwFlips];
+      if (kp.retire && tclr >= 0) working = false;
+    }
+  }
+
+  // ---- results. The group index passes through an empty asm statement so
+  // that the job's output pointers are not computed before the rounds and
+  // kept in registers through them.
+  int32_t g_res = g;
+  asm volatile("" : "+v"(g_res));
+  if (alive) {
+    const GroupJob job = job_at(g_res);
+    if (job.z_out) {
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v < c.n) job.z_out[v] = (uint8_t)((zb >> k) & 1u);
+      }
+    }
+    if (job.s_out) {
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * u.nt;
+        if (ch < c.m) job.s_out[ch] = (uint8_t)((sb >> k) & 1u);
+      }
+    }
+    if (job.t_out && t == 0) job.t_out[0] = tclr;
+    if (job.L_out) {
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v >= c.n) continue;
+        const int32_t dv = c.var_deg[v];
+        float acc = pi;
+        for (int32_t q = 0; q < dv; ++q) {
+          const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+          acc = acc + msg[edge_slot(e) * u.mpad + edge_check(e)];
+        }
+        job.L_out[v] = clampf(acc, C);
+      }
+    }
+    if (job.st_msg) {
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * u.nt;
+        if (ch >= c.m) continue;
+        for (int j = 0; j < c.dcmax && j < DC; ++j)
+          job.st_msg[(int64_t)ch * c.dcmax + j] = msg[j * u.mpad + ch];
+        job.st_s[ch] = (uint8_t)((sb >> k) & 1u);
+      }
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v < c.n) job.st_z[v] = (uint8_t)((zb >> k) & 1u);
+      }
+      if (t == 0) job.st_hdr[0] = tclr;
+    }
+    // fused success test: odd overlap of e0 ^ z with a logical, or s != 0
+    if (job.f_out || job.ev_out) {
+      uint32_t lp[kFusedMaxWords] = {0u, 0u, 0u, 0u};
+#pragma unroll 1
+      for (int k = 0; k < u.vpt; ++k) {
+        const int32_t v = t + k * u.nt;
+        if (v >= c.n || !(((eb ^ zb) >> k) & 1u)) continue;
+#pragma unroll
+        for (int w = 0; w < kFusedMaxWords; ++w)
+          if (w < c.kw) lp[w] ^= c.lcol[(int64_t)v * c.kw + w];
+      }
+#pragma unroll
+      for (int w = 0; w < kFusedMaxWords; ++w)
+        if (lp[w]) atomicXor(reinterpret_cast<uint32_t*>(&gw[kGwLpar + w]), lp[w]);
+    }
+    if (job.ev_out && sb) atomicAdd(&gw[kGwDefects], __popc(sb));
+  }
+  __syncthreads();
+  if (alive && t == 0) {
+    const GroupJob job = job_at(g_res);
+    uint32_t f = (tclr < 0) ? 1u : 0u;
+    for (int w = 0; w < kFusedMaxWords; ++w) f |= (uint32_t)gw[kGwLpar + w];
+    if (job.f_out) job.f_out[0] = f ? 1 : 0;
+    if (job.ev_out) {
+      job.ev_out[0] = flips_last;
+      job.ev_out[1] = gw[kGwDefects];
+      job.ev_out[2] = tclr;
+      job.ev_out[3] = f ? 1 : 0;
+    }
+  }
+}
+
+// ---- the single-code persistent kernel
 struct ResArgs {
-  int32_t nt, vpt, spb, mpad;
-  int32_t group_bytes;
+  UnitCtx u;
   const uint8_t* e0;
   uint64_t shot0;
   int32_t nshots;
@@ -152,337 +602,163 @@ struct ResArgs {
   uint8_t* s;
   int32_t* tclr;
   float* L;
+  uint8_t* fail;
 };
 
-// LDS control words at the start of the block's LDS.
-constexpr int kCtrlWords = 128;  // [0] queue base; flags per group follow
-constexpr int kMaxShotsPerBlock = 31;
+struct ResJobs {
+  // copied by value: taking the address of a kernel argument would force it
+  // into scratch memory
+  const uint8_t* e0;
+  uint64_t shot0;
+  int32_t nshots, n, m, base;
+  uint8_t* z;
+  uint8_t* s;
+  int32_t* tclr;
+  float* L;
+  uint8_t* fail;
+  __device__ GroupJob operator()(int32_t g) const {
+    GroupJob j = dead_job();
+    const int32_t idx = base + g;
+    if (idx >= nshots) return j;
+    j.alive = 1;
+    j.r0 = 0;
+    j.shot = shot0 + (uint64_t)idx;
+    j.e0row = e0 + (int64_t)idx * n;
+    j.z_out = z + (int64_t)idx * n;
+    j.s_out = s + (int64_t)idx * m;
+    j.t_out = tclr + idx;
+    j.L_out = L ? L + (int64_t)idx * n : nullptr;
+    j.f_out = fail ? fail + idx : nullptr;
+    return j;
+  }
+};
 
 template <int DC, int DV, int CPT, int BP, bool REG>
 __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, ResArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
-  // ctrl layout: [0] base, [1 + g] init flag, [1 + spb + g] round-parity-0 flag,
-  // [1 + 2 spb + g] round-parity-1 flag, [1 + 3 spb + g] group still working.
-  const int32_t spb = a.spb;
-  const int32_t tid = threadIdx.x;
-  const int32_t g = tid / a.nt;
-  const int32_t t = tid - g * a.nt;
-  float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)g * a.group_bytes);
-  const int32_t zslot = DC * a.mpad;
-  uint8_t* fl = reinterpret_cast<uint8_t*>(msg + zslot + 4);
-  const float C = kp.clamp;
-  const float pi = kp.pi;
-
-  // ---- per-thread graph tables, loaded once
-  int32_t cidx[CPT];
-  int32_t deg[CPT];
-  int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const int32_t ch = t + k * a.nt;
-    const bool valid = ch < c.m;
-    cidx[k] = valid ? ch : -1;
-    deg[k] = valid ? c.chk_deg[ch] : 0;
-#pragma unroll
-    for (int j = 0; j < DC; ++j) {
-#pragma unroll
-      for (int p = 0; p < DV - 1; ++p) {
-        int32_t e = -1;
-        if (valid && j < c.dcmax && p < c.dvmax - 1)
-          e = c.partner[((int64_t)ch * c.dcmax + j) * (c.dvmax - 1) + p];
-        pidx[k][j][p] = (e >= 0) ? edge_slot(e) * a.mpad + edge_check(e) : zslot;
-      }
-    }
-  }
-  if (t == 0) msg[zslot] = -0.0f;
-
   for (;;) {
     __syncthreads();
-    if (tid == 0) ctrl[0] = (int32_t)atomicAdd(a.counter, (uint32_t)spb);
+    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(a.counter, (uint32_t)a.u.spb);
     __syncthreads();
     const int32_t base = ctrl[0];
     if (base >= a.nshots) break;
-    const int32_t idx = base + g;
-    const bool alive = idx < a.nshots;
-    const uint64_t shot = a.shot0 + (uint64_t)(alive ? idx : 0);
-    const uint8_t* e0row = a.e0 + (int64_t)(alive ? idx : 0) * c.n;
-
-    // ---- shot start: e0, z = 0, s = H e0, messages 0, no flip requests
-    uint32_t zb = 0, sb = 0;
-#pragma unroll 1
-    for (int k = 0; k < a.vpt; ++k) {
-      const int32_t v = t + k * a.nt;
-      if (v < c.n) fl[v] = 0;
-    }
-#pragma unroll 1
-    for (int k = 0; k < CPT; ++k) {
-      const int32_t ch = t + k * a.nt;
-      if (ch >= c.m) continue;
-      for (int j = 0; j < DC; ++j) msg[j * a.mpad + ch] = 0.0f;
-      uint32_t x = 0;
-      if (alive) {
-        const int32_t d = c.chk_deg[ch];
-        for (int32_t j = 0; j < d; ++j) x ^= e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
-      }
-      sb |= (x & 1u) << k;
-    }
-    if (t == 0) {
-      ctrl[1 + g] = 0;
-      ctrl[1 + spb + g] = 0;
-    }
-    __syncthreads();
-    if (sb) ctrl[1 + g] = 1;
-    __syncthreads();
-    int32_t tclr = ctrl[1 + g] ? -1 : 0;
-    bool working = alive && !(kp.retire && tclr >= 0);
-    bool fresh = true;
-
-    for (int32_t r = 0; r < kp.rounds; ++r) {
-      __syncthreads();
-      if (t == 0) {
-        ctrl[1 + 3 * spb + g] = working ? 1 : 0;
-        ctrl[1 + (((r + 1) & 1) ? 2 : 1) * spb + g] = 0;
-      }
-      __syncthreads();
-      int32_t anyw = 0;
-      for (int32_t h = 0; h < spb; ++h) anyw |= ctrl[1 + 3 * spb + h];
-      if (!anyw) break;
-
-      // ---- BP sweeps
-      int32_t it0 = 0;
-      if (fresh && REG && kp.iters > 0) {
-        // First sweep of a shot: every m_{v->c} is 0, so each check sends
-        // (-1)^{s_c + d_c} * 0 (min-sum: alpha * 0; sum-product: 0 [+] 0 = +0).
-        if (working) {
-#pragma unroll
-          for (int k = 0; k < CPT; ++k) {
-            if (cidx[k] < 0) continue;
-            const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
-#pragma unroll
-            for (int j = 0; j < DC; ++j) msg[j * a.mpad + cidx[k]] = z0;
-          }
-        }
-        fresh = false;
-        it0 = 1;
-        __syncthreads();
-      }
-      for (int32_t it = it0; it < kp.iters; ++it) {
-        float x[CPT][DC];
-        if (!REG && fresh) {
-#pragma unroll
-          for (int k = 0; k < CPT; ++k)
-#pragma unroll
-            for (int j = 0; j < DC; ++j) x[k][j] = (j >= deg[k]) ? __builtin_inff() : 0.0f;
-        } else {
-#pragma unroll
-          for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-            for (int j = 0; j < DC; ++j) {
-              float acc = pi;
-#pragma unroll
-              for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
-              acc = __builtin_amdgcn_fmed3f(acc, -C, C);
-              if (!REG && j >= deg[k]) acc = __builtin_inff();
-              x[k][j] = acc;
-            }
-          }
-        }
-        __syncthreads();
-        if (working) {
-#pragma unroll
-          for (int k = 0; k < CPT; ++k) {
-            if (cidx[k] < 0) continue;
-            const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)deg[k]) & 1u;
-            float out[DC];
-            if (BP == 0) {
-              // normalised min-sum: alpha * (smallest other |m|) with the
-              // sign product. No input is -0 (pi + messages with pi != -0,
-              // or +0 on a fresh sweep), so the sign bit is sg(). The sign
-              // product of all inputs goes into the scale (alpha * min
-              // rounds the same for either sign); each output then removes
-              // its own input's sign with one bit operation.
-              uint32_t par = sigma_neg << 31;
-#pragma unroll
-              for (int j = 0; j < DC; ++j) par ^= __float_as_uint(x[k][j]);
-              const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
-              float ex[DC];  // smallest |m| over the other inputs
-              if (DC == 2) {
-                ex[0] = fabsf(x[k][1]);
-                ex[1] = fabsf(x[k][0]);
-              } else if (DC == 4) {
-                ex[0] = min3f(fabsf(x[k][1]), fabsf(x[k][2]), fabsf(x[k][3]));
-                ex[1] = min3f(fabsf(x[k][0]), fabsf(x[k][2]), fabsf(x[k][3]));
-                ex[2] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][3]));
-                ex[3] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][2]));
-              } else {
-                float pre[DC], suf[DC];
-                pre[1] = fabsf(x[k][0]);
-#pragma unroll
-                for (int j = 2; j < DC; ++j) pre[j] = fminf(pre[j - 1], fabsf(x[k][j - 1]));
-                suf[DC - 2] = fabsf(x[k][DC - 1]);
-#pragma unroll
-                for (int j = DC - 3; j >= 0; --j) suf[j] = fminf(suf[j + 1], fabsf(x[k][j + 1]));
-                ex[0] = suf[0];
-                ex[DC - 1] = pre[DC - 1];
-#pragma unroll
-                for (int j = 1; j < DC - 1; ++j) ex[j] = fminf(pre[j], suf[j]);
-              }
-#pragma unroll
-              for (int j = 0; j < DC; ++j) {
-                // With degree >= 2 there is an input to take the minimum of,
-                // so |v| <= alpha * clamp <= clamp (the resident min-sum path
-                // runs only with alpha <= 1) and the output clamp cannot bind;
-                // a degree-1 check of an irregular code has an empty minimum
-                // (+inf) and is clamped.
-                float v = alpha_s * ex[j];
-                if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
-                out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
-              }
-            } else {
-              // sum-product: box-plus fold of the other inputs, ascending
-#pragma unroll
-              for (int j = 0; j < DC; ++j) {
-                float acc = __builtin_inff();
-                bool first = true;
-#pragma unroll
-                for (int i = 0; i < DC; ++i) {
-                  if (i == j) continue;
-                  if (!REG && i >= deg[k]) continue;
-                  if (first) {
-                    acc = x[k][i] + 0.0f;  // (+inf) [+] x == x + 0
-                    first = false;
-                  } else {
-                    acc = boxplus(acc, x[k][i]);
-                  }
-                }
-                out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
-              }
-            }
-#pragma unroll
-            for (int j = 0; j < DC; ++j) msg[j * a.mpad + cidx[k]] = out[j];
-          }
-        }
-        fresh = false;
-        __syncthreads();
-      }
-
-      // ---- feedback: every active check whose clock rang tests Evidence
-      // and requests a flip of its LocalMove qubit
-      if (working) {
-#pragma unroll 1
-        for (int k = 0; k < CPT; ++k) {
-          const int32_t ch = t + k * a.nt;
-          if (ch >= c.m || !((sb >> k) & 1u)) continue;
-          const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
-                                          ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
-                                          (uint32_t)(kp.seed >> 32));
-          if (!below(w.w0, kp.mask_bound)) continue;
-          const int32_t d = c.chk_deg[ch];
-          const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
-          float Lv[DC];
-          float Lmax = -__builtin_inff();
-#pragma unroll
-          for (int j = 0; j < DC; ++j) {
-            if (j >= d) continue;
-            const int32_t v = nb[j];
-            const int32_t dv = c.var_deg[v];
-            float acc = pi;
-            if (!fresh)
-              for (int32_t q = 0; q < dv; ++q) {
-                const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-                acc = acc + msg[edge_slot(e) * a.mpad + edge_check(e)];
-              }
-            else
-              for (int32_t q = 0; q < dv; ++q) acc = acc + 0.0f;
-            acc = clampf(acc, C);
-            Lv[j] = acc;
-            if (j == 0 || acc > Lmax) Lmax = acc;
-          }
-          if (d == 0) continue;
-          if (kp.evidence && !(Lmax >= c.thr[d])) continue;
-          uint32_t ntie = 0;
-#pragma unroll
-          for (int j = 0; j < DC; ++j)
-            if (j < d && Lv[j] == Lmax) ++ntie;
-          uint32_t pick = (uint32_t)(((uint64_t)w.w1 * (uint64_t)ntie) >> 32);
-          int32_t chosen = -1;
-#pragma unroll
-          for (int j = 0; j < DC; ++j) {
-            if (j < d && Lv[j] == Lmax && chosen < 0) {
-              if (pick == 0)
-                chosen = nb[j];
-              else
-                --pick;
-            }
-          }
-          if (chosen >= 0) fl[chosen] = 1;
-        }
-      }
-      __syncthreads();
-      // ---- syndrome update s ^= H f and correction z ^= f
-      if (working) {
-#pragma unroll 1
-        for (int k = 0; k < CPT; ++k) {
-          const int32_t ch = t + k * a.nt;
-          if (ch >= c.m) continue;
-          uint32_t x = 0;
-          const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
-          const int32_t d = c.chk_deg[ch];
-          for (int32_t j = 0; j < d; ++j) x ^= fl[nb[j]];
-          sb ^= (x & 1u) << k;
-        }
-        for (int k = 0; k < a.vpt; ++k) {
-          const int32_t v = t + k * a.nt;
-          if (v < c.n && fl[v]) zb ^= 1u << k;
-        }
-        if (sb) ctrl[1 + ((r & 1) ? 2 : 1) * spb + g] = 1;
-      }
-      __syncthreads();
-      if (working) {
-        for (int k = 0; k < a.vpt; ++k) {
-          const int32_t v = t + k * a.nt;
-          if (v < c.n) fl[v] = 0;
-        }
-        const bool any = ctrl[1 + ((r & 1) ? 2 : 1) * spb + g] != 0;
-        if (!any && tclr < 0) tclr = r + 1;
-        if (kp.retire && tclr >= 0) working = false;
-      }
-    }
-
-    // ---- results of this group's shot
-    if (alive) {
-      uint8_t* zrow = a.z + (int64_t)idx * c.n;
-      for (int k = 0; k < a.vpt; ++k) {
-        const int32_t v = t + k * a.nt;
-        if (v < c.n) zrow[v] = (uint8_t)((zb >> k) & 1u);
-      }
-#pragma unroll 1
-      for (int k = 0; k < CPT; ++k) {
-        const int32_t ch = t + k * a.nt;
-        if (ch < c.m) a.s[(int64_t)idx * c.m + ch] = (uint8_t)((sb >> k) & 1u);
-      }
-      if (t == 0) a.tclr[idx] = tclr;
-      if (a.L) {
-        for (int k = 0; k < a.vpt; ++k) {
-          const int32_t v = t + k * a.nt;
-          if (v >= c.n) continue;
-          const int32_t dv = c.var_deg[v];
-          float acc = pi;
-          for (int32_t q = 0; q < dv; ++q) {
-            const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-            acc = acc + msg[edge_slot(e) * a.mpad + edge_check(e)];
-          }
-          a.L[(int64_t)idx * c.n + v] = clampf(acc, C);
-        }
-      }
-    }
+    const ResJobs jobs{a.e0, a.shot0, a.nshots, c.n, c.m, base, a.z, a.s, a.tclr, a.L, a.fail};
+    run_unit<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem);
   }
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) p[i] = 0u;
+}
+
+// ---- multi-code persistent kernel (one launch over many codes' shots)
+struct BatchJobs {
+  const BatchItemDev* I;
+  int32_t base;
+  __device__ GroupJob operator()(int32_t g) const {
+    GroupJob j = dead_job();
+    const int32_t idx = base + g;
+    if (idx >= I->nshots) return j;
+    const int32_t n = I->c.n, m = I->c.m;
+    j.alive = 1;
+    j.r0 = 0;
+    j.shot = I->shot0 + (uint64_t)idx;
+    j.e0row = I->e0 + (int64_t)idx * n;
+    j.z_out = I->z + (int64_t)idx * n;
+    j.s_out = I->s + (int64_t)idx * m;
+    j.t_out = I->tclr + idx;
+    j.f_out = I->fail ? I->fail + idx : nullptr;
+    return j;
+  }
+};
+
+// ---- serving: one round for every scheduled request, state in HBM
+struct ServerJobs {
+  const ServerReqDev* R;
+  int32_t first, count;
+  __device__ GroupJob operator()(int32_t g) const {
+    GroupJob j = dead_job();
+    if (g >= count) return j;
+    const ServerReqDev& q = R[first + g];
+    j.alive = 1;
+    j.r0 = q.round;
+    j.shot = q.shot;
+    j.e0row = q.e0;
+    j.st_msg = q.msg;
+    j.st_z = q.z;
+    j.st_s = q.s;
+    j.st_hdr = q.hdr;
+    j.f_out = q.fail;
+    j.ev_out = q.ev;
+    return j;
+  }
+};
+
+// The (degrees, checks per thread) variants compiled into the multi-code
+// kernels; the host picks one per code (batch_variant below).
+#define LAIM_BATCH_SWITCH(V, BP, CALL)                \
+  switch (V) {                                        \
+    case 0: CALL(2, 2, 1, BP, true); break;           \
+    case 1: CALL(2, 2, 2, BP, true); break;           \
+    case 2: CALL(4, 2, 1, BP, true); break;           \
+    case 3: CALL(4, 2, 2, BP, true); break;           \
+    case 4: CALL(4, 2, 4, BP, true); break;           \
+    case 5: CALL(6, 2, 1, BP, true); break;           \
+    case 6: CALL(6, 2, 2, BP, true); break;           \
+    case 7: CALL(4, 4, 1, BP, true); break;           \
+    case 8: CALL(4, 4, 2, BP, true); break;           \
+    case 9: CALL(6, 3, 1, BP, true); break;           \
+    case 10: CALL(6, 3, 2, BP, true); break;          \
+    default: CALL(8, 4, 1, BP, false); break;         \
+  }
+
+static const int kBatchVariants[][4] = {  // dc, dv, cpt, regular
+    {2, 2, 1, 1}, {2, 2, 2, 1}, {4, 2, 1, 1}, {4, 2, 2, 1}, {4, 2, 4, 1}, {6, 2, 1, 1},
+    {6, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {6, 3, 1, 1}, {6, 3, 2, 1}, {8, 4, 1, 0}};
+
+template <int BP>
+__global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
+                                                     const BatchUnitDev* units, int32_t nunits,
+                                                     uint32_t* counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int32_t un = __builtin_amdgcn_readfirstlane(ctrl[0]);
+    if (un >= nunits) break;
+    const BatchUnitDev U = units[un];
+    const BatchItemDev* I = items + U.item;
+    const DevCode c = I->c;
+    const KParams kp = I->kp;
+    const UnitCtx ctx = I->u;
+    const BatchJobs jobs{I, U.base};
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem)
+    LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
+#undef LAIM_CALL
+  }
+}
+
+template <int BP>
+__global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
+                                                      const ServerUnitDev* units,
+                                                      const ServerReqDev* reqs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ServerUnitDev U = units[blockIdx.x];
+  const BatchItemDev* I = items + U.item;
+  const DevCode c = I->c;
+  const KParams kp = I->kp;
+  UnitCtx ctx = I->u;
+  ctx.rounds = 1;
+  ctx.resume = U.resume;
+  ctx.events = 1;
+  const ServerJobs jobs{reqs, U.first, U.count};
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem)
+  LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
+#undef LAIM_CALL
 }
 
 // ---- instantiation table
@@ -538,7 +814,7 @@ static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) 
 }
 
 static size_t group_bytes_for(int dc, int mpad, int n) {
-  size_t b = (size_t)(dc * mpad + 4) * 4 + (size_t)((n + 15) / 16) * 16;
+  size_t b = (size_t)(dc * mpad + kGroupWords) * 4 + (size_t)((n + 15) / 16) * 16;
   return (b + 15) / 16 * 16;
 }
 
@@ -614,22 +890,111 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
   return true;
 }
 
+
+// Variant and unit shape of a code inside the multi-code kernels. The
+// launch shape follows the code's resident shape, with checks per thread
+// limited to the compiled variants (at most the shape's value).
+bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, UnitCtx* u,
+                   int* variant, size_t* lds, int* block) {
+  int dc, dv, reg;
+  if (!pick_degrees(c, &dc, &dv, &reg)) {
+    set_error("the batched form needs check degree <= 8 and qubit degree <= 4");
+    return false;
+  }
+  ResidentShape sh;
+  if (!resident_shape(c, bp, want, &sh, device)) return false;
+  int best = -1;
+  for (int i = 0; i < (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0])); ++i) {
+    const int* v = kBatchVariants[i];
+    if (v[0] != dc || v[1] != dv || v[3] != reg) continue;
+    if (v[2] <= sh.cpt && (best < 0 || v[2] > kBatchVariants[best][2])) best = i;
+  }
+  if (best < 0) {
+    set_error("no batched variant for degrees %d/%d", dc, dv);
+    return false;
+  }
+  const int cpt = kBatchVariants[best][2];
+  laim_resident_cfg cfg = {0, cpt, want ? want->shots_per_block : 0};
+  if (cpt != sh.cpt && !resident_shape(c, bp, &cfg, &sh, device)) return false;
+  u->nt = sh.nt;
+  u->vpt = sh.vpt;
+  u->spb = sh.spb;
+  u->mpad = sh.mpad;
+  u->group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  u->rounds = 0;
+  u->resume = 0;
+  u->events = 0;
+  *variant = best;
+  *lds = sh.lds;
+  *block = sh.nt * sh.spb;
+  return true;
+}
+
+hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
+                        int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, counter, 1);
+  const void* fn = bp ? reinterpret_cast<const void*>(batch_kernel<1>)
+                      : reinterpret_cast<const void*>(batch_kernel<0>);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+  }
+  if (bp)
+    hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter);
+  else
+    hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter);
+  return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int bp, int block, size_t lds) {
+  const void* fn = bp ? reinterpret_cast<const void*>(batch_kernel<1>)
+                      : reinterpret_cast<const void*>(batch_kernel<0>);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return 0;
+  return per_cu;
+}
+
+hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev* units,
+                         int32_t nunits, const ServerReqDev* reqs, size_t lds, int block,
+                         hipStream_t st) {
+  if (nunits <= 0) return hipSuccess;
+  const void* fn = bp ? reinterpret_cast<const void*>(server_kernel<1>)
+                      : reinterpret_cast<const void*>(server_kernel<0>);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+  }
+  if (bp)
+    hipLaunchKernelGGL(server_kernel<1>, dim3(nunits), dim3(block), lds, st, items, units, reqs);
+  else
+    hipLaunchKernelGGL(server_kernel<0>, dim3(nunits), dim3(block), lds, st, items, units, reqs);
+  return hipGetLastError();
+}
+
 size_t resident_workspace_bytes() { return 256; }
 
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
-                           uint8_t* s, int32_t* tclr, float* L, hipStream_t st) {
+                           uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   int dc, dv, reg;
   if (!pick_degrees(c, &dc, &dv, &reg)) return hipErrorInvalidValue;
   const ResVariant* var = find_variant(dc, dv, sh.cpt, kp.bp, reg);
   if (!var) return hipErrorInvalidValue;
   ResArgs a;
-  a.nt = sh.nt;
-  a.vpt = sh.vpt;
-  a.spb = sh.spb;
-  a.mpad = sh.mpad;
-  a.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  a.u.nt = sh.nt;
+  a.u.vpt = sh.vpt;
+  a.u.spb = sh.spb;
+  a.u.mpad = sh.mpad;
+  a.u.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  a.u.rounds = kp.rounds;
+  a.u.resume = 0;
+  a.u.events = 0;
   a.e0 = e0;
   a.shot0 = shot0;
   a.nshots = nshots;
@@ -638,6 +1003,7 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.s = s;
   a.tclr = tclr;
   a.L = L;
+  a.fail = fail;
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, a.counter, 1);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;

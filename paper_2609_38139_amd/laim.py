@@ -59,7 +59,8 @@ class BatchItem(C.Structure):
 
 class ServerEvent(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("round", C.c_int32), ("done", C.c_int32),
-                ("tclr", C.c_int32), ("flips", C.c_int32), ("defects", C.c_int32)]
+                ("tclr", C.c_int32), ("flips", C.c_int32), ("defects", C.c_int32),
+                ("fail", C.c_int32), ("latency_ns", C.c_int64)]
 
 
 @dataclass
@@ -299,3 +300,101 @@ def logical_failure(code: Code, e0, z, stream=None):
     check(lib().laim_logical_failure(code.handle, _ptr(e0), _ptr(z), ns, _ptr(f), _stream(stream)),
           "laim_logical_failure")
     return f
+
+
+class BatchPlan:
+    """``laim_batch_plan_*``: one persistent launch over shots of several
+    codes, captured in a HIP graph. ``items`` is a list of dicts with keys
+    code, params, e0 (device uint8 [nshots, n]) and optionally shot0 and
+    want_fail; outputs are allocated here and rewritten by every launch."""
+
+    def __init__(self, items, stream=None):
+        import torch
+        self.items = []
+        arr = (BatchItem * len(items))()
+        for i, it in enumerate(items):
+            code, P, e0 = it["code"], it["params"], it["e0"]
+            ns = e0.shape[0]
+            _dev(e0, torch.uint8, (ns, code.n), "e0")
+            o = {"code": code, "e0": e0, "shot0": it.get("shot0", 0),
+                 "z": torch.empty((ns, code.n), dtype=torch.uint8, device=e0.device),
+                 "s": torch.empty((ns, code.m), dtype=torch.uint8, device=e0.device),
+                 "tclr": torch.empty((ns,), dtype=torch.int32, device=e0.device),
+                 "fail": torch.empty((ns,), dtype=torch.uint8, device=e0.device)
+                 if it.get("want_fail", True) else None}
+            self.items.append(o)
+            arr[i] = BatchItem(code.handle, P.c(), C.c_void_p(e0.data_ptr()), o["shot0"], ns,
+                               C.c_void_p(o["z"].data_ptr()), C.c_void_p(o["s"].data_ptr()),
+                               C.c_void_p(o["tclr"].data_ptr()),
+                               C.c_void_p(o["fail"].data_ptr()) if o["fail"] is not None else None)
+        h = C.c_void_p()
+        check(lib().laim_batch_plan_create(arr, len(items), _stream(stream), C.byref(h)),
+              "laim_batch_plan_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        check(lib().laim_batch_plan_launch(self.handle, _stream(stream)), "laim_batch_plan_launch")
+        return self.items
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.laim_batch_plan_destroy(h)
+            self.handle = None
+
+
+class Server:
+    """``laim_server_*``: continuous batching of single-shot decode requests
+    with device-resident state; every ``step`` advances each resident request
+    by one round and returns its per-round event."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 1 << 30, max_slots: int = 4096):
+        h = C.c_void_p()
+        check(lib().laim_server_create(device, mem_budget, max_slots, C.byref(h)), "laim_server_create")
+        self.handle = h
+        self.max_slots = max_slots
+        self._ev = (ServerEvent * max_slots)()
+        self._codes = {}
+
+    def submit(self, code: Code, params: DecodeParams, shot_id: int, e0) -> int:
+        e0 = np.ascontiguousarray(e0, dtype=np.uint8).ravel()
+        if e0.size != code.n:
+            raise ValueError("e0 must hold n bits")
+        P = params.c()
+        t = C.c_uint64()
+        check(lib().laim_server_submit(self.handle, code.handle, C.byref(P), shot_id,
+                                       e0.ctypes.data_as(C.c_void_p), C.byref(t)), "laim_server_submit")
+        self._codes[t.value] = code
+        return t.value
+
+    def step(self) -> list:
+        n = C.c_int32()
+        check(lib().laim_server_step(self.handle, self._ev, self.max_slots, C.byref(n)), "laim_server_step")
+        out = []
+        for i in range(n.value):
+            e = self._ev[i]
+            out.append({"ticket": e.ticket, "round": e.round, "done": bool(e.done), "tclr": e.tclr,
+                        "flips": e.flips, "defects": e.defects, "fail": e.fail,
+                        "latency_ns": e.latency_ns})
+        return out
+
+    def result(self, ticket: int) -> dict:
+        code = self._codes.pop(ticket)
+        z = np.zeros(code.n, dtype=np.uint8)
+        s = np.zeros(code.m, dtype=np.uint8)
+        t = C.c_int32()
+        check(lib().laim_server_result(self.handle, ticket, z.ctypes.data_as(C.c_void_p),
+                                       s.ctypes.data_as(C.c_void_p), C.byref(t)), "laim_server_result")
+        return {"z": z, "s": s, "tclr": t.value}
+
+    def stats(self) -> dict:
+        r, w = C.c_int32(), C.c_int32()
+        b = C.c_size_t()
+        check(lib().laim_server_stats(self.handle, C.byref(r), C.byref(w), C.byref(b)), "laim_server_stats")
+        return {"resident": r.value, "waiting": w.value, "bytes": b.value}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.laim_server_destroy(h)
+            self.handle = None

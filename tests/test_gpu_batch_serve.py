@@ -1,0 +1,141 @@
+"""The batched plan (one persistent launch over several codes, replayed
+from a HIP graph) and the continuous-batching server give every shot
+exactly the result it gets alone (and that the oracle gives)."""
+import numpy as np
+import pytest
+
+from paper_2609_38139_amd import codes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2609_38139_amd import laim
+    laim.lib()
+    return laim
+
+
+MIX = [  # code, p, q, bp, rounds, shots, shot0
+    ("toric2d:8", 0.05, 0.05, "minsum", 32, 500, 0),
+    ("bb:12x6", 0.01, 0.05, "minsum", 64, 300, 1000),
+    ("toric3d_point:4", 0.02, 0.05, "sumproduct", 16, 200, 7),
+    ("toric3d_membrane:3", 0.05, 0.125, "minsum", 12, 150, 3),
+    ("toric2d:16", 0.05, 0.05, "sumproduct", 64, 100, 99),
+    ("bb:6x6", 0.02, 0.05, "sumproduct", 32, 257, 5),
+]
+
+
+def _mix(L):
+    import torch
+    out = []
+    for name, p, q, bp, R, S, s0 in MIX:
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(bp=bp, q=q, rounds=R)
+        e0 = L.sample_noise(code, p, 1, s0, S)
+        out.append({"spec": spec, "code": code, "params": P, "e0": e0, "shot0": s0})
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_plan_matches_single_launches_and_oracle(L, orc):
+    import torch
+    mix = _mix(L)
+    plan = L.BatchPlan(mix)
+    singles = []
+    for it in mix:
+        r = L.decode_rounds(it["code"], it["params"], it["e0"], shot0=it["shot0"])
+        r["fail"] = L.logical_failure(it["code"], it["e0"], r["z"])
+        singles.append(r)
+    torch.cuda.synchronize()
+    for replay in range(3):
+        print(f"[batch] replay {replay}", flush=True)
+        outs = plan.launch()
+        torch.cuda.synchronize()
+        for it, o, ref in zip(mix, outs, singles):
+            for k in ("z", "s", "tclr", "fail"):
+                assert torch.equal(o[k], ref[k]), (it["spec"].name, k, replay)
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        del junk
+    # and the oracle on a slice of every item
+    for it, ref in zip(mix, singles):
+        P = it["params"]
+        e0 = it["e0"][:40].cpu().numpy()
+        o = orc.decode(it["spec"], orc.DecodeParams(bp=P.bp, q=P.q, rounds=P.rounds), e0,
+                       shot0=it["shot0"], nthreads=8)
+        assert np.array_equal(ref["z"][:40].cpu().numpy(), o["z"])
+        assert np.array_equal(ref["tclr"][:40].cpu().numpy(), o["tclr"])
+
+
+def _serve(L, mix, order, budget=1 << 30, slots=4096):
+    srv = L.Server(0, budget, slots)
+    pending = {}
+    rounds_seen = {}
+    submitted = 0
+    results = {}
+    it_order = list(order)
+    while it_order or pending:
+        # admit a few new requests per step: arrivals interleave with work
+        for _ in range(7):
+            if not it_order:
+                break
+            i, k = it_order.pop(0)
+            it = mix[i]
+            e0 = it["e0"][k].cpu().numpy()
+            t = srv.submit(it["code"], it["params"], it["shot0"] + k, e0)
+            pending[t] = (i, k)
+            submitted += 1
+        for ev in srv.step():
+            assert ev["round"] == rounds_seen.get(ev["ticket"], 0) + 1
+            rounds_seen[ev["ticket"]] = ev["round"]
+            if ev["done"]:
+                i, k = pending.pop(ev["ticket"])
+                r = srv.result(ev["ticket"])
+                r["fail"] = ev["fail"]
+                results[(i, k)] = r
+    return results, srv
+
+
+def test_server_results_equal_alone_and_in_any_mix(L):
+    import torch
+    mix = _mix(L)
+    singles = []
+    for it in mix:
+        r = L.decode_rounds(it["code"], it["params"], it["e0"], shot0=it["shot0"])
+        r["fail"] = L.logical_failure(it["code"], it["e0"], r["z"])
+        singles.append({k: v.cpu().numpy() for k, v in r.items() if k != "workspace" and v is not None})
+    torch.cuda.synchronize()
+    reqs = [(i, k) for i, it in enumerate(mix) for k in range(0, it["e0"].shape[0], 9)]
+    rng = np.random.default_rng(3)
+    for trial, order in enumerate([reqs, [reqs[j] for j in rng.permutation(len(reqs))]]):
+        print(f"[serve] trial {trial}: {len(order)} requests", flush=True)
+        res, _ = _serve(L, mix, order)
+        assert len(res) == len(order)
+        for (i, k), r in res.items():
+            ref = singles[i]
+            assert np.array_equal(r["z"], ref["z"][k]), (i, k)
+            assert np.array_equal(r["s"], ref["s"][k]), (i, k)
+            assert r["tclr"] == ref["tclr"][k], (i, k)
+            assert r["fail"] == ref["fail"][k], (i, k)
+
+
+def test_server_admits_by_memory(L):
+    """With room for only a few requests the rest wait (FIFO) and still get
+    the same results."""
+    import torch
+    mix = _mix(L)[:2]
+    singles = [L.decode_rounds(it["code"], it["params"], it["e0"], shot0=it["shot0"]) for it in mix]
+    torch.cuda.synchronize()
+    order = [(i, k) for i in range(2) for k in range(12)]
+    res, srv = _serve(L, mix, order, budget=64 * 1024, slots=64)
+    for (i, k), r in res.items():
+        assert np.array_equal(r["z"], singles[i]["z"][k].cpu().numpy())
+        assert r["tclr"] == int(singles[i]["tclr"][k])
+    st = srv.stats()
+    assert st["resident"] == 0 and st["waiting"] == 0 and st["bytes"] == 0
