@@ -54,7 +54,79 @@ def parse():
     ap.add_argument("--cfg", default="", help="resident shape 'checks_per_thread,shots_per_block'")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="copy this many MiB device-to-device first (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-plan comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="open-loop time per arrival rate")
     return ap.parse_args()
+
+
+def batch_vs_plain(laim, codes):
+    """Several codes' shots in one batched plan (one persistent launch,
+    replayed from a HIP graph) against plain launches: one stream-form decode
+    per code (messages in HBM, one launch per sweep). Same shots, same
+    outputs; shots/s of each."""
+    import torch
+    mix = [("bb:6x6", 0.005, 64, 65536), ("bb:12x6", 0.005, 64, 65536),
+           ("toric2d:16", 0.05, 64, 16384), ("toric2d:32", 0.05, 128, 16384)]
+    items = []
+    for name, p, R, S in mix:
+        code = laim.Code(codes.by_name(name), 0)
+        P = laim.DecodeParams(rounds=R)
+        e0 = laim.sample_noise(code, p, 0, 0, S)
+        items.append({"code": code, "params": P, "e0": e0, "shot0": 0})
+    plan = laim.BatchPlan(items)
+    plan.launch()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    outs = plan.launch()
+    b.record()
+    torch.cuda.synchronize()
+    t_batch = a.elapsed_time(b) / 1000
+    fails_b = [int(o["fail"].sum()) for o in outs]
+    t_plain = 0.0
+    fails_p = []
+    for it in items:
+        ws = torch.empty((laim.workspace_bytes(it["code"], it["params"], it["e0"].shape[0], "stream"),),
+                         dtype=torch.uint8, device="cuda")
+        a.record()
+        r = laim.decode_rounds(it["code"], it["params"], it["e0"], form="stream", workspace=ws)
+        f = laim.logical_failure(it["code"], it["e0"], r["z"])
+        b.record()
+        torch.cuda.synchronize()
+        t_plain += a.elapsed_time(b) / 1000
+        fails_p.append(int(f.sum()))
+        del ws
+    shots = sum(S for _, _, _, S in mix)
+    return {"codes": [f"{n} p={p} R={R} S={S}" for n, p, R, S in mix],
+            "batched_shots_per_s": round(shots / t_batch, 1),
+            "plain_stream_shots_per_s": round(shots / t_plain, 1),
+            "speedup": round(t_plain / t_batch, 2),
+            "failures_batched": fails_b, "failures_plain": fails_p,
+            "identical_failures": fails_b == fails_p}
+
+
+def serving(laim, seconds):
+    """Continuous batching of single-shot requests over the mixed workload:
+    2D toric L=16/32/48, 3D toric L=12, bivariate-bicycle [[144,12,12]], each
+    decoded for up to 8L rounds (96 for the 3D and BB codes) at p=0.03.
+    Saturation is measured closed-loop (every request queued at once); then
+    Poisson arrivals at 0.5, 0.8 and 0.95 of it."""
+    from paper_2609_38139_amd import serve
+    wl = serve.Workload(laim, nreq=4096, p=0.03)
+    srv = laim.Server(0, mem_budget=2 << 30, max_slots=4096)
+    serve.run(srv, wl, None, 64)  # warm-up
+    sat = serve.run(srv, wl, None, 1024)
+    out = {"workload": "toric2d L=16/32/48, toric3d_point L=12, bb 12x6; p=0.03; rounds 8L "
+                       "(96 for 3D and BB); min-sum, retire on clear; request i = code i mod 5, "
+                       "shot id i", "saturation": sat, "open_loop": []}
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * sat["requests_per_s"]
+        n = max(32, min(4096, int(rate * seconds)))
+        r = serve.run(srv, wl, rate, n, rng_seed=1)
+        r["fraction_of_saturation"] = frac
+        out["open_loop"].append(r)
+    return out
 
 
 def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
@@ -197,9 +269,9 @@ def main():
           "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
 
     extras = {}
+    if args.no_extras:
+        args.no_batch = args.no_serve = True
     if not args.no_extras:
-        import copy
-        small = copy.copy(args)
         # stream form (messages in HBM, one launch per sweep): the plain baseline
         rs = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
         sec_s = rs["ms_per_step"] / 1000.0
@@ -222,6 +294,10 @@ def main():
                          "msg_updates_per_s": 2 * E * args.iters * ro["rounds_exec"] / (ro["ms_per_step"] / 1000),
                          "decode_ms": round(ro["decode_ms"], 2), "failures": ro["failures"],
                          "logical_error_rate": ro["failures"] / ro["shots"]}
+    if not args.no_batch:
+        extras["batched_vs_plain"] = batch_vs_plain(laim, codes)
+    if not args.no_serve:
+        extras["serving"] = serving(laim, args.serve_seconds)
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -256,6 +332,12 @@ def main():
                    "autotuned": tuned is not None},
         "msg_updates_per_s": msg_per_s,
         "logical_error_rate": main_run["failures"] / S_total,
+        "served_latency": (
+            {"p50_round_ms": extras["serving"]["open_loop"][1]["p50_round_ms"],
+             "p99_round_ms": extras["serving"]["open_loop"][1]["p99_round_ms"],
+             "requests_per_s": extras["serving"]["open_loop"][1]["requests_per_s"],
+             "at": "Poisson arrivals at 0.8x the saturation rate of the mixed serving workload"}
+            if "serving" in extras else None),
         "roofline": rl,
         "cpu_baseline": cpu,
         "extras": extras,
