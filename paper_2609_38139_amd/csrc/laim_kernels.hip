@@ -137,8 +137,9 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // t + k nt (k < vpt). Per group, LDS holds the current m_{c->v} in
 // slot-major order msg[j * mpad + c] (consecutive lanes touch consecutive
 // words), a few scratch words -- the first holds -0.0, which padded
-// qubit-side partners point at (x + (-0.0) == x for every x) -- and one byte
-// per qubit for the flip requests of the feedback step. A shot either
+// qubit-side partners point at (x + (-0.0) == x for every x) -- and three
+// bitmaps: flip requests of the current feedback step (n bits), the
+// correction z (n bits) and the syndrome s (m bits). A shot either
 // starts fresh from its initial error or resumes from state saved in device
 // memory (used by the serving loop, which runs one round per launch).
 // ====================================================================
@@ -211,7 +212,10 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
   float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)(member ? g : 0) * u.group_bytes);
   const int32_t zslot = DC * u.mpad;
   int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
-  uint8_t* fl = reinterpret_cast<uint8_t*>(gw + kGroupWords);
+  const int32_t nw = (c.n + 31) >> 5;
+  uint32_t* flw = reinterpret_cast<uint32_t*>(gw + kGroupWords);  // [nw] flip requests
+  uint32_t* zw = flw + nw;                                         // [nw] correction
+  uint32_t* sw = zw + nw;                                          // [(m + 31) / 32] syndrome
   const float C = kp.clamp;
   const float pi = kp.pi;
 
@@ -237,8 +241,9 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     }
   }
 
-  // ---- start: e0 bits, z, s, messages, flip requests, scratch words
-  uint32_t zb = 0, sb = 0, eb = 0;
+  // ---- start: messages, bitmaps, scratch words; bit k of sb is the
+  // syndrome of check t + k nt (kept in registers for the sweeps)
+  uint32_t sb = 0;
   int32_t tclr = -1;
   if (member) {
     const GroupJob job = job_at(g);
@@ -247,15 +252,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
       for (int w = 1; w < kGroupWords; ++w) gw[w] = 0;
     }
 #pragma unroll 1
-    for (int k = 0; k < u.vpt; ++k) {
-      const int32_t v = t + k * u.nt;
-      if (v >= c.n) continue;
-      fl[v] = 0;
-      if (alive) {
-        eb |= (uint32_t)(job.e0row[v] & 1u) << k;
-        if (u.resume) zb |= (uint32_t)(job.st_z[v] & 1u) << k;
-      }
-    }
+    for (int32_t w = t; w < 2 * nw + ((c.m + 31) >> 5); w += u.nt) flw[w] = 0u;
 #pragma unroll 1
     for (int k = 0; k < CPT; ++k) {
       const int32_t ch = t + k * u.nt;
@@ -276,6 +273,20 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     }
   }
   __syncthreads();
+  if (member && alive) {
+    if (u.resume) {
+      const GroupJob job = job_at(g);
+#pragma unroll 1
+      for (int32_t v = t; v < c.n; v += u.nt)
+        if (job.st_z[v] & 1u) atomicOr(&zw[v >> 5], 1u << (v & 31));
+    }
+#pragma unroll 1
+    for (int k = 0; k < CPT; ++k)
+      if ((sb >> k) & 1u) {
+        const int32_t ch = t + k * u.nt;
+        atomicOr(&sw[ch >> 5], 1u << (ch & 31));
+      }
+  }
   if (member && sb) gw[kGwInit] = 1;
   __syncthreads();
   if (member) {
@@ -420,12 +431,19 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     }
 
     // ---- feedback: every active check whose clock rang tests Evidence
-    // and requests a flip of its LocalMove qubit
+    // and requests a flip of its LocalMove qubit. A lane visits only its
+    // own active checks, so a wavefront runs as many passes as its busiest
+    // lane has defects. Requests combine by OR: the request that sets a
+    // qubit's bit first applies the flip, toggling the qubit's correction
+    // bit and the syndrome bits of its checks (s ^= H f, z ^= f).
     if (working) {
+      uint32_t act = sb;
+      int32_t nflip = 0;
 #pragma unroll 1
-      for (int k = 0; k < CPT; ++k) {
+      while (act) {
+        const int32_t k = __builtin_ctz(act);
+        act &= act - 1u;
         const int32_t ch = t + k * u.nt;
-        if (ch >= c.m || !((sb >> k) & 1u)) continue;
         const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
                                         ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
                                         (uint32_t)(kp.seed >> 32));
@@ -465,41 +483,33 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
               --pick;
           }
         }
-        if (chosen >= 0) fl[chosen] = 1;
-      }
-    }
-    __syncthreads();
-    // ---- syndrome update s ^= H f and correction z ^= f
-    if (working) {
-#pragma unroll 1
-      for (int k = 0; k < CPT; ++k) {
-        const int32_t ch = t + k * u.nt;
-        if (ch >= c.m) continue;
-        uint32_t x = 0;
-        const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
-        const int32_t d = c.chk_deg[ch];
-        for (int32_t j = 0; j < d; ++j) x ^= fl[nb[j]];
-        sb ^= (x & 1u) << k;
-      }
-      int32_t nflip = 0;
-#pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v < c.n && fl[v]) {
-          zb ^= 1u << k;
-          ++nflip;
+        if (chosen < 0) continue;
+        const uint32_t bit = 1u << (chosen & 31);
+        if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
+        atomicXor(&zw[chosen >> 5], bit);
+        const int32_t dv = c.var_deg[chosen];
+        for (int32_t q = 0; q < dv; ++q) {
+          const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
+          atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
         }
+        ++nflip;
       }
-      if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
       if (u.events && nflip) atomicAdd(&gw[kGwFlips], nflip);
     }
     __syncthreads();
+    // ---- the new syndrome bits of this thread's checks
+    if (working) {
+      uint32_t nsb = 0;
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        if (cidx[k] >= 0) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+      sb = nsb;
+      if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
+    }
+    __syncthreads();
     if (working) {
 #pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v < c.n) fl[v] = 0;
-      }
+      for (int32_t w = t; w < nw; w += u.nt) flw[w] = 0u;
       const bool any = gw[(rr & 1) ? kGwAct1 : kGwAct0] != 0;
       if (!any && tclr < 0) tclr = r + 1;
       flips_last = gw[kGwFlips];
@@ -516,10 +526,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     const GroupJob job = job_at(g_res);
     if (job.z_out) {
 #pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v < c.n) job.z_out[v] = (uint8_t)((zb >> k) & 1u);
-      }
+      for (int32_t v = t; v < c.n; v += u.nt) job.z_out[v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
     }
     if (job.s_out) {
 #pragma unroll 1
@@ -531,9 +538,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     if (job.t_out && t == 0) job.t_out[0] = tclr;
     if (job.L_out) {
 #pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v >= c.n) continue;
+      for (int32_t v = t; v < c.n; v += u.nt) {
         const int32_t dv = c.var_deg[v];
         float acc = pi;
         for (int32_t q = 0; q < dv; ++q) {
@@ -553,19 +558,15 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         job.st_s[ch] = (uint8_t)((sb >> k) & 1u);
       }
 #pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v < c.n) job.st_z[v] = (uint8_t)((zb >> k) & 1u);
-      }
+      for (int32_t v = t; v < c.n; v += u.nt) job.st_z[v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
       if (t == 0) job.st_hdr[0] = tclr;
     }
     // fused success test: odd overlap of e0 ^ z with a logical, or s != 0
     if (job.f_out || job.ev_out) {
       uint32_t lp[kFusedMaxWords] = {0u, 0u, 0u, 0u};
 #pragma unroll 1
-      for (int k = 0; k < u.vpt; ++k) {
-        const int32_t v = t + k * u.nt;
-        if (v >= c.n || !(((eb ^ zb) >> k) & 1u)) continue;
+      for (int32_t v = t; v < c.n; v += u.nt) {
+        if (!((job.e0row[v] ^ (zw[v >> 5] >> (v & 31))) & 1u)) continue;
 #pragma unroll
         for (int w = 0; w < kFusedMaxWords; ++w)
           if (w < c.kw) lp[w] ^= c.lcol[(int64_t)v * c.kw + w];
@@ -813,8 +814,10 @@ static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) 
   return nullptr;
 }
 
-static size_t group_bytes_for(int dc, int mpad, int n) {
-  size_t b = (size_t)(dc * mpad + kGroupWords) * 4 + (size_t)((n + 15) / 16) * 16;
+// msg, scratch words, flip and correction bitmaps (n bits each), syndrome
+// bitmap (m bits)
+static size_t group_bytes_for(int dc, int mpad, int n, int m) {
+  const size_t b = (size_t)(dc * mpad + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
   return (b + 15) / 16 * 16;
 }
 
@@ -864,10 +867,6 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
     return false;
   }
   const int vpt = (c.n + nt - 1) / nt;
-  if (vpt > 32) {
-    set_error("more than 32 qubits per thread (n = %d, threads_per_shot = %d)", c.n, nt);
-    return false;
-  }
   if (spb <= 0) spb = (nt >= 256) ? 1 : 256 / nt;
   if (spb > kMaxShotsPerBlock) spb = kMaxShotsPerBlock;
   if (nt * spb > 1024) {
@@ -875,7 +874,7 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
     return false;
   }
   const int mpad = nt * cpt;
-  const size_t gb = group_bytes_for(dc, mpad, c.n);
+  const size_t gb = group_bytes_for(dc, mpad, c.n, c.m);
   const size_t lds = kCtrlWords * 4 + gb * (size_t)spb;
   if (lds > (size_t)lds_max) {
     set_error("resident form needs %zu bytes of LDS per block (device limit %d)", lds, lds_max);
@@ -920,7 +919,7 @@ bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int 
   u->vpt = sh.vpt;
   u->spb = sh.spb;
   u->mpad = sh.mpad;
-  u->group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  u->group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n, c.m);
   u->rounds = 0;
   u->resume = 0;
   u->events = 0;
@@ -991,7 +990,7 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.u.vpt = sh.vpt;
   a.u.spb = sh.spb;
   a.u.mpad = sh.mpad;
-  a.u.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n);
+  a.u.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n, c.m);
   a.u.rounds = kp.rounds;
   a.u.resume = 0;
   a.u.events = 0;
