@@ -244,17 +244,20 @@ def main():
     # Roofline of the dominant kernel (the resident decode launch). It keeps
     # every message on chip, so HBM carries only e0 in and z, s, t_clr out;
     # its bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is
-    # the algorithmic operation count of the sweeps: per check and sweep,
-    # d_c d_v for the qubit-side sums and clamps, then for min-sum
-    # 2(d_c - 1) for the smallest and second-smallest |m|, d_c - 1 sign
-    # parities, 2 scalings and 2 per output (pick, sign) = d_c (d_v + 5) - 1;
-    # for sum-product d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus
-    # d_c clamps. The bytes a streaming sweep would move (8 B per update)
-    # are reported beside it as the HBM-equivalent rate.
+    # the operation count of the sweeps on this instruction set (three-input
+    # min, median and xor exist), per check and sweep:
+    #   d_c d_v       qubit-side sums (d_v - 1 each) and one clamp per input
+    #   ceil(d_c/2)+1 sign parity by three-input xors, folded into +-alpha
+    #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
+    #   2 d_c         scale and sign per output
+    # = 23 for d_c = 4, d_v = 2 (2.875 per message update). For sum-product,
+    # d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus d_c clamps. The
+    # bytes a streaming sweep would move (8 B per update) are reported beside
+    # it as the HBM-equivalent rate.
     dc, dv = code.dc_max, code.dv_max
     BOXPLUS_OPS = 100
     if args.bp == "minsum":
-        ops_check = dc * (dv + 5) - 1
+        ops_check = dc * dv + (dc + 1) // 2 + 1 + dc * max(0, (dc - 1) // 2) + 2 * dc
     else:
         ops_check = dc * dv + BOXPLUS_OPS * dc * (dc - 2) + dc
     ops_per_update = ops_check / (2.0 * dc)

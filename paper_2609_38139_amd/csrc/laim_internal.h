@@ -68,7 +68,7 @@ struct ResidentShape {
   int32_t cpt;   // checks per thread
   int32_t vpt;   // qubits per thread
   int32_t spb;   // shots per block
-  int32_t mpad;  // LDS stride of one edge slot (>= nt * cpt)
+  int32_t mpad;  // nt * cpt rounded up to a multiple of 64 (LDS holds DC * mpad messages)
   size_t lds;    // dynamic LDS bytes per block
 };
 

@@ -135,14 +135,21 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // once, one shot per group of `nt` threads, in lockstep through the same
 // rounds. Thread t of a group owns checks t + k nt (k < CPT) and qubits
 // t + k nt (k < vpt). Per group, LDS holds the current m_{c->v} in
-// slot-major order msg[j * mpad + c] (consecutive lanes touch consecutive
-// words), a few scratch words -- the first holds -0.0, which padded
+// tiles of 64 checks, slot-major within a tile: message (c, j) is word
+// ((c / 64) DC + j) 64 + c mod 64, so consecutive lanes touch consecutive
+// words and the slots of one check sit at fixed offsets of 64 words, a few scratch words -- the first holds -0.0, which padded
 // qubit-side partners point at (x + (-0.0) == x for every x) -- and three
 // bitmaps: flip requests of the current feedback step (n bits), the
 // correction z (n bits) and the syndrome s (m bits). A shot either
 // starts fresh from its initial error or resumes from state saved in device
 // memory (used by the serving loop, which runs one round per launch).
 // ====================================================================
+
+// LDS word of message (check c, slot j) in the resident layout.
+template <int DC>
+__device__ __forceinline__ int32_t msg_word(int32_t c, int32_t j) {
+  return ((c >> 6) * DC + j) * 64 + (c & 63);
+}
 
 // What one group of a unit works on.
 struct GroupJob {
@@ -210,7 +217,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     r0 = job.r0;
   }
   float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)(member ? g : 0) * u.group_bytes);
-  const int32_t zslot = DC * u.mpad;
+  const int32_t zslot = DC * u.mpad;  // mpad is a multiple of 64
   int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
   const int32_t nw = (c.n + 31) >> 5;
   uint32_t* flw = reinterpret_cast<uint32_t*>(gw + kGroupWords);  // [nw] flip requests
@@ -236,7 +243,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         int32_t e = -1;
         if (valid && j < c.dcmax && p < c.dvmax - 1)
           e = c.partner[((int64_t)ch * c.dcmax + j) * (c.dvmax - 1) + p];
-        pidx[k][j][p] = (e >= 0) ? edge_slot(e) * u.mpad + edge_check(e) : zslot;
+        pidx[k][j][p] = (e >= 0) ? msg_word<DC>(edge_check(e), edge_slot(e)) : zslot;
       }
     }
   }
@@ -260,10 +267,10 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
       uint32_t x = 0;
       if (u.resume) {
         for (int j = 0; j < DC; ++j)
-          msg[j * u.mpad + ch] = (alive && j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
+          msg[msg_word<DC>(ch, j)] = (alive && j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
         if (alive) x = job.st_s[ch] & 1u;
       } else {
-        for (int j = 0; j < DC; ++j) msg[j * u.mpad + ch] = 0.0f;
+        for (int j = 0; j < DC; ++j) msg[msg_word<DC>(ch, j)] = 0.0f;
         if (alive) {
           const int32_t d = c.chk_deg[ch];
           for (int32_t j = 0; j < d; ++j) x ^= job.e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
@@ -322,8 +329,9 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         for (int k = 0; k < CPT; ++k) {
           if (cidx[k] < 0) continue;
           const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
+          float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
-          for (int j = 0; j < DC; ++j) msg[j * u.mpad + cidx[k]] = z0;
+          for (int j = 0; j < DC; ++j) mk[j * 64] = z0;
         }
       }
       fresh = false;
@@ -367,17 +375,19 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
             // its own input's sign with one bit operation.
             uint32_t par = sigma_neg << 31;
 #pragma unroll
-            for (int j = 0; j < DC; ++j) par ^= __float_as_uint(x[k][j]);
+            for (int j = 0; j + 1 < DC; j += 2)
+              par = xor3(par, __float_as_uint(x[k][j]), __float_as_uint(x[k][j + 1]));
+            if (DC & 1) par ^= __float_as_uint(x[k][DC - 1]);
             const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
             float ex[DC];  // smallest |m| over the other inputs
             if (DC == 2) {
               ex[0] = fabsf(x[k][1]);
               ex[1] = fabsf(x[k][0]);
             } else if (DC == 4) {
-              ex[0] = min3f(fabsf(x[k][1]), fabsf(x[k][2]), fabsf(x[k][3]));
-              ex[1] = min3f(fabsf(x[k][0]), fabsf(x[k][2]), fabsf(x[k][3]));
-              ex[2] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][3]));
-              ex[3] = min3f(fabsf(x[k][0]), fabsf(x[k][1]), fabsf(x[k][2]));
+              ex[0] = min3_abs(x[k][1], x[k][2], x[k][3]);
+              ex[1] = min3_abs(x[k][0], x[k][2], x[k][3]);
+              ex[2] = min3_abs(x[k][0], x[k][1], x[k][3]);
+              ex[3] = min3_abs(x[k][0], x[k][1], x[k][2]);
             } else {
               float pre[DC], suf[DC];
               pre[1] = fabsf(x[k][0]);
@@ -422,8 +432,9 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
               out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
             }
           }
+          float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
-          for (int j = 0; j < DC; ++j) msg[j * u.mpad + cidx[k]] = out[j];
+          for (int j = 0; j < DC; ++j) mk[j * 64] = out[j];
         }
       }
       fresh = false;
@@ -460,7 +471,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
           float acc = pi;
           for (int32_t q = 0; q < dv; ++q) {
             const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-            acc = acc + msg[edge_slot(e) * u.mpad + edge_check(e)];
+            acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
           }
           acc = clampf(acc, C);
           Lv[j] = acc;
@@ -543,7 +554,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         float acc = pi;
         for (int32_t q = 0; q < dv; ++q) {
           const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-          acc = acc + msg[edge_slot(e) * u.mpad + edge_check(e)];
+          acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
         }
         job.L_out[v] = clampf(acc, C);
       }
@@ -554,7 +565,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         const int32_t ch = t + k * u.nt;
         if (ch >= c.m) continue;
         for (int j = 0; j < c.dcmax && j < DC; ++j)
-          job.st_msg[(int64_t)ch * c.dcmax + j] = msg[j * u.mpad + ch];
+          job.st_msg[(int64_t)ch * c.dcmax + j] = msg[msg_word<DC>(ch, j)];
         job.st_s[ch] = (uint8_t)((sb >> k) & 1u);
       }
 #pragma unroll 1
@@ -873,7 +884,7 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
     set_error("block of %d threads exceeds 1024", nt * spb);
     return false;
   }
-  const int mpad = nt * cpt;
+  const int mpad = (nt * cpt + 63) / 64 * 64;
   const size_t gb = group_bytes_for(dc, mpad, c.n, c.m);
   const size_t lds = kCtrlWords * 4 + gb * (size_t)spb;
   if (lds > (size_t)lds_max) {
