@@ -136,8 +136,11 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // rounds. Thread t of a group owns checks t + k nt (k < CPT) and qubits
 // t + k nt (k < vpt). Per group, LDS holds the current m_{c->v} in
 // tiles of 64 checks, slot-major within a tile: message (c, j) is word
-// ((c / 64) DC + j) 64 + c mod 64, so consecutive lanes touch consecutive
-// words and the slots of one check sit at fixed offsets of 64 words, a few scratch words -- the first holds -0.0, which padded
+// ((c / 64) DC + j) S + c mod 64 with a slot stride S of 65 words, so
+// consecutive lanes touch consecutive words, the slots of one check sit at
+// fixed offsets (immediate operands of the LDS writes) and neighbouring
+// checks' messages in different slots fall in different banks. After the
+// messages come a few scratch words -- the first holds -0.0, which padded
 // qubit-side partners point at (x + (-0.0) == x for every x) -- and three
 // bitmaps: flip requests of the current feedback step (n bits), the
 // correction z (n bits) and the syndrome s (m bits). A shot either
@@ -145,10 +148,13 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // memory (used by the serving loop, which runs one round per launch).
 // ====================================================================
 
-// LDS word of message (check c, slot j) in the resident layout.
+// LDS word of message (check c, slot j) in the resident layout. A slot of
+// a tile spans kSlotStride words (64 used), so that messages of
+// neighbouring checks in different slots fall in different LDS banks.
+constexpr int kSlotStride = 65;
 template <int DC>
 __device__ __forceinline__ int32_t msg_word(int32_t c, int32_t j) {
-  return ((c >> 6) * DC + j) * 64 + (c & 63);
+  return ((c >> 6) * DC + j) * kSlotStride + (c & 63);
 }
 
 // What one group of a unit works on.
@@ -217,7 +223,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     r0 = job.r0;
   }
   float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)(member ? g : 0) * u.group_bytes);
-  const int32_t zslot = DC * u.mpad;  // mpad is a multiple of 64
+  const int32_t zslot = (u.mpad >> 6) * DC * kSlotStride;  // mpad is a multiple of 64
   int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
   const int32_t nw = (c.n + 31) >> 5;
   uint32_t* flw = reinterpret_cast<uint32_t*>(gw + kGroupWords);  // [nw] flip requests
@@ -331,7 +337,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
           const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
           float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
-          for (int j = 0; j < DC; ++j) mk[j * 64] = z0;
+          for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = z0;
         }
       }
       fresh = false;
@@ -434,7 +440,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
           }
           float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
-          for (int j = 0; j < DC; ++j) mk[j * 64] = out[j];
+          for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = out[j];
         }
       }
       fresh = false;
@@ -828,7 +834,7 @@ static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) 
 // msg, scratch words, flip and correction bitmaps (n bits each), syndrome
 // bitmap (m bits)
 static size_t group_bytes_for(int dc, int mpad, int n, int m) {
-  const size_t b = (size_t)(dc * mpad + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
+  const size_t b = (size_t)(dc * (mpad / 64) * kSlotStride + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
   return (b + 15) / 16 * 16;
 }
 
