@@ -461,10 +461,6 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         const int32_t k = __builtin_ctz(act);
         act &= act - 1u;
         const int32_t ch = t + k * u.nt;
-        const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
-                                        ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
-                                        (uint32_t)(kp.seed >> 32));
-        if (!below(w.w0, kp.mask_bound)) continue;
         const int32_t d = c.chk_deg[ch];
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
@@ -484,7 +480,14 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
           if (j == 0 || acc > Lmax) Lmax = acc;
         }
         if (d == 0) continue;
+        // The move needs both the Evidence bound and the check's clock; the
+        // bound is tested first, so the random words are drawn only when
+        // it holds.
         if (kp.evidence && !(Lmax >= c.thr[d])) continue;
+        const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                        ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                        (uint32_t)(kp.seed >> 32));
+        if (!below(w.w0, kp.mask_bound)) continue;
         uint32_t ntie = 0;
 #pragma unroll
         for (int j = 0; j < DC; ++j)
@@ -1231,10 +1234,6 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
   if (ch >= c.m || i >= nshots) return;
   if (w.done[i] || !w.s[(tile * c.m + ch) * kStreamTile + lane]) return;
   const uint64_t shot = shot0 + (uint64_t)i;
-  const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
-                                   ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
-                                   (uint32_t)(kp.seed >> 32));
-  if (!below(rw.w0, kp.mask_bound)) return;
   const int32_t d = c.chk_deg[ch];
   if (d == 0) return;
   const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
@@ -1254,7 +1253,11 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
     Lv[j] = L;
     if (j == 0 || L > Lmax) Lmax = L;
   }
-  if (kp.evidence && !(Lmax >= c.thr[d])) return;
+  if (kp.evidence && !(Lmax >= c.thr[d])) return;  // Evidence first, then the clock
+  const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                   ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                   (uint32_t)(kp.seed >> 32));
+  if (!below(rw.w0, kp.mask_bound)) return;
   uint32_t ntie = 0;
 #pragma unroll
   for (int j = 0; j < DCT; ++j)
