@@ -204,8 +204,7 @@ __device__ __forceinline__ GroupJob dead_job() {
 // spb * nt only take part in the barriers).
 template <int DC, int DV, int CPT, int BP, bool REG, class JobAt>
 __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, const JobAt& job_at,
-                         unsigned char* smem) {
-  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+                         unsigned char* smem, int32_t* ctrl) {
   const int32_t spb = u.spb;
   const int32_t tid = threadIdx.x;
   const int32_t g = tid / u.nt;
@@ -222,7 +221,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     shot = job.shot;
     r0 = job.r0;
   }
-  float* msg = reinterpret_cast<float*>(smem + kCtrlWords * 4 + (size_t)(member ? g : 0) * u.group_bytes);
+  float* msg = reinterpret_cast<float*>(smem + (size_t)(member ? g : 0) * u.group_bytes);
   const int32_t zslot = (u.mpad >> 6) * DC * kSlotStride;  // mpad is a multiple of 64
   int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
   const int32_t nw = (c.n + 31) >> 5;
@@ -657,7 +656,9 @@ struct ResJobs {
 template <int DC, int DV, int CPT, int BP, bool REG>
 __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, ResArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+  // control words after the groups, so that group 0's messages start at
+  // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(a.counter, (uint32_t)a.u.spb);
@@ -665,7 +666,7 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
     const int32_t base = ctrl[0];
     if (base >= a.nshots) break;
     const ResJobs jobs{a.e0, a.shot0, a.nshots, c.n, c.m, base, a.z, a.s, a.tclr, a.L, a.fail};
-    run_unit<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem);
+    run_unit<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
   }
 }
 
@@ -742,9 +743,9 @@ static const int kBatchVariants[][4] = {  // dc, dv, cpt, regular
 template <int BP>
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
                                                      const BatchUnitDev* units, int32_t nunits,
-                                                     uint32_t* counter) {
+                                                     uint32_t* counter, int32_t ctrl_off) {
   extern __shared__ __align__(16) unsigned char smem[];
-  int32_t* ctrl = reinterpret_cast<int32_t*>(smem);
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem + ctrl_off);  // after the largest unit's groups
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(counter, 1u);
@@ -757,7 +758,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
     const KParams kp = I->kp;
     const UnitCtx ctx = I->u;
     const BatchJobs jobs{I, U.base};
-#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem)
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
     LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
 #undef LAIM_CALL
   }
@@ -766,8 +767,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
 template <int BP>
 __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
                                                       const ServerUnitDev* units,
-                                                      const ServerReqDev* reqs) {
+                                                      const ServerReqDev* reqs, int32_t ctrl_off) {
   extern __shared__ __align__(16) unsigned char smem[];
+  int32_t* ctrl = reinterpret_cast<int32_t*>(smem + ctrl_off);
   const ServerUnitDev U = units[blockIdx.x];
   const BatchItemDev* I = items + U.item;
   const DevCode c = I->c;
@@ -777,7 +779,7 @@ __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
   ctx.resume = U.resume;
   ctx.events = 1;
   const ServerJobs jobs{reqs, U.first, U.count};
-#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem)
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
   LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
 #undef LAIM_CALL
 }
@@ -959,10 +961,13 @@ hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* u
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
+  const int32_t ctrl_off = (int32_t)(lds - kCtrlWords * 4);
   if (bp)
-    hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter);
+    hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter,
+                       ctrl_off);
   else
-    hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter);
+    hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter,
+                       ctrl_off);
   return hipGetLastError();
 }
 
@@ -988,10 +993,11 @@ hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev*
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
   }
+  const int32_t ctrl_off = (int32_t)(lds - kCtrlWords * 4);
   if (bp)
-    hipLaunchKernelGGL(server_kernel<1>, dim3(nunits), dim3(block), lds, st, items, units, reqs);
+    hipLaunchKernelGGL(server_kernel<1>, dim3(nunits), dim3(block), lds, st, items, units, reqs, ctrl_off);
   else
-    hipLaunchKernelGGL(server_kernel<0>, dim3(nunits), dim3(block), lds, st, items, units, reqs);
+    hipLaunchKernelGGL(server_kernel<0>, dim3(nunits), dim3(block), lds, st, items, units, reqs, ctrl_off);
   return hipGetLastError();
 }
 
