@@ -460,7 +460,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         const int32_t k = __builtin_ctz(act);
         act &= act - 1u;
         const int32_t ch = t + k * u.nt;
-        const int32_t d = c.chk_deg[ch];
+        const int32_t d = REG ? DC : c.chk_deg[ch];
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
         float Lmax = -__builtin_inff();
@@ -468,9 +468,10 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         for (int j = 0; j < DC; ++j) {
           if (j >= d) continue;
           const int32_t v = nb[j];
-          const int32_t dv = c.var_deg[v];
+          const int32_t dv = REG ? DV : c.var_deg[v];
           float acc = pi;
-          for (int32_t q = 0; q < dv; ++q) {
+#pragma unroll
+          for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
             const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
             acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
           }
@@ -506,32 +507,39 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
         const uint32_t bit = 1u << (chosen & 31);
         if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
         atomicXor(&zw[chosen >> 5], bit);
-        const int32_t dv = c.var_deg[chosen];
-        for (int32_t q = 0; q < dv; ++q) {
+        const int32_t dv = REG ? DV : c.var_deg[chosen];
+#pragma unroll
+        for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
           const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
           atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
         }
         ++nflip;
       }
-      if (u.events && nflip) atomicAdd(&gw[kGwFlips], nflip);
+      if (nflip) atomicAdd(&gw[kGwFlips], nflip);
     }
     __syncthreads();
-    // ---- the new syndrome bits of this thread's checks
+    // ---- the new syndrome bits of this thread's checks (unchanged when
+    // no qubit of the group flipped this round)
+    const int32_t nfl = member ? gw[kGwFlips] : 0;
     if (working) {
-      uint32_t nsb = 0;
+      if (nfl) {
+        uint32_t nsb = 0;
 #pragma unroll
-      for (int k = 0; k < CPT; ++k)
-        if (cidx[k] >= 0) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
-      sb = nsb;
+        for (int k = 0; k < CPT; ++k)
+          if (cidx[k] >= 0) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+        sb = nsb;
+      }
       if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
     }
     __syncthreads();
     if (working) {
+      if (nfl) {
 #pragma unroll 1
-      for (int32_t w = t; w < nw; w += u.nt) flw[w] = 0u;
+        for (int32_t w = t; w < nw; w += u.nt) flw[w] = 0u;
+      }
       const bool any = gw[(rr & 1) ? kGwAct1 : kGwAct0] != 0;
       if (!any && tclr < 0) tclr = r + 1;
-      flips_last = gw[kGwFlips];
+      flips_last = nfl;
       if (kp.retire && tclr >= 0) working = false;
     }
   }
