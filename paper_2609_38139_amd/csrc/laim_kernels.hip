@@ -200,27 +200,18 @@ __device__ __forceinline__ GroupJob dead_job() {
   return j;
 }
 
-// Runs one unit; every thread of the block calls it (threads beyond
+// Runs the units `src` hands out, one after another, all with the same
+// code and launch shape: the per-thread graph tables are built once and
+// stay in registers. Every thread of the block calls it (threads beyond
 // spb * nt only take part in the barriers).
-template <int DC, int DV, int CPT, int BP, bool REG, class JobAt>
-__device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, const JobAt& job_at,
-                         unsigned char* smem, int32_t* ctrl) {
+template <int DC, int DV, int CPT, int BP, bool REG, class Src>
+__device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u, Src& src,
+                          unsigned char* smem, int32_t* ctrl) {
   const int32_t spb = u.spb;
   const int32_t tid = threadIdx.x;
   const int32_t g = tid / u.nt;
   const bool member = g < spb;
   const int32_t t = member ? tid - g * u.nt : 0;
-  // The job is read twice (here and for the results) rather than kept in
-  // registers through the rounds: only the shot id and first round live on.
-  bool alive;
-  uint64_t shot;
-  int32_t r0;
-  {
-    const GroupJob job = member ? job_at(g) : dead_job();
-    alive = member && job.alive;
-    shot = job.shot;
-    r0 = job.r0;
-  }
   float* msg = reinterpret_cast<float*>(smem + (size_t)(member ? g : 0) * u.group_bytes);
   const int32_t zslot = (u.mpad >> 6) * DC * kSlotStride;  // mpad is a multiple of 64
   int32_t* gw = reinterpret_cast<int32_t*>(msg + zslot);
@@ -253,6 +244,20 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
     }
   }
 
+  while (src.next(ctrl)) {
+  const Src& job_at = src;
+  // The job is read three times (here, at the start and for the results)
+  // rather than kept in registers through the rounds: only the shot id and
+  // first round live on.
+  bool alive;
+  uint64_t shot;
+  int32_t r0;
+  {
+    const GroupJob job = member ? job_at(g) : dead_job();
+    alive = member && job.alive;
+    shot = job.shot;
+    r0 = job.r0;
+  }
   // ---- start: messages, bitmaps, scratch words; bit k of sb is the
   // syndrome of check t + k nt (kept in registers for the sweeps)
   uint32_t sb = 0;
@@ -617,6 +622,7 @@ __device__ void run_unit(const DevCode& c, const KParams& kp, const UnitCtx& u, 
       job.ev_out[3] = f ? 1 : 0;
     }
   }
+  }  // units
 }
 
 // ---- the single-code persistent kernel
@@ -644,6 +650,16 @@ struct ResJobs {
   int32_t* tclr;
   float* L;
   uint8_t* fail;
+  uint32_t* counter;
+  int32_t spb;
+  // Takes the next spb shots from the launch's queue; false once it is empty.
+  __device__ bool next(int32_t* ctrl) {
+    __syncthreads();
+    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(counter, (uint32_t)spb);
+    __syncthreads();
+    base = ctrl[0];
+    return base < nshots;
+  }
   __device__ GroupJob operator()(int32_t g) const {
     GroupJob j = dead_job();
     const int32_t idx = base + g;
@@ -667,15 +683,8 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
   // control words after the groups, so that group 0's messages start at
   // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(a.counter, (uint32_t)a.u.spb);
-    __syncthreads();
-    const int32_t base = ctrl[0];
-    if (base >= a.nshots) break;
-    const ResJobs jobs{a.e0, a.shot0, a.nshots, c.n, c.m, base, a.z, a.s, a.tclr, a.L, a.fail};
-    run_unit<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
-  }
+  ResJobs jobs{a.e0, a.shot0, a.nshots, c.n, c.m, 0, a.z, a.s, a.tclr, a.L, a.fail, a.counter, a.u.spb};
+  run_units<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
@@ -687,6 +696,12 @@ __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
 struct BatchJobs {
   const BatchItemDev* I;
   int32_t base;
+  bool given;
+  __device__ bool next(int32_t*) {  // a single unit
+    const bool first = !given;
+    given = true;
+    return first;
+  }
   __device__ GroupJob operator()(int32_t g) const {
     GroupJob j = dead_job();
     const int32_t idx = base + g;
@@ -708,6 +723,12 @@ struct BatchJobs {
 struct ServerJobs {
   const ServerReqDev* R;
   int32_t first, count;
+  bool given;
+  __device__ bool next(int32_t*) {  // a single unit
+    const bool once = !given;
+    given = true;
+    return once;
+  }
   __device__ GroupJob operator()(int32_t g) const {
     GroupJob j = dead_job();
     if (g >= count) return j;
@@ -765,8 +786,8 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
     const DevCode c = I->c;
     const KParams kp = I->kp;
     const UnitCtx ctx = I->u;
-    const BatchJobs jobs{I, U.base};
-#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
+    BatchJobs jobs{I, U.base, false};
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_units<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
     LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
 #undef LAIM_CALL
   }
@@ -786,8 +807,8 @@ __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
   ctx.rounds = 1;
   ctx.resume = U.resume;
   ctx.events = 1;
-  const ServerJobs jobs{reqs, U.first, U.count};
-#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_unit<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
+  ServerJobs jobs{reqs, U.first, U.count, false};
+#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_units<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
   LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
 #undef LAIM_CALL
 }
