@@ -34,6 +34,32 @@ LANES_PER_CU = 64  # one VALU instruction per lane per clock per CU (4 SIMD x 16
 VALU_PEAK_TOPS = CU_COUNT * LANES_PER_CU * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s
 
 
+def profiled_traffic(profile: str, shape: str):
+    """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's counts), or None when the kernel
+    sources or the launch shape differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ": " in line:
+            k, v = line.strip().split(": ", 1)
+            fields[k] = v
+    h = hashlib.sha256()
+    for f in ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38139_amd/csrc/device_math.h",
+              "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or fields.get("launch_shape") != shape:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,19 +267,23 @@ def main():
     dec_s = main_run["decode_ms"] / 1000.0
     msg_per_launch = msg_updates / args.steps
 
-    # Roofline of the dominant kernel (the resident decode launch). It keeps
-    # every message on chip, so HBM carries only e0 in and z, s, t_clr out;
-    # its bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is
-    # the operation count of the sweeps on this instruction set (three-input
-    # min, median and xor exist), per check and sweep:
+    # Roofline of the dominant kernel. The resident decode launch keeps every
+    # message on chip, so HBM carries only e0 in and z, s, t_clr out; its
+    # bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is the
+    # operation count of the sweeps on this instruction set (three-input min,
+    # median and xor exist), per check and sweep:
     #   d_c d_v       qubit-side sums (d_v - 1 each) and one clamp per input
     #   ceil(d_c/2)+1 sign parity by three-input xors, folded into +-alpha
     #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
     #   2 d_c         scale and sign per output
     # = 23 for d_c = 4, d_v = 2 (2.875 per message update). For sum-product,
-    # d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus d_c clamps. The
-    # bytes a streaming sweep would move (8 B per update) are reported beside
-    # it as the HBM-equivalent rate.
+    # d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus d_c clamps.
+    # Beside it: the rate the stream form's HBM traffic would need for the
+    # same sweeps (each check-to-qubit message written once and read once by
+    # its partner's gather, 4 B each way, i.e. 4 B per message update
+    # counting both directions, plus 1 B of syndrome per check and sweep).
+    # In the stream form the sweeps themselves stream through HBM and the
+    # roofline is that traffic against the 8 TB/s peak.
     dc, dv = code.dc_max, code.dv_max
     BOXPLUS_OPS = 100
     if args.bp == "minsum":
@@ -261,15 +291,30 @@ def main():
     else:
         ops_check = dc * dv + BOXPLUS_OPS * dc * (dc - 2) + dc
     ops_per_update = ops_check / (2.0 * dc)
-    achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12
-    hbm_equiv_gbs = msg_per_launch * 8.0 / dec_s / 1e9
-    rl = {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 1),
-          "unit": "Tops/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
-          "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
-          "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
-          "msg_updates_per_launch": msg_per_launch,
-          "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
-          "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
+    bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
+    hbm_equiv_gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
+    default_workload = (L == 32 and args.p == 0.05 and args.shots == 65536 and R == 128
+                        and args.iters == 20 and args.bp == "minsum" and not args.no_retire)
+    if form != "stream":
+        shape = code.resident_cfg(args.bp)
+        traffic = None
+        if default_workload:
+            traffic = profiled_traffic("resident_kernel_toric2d_L32_minsum.md",
+                                       f"{shape['checks_per_thread']},{shape['shots_per_block']}")
+        achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12
+        rl = {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 1),
+              "unit": "Tops/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+              "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
+              "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
+              "msg_updates_per_launch": msg_per_launch,
+              "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
+              "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
+    else:
+        rl = {"bound": "hbm", "achieved": round(hbm_equiv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+              "kernel": f"stream form decode, sweeps and feedback kernels (2D toric L={L}, {args.bp})",
+              "bytes_per_msg_update": bytes_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
+              "msg_updates_per_launch": msg_per_launch}
 
     extras = {}
     if args.no_extras:
@@ -279,7 +324,9 @@ def main():
         rs = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
         sec_s = rs["ms_per_step"] / 1000.0
         upd = 2 * E * args.iters * rs["rounds_exec"]
-        sweeps_bytes = upd * 8.0  # m_{c->v} read by the partner gather + written, 4 B each
+        # each m_{c->v} read once by the partner gather and written once (4 B
+        # each) per check-to-qubit update, plus 1 B of syndrome per check
+        sweeps_bytes = upd * (4.0 + 1.0 / (2.0 * code.dc_max))
         extras["stream_form"] = {"shots_per_s": round(rs["shots"] / sec_s, 1),
                                  "msg_updates_per_s": upd / sec_s,
                                  "decode_ms": round(rs["decode_ms"], 2),
