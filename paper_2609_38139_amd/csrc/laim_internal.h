@@ -15,7 +15,7 @@ namespace laim {
 // Limits of the device layout.
 constexpr int kMaxCheckDegree = 32;
 constexpr int kMaxQubitDegree = 16;
-constexpr int kStreamTile = 64;  // shots per tile in the stream form (one wavefront)
+constexpr int kStreamTile = 256;  // shots per tile in the stream form (one wavefront, 4 per lane)
 
 // Edge reference (c, j): the j-th qubit of check c, packed as (c << 5) | j.
 __host__ __device__ inline int32_t pack_edge(int32_t c, int32_t j) { return (c << 5) | j; }

@@ -1083,32 +1083,39 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
 }
 
 // ====================================================================
-// Stream form: messages live in HBM in 64-shot tiles, msg[tile][edge][lane]
-// with edges in ELL order (c * dcmax + j); every graph lookup is uniform
-// across a wavefront (one check, 64 shots) and every data access is a
-// contiguous 256-byte row. One launch per BP sweep (double-buffered
-// m_{c->v}) and a few small launches per round for the feedback step.
+// Stream form: messages live in HBM in tiles of 256 shots,
+// msg[tile][edge][shot in tile] with edges in ELL order (c * dcmax + j).
+// A wavefront handles one row (one check or qubit, all shots of a tile);
+// lane l holds shots 4l .. 4l + 3, so every data access is a contiguous
+// row (1 KiB of messages, 256 B of bytes) read or written with 16- or
+// 4-byte vector accesses, and every graph lookup is uniform across the
+// wavefront. One launch per BP sweep (double-buffered m_{c->v}) and a few
+// small launches per round for the feedback step.
 // ====================================================================
+constexpr int kSV = 4;  // shots per lane
+static_assert(kStreamTile == 64 * kSV, "a stream tile is one wavefront of kSV shots per lane");
+
 struct StreamWS {
-  float* msg[2];     // [ntile][m * dcmax][64]
-  uint8_t* s;        // [ntile][m][64]
-  uint8_t* z;        // [ntile][n][64]
-  uint8_t* fl;       // [ntile][n][64]
-  uint32_t* anys;    // [nshots]
-  int32_t* tclr;     // [nshots]
-  uint8_t* done;     // [nshots]
-  uint8_t* newdone;  // [nshots]
+  float* msg[2];     // [ntile][m * dcmax][kStreamTile]
+  uint8_t* s;        // [ntile][m][kStreamTile]
+  uint8_t* z;        // [ntile][n][kStreamTile]
+  uint8_t* fl;       // [ntile][n][kStreamTile]
+  uint32_t* anys;    // [ntile * kStreamTile]
+  int32_t* tclr;     // [ntile * kStreamTile]
+  uint8_t* done;     // [ntile * kStreamTile]: retired shots and the last tile's padding
+  uint8_t* newdone;  // [ntile * kStreamTile]
 };
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t* total) {
   const int64_t ntile = ((int64_t)nshots + kStreamTile - 1) / kStreamTile;
-  const size_t msg_b = align256((size_t)ntile * c.m * c.dcmax * kStreamTile * 4);
-  const size_t s_b = align256((size_t)ntile * c.m * kStreamTile);
-  const size_t z_b = align256((size_t)ntile * c.n * kStreamTile);
-  const size_t sh4 = align256((size_t)nshots * 4);
-  const size_t sh1 = align256((size_t)nshots);
+  const int64_t ns = ntile * kStreamTile;
+  const size_t msg_b = align256((size_t)ns * c.m * c.dcmax * 4);
+  const size_t s_b = align256((size_t)ns * c.m);
+  const size_t z_b = align256((size_t)ns * c.n);
+  const size_t sh4 = align256((size_t)ns * 4);
+  const size_t sh1 = align256((size_t)ns);
   StreamWS w;
   char* p = reinterpret_cast<char*>(ws);
   size_t off = 0;
@@ -1140,70 +1147,62 @@ size_t stream_workspace_bytes(const DevCode& c, int32_t nshots) {
   return t;
 }
 
-constexpr int kStreamChecksPerBlock = 4;
+constexpr int kStreamRowsPerBlock = 4;  // 256 threads: one row per wavefront
 
-// Shot start: z = 0, no flip requests (one thread per (tile, qubit, lane)).
-__global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w, int32_t nshots) {
-  const int32_t lane = threadIdx.x & 63;
-  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t tile = blockIdx.y;
-  if (v >= c.n) return;
-  const int64_t o = (tile * c.n + v) * kStreamTile + lane;
-  w.z[o] = 0;
-  w.fl[o] = 0;
+// Row handled by this wavefront (uniform, so table reads become scalar loads).
+__device__ __forceinline__ int32_t stream_row() {
+  return (int32_t)blockIdx.x * kStreamRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-// Shot start: s = H e0 and messages 0 (one thread per (tile, check, lane)).
+// Offset of this lane's first shot in row `row` of tile `tile` of an array of rows.
+__device__ __forceinline__ int64_t stream_at(int64_t tile, int32_t rows, int64_t row, int32_t lane) {
+  return (tile * rows + row) * kStreamTile + kSV * lane;
+}
+
+__device__ __forceinline__ uint32_t ld4b(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+__device__ __forceinline__ void st4b(uint8_t* p, uint32_t v) { *reinterpret_cast<uint32_t*>(p) = v; }
+
+// Shot start: z = 0, no flip requests.
+__global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = stream_row();
+  if (v >= c.n) return;
+  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  st4b(w.z + o, 0u);
+  st4b(w.fl + o, 0u);
+}
+
+// Shot start: s = H e0 and messages 0 (shots beyond nshots get s = 0).
 __global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, const uint8_t* e0,
                                                        int32_t nshots) {
   const int32_t lane = threadIdx.x & 63;
-  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
   if (ch >= c.m) return;
-  uint32_t x = 0;
   const int32_t d = c.chk_deg[ch];
-  if (i < nshots)
+  uint32_t x4 = 0;
+#pragma unroll
+  for (int q = 0; q < kSV; ++q) {
+    const int64_t i = tile * kStreamTile + kSV * lane + q;
+    if (i >= nshots) continue;
+    uint32_t x = 0;
     for (int32_t j = 0; j < d; ++j) x ^= e0[i * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]];
-  x &= 1u;
-  w.s[(tile * c.m + ch) * kStreamTile + lane] = (uint8_t)x;
+    x &= 1u;
+    x4 |= x << (8 * q);
+    if (x) w.anys[i] = 1u;
+  }
+  st4b(w.s + stream_at(tile, c.m, ch, lane), x4);
   for (int32_t j = 0; j < c.dcmax; ++j)
-    w.msg[0][((tile * c.m + ch) * c.dcmax + j) * kStreamTile + lane] = 0.0f;
-  if (x && i < nshots) w.anys[i] = 1u;
+    *reinterpret_cast<float4*>(w.msg[0] + stream_at(tile, c.m * c.dcmax, (int64_t)ch * c.dcmax + j, lane)) =
+        make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// One BP sweep: m_{c->v} (src) -> m_{c->v} (dst), one thread per (tile,
-// check, lane). `fresh` marks the first sweep of every shot (m_{v->c} = 0).
+// The check rule for one shot: x[j] = m_{v->c} of the check's j-th qubit
+// (j < d), out[j] = m_{c->v}.
 template <int DCT>
-__global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
-                                                    const float* __restrict__ src,
-                                                    float* __restrict__ dst, int32_t fresh,
-                                                    int32_t nshots) {
-  const int32_t lane = threadIdx.x & 63;
-  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
-  const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
-  if (ch >= c.m || i >= nshots) return;
-  if (w.done[i]) return;
+__device__ __forceinline__ void stream_check_rule(const KParams& kp, const float* x, int32_t d,
+                                                  uint32_t sigma_neg, float* out) {
   const float C = kp.clamp;
-  const int32_t d = c.chk_deg[ch];
-  const int32_t pw = c.dvmax - 1;
-  float x[DCT];
-#pragma unroll
-  for (int j = 0; j < DCT; ++j) {
-    if (j >= d) continue;
-    float acc = kp.pi;
-    for (int32_t p = 0; p < pw; ++p) {
-      const int32_t e = c.partner[((int64_t)ch * c.dcmax + j) * pw + p];
-      if (e < 0) break;
-      acc = acc + src[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + lane];
-    }
-    acc = clampf(acc, C);
-    x[j] = fresh ? 0.0f : acc;
-  }
-  const uint32_t sigma_neg =
-      ((uint32_t)w.s[(tile * c.m + ch) * kStreamTile + lane] ^ (uint32_t)d) & 1u;
-  float* out = dst + ((tile * c.m + ch) * c.dcmax) * kStreamTile + lane;
   if (kp.bp == 0) {
     float mn1 = __builtin_inff(), mn2 = __builtin_inff();
     uint32_t par = sigma_neg;
@@ -1222,7 +1221,7 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
       if (j >= d) continue;
       const float mag = (fabsf(x[j]) == mn1) ? m2 : m1;
       const uint32_t ng = par ^ ((x[j] < 0.0f) ? 1u : 0u);
-      out[(int64_t)j * kStreamTile] = ng ? -mag : mag;
+      out[j] = ng ? -mag : mag;
     }
   } else {
 #pragma unroll
@@ -1240,106 +1239,166 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
           acc = boxplus(acc, x[i2]);
         }
       }
-      out[(int64_t)j * kStreamTile] = clampf(sigma_neg ? -acc : acc, C);
+      out[j] = clampf(sigma_neg ? -acc : acc, C);
     }
   }
 }
 
+// One BP sweep: m_{c->v} (src) -> m_{c->v} (dst), one wavefront per (tile,
+// check). `fresh` marks the first sweep of every shot (m_{v->c} = 0). A tile
+// whose shots have all retired is skipped; the other tiles are swept whole,
+// since the messages of retired shots are never read again.
+template <int DCT>
+__global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
+                                                    const float* __restrict__ src,
+                                                    float* __restrict__ dst, int32_t fresh) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (ch >= c.m) return;
+  if (!__any(ld4b(w.done + tile * kStreamTile + kSV * lane) != 0x01010101u)) return;
+  const float C = kp.clamp;
+  const int32_t d = c.chk_deg[ch];
+  const int32_t pw = c.dvmax - 1;
+  const int32_t erows = c.m * c.dcmax;
+  float x[kSV][DCT];
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    float4 acc = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
+    for (int32_t p = 0; p < pw; ++p) {
+      const int32_t e = c.partner[((int64_t)ch * c.dcmax + j) * pw + p];
+      if (e < 0) break;
+      const float4 v = *reinterpret_cast<const float4*>(
+          src + stream_at(tile, erows, (int64_t)edge_check(e) * c.dcmax + edge_slot(e), lane));
+      acc.x = acc.x + v.x;
+      acc.y = acc.y + v.y;
+      acc.z = acc.z + v.z;
+      acc.w = acc.w + v.w;
+    }
+    x[0][j] = fresh ? 0.0f : clampf(acc.x, C);
+    x[1][j] = fresh ? 0.0f : clampf(acc.y, C);
+    x[2][j] = fresh ? 0.0f : clampf(acc.z, C);
+    x[3][j] = fresh ? 0.0f : clampf(acc.w, C);
+  }
+  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
+  float out[kSV][DCT];
+#pragma unroll
+  for (int q = 0; q < kSV; ++q)
+    stream_check_rule<DCT>(kp, x[q], d, ((s4 >> (8 * q)) ^ (uint32_t)d) & 1u, out[q]);
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    *reinterpret_cast<float4*>(dst + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane)) =
+        make_float4(out[0][j], out[1][j], out[2][j], out[3][j]);
+  }
+}
+
+// Belief of qubit v for shot column `col` of a tile.
 __device__ __forceinline__ float stream_belief(const DevCode& c, const float* msg, int64_t tile,
-                                               int32_t lane, int32_t v, float pi, float C) {
+                                               int32_t col, int32_t v, float pi, float C) {
   float acc = pi;
   const int32_t dv = c.var_deg[v];
   for (int32_t q = 0; q < dv; ++q) {
     const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-    acc = acc + msg[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + lane];
+    acc = acc + msg[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + col];
   }
   return clampf(acc, C);
 }
 
-// Feedback: active checks whose clock rang and whose Evidence holds
-// request a flip of their LocalMove qubit.
+// Feedback: active checks whose Evidence holds and whose clock rang request
+// a flip of their LocalMove qubit.
 template <int DCT>
 __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ msg, int32_t r,
-                                                    int32_t fresh, uint64_t shot0, int32_t nshots) {
+                                                    int32_t fresh, uint64_t shot0) {
   const int32_t lane = threadIdx.x & 63;
-  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
-  if (ch >= c.m || i >= nshots) return;
-  if (w.done[i] || !w.s[(tile * c.m + ch) * kStreamTile + lane]) return;
-  const uint64_t shot = shot0 + (uint64_t)i;
+  if (ch >= c.m) return;
+  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
+  const uint32_t dn = ld4b(w.done + tile * kStreamTile + kSV * lane);
+  const uint32_t act = s4 & ~dn & 0x01010101u;
+  if (!act) return;
   const int32_t d = c.chk_deg[ch];
   if (d == 0) return;
   const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
-  float Lv[DCT];
-  float Lmax = 0.0f;
+#pragma unroll 1
+  for (int q = 0; q < kSV; ++q) {
+    if (!((act >> (8 * q)) & 1u)) continue;
+    const int32_t col = kSV * lane + q;
+    const uint64_t shot = shot0 + (uint64_t)(tile * kStreamTile + col);
+    float Lv[DCT];
+    float Lmax = 0.0f;
 #pragma unroll
-  for (int j = 0; j < DCT; ++j) {
-    if (j >= d) continue;
-    float L;
-    if (fresh) {
-      L = kp.pi;
-      for (int32_t q = 0; q < c.var_deg[nb[j]]; ++q) L = L + 0.0f;
-      L = clampf(L, kp.clamp);
-    } else {
-      L = stream_belief(c, msg, tile, lane, nb[j], kp.pi, kp.clamp);
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      float L;
+      if (fresh) {
+        L = kp.pi;
+        for (int32_t qq = 0; qq < c.var_deg[nb[j]]; ++qq) L = L + 0.0f;
+        L = clampf(L, kp.clamp);
+      } else {
+        L = stream_belief(c, msg, tile, col, nb[j], kp.pi, kp.clamp);
+      }
+      Lv[j] = L;
+      if (j == 0 || L > Lmax) Lmax = L;
     }
-    Lv[j] = L;
-    if (j == 0 || L > Lmax) Lmax = L;
-  }
-  if (kp.evidence && !(Lmax >= c.thr[d])) return;  // Evidence first, then the clock
-  const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
-                                   ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
-                                   (uint32_t)(kp.seed >> 32));
-  if (!below(rw.w0, kp.mask_bound)) return;
-  uint32_t ntie = 0;
+    if (kp.evidence && !(Lmax >= c.thr[d])) continue;  // Evidence first, then the clock
+    const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                     ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                     (uint32_t)(kp.seed >> 32));
+    if (!below(rw.w0, kp.mask_bound)) continue;
+    uint32_t ntie = 0;
 #pragma unroll
-  for (int j = 0; j < DCT; ++j)
-    if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
-  uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
-  int32_t chosen = -1;
+    for (int j = 0; j < DCT; ++j)
+      if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
+    uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
+    int32_t chosen = -1;
 #pragma unroll
-  for (int j = 0; j < DCT; ++j) {
-    if (j < d && Lv[j] == Lmax && chosen < 0) {
-      if (pick == 0)
-        chosen = nb[j];
-      else
-        --pick;
+    for (int j = 0; j < DCT; ++j) {
+      if (j < d && Lv[j] == Lmax && chosen < 0) {
+        if (pick == 0)
+          chosen = nb[j];
+        else
+          --pick;
+      }
     }
+    if (chosen >= 0) w.fl[(tile * c.n + chosen) * kStreamTile + col] = 1;
   }
-  if (chosen >= 0) w.fl[(tile * c.n + chosen) * kStreamTile + lane] = 1;
 }
 
-// s ^= H f (one thread per (tile, check, lane)); flags shots with s != 0.
-__global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w, int32_t nshots) {
+// s ^= H f for live shots; flags shots with s != 0.
+__global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
   const int32_t lane = threadIdx.x & 63;
-  const int32_t ch = blockIdx.x * kStreamChecksPerBlock + (threadIdx.x >> 6);
+  const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
-  if (ch >= c.m || i >= nshots) return;
-  if (w.done[i]) return;
+  if (ch >= c.m) return;
+  const uint32_t live = ~ld4b(w.done + tile * kStreamTile + kSV * lane) & 0x01010101u;
+  if (!live) return;
   const int32_t d = c.chk_deg[ch];
-  uint32_t x = 0;
+  uint32_t x4 = 0;
   for (int32_t j = 0; j < d; ++j)
-    x ^= w.fl[(tile * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]) * kStreamTile + lane];
-  const int64_t so = (tile * c.m + ch) * kStreamTile + lane;
-  const uint32_t s = (w.s[so] ^ x) & 1u;
-  w.s[so] = (uint8_t)s;
-  if (s) w.anys[i] = 1u;
+    x4 ^= ld4b(w.fl + stream_at(tile, c.n, c.chk_var[(int64_t)ch * c.dcmax + j], lane));
+  const int64_t so = stream_at(tile, c.m, ch, lane);
+  const uint32_t s4 = ld4b(w.s + so) ^ (x4 & live);
+  st4b(w.s + so, s4);
+  const uint32_t hit = s4 & live;
+#pragma unroll
+  for (int q = 0; q < kSV; ++q)
+    if ((hit >> (8 * q)) & 1u) w.anys[tile * kStreamTile + kSV * lane + q] = 1u;
 }
 
-// z ^= f and clear the requests (one thread per (tile, qubit, lane)).
-__global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w, int32_t nshots) {
+// z ^= f and clear the requests (requests exist for live shots only).
+__global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
   const int32_t lane = threadIdx.x & 63;
-  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
-  if (v >= c.n || i >= nshots) return;
-  if (w.done[i]) return;
-  const int64_t o = (tile * c.n + v) * kStreamTile + lane;
-  w.z[o] ^= w.fl[o];
-  w.fl[o] = 0;
+  const int32_t v = stream_row();
+  if (v >= c.n) return;
+  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  const uint32_t f4 = ld4b(w.fl + o);
+  if (!f4) return;
+  st4b(w.z + o, ld4b(w.z + o) ^ f4);
+  st4b(w.fl + o, 0u);
 }
 
 // Per shot: t_clr at the first clear syndrome, retirement.
@@ -1359,11 +1418,12 @@ __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int
   }
 }
 
-__global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots) {
+// Every shot slot of the tiles: shots beyond nshots start retired.
+__global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots, int32_t ntot) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nshots) return;
+  if (i >= ntot) return;
   w.anys[i] = 0u;
-  w.done[i] = 0;
+  w.done[i] = (i >= nshots) ? 1 : 0;
   w.newdone[i] = 0;
   w.tclr[i] = -1;
 }
@@ -1375,20 +1435,25 @@ __global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp,
                                                           int32_t only_new, int32_t fresh,
                                                           float* __restrict__ L, int32_t nshots) {
   const int32_t lane = threadIdx.x & 63;
-  const int32_t v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int32_t v = stream_row();
   const int64_t tile = blockIdx.y;
-  const int64_t i = tile * kStreamTile + lane;
-  if (v >= c.n || i >= nshots) return;
-  if (only_new ? !w.newdone[i] : (w.done[i] && !w.newdone[i])) return;
-  float val;
-  if (fresh) {
-    val = kp.pi;
-    for (int32_t q = 0; q < c.var_deg[v]; ++q) val = val + 0.0f;
-    val = clampf(val, kp.clamp);
-  } else {
-    val = stream_belief(c, msg, tile, lane, v, kp.pi, kp.clamp);
+  if (v >= c.n) return;
+#pragma unroll 1
+  for (int q = 0; q < kSV; ++q) {
+    const int32_t col = kSV * lane + q;
+    const int64_t i = tile * kStreamTile + col;
+    if (i >= nshots) continue;
+    if (only_new ? !w.newdone[i] : (w.done[i] && !w.newdone[i])) continue;
+    float val;
+    if (fresh) {
+      val = kp.pi;
+      for (int32_t qq = 0; qq < c.var_deg[v]; ++qq) val = val + 0.0f;
+      val = clampf(val, kp.clamp);
+    } else {
+      val = stream_belief(c, msg, tile, col, v, kp.pi, kp.clamp);
+    }
+    L[i * c.n + v] = val;
   }
-  L[i * c.n + v] = val;
 }
 
 // Interleaved state -> caller's row-major outputs.
@@ -1412,9 +1477,8 @@ __global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t
   }
 }
 
-typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t, int32_t);
-typedef void (*MovesFn)(DevCode, KParams, StreamWS, const float*, int32_t, int32_t, uint64_t,
-                        int32_t);
+typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t);
+typedef void (*MovesFn)(DevCode, KParams, StreamWS, const float*, int32_t, int32_t, uint64_t);
 
 static void stream_fns(int dcmax, SweepFn* sw, MovesFn* mv) {
   if (dcmax <= 2) {
@@ -1447,12 +1511,14 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
   stream_fns(c.dcmax, &sweep_fn, &moves_fn);
   StreamWS w = stream_carve(c, nshots, ws, nullptr);
   const unsigned ntile = (unsigned)((nshots + kStreamTile - 1) / kStreamTile);
-  const dim3 gchk((unsigned)((c.m + kStreamChecksPerBlock - 1) / kStreamChecksPerBlock), ntile);
-  const dim3 gvar((unsigned)((c.n + 3) / 4), ntile);
-  const dim3 blk(256);
+  const int32_t ntot = (int32_t)(ntile * kStreamTile);
+  const dim3 gchk((unsigned)((c.m + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const dim3 gvar((unsigned)((c.n + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const dim3 blk(64 * kStreamRowsPerBlock);
   const unsigned gshot = (unsigned)((nshots + 255) / 256);
-  hipLaunchKernelGGL(stream_clear_shots, dim3(gshot), blk, 0, st, w, nshots);
-  hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w, nshots);
+  hipLaunchKernelGGL(stream_clear_shots, dim3((unsigned)((ntot + 255) / 256)), blk, 0, st, w, nshots,
+                     ntot);
+  hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w);
   hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, nshots);
   hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, -1, nshots);
   int cur = 0;
@@ -1462,14 +1528,13 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
   for (int32_t r = 0; r < kp.rounds; ++r) {
     for (int32_t it = 0; it < kp.iters; ++it) {
       hipLaunchKernelGGL(sweep_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], w.msg[cur ^ 1],
-                         fresh ? 1 : 0, nshots);
+                         fresh ? 1 : 0);
       cur ^= 1;
       fresh = false;
     }
-    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0,
-                       nshots);
-    hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w, nshots);
-    hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w, nshots);
+    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0);
+    hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w);
+    hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w);
     hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, r, nshots);
     if (L)
       hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1,
