@@ -34,10 +34,15 @@ LANES_PER_CU = 64  # one VALU instruction per lane per clock per CU (4 SIMD x 16
 VALU_PEAK_TOPS = CU_COUNT * LANES_PER_CU * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s
 
 
-def profiled_traffic(profile: str, shape: str):
+RESIDENT_SOURCES = ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38139_amd/csrc/device_math.h",
+                    "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py")
+
+
+def profiled_traffic(profile: str, shape: str, sources=RESIDENT_SOURCES):
     """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
     WRITE_SIZE, scaled by a plain copy's counts), or None when the kernel
-    sources or the launch shape differ from the profiled ones."""
+    sources (hashed in order) or the launch shape differ from the profiled
+    ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -48,8 +53,7 @@ def profiled_traffic(profile: str, shape: str):
             k, v = line.strip().split(": ", 1)
             fields[k] = v
     h = hashlib.sha256()
-    for f in ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38139_amd/csrc/device_math.h",
-              "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py"):
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256") != h.hexdigest() or fields.get("launch_shape") != shape:

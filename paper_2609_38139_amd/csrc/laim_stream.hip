@@ -1,0 +1,481 @@
+// laim_stream.hip -- the stream form of the decoder: BP messages in HBM,
+// one launch per sweep, plus the per-round feedback kernels. As in the
+// resident form only m_{c->v} is stored; each sweep recomputes
+// m_{v->c} = clamp(pi + sum_{c' != c} m_{c'->v}) in ascending check order
+// where the check phase reads it (Eqs. (BP-LLR1), (BP-LLR2)).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "laim_internal.h"
+
+namespace laim {
+
+// ====================================================================
+// Stream form: messages live in HBM in tiles of 256 shots,
+// msg[tile][edge][shot in tile] with edges in ELL order (c * dcmax + j).
+// A wavefront handles one row (one check or qubit, all shots of a tile);
+// lane l holds shots 4l .. 4l + 3, so every data access is a contiguous
+// row (1 KiB of messages, 256 B of bytes) read or written with 16- or
+// 4-byte vector accesses, and every graph lookup is uniform across the
+// wavefront. One launch per BP sweep (double-buffered m_{c->v}) and a few
+// small launches per round for the feedback step.
+// ====================================================================
+constexpr int kSV = 4;  // shots per lane
+static_assert(kStreamTile == 64 * kSV, "a stream tile is one wavefront of kSV shots per lane");
+
+struct StreamWS {
+  float* msg[2];     // [ntile][m * dcmax][kStreamTile]
+  uint8_t* s;        // [ntile][m][kStreamTile]
+  uint8_t* z;        // [ntile][n][kStreamTile]
+  uint8_t* fl;       // [ntile][n][kStreamTile]
+  uint32_t* anys;    // [ntile * kStreamTile]
+  int32_t* tclr;     // [ntile * kStreamTile]
+  uint8_t* done;     // [ntile * kStreamTile]: retired shots and the last tile's padding
+  uint8_t* newdone;  // [ntile * kStreamTile]
+};
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t* total) {
+  const int64_t ntile = ((int64_t)nshots + kStreamTile - 1) / kStreamTile;
+  const int64_t ns = ntile * kStreamTile;
+  const size_t msg_b = align256((size_t)ns * c.m * c.dcmax * 4);
+  const size_t s_b = align256((size_t)ns * c.m);
+  const size_t z_b = align256((size_t)ns * c.n);
+  const size_t sh4 = align256((size_t)ns * 4);
+  const size_t sh1 = align256((size_t)ns);
+  StreamWS w;
+  char* p = reinterpret_cast<char*>(ws);
+  size_t off = 0;
+  w.msg[0] = reinterpret_cast<float*>(p + off);
+  off += msg_b;
+  w.msg[1] = reinterpret_cast<float*>(p + off);
+  off += msg_b;
+  w.s = reinterpret_cast<uint8_t*>(p + off);
+  off += s_b;
+  w.z = reinterpret_cast<uint8_t*>(p + off);
+  off += z_b;
+  w.fl = reinterpret_cast<uint8_t*>(p + off);
+  off += z_b;
+  w.anys = reinterpret_cast<uint32_t*>(p + off);
+  off += sh4;
+  w.tclr = reinterpret_cast<int32_t*>(p + off);
+  off += sh4;
+  w.done = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  w.newdone = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  if (total) *total = off;
+  return w;
+}
+
+size_t stream_workspace_bytes(const DevCode& c, int32_t nshots) {
+  size_t t = 0;
+  stream_carve(c, nshots, nullptr, &t);
+  return t;
+}
+
+constexpr int kStreamRowsPerBlock = 4;  // 256 threads: one row per wavefront
+
+// Row handled by this wavefront (uniform, so table reads become scalar loads).
+__device__ __forceinline__ int32_t stream_row() {
+  return (int32_t)blockIdx.x * kStreamRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Offset of this lane's first shot in row `row` of tile `tile` of an array of rows.
+__device__ __forceinline__ int64_t stream_at(int64_t tile, int32_t rows, int64_t row, int32_t lane) {
+  return (tile * rows + row) * kStreamTile + kSV * lane;
+}
+
+__device__ __forceinline__ uint32_t ld4b(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+__device__ __forceinline__ void st4b(uint8_t* p, uint32_t v) { *reinterpret_cast<uint32_t*>(p) = v; }
+
+// Shot start: z = 0, no flip requests.
+__global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = stream_row();
+  if (v >= c.n) return;
+  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  st4b(w.z + o, 0u);
+  st4b(w.fl + o, 0u);
+}
+
+// Shot start: s = H e0 and messages 0 (shots beyond nshots get s = 0).
+__global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, const uint8_t* e0,
+                                                       int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (ch >= c.m) return;
+  const int32_t d = c.chk_deg[ch];
+  uint32_t x4 = 0;
+#pragma unroll
+  for (int q = 0; q < kSV; ++q) {
+    const int64_t i = tile * kStreamTile + kSV * lane + q;
+    if (i >= nshots) continue;
+    uint32_t x = 0;
+    for (int32_t j = 0; j < d; ++j) x ^= e0[i * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]];
+    x &= 1u;
+    x4 |= x << (8 * q);
+    if (x) w.anys[i] = 1u;
+  }
+  st4b(w.s + stream_at(tile, c.m, ch, lane), x4);
+  for (int32_t j = 0; j < c.dcmax; ++j)
+    *reinterpret_cast<float4*>(w.msg[0] + stream_at(tile, c.m * c.dcmax, (int64_t)ch * c.dcmax + j, lane)) =
+        make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// The check rule for one shot: x[j] = m_{v->c} of the check's j-th qubit
+// (j < d), out[j] = m_{c->v}.
+template <int DCT>
+__device__ __forceinline__ void stream_check_rule(const KParams& kp, const float* x, int32_t d,
+                                                  uint32_t sigma_neg, float* out) {
+  const float C = kp.clamp;
+  if (kp.bp == 0) {
+    float mn1 = __builtin_inff(), mn2 = __builtin_inff();
+    uint32_t par = sigma_neg;
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      const float av = fabsf(x[j]);
+      par ^= (x[j] < 0.0f) ? 1u : 0u;
+      mn2 = fminf(mn2, fmaxf(mn1, av));
+      mn1 = fminf(mn1, av);
+    }
+    const float m1 = clampf(kp.alpha * mn1, C);
+    const float m2 = clampf(kp.alpha * mn2, C);
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      const float mag = (fabsf(x[j]) == mn1) ? m2 : m1;
+      const uint32_t ng = par ^ ((x[j] < 0.0f) ? 1u : 0u);
+      out[j] = ng ? -mag : mag;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      float acc = __builtin_inff();
+      bool first = true;
+#pragma unroll
+      for (int i2 = 0; i2 < DCT; ++i2) {
+        if (i2 == j || i2 >= d) continue;
+        if (first) {
+          acc = x[i2] + 0.0f;
+          first = false;
+        } else {
+          acc = boxplus(acc, x[i2]);
+        }
+      }
+      out[j] = clampf(sigma_neg ? -acc : acc, C);
+    }
+  }
+}
+
+// One BP sweep: m_{c->v} (src) -> m_{c->v} (dst), one wavefront per (tile,
+// check). `fresh` marks the first sweep of every shot (m_{v->c} = 0). A tile
+// whose shots have all retired is skipped; the other tiles are swept whole,
+// since the messages of retired shots are never read again.
+template <int DCT>
+__global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
+                                                    const float* __restrict__ src,
+                                                    float* __restrict__ dst, int32_t fresh) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (ch >= c.m) return;
+  if (!__any(ld4b(w.done + tile * kStreamTile + kSV * lane) != 0x01010101u)) return;
+  const float C = kp.clamp;
+  const int32_t d = c.chk_deg[ch];
+  const int32_t pw = c.dvmax - 1;
+  const int32_t erows = c.m * c.dcmax;
+  float x[kSV][DCT];
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    float4 acc = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
+    for (int32_t p = 0; p < pw; ++p) {
+      const int32_t e = c.partner[((int64_t)ch * c.dcmax + j) * pw + p];
+      if (e < 0) break;
+      const float4 v = *reinterpret_cast<const float4*>(
+          src + stream_at(tile, erows, (int64_t)edge_check(e) * c.dcmax + edge_slot(e), lane));
+      acc.x = acc.x + v.x;
+      acc.y = acc.y + v.y;
+      acc.z = acc.z + v.z;
+      acc.w = acc.w + v.w;
+    }
+    x[0][j] = fresh ? 0.0f : clampf(acc.x, C);
+    x[1][j] = fresh ? 0.0f : clampf(acc.y, C);
+    x[2][j] = fresh ? 0.0f : clampf(acc.z, C);
+    x[3][j] = fresh ? 0.0f : clampf(acc.w, C);
+  }
+  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
+  float out[kSV][DCT];
+#pragma unroll
+  for (int q = 0; q < kSV; ++q)
+    stream_check_rule<DCT>(kp, x[q], d, ((s4 >> (8 * q)) ^ (uint32_t)d) & 1u, out[q]);
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d) continue;
+    *reinterpret_cast<float4*>(dst + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane)) =
+        make_float4(out[0][j], out[1][j], out[2][j], out[3][j]);
+  }
+}
+
+// Belief of qubit v for shot column `col` of a tile.
+__device__ __forceinline__ float stream_belief(const DevCode& c, const float* msg, int64_t tile,
+                                               int32_t col, int32_t v, float pi, float C) {
+  float acc = pi;
+  const int32_t dv = c.var_deg[v];
+  for (int32_t q = 0; q < dv; ++q) {
+    const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+    acc = acc + msg[((tile * c.m + edge_check(e)) * c.dcmax + edge_slot(e)) * kStreamTile + col];
+  }
+  return clampf(acc, C);
+}
+
+// Feedback: active checks whose Evidence holds and whose clock rang request
+// a flip of their LocalMove qubit.
+template <int DCT>
+__global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, StreamWS w,
+                                                    const float* __restrict__ msg, int32_t r,
+                                                    int32_t fresh, uint64_t shot0) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (ch >= c.m) return;
+  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
+  const uint32_t dn = ld4b(w.done + tile * kStreamTile + kSV * lane);
+  const uint32_t act = s4 & ~dn & 0x01010101u;
+  if (!act) return;
+  const int32_t d = c.chk_deg[ch];
+  if (d == 0) return;
+  const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+#pragma unroll 1
+  for (int q = 0; q < kSV; ++q) {
+    if (!((act >> (8 * q)) & 1u)) continue;
+    const int32_t col = kSV * lane + q;
+    const uint64_t shot = shot0 + (uint64_t)(tile * kStreamTile + col);
+    float Lv[DCT];
+    float Lmax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      float L;
+      if (fresh) {
+        L = kp.pi;
+        for (int32_t qq = 0; qq < c.var_deg[nb[j]]; ++qq) L = L + 0.0f;
+        L = clampf(L, kp.clamp);
+      } else {
+        L = stream_belief(c, msg, tile, col, nb[j], kp.pi, kp.clamp);
+      }
+      Lv[j] = L;
+      if (j == 0 || L > Lmax) Lmax = L;
+    }
+    if (kp.evidence && !(Lmax >= c.thr[d])) continue;  // Evidence first, then the clock
+    const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                     ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
+                                     (uint32_t)(kp.seed >> 32));
+    if (!below(rw.w0, kp.mask_bound)) continue;
+    uint32_t ntie = 0;
+#pragma unroll
+    for (int j = 0; j < DCT; ++j)
+      if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
+    uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
+    int32_t chosen = -1;
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j < d && Lv[j] == Lmax && chosen < 0) {
+        if (pick == 0)
+          chosen = nb[j];
+        else
+          --pick;
+      }
+    }
+    if (chosen >= 0) w.fl[(tile * c.n + chosen) * kStreamTile + col] = 1;
+  }
+}
+
+// s ^= H f for live shots; flags shots with s != 0.
+__global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t ch = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (ch >= c.m) return;
+  const uint32_t live = ~ld4b(w.done + tile * kStreamTile + kSV * lane) & 0x01010101u;
+  if (!live) return;
+  const int32_t d = c.chk_deg[ch];
+  uint32_t x4 = 0;
+  for (int32_t j = 0; j < d; ++j)
+    x4 ^= ld4b(w.fl + stream_at(tile, c.n, c.chk_var[(int64_t)ch * c.dcmax + j], lane));
+  const int64_t so = stream_at(tile, c.m, ch, lane);
+  const uint32_t s4 = ld4b(w.s + so) ^ (x4 & live);
+  st4b(w.s + so, s4);
+  const uint32_t hit = s4 & live;
+#pragma unroll
+  for (int q = 0; q < kSV; ++q)
+    if ((hit >> (8 * q)) & 1u) w.anys[tile * kStreamTile + kSV * lane + q] = 1u;
+}
+
+// z ^= f and clear the requests (requests exist for live shots only).
+__global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = stream_row();
+  if (v >= c.n) return;
+  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  const uint32_t f4 = ld4b(w.fl + o);
+  if (!f4) return;
+  st4b(w.z + o, ld4b(w.z + o) ^ f4);
+  st4b(w.fl + o, 0u);
+}
+
+// Per shot: t_clr at the first clear syndrome, retirement.
+__global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int32_t r,
+                                                     int32_t nshots) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nshots) return;
+  w.newdone[i] = 0;
+  if (w.done[i]) return;
+  const bool any = w.anys[i] != 0u;
+  w.anys[i] = 0u;
+  if (r < 0) w.tclr[i] = any ? -1 : 0;
+  else if (!any && w.tclr[i] < 0) w.tclr[i] = r + 1;
+  if (kp.retire && w.tclr[i] >= 0) {
+    w.done[i] = 1;
+    w.newdone[i] = 1;
+  }
+}
+
+// Every shot slot of the tiles: shots beyond nshots start retired.
+__global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots, int32_t ntot) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  w.anys[i] = 0u;
+  w.done[i] = (i >= nshots) ? 1 : 0;
+  w.newdone[i] = 0;
+  w.tclr[i] = -1;
+}
+
+// Beliefs of the current message state for shots that just retired
+// (only_new) or for every shot not retired before (!only_new).
+__global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp, StreamWS w,
+                                                          const float* __restrict__ msg,
+                                                          int32_t only_new, int32_t fresh,
+                                                          float* __restrict__ L, int32_t nshots) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t v = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (v >= c.n) return;
+#pragma unroll 1
+  for (int q = 0; q < kSV; ++q) {
+    const int32_t col = kSV * lane + q;
+    const int64_t i = tile * kStreamTile + col;
+    if (i >= nshots) continue;
+    if (only_new ? !w.newdone[i] : (w.done[i] && !w.newdone[i])) continue;
+    float val;
+    if (fresh) {
+      val = kp.pi;
+      for (int32_t qq = 0; qq < c.var_deg[v]; ++qq) val = val + 0.0f;
+      val = clampf(val, kp.clamp);
+    } else {
+      val = stream_belief(c, msg, tile, col, v, kp.pi, kp.clamp);
+    }
+    L[i * c.n + v] = val;
+  }
+}
+
+// Interleaved state -> caller's row-major outputs.
+__global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t* z, uint8_t* s,
+                                                  int32_t* tclr, int32_t nshots) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tz = (int64_t)nshots * c.n;
+  const int64_t ts = (int64_t)nshots * c.m;
+  if (idx < tz) {
+    const int64_t i = idx / c.n;
+    const int32_t v = (int32_t)(idx - i * c.n);
+    z[idx] = w.z[((i / kStreamTile) * c.n + v) * kStreamTile + (i % kStreamTile)];
+  } else if (idx < tz + ts) {
+    const int64_t k = idx - tz;
+    const int64_t i = k / c.m;
+    const int32_t ch = (int32_t)(k - i * c.m);
+    s[k] = w.s[((i / kStreamTile) * c.m + ch) * kStreamTile + (i % kStreamTile)];
+  } else if (idx < tz + ts + nshots) {
+    const int64_t i = idx - tz - ts;
+    tclr[i] = w.tclr[i];
+  }
+}
+
+typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t);
+typedef void (*MovesFn)(DevCode, KParams, StreamWS, const float*, int32_t, int32_t, uint64_t);
+
+static void stream_fns(int dcmax, SweepFn* sw, MovesFn* mv) {
+  if (dcmax <= 2) {
+    *sw = stream_sweep<2>;
+    *mv = stream_moves<2>;
+  } else if (dcmax <= 4) {
+    *sw = stream_sweep<4>;
+    *mv = stream_moves<4>;
+  } else if (dcmax <= 6) {
+    *sw = stream_sweep<6>;
+    *mv = stream_moves<6>;
+  } else if (dcmax <= 8) {
+    *sw = stream_sweep<8>;
+    *mv = stream_moves<8>;
+  } else if (dcmax <= 16) {
+    *sw = stream_sweep<16>;
+    *mv = stream_moves<16>;
+  } else {
+    *sw = stream_sweep<32>;
+    *mv = stream_moves<32>;
+  }
+}
+
+hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
+                         int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
+                         hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  SweepFn sweep_fn;
+  MovesFn moves_fn;
+  stream_fns(c.dcmax, &sweep_fn, &moves_fn);
+  StreamWS w = stream_carve(c, nshots, ws, nullptr);
+  const unsigned ntile = (unsigned)((nshots + kStreamTile - 1) / kStreamTile);
+  const int32_t ntot = (int32_t)(ntile * kStreamTile);
+  const dim3 gchk((unsigned)((c.m + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const dim3 gvar((unsigned)((c.n + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const dim3 blk(64 * kStreamRowsPerBlock);
+  const unsigned gshot = (unsigned)((nshots + 255) / 256);
+  hipLaunchKernelGGL(stream_clear_shots, dim3((unsigned)((ntot + 255) / 256)), blk, 0, st, w, nshots,
+                     ntot);
+  hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w);
+  hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, nshots);
+  hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, -1, nshots);
+  int cur = 0;
+  bool fresh = true;
+  if (L) hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1, 1, L,
+                            nshots);
+  for (int32_t r = 0; r < kp.rounds; ++r) {
+    for (int32_t it = 0; it < kp.iters; ++it) {
+      hipLaunchKernelGGL(sweep_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], w.msg[cur ^ 1],
+                         fresh ? 1 : 0);
+      cur ^= 1;
+      fresh = false;
+    }
+    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0);
+    hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w);
+    hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w);
+    hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, r, nshots);
+    if (L)
+      hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1,
+                         fresh ? 1 : 0, L, nshots);
+  }
+  if (L)
+    hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 0, fresh ? 1 : 0,
+                       L, nshots);
+  const int64_t tot = (int64_t)nshots * (c.n + c.m + 1);
+  hipLaunchKernelGGL(stream_out, dim3((unsigned)((tot + 255) / 256)), blk, 0, st, c, w, z, s, tclr,
+                     nshots);
+  return hipGetLastError();
+}
+
+}  // namespace laim
