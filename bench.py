@@ -208,16 +208,17 @@ def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
             "shots": S * steps}
 
 
-def cpu_baseline(args, spec, P_or, seconds):
+def cpu_baseline(args, spec, P_or, seconds, nthreads=None, max_shots=4096):
     """The oracle, as it is, on shot ids 0.. of the same workload, in chunks
     until `seconds` of wall time have passed."""
     from oracle import oracle as O
-    nthreads = min(16, os.cpu_count() or 1)
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
     done = 0
     rounds = 0
     t0 = time.perf_counter()
-    chunk = max(nthreads * 2, 16)
-    while time.perf_counter() - t0 < seconds and done < 4096:
+    chunk = max(nthreads * 2, 8)
+    while time.perf_counter() - t0 < seconds and done < max_shots:
         e0 = O.sample_noise(spec, args.p, 0, done, chunk)
         r = O.decode(spec, P_or, e0, shot0=done, nthreads=nthreads)
         O.logical_failure(spec, e0, r["z"])
@@ -361,6 +362,9 @@ def main():
                "msg_updates_per_s": 2 * E * args.iters * rounds / el,
                "sample": f"shot ids 0..{n_done - 1} of the same workload ({el:.1f} s wall, "
                          f"{nth} OpenMP threads over shots)"}
+        n1, el1, _, _ = cpu_baseline(args, spec, P_or, min(3.0, args.cpu_seconds), nthreads=1, max_shots=256)
+        cpu["single_thread"] = {"value": round(n1 / el1, 2), "unit": "shots/s", "cores": 1,
+                                "sample": f"shot ids 0..{n1 - 1} ({el1:.1f} s wall)"}
 
     line = {
         "metric": "shots/s and BP msg-updates/s (2D toric L=32, p=0.05); served p50/p99 latency",
