@@ -19,6 +19,8 @@
  *     flips the argmax qubit (LocalMove), then the syndrome update,
  *   - the decoding-success test (Preliminaries, conditions (1) and (2)) by an
  *     independent GF(2) rank test,
+ *   - the continuous-time machine of Algorithm 1 as stated: Euler-damped
+ *     BP and Poisson clock events (SM "Numerical details"),
  *   - for pins only: the discrete bit-centric machine of the SM ("Setup and
  *     algorithm"), in double precision.
  *
@@ -485,6 +487,260 @@ int32_t orc_decode(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* c
   free(thr);
   tanner_free(&T);
   return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * The continuous-time machine (Algorithm 1 as stated; SM "Numerical
+ * details" for its simulation): BP relaxes by tau dm/dt = F_BP(m; S) - m,
+ * integrated with Euler steps of dt, while unit-rate Poisson clocks ring at
+ * the checks. Only active checks can act, so the next ring is simulated by
+ * a waiting time ~ Exp(|S|) and a uniformly chosen active check.
+ *
+ * One Euler step (the Jacobi form: both message directions from the state
+ * before the step), lambda = (float)(dt / tau):
+ *   Fc(c,v) = check rule of the current m_{v->c} and s   (BP-LLR2),
+ *   Fv(v,c) = clamp(pi + sum over c' in N(v)\c of m_{c'->v}) (BP-LLR1),
+ *   m_{c->v} <- clamp(m_{c->v} + lambda (Fc - m_{c->v})),
+ *   m_{v->c} <- clamp(m_{v->c} + lambda (Fv - m_{v->c})).
+ *
+ * Events. Event j draws Philox(key = seed, ctr = (shot_lo, shot_hi, j, 2))
+ * = (w0, w1, w2, w3): its waiting time is -ln((w0 + 1) 2^-32) / |S| (FP64,
+ * with |S| the number of active checks after event j - 1), the ringing
+ * check is active check number floor(w1 |S| / 2^32) in ascending order, and
+ * w2 breaks LocalMove ties as in the round machine. An event at time T acts
+ * on the BP state after floor-many steps: at step k (time k dt) every event
+ * with T <= k dt is applied, in order, before the next Euler step. A ringing
+ * check with Evidence (Lmax >= -log(d_c - 1) over the beliefs of N(c))
+ * flips its LocalMove qubit: z_v ^= 1, s ^= H e_v.
+ *
+ * t_clr is the time of the event that clears the syndrome (0 if H e0 = 0).
+ * The run stops unsuccessfully after K = max_steps Euler steps (events up
+ * to time K dt are applied); then t_clr = -1.
+ * ---------------------------------------------------------------------- */
+
+/* ln(u) for 0 < u <= 1 in double: u = f 2^e with f in [sqrt(1/2), sqrt(2)),
+ * ln f = 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ... + s^24/25) with
+ * s = (f - 1) / (f + 1), |s| <= 0.1716, ln u = e ln2 + ln f. */
+double orc_ln_unit(double u) {
+  uint64_t b;
+  memcpy(&b, &u, 8);
+  int32_t e = (int32_t)((b >> 52) & 0x7ffu) - 1023;
+  uint64_t fb = (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
+  double f;
+  memcpy(&f, &fb, 8);
+  if (f > 1.4142135623730951) {
+    f = f * 0.5;
+    e = e + 1;
+  }
+  double s = (f - 1.0) / (f + 1.0);
+  double s2 = s * s;
+  double p = 1.0 / 25.0;
+  for (int32_t k = 11; k >= 0; --k) p = p * s2 + 1.0 / (double)(2 * k + 1);
+  return (double)e * 0.6931471805599453 + 2.0 * s * p;
+}
+
+typedef struct {
+  int32_t bp;
+  float alpha;
+  double q;
+  float clamp;
+  double dt;
+  double tau;
+  int32_t max_steps;  /* Euler steps before an unsuccessful stop */
+  int32_t evidence;
+  uint64_t seed;
+} orc_ctm_params;
+
+/* waiting time of event j at rate nS */
+static double ctm_wait(uint64_t seed, uint64_t shot, uint32_t j, int32_t nS, uint32_t w[4]) {
+  philox_for(seed, shot, j, 2u, w);
+  double u = ((double)w[0] + 1.0) * (1.0 / 4294967296.0);
+  return -orc_ln_unit(u) / (double)nS;
+}
+
+/* One Euler step of the damped Jacobi BP on caller arrays. */
+static void ctm_euler(const tanner* T, const orc_params* P, float pi, float lam, const uint8_t* s,
+                      float* mcv, float* mvc, float* Fc, float* Fv) {
+  for (int32_t c = 0; c < T->m; ++c) {
+    int32_t b = T->rowptr[c], dc = T->rowptr[c + 1] - b;
+    for (int32_t j = 0; j < dc; ++j) Fc[b + j] = check_rule(P, mvc + b, dc, j, s[c]);
+  }
+  for (int32_t v = 0; v < T->n; ++v) {
+    int32_t b = T->vptr[v], dv = T->vptr[v + 1] - b;
+    for (int32_t j = 0; j < dv; ++j) {
+      float acc = pi;
+      for (int32_t i = 0; i < dv; ++i)
+        if (i != j) acc = acc + mcv[T->vedge[b + i]];
+      Fv[T->vedge[b + j]] = clampf_(acc, P->clamp);
+    }
+  }
+  for (int32_t e = 0; e < T->E; ++e) {
+    mcv[e] = clampf_(mcv[e] + lam * (Fc[e] - mcv[e]), P->clamp);
+    mvc[e] = clampf_(mvc[e] + lam * (Fv[e] - mvc[e]), P->clamp);
+  }
+}
+
+static void ctm_set(const orc_ctm_params* C, orc_params* P) {
+  memset(P, 0, sizeof(*P));
+  P->bp = C->bp;
+  P->alpha = C->alpha;
+  P->q = C->q;
+  P->clamp = C->clamp;
+  P->evidence = C->evidence;
+  P->seed = C->seed;
+}
+
+/* K Euler steps from m = 0 on a fixed syndrome s (for pins); final m_{c->v}
+ * and m_{v->c} in edge order. */
+int32_t orc_ctm_bp_steps(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                         const orc_ctm_params* C, const uint8_t* s, int32_t K, float* mcv_out,
+                         float* mvc_out) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  orc_params P;
+  ctm_set(C, &P);
+  const float pi = (float)log(C->q / (1.0 - C->q));
+  const float lam = (float)(C->dt / C->tau);
+  size_t E = (size_t)(T.E > 0 ? T.E : 1);
+  float* Fc = (float*)malloc(sizeof(float) * E);
+  float* Fv = (float*)malloc(sizeof(float) * E);
+  for (int32_t e = 0; e < T.E; ++e) mcv_out[e] = mvc_out[e] = 0.0f;
+  for (int32_t k = 0; k < K; ++k) ctm_euler(&T, &P, pi, lam, s, mcv_out, mvc_out, Fc, Fv);
+  free(Fc);
+  free(Fv);
+  tanner_free(&T);
+  return 0;
+}
+
+/* Per shot. trace (one shot only, may be NULL): per event j, 4 doubles:
+ * time, |S| before it, the ringing check, the flipped qubit (-1 if none). */
+static int32_t ctm_one(const tanner* T, const orc_ctm_params* C, const orc_params* P,
+                       const float* thr, float pi, float lam, const uint8_t* e0, uint64_t shot,
+                       uint8_t* z, uint8_t* s, double* tclr, int32_t* counts, double* trace,
+                       int32_t trace_cap) {
+  const int32_t m = T->m, n = T->n;
+  const size_t E = (size_t)(T->E > 0 ? T->E : 1);
+  float* mcv = (float*)calloc(E, sizeof(float));
+  float* mvc = (float*)calloc(E, sizeof(float));
+  float* Fc = (float*)malloc(sizeof(float) * E);
+  float* Fv = (float*)malloc(sizeof(float) * E);
+  float Lv[64];
+  if (!mcv || !mvc || !Fc || !Fv) {
+    free(mcv); free(mvc); free(Fc); free(Fv);
+    return -2;
+  }
+  for (int32_t v = 0; v < n; ++v) z[v] = 0;
+  orc_syndrome(m, n, T->rowptr, T->col, e0, 1, s);
+  int32_t nS = 0;
+  for (int32_t c = 0; c < m; ++c) nS += s[c];
+  int32_t events = 0, moves = 0;
+  uint32_t j = 0;
+  *tclr = (nS == 0) ? 0.0 : -1.0;
+  double Tev = 0.0;
+  uint32_t w[4];
+  if (nS > 0) Tev = ctm_wait(C->seed, shot, j, nS, w);
+  for (int32_t k = 0; nS > 0; ++k) {
+    const double tk = (double)k * C->dt;
+    while (nS > 0 && Tev <= tk) {
+      philox_for(C->seed, shot, j, 2u, w);
+      uint32_t idx = (uint32_t)(((uint64_t)w[1] * (uint64_t)nS) >> 32);
+      int32_t c = 0;
+      for (; c < m; ++c)
+        if (s[c]) {
+          if (idx == 0) break;
+          idx--;
+        }
+      int32_t b = T->rowptr[c], dc = T->rowptr[c + 1] - b;
+      int32_t flipped = -1;
+      if (dc > 0 && dc <= 64) {
+        float Lmax = 0.0f;
+        for (int32_t jj = 0; jj < dc; ++jj) {
+          int32_t v = T->col[b + jj];
+          float acc = pi;
+          for (int32_t i = T->vptr[v]; i < T->vptr[v + 1]; ++i) acc = acc + mcv[T->vedge[i]];
+          Lv[jj] = clampf_(acc, C->clamp);
+          if (jj == 0 || Lv[jj] > Lmax) Lmax = Lv[jj];
+        }
+        if (!C->evidence || Lmax >= thr[dc]) {
+          uint32_t ntie = 0;
+          for (int32_t jj = 0; jj < dc; ++jj) ntie += (Lv[jj] == Lmax) ? 1u : 0u;
+          uint32_t pick = (uint32_t)(((uint64_t)w[2] * (uint64_t)ntie) >> 32);
+          for (int32_t jj = 0; jj < dc; ++jj)
+            if (Lv[jj] == Lmax) {
+              if (pick == 0) {
+                flipped = T->col[b + jj];
+                break;
+              }
+              pick--;
+            }
+        }
+      }
+      if (trace && events < trace_cap) {
+        trace[4 * events + 0] = Tev;
+        trace[4 * events + 1] = (double)nS;
+        trace[4 * events + 2] = (double)c;
+        trace[4 * events + 3] = (double)flipped;
+      }
+      if (flipped >= 0) {
+        z[flipped] ^= 1u;
+        for (int32_t i = T->vptr[flipped]; i < T->vptr[flipped + 1]; ++i) {
+          int32_t c2 = 0;
+          /* the check of edge vedge[i] */
+          int32_t e = T->vedge[i];
+          while (T->rowptr[c2 + 1] <= e) c2++;
+          s[c2] ^= 1u;
+          nS += s[c2] ? 1 : -1;
+        }
+        moves++;
+      }
+      events++;
+      j++;
+      if (nS == 0) {
+        *tclr = Tev;
+        break;
+      }
+      Tev = Tev + ctm_wait(C->seed, shot, j, nS, w);
+    }
+    if (nS == 0 || k >= C->max_steps) break;
+    ctm_euler(T, P, pi, lam, s, mcv, mvc, Fc, Fv);
+  }
+  counts[0] = events;
+  counts[1] = moves;
+  free(mcv); free(mvc); free(Fc); free(Fv);
+  return 0;
+}
+
+int32_t orc_ctm_decode(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                       const orc_ctm_params* C, const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                       uint8_t* z_out, uint8_t* s_out, double* tclr_out, int32_t* counts_out,
+                       double* trace, int32_t trace_cap, int32_t nthreads) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  int32_t dmax = 0;
+  for (int32_t c = 0; c < m; ++c)
+    if (rowptr[c + 1] - rowptr[c] > dmax) dmax = rowptr[c + 1] - rowptr[c];
+  float* thr = (float*)malloc(sizeof(float) * (size_t)(dmax + 1));
+  orc_evidence_thresholds(dmax, thr);
+  orc_params P;
+  ctm_set(C, &P);
+  const float pi = (float)log(C->q / (1.0 - C->q));
+  const float lam = (float)(C->dt / C->tau);
+  int32_t rc = 0;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(min : rc)
+  for (int32_t i = 0; i < nshots; ++i) {
+    int32_t r1 = ctm_one(&T, C, &P, thr, pi, lam, e0 + (size_t)i * n, shot0 + (uint64_t)i,
+                         z_out + (size_t)i * n, s_out + (size_t)i * m, tclr_out + i,
+                         counts_out + 2 * (size_t)i, (nshots == 1) ? trace : NULL, trace_cap);
+    if (r1 < rc) rc = r1;
+  }
+  free(thr);
+  tanner_free(&T);
+  return rc;
+}
+
+void orc_vec_ln_unit(const double* x, int32_t k, double* y) {
+  for (int32_t i = 0; i < k; ++i) y[i] = orc_ln_unit(x[i]);
 }
 
 /* ------------------------------------------------------------------------

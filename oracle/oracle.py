@@ -66,6 +66,35 @@ class DecodeParams:
                       int(self.evidence), int(self.retire), self.seed)
 
 
+class CtmParams(C.Structure):
+    _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
+                ("dt", C.c_double), ("tau", C.c_double), ("max_steps", C.c_int32),
+                ("evidence", C.c_int32), ("seed", C.c_uint64)]
+
+
+@dataclass
+class ContinuousParams:
+    """Continuous-time machine knobs (defaults: Table S1, 2D toric code row)."""
+
+    bp: str = "minsum"
+    alpha: float = 0.75
+    q: float = 0.05
+    clamp: float = 1000.0
+    dt: float = 0.001
+    tau: float = 0.1
+    t_max: float = 100.0  # clock units; the run stops unsuccessfully after t_max / dt steps
+    evidence: bool = True
+    seed: int = 0
+
+    @property
+    def max_steps(self) -> int:
+        return int(round(self.t_max / self.dt))
+
+    def c(self) -> CtmParams:
+        return CtmParams(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
+                         self.dt, self.tau, self.max_steps, int(self.evidence), self.seed)
+
+
 def _p(a, t):
     return a.ctypes.data_as(C.POINTER(t))
 
@@ -106,6 +135,17 @@ def lib():
         L.orc_gf2_rank.restype = C.c_int32
         L.orc_gf2_rank.argtypes = [C.c_int32, C.c_int32, i32p, i32p]
         L.orc_evidence_thresholds.argtypes = [C.c_int32, f32p]
+        f64p = C.POINTER(C.c_double)
+        L.orc_ln_unit.restype = C.c_double
+        L.orc_ln_unit.argtypes = [C.c_double]
+        L.orc_vec_ln_unit.argtypes = [f64p, C.c_int32, f64p]
+        L.orc_ctm_bp_steps.restype = C.c_int32
+        L.orc_ctm_bp_steps.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(CtmParams), u8p,
+                                       C.c_int32, f32p, f32p]
+        L.orc_ctm_decode.restype = C.c_int32
+        L.orc_ctm_decode.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(CtmParams), u8p,
+                                     C.c_uint64, C.c_int32, u8p, u8p, f64p, i32p, f64p, C.c_int32,
+                                     C.c_int32]
         L.orc_bitcentric_machine.restype = C.c_int32
         L.orc_bitcentric_machine.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_double, u8p,
                                              C.c_int32, u8p, C.POINTER(C.c_double), i32p]
@@ -259,3 +299,57 @@ def bitcentric_machine(code, q: float, e0, iters: int):
                                       Lt.ctypes.data_as(C.POINTER(C.c_double)), _p(ic, C.c_int32))
     assert rc == 0
     return et, Lt, int(ic[0])
+
+
+# ---------------------------------------------------------------- continuous-time machine
+def ln_unit(x) -> np.ndarray:
+    """The oracle's FP64 natural logarithm on (0, 1]."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y = np.zeros_like(x)
+    lib().orc_vec_ln_unit(x.ctypes.data_as(C.POINTER(C.c_double)), x.size,
+                          y.ctypes.data_as(C.POINTER(C.c_double)))
+    return y
+
+
+def ctm_bp_steps(code, params: ContinuousParams, s, K: int):
+    """K Euler steps of the damped Jacobi BP from m = 0 on the fixed syndrome
+    s. Returns (m_cv, m_vc) in edge order."""
+    rp, cl = _csr(code.H)
+    E = code.H.nnz
+    s = np.ascontiguousarray(s, dtype=np.uint8).ravel()
+    mcv = np.zeros(E, dtype=np.float32)
+    mvc = np.zeros(E, dtype=np.float32)
+    P = params.c()
+    rc = lib().orc_ctm_bp_steps(code.H.rows, code.H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32),
+                                C.byref(P), _p(s, C.c_uint8), K, _p(mcv, C.c_float), _p(mvc, C.c_float))
+    assert rc == 0
+    return mcv, mvc
+
+
+def ctm_decode(code, params: ContinuousParams, e0, shot0: int = 0, nthreads: int = 1,
+               trace_cap: int = 0) -> dict:
+    """Run the continuous-time machine on every row of e0. With one shot and
+    trace_cap > 0 the first trace_cap events are returned as rows
+    (time, |S| before, ringing check, flipped qubit or -1)."""
+    e0 = np.ascontiguousarray(np.atleast_2d(e0), dtype=np.uint8)
+    ns, n = e0.shape
+    m = code.H.rows
+    rp, cl = _csr(code.H)
+    z = np.zeros((ns, n), dtype=np.uint8)
+    s = np.zeros((ns, m), dtype=np.uint8)
+    t = np.zeros(ns, dtype=np.float64)
+    cnt = np.zeros((ns, 2), dtype=np.int32)
+    tr = np.zeros((max(trace_cap, 1), 4), dtype=np.float64)
+    P = params.c()
+    f64p = C.POINTER(C.c_double)
+    rc = lib().orc_ctm_decode(m, n, _p(rp, C.c_int32), _p(cl, C.c_int32), C.byref(P),
+                              _p(e0, C.c_uint8), shot0, ns, _p(z, C.c_uint8), _p(s, C.c_uint8),
+                              t.ctypes.data_as(f64p), _p(cnt, C.c_int32),
+                              tr.ctypes.data_as(f64p) if trace_cap > 0 else None, trace_cap, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"oracle ctm_decode failed with status {rc}")
+    out = {"z": z, "s": s, "tclr": t, "events": cnt[:, 0].copy(), "moves": cnt[:, 1].copy()}
+    if trace_cap > 0:
+        k = min(int(cnt[0, 0]), trace_cap)
+        out["trace"] = tr[:k].copy()
+    return out
