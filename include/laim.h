@@ -209,6 +209,63 @@ laim_status laim_get_resident_cfg(const laim_code* code, int32_t bp, laim_reside
 laim_status laim_logical_failure(const laim_code* code, const uint8_t* e0, const uint8_t* z,
                                  int32_t nshots, uint8_t* fail_out, laim_stream stream);
 
+/* ------------------------------------------------- continuous-time machine
+ * Algorithm 1 as stated: BP relaxes by tau dm/dt = F_BP(m; S) - m while
+ * unit-rate Poisson clocks ring at the checks (SM numerical details: Euler
+ * steps of dt, waiting times ~ Exp(|S|), Table S1's dt, tau, t_max).
+ * One Euler step updates both message directions from the state before it
+ * (Jacobi form): m <- clamp(m + lambda (F - m)) with lambda = (float)(dt / tau),
+ * F_{c->v} by BP-LLR2 and F_{v->c} = clamp(pi + sum over N(v)\c of m_{c'->v})
+ * by BP-LLR1; all messages start at 0.
+ * Events: event j draws Philox(key = seed, counter = (shot_lo, shot_hi, j, 2))
+ * = (w0, w1, w2, w3). Its time is the previous event's (0 for j = 0) plus
+ * -ln((w0 + 1) 2^-32) / |S| in double precision (|S| = active checks after
+ * the previous event); the ringing check is active check number
+ * floor(w1 |S| / 2^32) in ascending order; if its Evidence holds (as in the
+ * round machine) it flips its LocalMove qubit, ties broken by w2. An event
+ * at time T acts on the BP state after floor(T / dt) Euler steps; events due
+ * at the same step act in order.
+ */
+typedef struct {
+  int32_t bp;       /* 0: normalised min-sum, 1: sum-product (as laim_decode_params) */
+  float alpha;      /* min-sum scale, > 0 */
+  double q;         /* decoder prior in (0, 1) */
+  float clamp;      /* CLAMP > 0 */
+  double dt;        /* Euler step in clock units, > 0 (Table S1: 0.001 or 0.01) */
+  double tau;       /* relaxation time, > 0 (Table S1: 0.1) */
+  double t_max;     /* a shot not clear by t_max fails; the run makes floor(t_max / dt + 1/2)
+                       Euler steps at most (t_max / dt <= 2^31 - 1) */
+  int32_t evidence; /* 1: apply the Evidence test */
+  uint64_t seed;    /* Philox key for the clocks and tie-breaks */
+} laim_continuous_params;
+
+/* Workspace of laim_decode_continuous (the shot queue), in bytes. */
+#define LAIM_CONTINUOUS_WORKSPACE_BYTES 256
+
+/* laim_decode_continuous -- the continuous-time machine on nshots shots
+ * (ids shot0 + i), one resident block per shot at a time.
+ *   e0         device [nshots][n] uint8: the initial errors (bit 0 read)
+ *   workspace  device, >= LAIM_CONTINUOUS_WORKSPACE_BYTES, 256-byte aligned
+ *   z_out      device [nshots][n] uint8: cumulative correction z
+ *   s_out      device [nshots][m] uint8: final syndrome H (e0 ^ z)
+ *   tclr_out   device [nshots] double: time of the event that cleared the
+ *              syndrome (0 if H e0 = 0), or -1 if it did not clear by t_max
+ *   counts_out device [nshots][2] int32 or NULL: events (clock rings of
+ *              active checks) and moves (flips) of each shot
+ *   fail_out   device [nshots] uint8 or NULL: logical failure, as
+ *              laim_logical_failure
+ *   checks_per_thread  0 to choose, else 1, 2, 4 or 8 (a launch shape;
+ *              results do not depend on it)
+ * Errors: LAIM_EINVAL for bad arguments, LAIM_EUNSUP for codes with check
+ * degree > 8 or qubit degree > 4 or too large for LDS, LAIM_ENOMEM for a
+ * short workspace; nothing is written then.
+ */
+laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_params* params,
+                                   const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                                   void* workspace, size_t ws_bytes, uint8_t* z_out, uint8_t* s_out,
+                                   double* tclr_out, int32_t* counts_out, uint8_t* fail_out,
+                                   int32_t checks_per_thread, laim_stream stream);
+
 /* ----------------------------------------------------------- batched form
  * One persistent launch over shots of several codes and sizes (each item a
  * contiguous range of shot ids of one code with its own parameters and

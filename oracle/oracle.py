@@ -11,6 +11,7 @@ over shots) into ``oracle/liblaim_oracle.so``.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -88,7 +89,7 @@ class ContinuousParams:
 
     @property
     def max_steps(self) -> int:
-        return int(round(self.t_max / self.dt))
+        return int(math.floor(self.t_max / self.dt + 0.5))
 
     def c(self) -> CtmParams:
         return CtmParams(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,

@@ -634,6 +634,60 @@ laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_para
                        L_out, LAIM_FORM_RESIDENT, cfg, stream);
 }
 
+laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_params* params,
+                                   const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                                   void* workspace, size_t ws_bytes, uint8_t* z_out, uint8_t* s_out,
+                                   double* tclr_out, int32_t* counts_out, uint8_t* fail_out,
+                                   int32_t checks_per_thread, laim_stream stream) {
+  if (!code || !params || nshots < 0 || (nshots > 0 && (!e0 || !z_out || !s_out || !tclr_out))) {
+    set_error("laim_decode_continuous: bad arguments");
+    return LAIM_EINVAL;
+  }
+  const laim_continuous_params& p = *params;
+  if (p.bp != 0 && p.bp != 1) {
+    set_error("bp must be 0 (min-sum) or 1 (sum-product)");
+    return LAIM_EINVAL;
+  }
+  if (!(p.q > 0.0 && p.q < 1.0) || !(p.clamp > 0.0f) || !(p.alpha > 0.0f)) {
+    set_error("q must lie in (0, 1); clamp and alpha must be positive");
+    return LAIM_EINVAL;
+  }
+  if (!(p.dt > 0.0) || !(p.tau > 0.0) || !(p.t_max >= 0.0) || !(p.t_max / p.dt <= 2147483647.0)) {
+    set_error("dt and tau must be positive and 0 <= t_max / dt <= 2^31 - 1");
+    return LAIM_EINVAL;
+  }
+  if (checks_per_thread != 0 && checks_per_thread != 1 && checks_per_thread != 2 &&
+      checks_per_thread != 4 && checks_per_thread != 8) {
+    set_error("checks_per_thread must be 0, 1, 2, 4 or 8");
+    return LAIM_EINVAL;
+  }
+  if (nshots == 0) return LAIM_OK;
+  if (!workspace || ws_bytes < LAIM_CONTINUOUS_WORKSPACE_BYTES || ((uintptr_t)workspace) % 256) {
+    set_error("a 256-byte aligned workspace of %d bytes is needed", LAIM_CONTINUOUS_WORKSPACE_BYTES);
+    return LAIM_ENOMEM;
+  }
+  if (fail_out && code->dev.kw > 64) {
+    set_error("more than 2048 logicals are not supported");
+    return LAIM_EUNSUP;
+  }
+  CtmShape sh;
+  if (!ctm_shape(code->dev, p.bp, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
+  CtmParamsDev P;
+  P.bp = p.bp;
+  P.alpha = p.alpha;
+  P.pi = (float)log(p.q / (1.0 - p.q));
+  P.clamp = p.clamp;
+  P.lam = (float)(p.dt / p.tau);
+  P.dt = p.dt;
+  P.max_steps = (int32_t)floor(p.t_max / p.dt + 0.5);
+  P.evidence = p.evidence ? 1 : 0;
+  P.seed = p.seed;
+  DeviceGuard g(code->device);
+  hipError_t er = launch_ctm(code->dev, P, sh, e0, shot0, nshots, workspace, z_out, s_out, tclr_out,
+                             counts_out, fail_out, (hipStream_t)stream);
+  return er == hipSuccess ? LAIM_OK : hip_fail(er, "continuous-machine kernel");
+}
+
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg) {
   if (!code || (bp != 0 && bp != 1)) {
     set_error("laim_set_resident_cfg: bad arguments");

@@ -146,6 +146,44 @@ hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev*
                          int32_t nunits, const ServerReqDev* reqs, size_t lds, int block,
                          hipStream_t st);
 
+// ---- continuous-time machine (laim_ctm.hip)
+struct CtmParamsDev {
+  int32_t bp;
+  float alpha;
+  float pi;
+  float clamp;
+  float lam;  // (float)(dt / tau)
+  double dt;
+  int32_t max_steps;
+  int32_t evidence;
+  uint64_t seed;
+};
+
+struct CtmShape {
+  int32_t nt;    // threads per shot (one shot per block)
+  int32_t cpt;   // checks per thread
+  int32_t mpad;  // nt * cpt rounded up to a multiple of 64
+  size_t lds;    // dynamic LDS bytes per block
+};
+
+struct CtmArgs {
+  const uint8_t* e0;
+  uint64_t shot0;
+  int32_t nshots;
+  uint32_t* counter;  // shot queue head
+  uint8_t* z;
+  uint8_t* s;
+  double* tclr;
+  int32_t* counts;  // [nshots][2]: events, moves (or null)
+  uint8_t* fail;    // or null
+  int32_t nt, mpad;
+};
+
+bool ctm_shape(const DevCode& c, int bp, int32_t cpt_want, int device, CtmShape* out);
+hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& sh, const uint8_t* e0,
+                      uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
+                      int32_t* counts, uint8_t* fail, hipStream_t st);
+
 }  // namespace laim
 
 // The code object behind the opaque ABI handle.

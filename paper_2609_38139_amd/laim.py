@@ -29,7 +29,7 @@ SYMBOLS = [
     "laim_decode_rounds_cfg", "laim_set_resident_cfg", "laim_get_resident_cfg",
     "laim_logical_failure", "laim_batch_plan_create", "laim_batch_plan_launch",
     "laim_batch_plan_destroy", "laim_server_create", "laim_server_submit", "laim_server_step",
-    "laim_server_result", "laim_server_stats", "laim_server_destroy",
+    "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
 ]
 
 
@@ -88,6 +88,36 @@ class DecodeParams:
                       int(self.evidence), int(self.retire), self.seed)
 
 
+class ContinuousParamsC(C.Structure):
+    _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
+                ("dt", C.c_double), ("tau", C.c_double), ("t_max", C.c_double),
+                ("evidence", C.c_int32), ("seed", C.c_uint64)]
+
+
+@dataclass
+class ContinuousParams:
+    """Knobs of the continuous-time machine (defaults: Table S1, 2D toric code
+    row: dt = 0.001, tau = 0.1, q = 0.05, CLAMP = 1000)."""
+
+    bp: str = "minsum"
+    alpha: float = 0.75
+    q: float = 0.05
+    clamp: float = 1000.0
+    dt: float = 0.001
+    tau: float = 0.1
+    t_max: float = 100.0
+    evidence: bool = True
+    seed: int = 0
+
+    def c(self) -> ContinuousParamsC:
+        if self.bp not in ("minsum", "sumproduct"):
+            raise ValueError("bp must be 'minsum' or 'sumproduct'")
+        return ContinuousParamsC(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
+                                 self.dt, self.tau, self.t_max, int(self.evidence), self.seed)
+
+
+CONTINUOUS_WORKSPACE_BYTES = 256
+
 _lib = None
 
 
@@ -132,6 +162,8 @@ def lib():
         L.laim_server_result.argtypes = [vp, u64, vp, vp, i32p]
         L.laim_server_stats.argtypes = [vp, i32p, i32p, C.POINTER(sz)]
         L.laim_server_destroy.argtypes = [vp]
+        L.laim_decode_continuous.argtypes = [vp, C.POINTER(ContinuousParamsC), vp, u64, i32, vp, sz,
+                                             vp, vp, vp, vp, vp, i32, vp]
         L.laim_server_destroy.restype = None
         _lib = L
     return _lib
@@ -288,6 +320,31 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
                                           _stream(stream))
     check(st, "laim_decode_rounds")
     out["workspace"] = workspace
+    return out
+
+
+def decode_continuous(code: Code, params: ContinuousParams, e0, shot0: int = 0,
+                      checks_per_thread: int = 0, want_fail: bool = False, workspace=None,
+                      stream=None) -> dict:
+    """``laim_decode_continuous``: returns device tensors z, s, tclr (float64),
+    counts ([nshots, 2] int32: events, moves) and, with want_fail, fail."""
+    import torch
+    ns = e0.shape[0]
+    _dev(e0, torch.uint8, (ns, code.n), "e0")
+    dev = e0.device
+    out = {"z": torch.empty((ns, code.n), dtype=torch.uint8, device=dev),
+           "s": torch.empty((ns, code.m), dtype=torch.uint8, device=dev),
+           "tclr": torch.empty((ns,), dtype=torch.float64, device=dev),
+           "counts": torch.empty((ns, 2), dtype=torch.int32, device=dev),
+           "fail": torch.empty((ns,), dtype=torch.uint8, device=dev) if want_fail else None}
+    if workspace is None:
+        workspace = torch.empty((CONTINUOUS_WORKSPACE_BYTES,), dtype=torch.uint8, device=dev)
+    P = params.c()
+    check(lib().laim_decode_continuous(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
+                                       workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
+                                       _ptr(out["tclr"]), _ptr(out["counts"]), _ptr(out["fail"]),
+                                       checks_per_thread, _stream(stream)),
+          "laim_decode_continuous")
     return out
 
 
