@@ -136,6 +136,65 @@ def batch_vs_plain(laim, codes):
             "identical_failures": fails_b == fails_p}
 
 
+def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
+    """The continuous-time machine (Algorithm 1 as stated) on the same code:
+    Table S1's dt = 0.001 and tau = 0.1, a shot failing if not clear by
+    t_max. Reports shots/s, Euler shot-steps/s and the VALU roofline of the
+    kernel. Work per check and Euler step: the check update of the round
+    machine (23 operations for a degree-4 check, gather included) plus, for
+    each of the 2 d_c messages, the Euler update (subtract, multiply, add)
+    and its clamp: 23 + 8 d_c = 55."""
+    import math
+
+    import torch
+
+    from paper_2609_38139_amd import codes
+    spec = codes.toric_2d(L)
+    code = laim.Code(spec, 0)
+    dt = 0.001
+    P = laim.ContinuousParams(bp=bp, dt=dt, tau=0.1, t_max=t_max)
+    e0 = laim.sample_noise(code, p, 0, 7 * 10**9, nshots)
+    ws = torch.empty((laim.CONTINUOUS_WORKSPACE_BYTES,), dtype=torch.uint8, device="cuda")
+    laim.decode_continuous(code, P, e0, shot0=7 * 10**9, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps):
+        ev0.record(st)
+        out = laim.decode_continuous(code, P, e0, shot0=7 * 10**9, want_fail=True, workspace=ws)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        ms.append(ev0.elapsed_time(ev1))
+    sec = min(ms) / 1000.0
+    tclr = out["tclr"].cpu().numpy()
+    K = int(math.floor(t_max / dt + 0.5))
+    # Euler steps run by each shot: up to the step whose time first reaches the
+    # clearing event, or all K
+    steps = 0
+    for T in tclr:
+        if T < 0:
+            steps += K
+        else:
+            k = max(0, math.ceil(T / dt) - 1)
+            while k * dt < T:
+                k += 1
+            steps += min(k, K)
+    m = code.m
+    ops_check = 23 + 8 * code.dc_max if bp == "minsum" else None
+    res = {"workload": f"2D toric L={L}, p={p}, {bp}, dt={dt}, tau=0.1, t_max={t_max}, {nshots} shots",
+           "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
+           "euler_shot_steps_per_s": steps / sec, "msg_updates_per_s": 2 * code.E * steps / sec,
+           "cleared": int((tclr >= 0).sum()), "logical_error_rate": float(out["fail"].float().mean().item()),
+           "mean_tclr_cleared": float(tclr[tclr >= 0].mean()) if (tclr >= 0).any() else None}
+    if ops_check is not None:
+        ach = steps * m * ops_check / sec / 1e12
+        res["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 1),
+                           "unit": "Tops/s", "frac": round(ach / VALU_PEAK_TOPS, 4),
+                           "ops_per_check_step": ops_check}
+    return res
+
+
 def serving(laim, seconds):
     """Continuous batching of single-shot requests over the mixed workload:
     2D toric L=16/32/48, 3D toric L=12, bivariate-bicycle [[144,12,12]], each
@@ -353,6 +412,10 @@ def main():
         extras["batched_vs_plain"] = batch_vs_plain(laim, codes)
     if not args.no_serve:
         extras["serving"] = serving(laim, args.serve_seconds)
+    if not args.no_extras:
+        extras["continuous_machine"] = {
+            "minsum": continuous_machine(laim, L, args.p, "minsum", 4096, 30.0),
+            "sumproduct": continuous_machine(laim, L, args.p, "sumproduct", 2048, 30.0)}
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O

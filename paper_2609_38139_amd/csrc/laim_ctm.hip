@@ -77,6 +77,18 @@ __device__ __forceinline__ Philox4 ctm_words(const CtmParamsDev& P, uint64_t sho
                        (uint32_t)(P.seed >> 32));
 }
 
+// The Euler step at which an event at time T acts: the least k >= 0 with
+// T <= k dt (k dt evaluated in double as in the step loop), or
+// max_steps + 1 if it would come after the last step.
+__device__ int32_t ctm_step_of(double T, double dt, int32_t max_steps) {
+  if (!(T <= (double)max_steps * dt)) return max_steps + 1;
+  double q = ceil(T / dt);
+  int32_t k = (q < 0.0) ? 0 : (int32_t)q;
+  while (k > 0 && (double)(k - 1) * dt >= T) --k;
+  while ((double)k * dt < T) ++k;
+  return k;
+}
+
 __device__ __forceinline__ double ctm_wait(uint32_t w0, int32_t nS) {
   const double u = ((double)w0 + 1.0) * (1.0 / 4294967296.0);
   return -ctm_ln_unit(u) / (double)nS;
@@ -118,7 +130,12 @@ __device__ __forceinline__ void ctm_check_rule(const CtmParamsDev& P, const floa
     }
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
-      const float v = __builtin_amdgcn_fmed3f(alpha_s * ex[j], -C, C);
+      // The regular-code kernels run with alpha <= 1 only (others use the
+      // padded variant): every input is clamped, so alpha min |m| <= C and
+      // the output clamp cannot bind. The padded variant clamps (a
+      // degree-1 check's minimum is empty, and alpha may exceed 1).
+      float v = alpha_s * ex[j];
+      if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
       out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[j]) & 0x80000000u));
     }
   } else {
@@ -329,14 +346,15 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
     __syncthreads();
     if (t == 0) *reinterpret_cast<double*>(gw + kCwTev) = Tev;
 
+    int32_t kev = (nS > 0) ? ctm_step_of(Tev, P.dt, P.max_steps) : 0;
     for (int32_t k = 0;; ++k) {
-      const double tk = (double)k * P.dt;
-      if (nS > 0 && Tev <= tk) {
-        if (t == 0) ctm_events<DC, REG>(c, P, shot, tk, msg, gw, zw, sw);
+      if (nS > 0 && k >= kev) {
+        if (t == 0) ctm_events<DC, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw);
         __syncthreads();
         nS = gw[kCwNs];
         Tev = *reinterpret_cast<const double*>(gw + kCwTev);
         if (nS == 0) tclr = *reinterpret_cast<const double*>(gw + kCwClear);
+        else kev = ctm_step_of(Tev, P.dt, P.max_steps);
         if (gw[kCwMoved]) {
           uint32_t nsb = 0;
 #pragma unroll
@@ -441,9 +459,11 @@ const CtmVariant kCtmVariants[] = {
     LAIM_CTM_IRR(8, 4, 1), LAIM_CTM_IRR(8, 4, 2), LAIM_CTM_IRR(8, 4, 4),
 };
 
-bool ctm_degrees(const DevCode& c, int* dc, int* dv, int* reg) {
+// Template degrees: exact ones for regular codes, else (and for min-sum
+// with alpha > 1, whose outputs need the clamp) the padded (8, 4) variant.
+bool ctm_degrees(const DevCode& c, bool allow_reg, int* dc, int* dv, int* reg) {
   static const int exact[][2] = {{2, 2}, {4, 2}, {6, 2}, {4, 4}, {6, 3}};
-  if (c.regular)
+  if (c.regular && allow_reg)
     for (auto& e : exact)
       if (e[0] == c.dcmax && e[1] == c.dvmax) {
         *dc = e[0];
@@ -468,9 +488,9 @@ const CtmVariant* ctm_find(int dc, int dv, int cpt, int bp, int reg) {
 
 }  // namespace
 
-bool ctm_shape(const DevCode& c, int bp, int32_t cpt_want, int device, CtmShape* out) {
+bool ctm_shape(const DevCode& c, int bp, float alpha, int32_t cpt_want, int device, CtmShape* out) {
   int dc, dv, reg;
-  if (!ctm_degrees(c, &dc, &dv, &reg)) {
+  if (!ctm_degrees(c, !(bp == 0 && alpha > 1.0f), &dc, &dv, &reg)) {
     set_error("the continuous machine needs check degree <= 8 and qubit degree <= 4 (have %d, %d)",
               c.dcmax, c.dvmax);
     return false;
@@ -516,7 +536,7 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
                       int32_t* counts, uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   int dc, dv, reg;
-  if (!ctm_degrees(c, &dc, &dv, &reg)) return hipErrorInvalidValue;
+  if (!ctm_degrees(c, !(P.bp == 0 && P.alpha > 1.0f), &dc, &dv, &reg)) return hipErrorInvalidValue;
   const CtmVariant* var = ctm_find(dc, dv, sh.cpt, P.bp, reg);
   if (!var) return hipErrorInvalidValue;
   CtmArgs a;

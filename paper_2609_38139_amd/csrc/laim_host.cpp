@@ -671,7 +671,7 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
     return LAIM_EUNSUP;
   }
   CtmShape sh;
-  if (!ctm_shape(code->dev, p.bp, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
+  if (!ctm_shape(code->dev, p.bp, p.alpha, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
   CtmParamsDev P;
   P.bp = p.bp;
   P.alpha = p.alpha;

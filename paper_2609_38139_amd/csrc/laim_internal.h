@@ -179,7 +179,7 @@ struct CtmArgs {
   int32_t nt, mpad;
 };
 
-bool ctm_shape(const DevCode& c, int bp, int32_t cpt_want, int device, CtmShape* out);
+bool ctm_shape(const DevCode& c, int bp, float alpha, int32_t cpt_want, int device, CtmShape* out);
 hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& sh, const uint8_t* e0,
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
                       int32_t* counts, uint8_t* fail, hipStream_t st);

@@ -107,6 +107,12 @@ def test_launch_shapes_agree(L, orc, cpt):
              tag="shape")
 
 
+def test_min_sum_scale_above_one(L, orc):
+    """alpha > 1 lets check outputs reach the clamp; such runs use the padded
+    kernel variant, which clamps them."""
+    run_both(L, orc, "toric2d:6", 0.06, 96, bp="minsum", alpha=1.25, dt=0.01, t_max=15.0, tag="alpha")
+
+
 def test_evidence_off_and_other_seed(L, orc):
     run_both(L, orc, "toric2d:6", 0.08, 96, evidence=False, seed=99, dt=0.01, t_max=10.0, tag="ablation")
 
