@@ -195,6 +195,33 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
     return res
 
 
+def bitcentric(laim, d=101, p=0.3, nshots=262144, q=0.1):
+    """The bit-centric machine on the periodic repetition code (SM "Setup and
+    algorithm"), d iterations: shots/s, and its logical error rate beside the
+    binomial tail P(|E| > d/2) it must equal."""
+    import torch
+    from scipy.stats import binom
+
+    from paper_2609_38139_amd import codes
+    code = laim.Code(codes.repetition(d, periodic=True), 0)
+    e0 = laim.sample_noise(code, p, 5, 0, nshots)
+    laim.decode_bitcentric(code, q, e0, d)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(st)
+    out = laim.decode_bitcentric(code, q, e0, d)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1000.0
+    fail = (e0 ^ out["z"]).any(dim=1).float().mean().item()
+    ic = out["iclr"]
+    return {"workload": f"periodic repetition d={d}, p={p}, q={q}, {d} iterations, {nshots} shots",
+            "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
+            "logical_error_rate": fail, "binomial_tail": float(binom.sf(d // 2, d, p)),
+            "mean_iclr_cleared": float(ic[ic > 0].float().mean().item()) if bool((ic > 0).any()) else None}
+
+
 def serving(laim, seconds):
     """Continuous batching of single-shot requests over the mixed workload:
     2D toric L=16/32/48, 3D toric L=12, bivariate-bicycle [[144,12,12]], each
@@ -413,6 +440,7 @@ def main():
     if not args.no_serve:
         extras["serving"] = serving(laim, args.serve_seconds)
     if not args.no_extras:
+        extras["bitcentric"] = bitcentric(laim)
         extras["continuous_machine"] = {
             "minsum": continuous_machine(laim, L, args.p, "minsum", 4096, 30.0),
             "sumproduct": continuous_machine(laim, L, args.p, "sumproduct", 2048, 30.0)}

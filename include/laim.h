@@ -266,6 +266,30 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
                                    double* tclr_out, int32_t* counts_out, uint8_t* fail_out,
                                    int32_t checks_per_thread, laim_stream stream);
 
+/* --------------------------------------------------- bit-centric machine
+ * The discrete bit-centric machine of the SM ("Setup and algorithm") for
+ * codes whose checks all have degree 2 (the repetition code). No randomness:
+ * iteration i updates, from the state of iteration i - 1 (Jacobi),
+ *   m_{c->v} = (-1)^{s_c} m_{w->c} (w the other bit of c; BP-LLR2, d_c = 2),
+ *   m_{v->c} = pi_v + sum over c' in N(v)\c of m_{c'->v} (BP-LLR1),
+ *   L_v = pi_v + sum over N(v) of m_{c->v} (ascending c),
+ * flips f_v = [L_v > 0], updates s ^= H f and negates pi_v and the new
+ * messages of flipped bits (the LLR switch). Double precision; messages
+ * start at 0, pi_v at log(q / (1 - q)).
+ */
+/* laim_decode_bitcentric -- `iters` iterations on each of nshots shots.
+ *   e0        device [nshots][n] uint8: the initial errors
+ *   z_out     device [nshots][n] uint8: cumulative flips z (error e0 ^ z)
+ *   iclr_out  device [nshots] int32: first iteration after which s = 0
+ *             (0 if H e0 = 0, -1 if never within iters)
+ *   L_out     device [nshots][n] double or NULL: beliefs of the last iteration
+ * Errors: LAIM_EUNSUP unless every check has degree 2 and every bit degree
+ * <= 4, n <= 32768 and the state fits in LDS; LAIM_EINVAL for bad arguments.
+ */
+laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_t* e0,
+                                   int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
+                                   double* L_out, laim_stream stream);
+
 /* ----------------------------------------------------------- batched form
  * One persistent launch over shots of several codes and sizes (each item a
  * contiguous range of shot ids of one code with its own parameters and

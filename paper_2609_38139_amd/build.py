@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblaim.so")
-SOURCES = ["laim_kernels.hip", "laim_stream.hip", "laim_ctm.hip", "laim_host.cpp", "laim_batch.cpp"]
+SOURCES = ["laim_kernels.hip", "laim_stream.hip", "laim_ctm.hip", "laim_bitcentric.hip", "laim_host.cpp",
+           "laim_batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

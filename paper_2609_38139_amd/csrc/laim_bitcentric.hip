@@ -1,0 +1,149 @@
+// laim_bitcentric.hip -- the discrete bit-centric machine of the SM ("Setup
+// and algorithm") on gfx950, for codes whose checks have degree 2 (the
+// repetition code of the paper's bit-centric analysis).
+//
+// Iteration i, all updates from the state of iteration i - 1 (Jacobi):
+//   check-to-bit  m_{c->v} = (-1)^{s_c} m_{w->c}, w the other bit of c
+//                 (BP-LLR2 with d_c = 2: the tanh product of one input);
+//   bit-to-check  m_{v->c} = pi_v + sum over c' in N(v)\c of m_{c'->v};
+//   beliefs       L_v = pi_v + sum over c in N(v) of m_{c->v} (ascending c);
+//   feedback      f_v = [L_v > 0]; s_c ^= XOR over N(c) of f;
+//   LLR switch    pi_v, the new m_{v->c} and m_{c->v} of flipped bits negated.
+// Messages start at 0 and pi_v at log(q / (1 - q)); all in double precision,
+// where every operation above is exact up to the additions' rounding.
+//
+// One block per shot; thread t owns bits t + k nt and writes the new
+// messages on their edges. LDS: old and new messages by edge (check-major
+// edge order, double-buffered), pi, f and s.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "laim_internal.h"
+
+namespace laim {
+
+__global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0, const uint8_t* e0,
+                                                          int32_t iters, uint8_t* z_out,
+                                                          int32_t* iclr_out, double* L_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int32_t t = threadIdx.x;
+  const int32_t nt = blockDim.x;
+  const int64_t shot = blockIdx.x;
+  const int32_t E = c.E;
+  // messages by edge (check-major: edge 2 ch + j), two buffers each
+  double* cv[2] = {reinterpret_cast<double*>(smem), reinterpret_cast<double*>(smem) + E};
+  double* vc[2] = {cv[1] + E, cv[1] + 2 * E};
+  double* piv = vc[1] + E;                             // [n]
+  uint8_t* f = reinterpret_cast<uint8_t*>(piv + c.n);  // [n]
+  uint8_t* s = f + c.n;                                // [m]
+  __shared__ int32_t any_s;
+
+  const uint8_t* e0row = e0 + shot * c.n;
+  for (int32_t e = t; e < E; e += nt) {
+    cv[0][e] = 0.0;
+    vc[0][e] = 0.0;
+  }
+  for (int32_t v = t; v < c.n; v += nt) piv[v] = pi0;
+  for (int32_t ch = t; ch < c.m; ch += nt) {
+    uint32_t x = 0;
+    for (int32_t j = 0; j < c.chk_deg[ch]; ++j) x ^= e0row[c.chk_var[ch * c.dcmax + j]];
+    s[ch] = (uint8_t)(x & 1u);
+  }
+  if (t == 0) any_s = 0;
+  __syncthreads();
+  for (int32_t ch = t; ch < c.m; ch += nt)
+    if (s[ch]) any_s = 1;
+  __syncthreads();
+  int32_t iclr = any_s ? -1 : 0;
+  uint32_t zbits = 0;  // correction of this thread's bits t + k nt (the host keeps k < 32)
+  int cur = 0;
+
+  for (int32_t it = 1; it <= iters; ++it) {
+    const double* mcv = cv[cur];
+    const double* mvc = vc[cur];
+    double* ncv = cv[cur ^ 1];
+    double* nvc = vc[cur ^ 1];
+    // new messages and beliefs of the owned bits from the old state; the LLR
+    // switch of a flipped bit negates its prior and its new messages
+#pragma unroll 1
+    for (int32_t k = 0, v = t; v < c.n; ++k, v += nt) {
+      const int32_t dv = c.var_deg[v];
+      const int32_t* ve = c.var_edge + v * c.dvmax;
+      double L = piv[v];
+      for (int32_t q = 0; q < dv; ++q) L = L + mcv[edge_check(ve[q]) * 2 + edge_slot(ve[q])];
+      const bool flip = L > 0.0;
+      if (L_out && it == iters) L_out[shot * c.n + v] = L;
+      for (int32_t q = 0; q < dv; ++q) {
+        const int32_t ch = edge_check(ve[q]);
+        const int32_t j = edge_slot(ve[q]);
+        const double other = mvc[ch * 2 + (1 - j)];
+        const double mc = s[ch] ? -other : other;
+        double acc = piv[v];
+        for (int32_t q2 = 0; q2 < dv; ++q2)
+          if (q2 != q) acc = acc + mcv[edge_check(ve[q2]) * 2 + edge_slot(ve[q2])];
+        ncv[ch * 2 + j] = flip ? -mc : mc;
+        nvc[ch * 2 + j] = flip ? -acc : acc;
+      }
+      f[v] = flip ? 1 : 0;
+      if (flip) {
+        piv[v] = -piv[v];
+        zbits ^= 1u << k;
+      }
+    }
+    if (t == 0) any_s = 0;
+    __syncthreads();
+    // syndrome update s_c ^= XOR over N(c) of f
+    for (int32_t ch = t; ch < c.m; ch += nt) {
+      uint32_t x = s[ch];
+      for (int32_t j = 0; j < c.chk_deg[ch]; ++j) x ^= f[c.chk_var[ch * c.dcmax + j]];
+      s[ch] = (uint8_t)(x & 1u);
+      if (x & 1u) any_s = 1;
+    }
+    __syncthreads();
+    if (!any_s && iclr < 0) iclr = it;
+    cur ^= 1;
+  }
+#pragma unroll 1
+  for (int32_t k = 0, v = t; v < c.n; ++k, v += nt) z_out[shot * c.n + v] = (uint8_t)((zbits >> k) & 1u);
+  if (t == 0) iclr_out[shot] = iclr;
+}
+
+bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds) {
+  if (c.dcmax != 2 || c.dvmax > 4) {
+    set_error("the bit-centric machine needs checks of degree 2 and qubit degree <= 4");
+    return false;
+  }
+  *nt = (c.n < 1024) ? ((c.n + 63) / 64) * 64 : 1024;
+  if ((int64_t)c.n > 32LL * *nt) {
+    set_error("the bit-centric machine supports at most 32768 bits");
+    return false;
+  }
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      lds_max <= 0)
+    lds_max = 64 * 1024;
+  *lds = ((size_t)4 * c.E + c.n) * 8 + (size_t)c.n + c.m;
+  *lds = (*lds + 15) / 16 * 16;
+  if (*lds > (size_t)lds_max) {
+    set_error("the bit-centric machine needs %zu bytes of LDS (device limit %d)", *lds, lds_max);
+    return false;
+  }
+  return true;
+}
+
+hipError_t launch_bitcentric(const DevCode& c, double q, const uint8_t* e0, int32_t nshots,
+                             int32_t iters, int32_t nt, size_t lds, uint8_t* z, int32_t* iclr,
+                             double* L, hipStream_t st) {
+  if (nshots <= 0) return hipSuccess;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bitcentric_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(bitcentric_kernel, dim3((unsigned)nshots), dim3(nt), lds, st, c,
+                     log(q / (1.0 - q)), e0, iters, z, iclr, L);
+  return hipGetLastError();
+}
+
+}  // namespace laim

@@ -688,6 +688,29 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "continuous-machine kernel");
 }
 
+laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_t* e0,
+                                   int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
+                                   double* L_out, laim_stream stream) {
+  if (!code || nshots < 0 || iters < 0 || !(q > 0.0 && q < 1.0) ||
+      (nshots > 0 && (!e0 || !z_out || !iclr_out))) {
+    set_error("laim_decode_bitcentric: bad arguments");
+    return LAIM_EINVAL;
+  }
+  if (nshots == 0) return LAIM_OK;
+  for (int32_t c = 0; c < code->m; ++c)
+    if (code->h_rowptr[c + 1] - code->h_rowptr[c] != 2) {
+      set_error("the bit-centric machine needs every check of degree 2");
+      return LAIM_EUNSUP;
+    }
+  int32_t nt = 0;
+  size_t lds = 0;
+  if (!bitcentric_shape(code->dev, code->device, &nt, &lds)) return LAIM_EUNSUP;
+  DeviceGuard g(code->device);
+  hipError_t er = launch_bitcentric(code->dev, q, e0, nshots, iters, nt, lds, z_out, iclr_out, L_out,
+                                    (hipStream_t)stream);
+  return er == hipSuccess ? LAIM_OK : hip_fail(er, "bit-centric kernel");
+}
+
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg) {
   if (!code || (bp != 0 && bp != 1)) {
     set_error("laim_set_resident_cfg: bad arguments");

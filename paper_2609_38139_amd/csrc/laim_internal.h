@@ -184,6 +184,12 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
                       int32_t* counts, uint8_t* fail, hipStream_t st);
 
+// ---- bit-centric machine (laim_bitcentric.hip)
+bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds);
+hipError_t launch_bitcentric(const DevCode& c, double q, const uint8_t* e0, int32_t nshots,
+                             int32_t iters, int32_t nt, size_t lds, uint8_t* z, int32_t* iclr,
+                             double* L, hipStream_t st);
+
 }  // namespace laim
 
 // The code object behind the opaque ABI handle.

@@ -30,6 +30,7 @@ SYMBOLS = [
     "laim_logical_failure", "laim_batch_plan_create", "laim_batch_plan_launch",
     "laim_batch_plan_destroy", "laim_server_create", "laim_server_submit", "laim_server_step",
     "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
+    "laim_decode_bitcentric",
 ]
 
 
@@ -164,6 +165,7 @@ def lib():
         L.laim_server_destroy.argtypes = [vp]
         L.laim_decode_continuous.argtypes = [vp, C.POINTER(ContinuousParamsC), vp, u64, i32, vp, sz,
                                              vp, vp, vp, vp, vp, i32, vp]
+        L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
         L.laim_server_destroy.restype = None
         _lib = L
     return _lib
@@ -345,6 +347,23 @@ def decode_continuous(code: Code, params: ContinuousParams, e0, shot0: int = 0,
                                        _ptr(out["tclr"]), _ptr(out["counts"]), _ptr(out["fail"]),
                                        checks_per_thread, _stream(stream)),
           "laim_decode_continuous")
+    return out
+
+
+def decode_bitcentric(code: Code, q: float, e0, iters: int, want_beliefs: bool = False,
+                      stream=None) -> dict:
+    """``laim_decode_bitcentric``: returns device tensors z, iclr and (with
+    want_beliefs) L, the float64 beliefs of the last iteration."""
+    import torch
+    ns = e0.shape[0]
+    _dev(e0, torch.uint8, (ns, code.n), "e0")
+    dev = e0.device
+    out = {"z": torch.empty((ns, code.n), dtype=torch.uint8, device=dev),
+           "iclr": torch.empty((ns,), dtype=torch.int32, device=dev),
+           "L": torch.empty((ns, code.n), dtype=torch.float64, device=dev) if want_beliefs else None}
+    check(lib().laim_decode_bitcentric(code.handle, q, _ptr(e0), ns, iters, _ptr(out["z"]),
+                                       _ptr(out["iclr"]), _ptr(out["L"]), _stream(stream)),
+          "laim_decode_bitcentric")
     return out
 
 
