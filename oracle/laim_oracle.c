@@ -142,18 +142,22 @@ float orc_exp_neg(float a) {
   return p * scale;
 }
 
-/* log(1 + u) for u in [0, 1]. */
+/* log(1 + u) for u in [0, 1] as u Q(u), Q the degree-9 polynomial that
+ * interpolates log(1 + u)/u at the 10 Chebyshev nodes of [0, 1] (computed in
+ * 40-digit arithmetic, coefficients rounded to FP32), in Horner form. No
+ * division; relative error below 3 ulp over [0, 1] in FP32. */
 float orc_log1p_unit(float u) {
-  float s = u / (2.0f + u);
-  float z = s * s;
-  float q = 1.0f / 15.0f;
-  q = q * z + 1.0f / 13.0f;
-  q = q * z + 1.0f / 11.0f;
-  q = q * z + 1.0f / 9.0f;
-  q = q * z + 1.0f / 7.0f;
-  q = q * z + 1.0f / 5.0f;
-  q = q * z + 1.0f / 3.0f;
-  return (s + s) + ((s + s) * z) * q;
+  float q = -0x1.a04acap-9f;
+  q = q * u + 0x1.402f4cp-6f;
+  q = q * u + -0x1.cdd008p-5f;
+  q = q * u + 0x1.afdde8p-4f;
+  q = q * u + -0x1.38b908p-3f;
+  q = q * u + 0x1.92b430p-3f;
+  q = q * u + -0x1.ff0254p-3f;
+  q = q * u + 0x1.554bd6p-2f;
+  q = q * u + -0x1.ffffb8p-2f;
+  q = q * u + 1.0f;
+  return u * q;
 }
 
 /* g(y) = log(1 + e^{-y}) for y >= 0. */
@@ -161,8 +165,10 @@ float orc_softplus_neg(float y) { return orc_log1p_unit(orc_exp_neg(y)); }
 
 /* a [+] b, with sg(x) = -1 if x < 0 else +1, evaluated on magnitudes:
  *   |a| [+] |b| = min(|a|, |b|) + g(|a| + |b|) - g(||a| - |b||) >= 0,
- * (a rounding below zero is set to +0), then the sign sg(a) sg(b). This
- * makes the FP32 result exactly odd in each argument and symmetric. */
+ * (a rounding below zero is set to +0), then the sign sg(a) sg(b) for a
+ * nonzero result; a zero result is +0. This makes the FP32 result exactly
+ * odd in each argument (up to the sign of zero) and symmetric, and
+ * (+inf) [+] x the value of x (+0 for -0). */
 float orc_boxplus(float a, float b) {
   float aa = fabsf(a), ab = fabsf(b);
   float mn = (ab < aa) ? ab : aa;
@@ -170,7 +176,7 @@ float orc_boxplus(float a, float b) {
   float mag = (mn + orc_softplus_neg(aa + ab)) - orc_softplus_neg(diff);
   if (mag < 0.0f) mag = 0.0f;
   int neg = (a < 0.0f) ^ (b < 0.0f);
-  return neg ? -mag : mag;
+  return (neg && mag > 0.0f) ? -mag : mag;
 }
 
 static float clampf_(float x, float C) {
@@ -265,8 +271,11 @@ typedef struct {
 
 /* Check-to-qubit rule (BP-LLR2) for edge j of check c:
  *   m_{c->v} = (-1)^{s_c + d_c} * CN_{w in N(c)\v}(m_{w->c}), then clamped;
- * sum-product: CN = 2 atanh(prod tanh(m/2)), evaluated as the box-plus fold
- * ((m_1 [+] m_2) [+] m_3) ... over the other edges in ascending order;
+ * sum-product: CN = 2 atanh(prod tanh(m/2)), evaluated with box-plus as
+ *   F_{j-1} [+] B_{j+1}, F_k = F_{k-1} [+] m_k (F_{-1} = +inf),
+ *   B_k = m_k [+] B_{k+1} (B_{d_c} = +inf), an empty side dropped,
+ * the prefix and suffix folds of the inputs in ascending order (so all
+ * outputs of a check need 3 (d_c - 2) box-plus steps);
  * min-sum:     CN = (alpha * min |m|) * prod sg(m), sg(x) = -1 if x < 0
  *              else +1. An empty product is 1 and an empty minimum is +inf. */
 static float check_rule(const orc_params* P, const float* mvc_row, int32_t dc, int32_t j,
@@ -274,9 +283,17 @@ static float check_rule(const orc_params* P, const float* mvc_row, int32_t dc, i
   int sigma_neg = (int)((s_c + dc) & 1);
   float out;
   if (P->bp == 1) {
-    float acc = INFINITY; /* identity of the fold: (+inf) [+] x == x exactly */
-    for (int32_t i = 0; i < dc; ++i)
-      if (i != j) acc = orc_boxplus(acc, mvc_row[i]);
+    /* (+inf) [+] x is x (with -0 made +0); an empty side is +inf */
+    float F = INFINITY, B = INFINITY;
+    for (int32_t i = 0; i < j; ++i) F = orc_boxplus(F, mvc_row[i]);
+    for (int32_t i = dc - 1; i > j; --i) B = orc_boxplus(mvc_row[i], B);
+    float acc;
+    if (j == 0)
+      acc = B;
+    else if (j == dc - 1)
+      acc = F;
+    else
+      acc = orc_boxplus(F, B);
     out = sigma_neg ? -acc : acc;
   } else {
     float minabs = INFINITY;
