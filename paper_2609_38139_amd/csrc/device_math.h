@@ -88,20 +88,22 @@ __device__ __forceinline__ float exp_neg(float a) {
   return p * __uint_as_float((uint32_t)(k + 127) << 23);
 }
 
-// log(1 + u) for u in [0, 1]: 2 atanh(s), s = u / (2 + u) <= 1/3, from the
-// atanh series s + s^3/3 + ... + s^15/15 (Horner in s^2).
+// log(1 + u) for u in [0, 1] as u Q(u), Q the degree-9 polynomial that
+// interpolates log(1 + u)/u at the 10 Chebyshev nodes of [0, 1] (computed in
+// high precision, coefficients rounded to FP32), in Horner form: no
+// division, under 3 ulp of relative error.
 __device__ __forceinline__ float log1p_unit(float u) {
-  const float s = u / (2.0f + u);
-  const float z = s * s;
-  float q = 1.0f / 15.0f;
-  q = q * z + 1.0f / 13.0f;
-  q = q * z + 1.0f / 11.0f;
-  q = q * z + 1.0f / 9.0f;
-  q = q * z + 1.0f / 7.0f;
-  q = q * z + 1.0f / 5.0f;
-  q = q * z + 1.0f / 3.0f;
-  const float s2 = s + s;
-  return s2 + (s2 * z) * q;
+  float q = -0x1.a04acap-9f;
+  q = q * u + 0x1.402f4cp-6f;
+  q = q * u + -0x1.cdd008p-5f;
+  q = q * u + 0x1.afdde8p-4f;
+  q = q * u + -0x1.38b908p-3f;
+  q = q * u + 0x1.92b430p-3f;
+  q = q * u + -0x1.ff0254p-3f;
+  q = q * u + 0x1.554bd6p-2f;
+  q = q * u + -0x1.ffffb8p-2f;
+  q = q * u + 1.0f;
+  return u * q;
 }
 
 // log(1 + e^{-y}), y >= 0.
@@ -111,7 +113,7 @@ __device__ __forceinline__ float softplus_neg(float y) { return log1p_unit(exp_n
 // rule; Hagenauer, Offer, Papke 1996), through its exact rewriting on the
 // magnitudes |a| [+] |b| = min + log(1 + e^{-(|a|+|b|)}) - log(1 + e^{-||a|-|b||}),
 // a negative rounding set to +0, and the sign sg(a) sg(b) with sg(x) = -1
-// iff x < 0.
+// iff x < 0 for a nonzero result (a zero result is +0).
 __device__ __forceinline__ float boxplus(float a, float b) {
   const float aa = fabsf(a);
   const float ab = fabsf(b);
@@ -120,7 +122,47 @@ __device__ __forceinline__ float boxplus(float a, float b) {
   float mag = (mn + softplus_neg(aa + ab)) - softplus_neg(d);
   if (mag < 0.0f) mag = 0.0f;
   const bool neg = (a < 0.0f) != (b < 0.0f);
-  return neg ? -mag : mag;
+  return (neg && mag > 0.0f) ? -mag : mag;
+}
+
+// The sum-product check rule's box-plus of all inputs but one, for every
+// output: acc[j] = F_{j-1} [+] B_{j+1} with the ascending prefix folds
+// F_k = F_{k-1} [+] x_k and the suffix folds B_k = x_k [+] B_{k+1}; an
+// empty side is dropped ((+inf) [+] y is y with -0 made +0, i.e. y + 0).
+// Inputs x[0 .. deg); deg = DC when REG. 3 (deg - 2) box-plus steps.
+template <int DC, bool REG>
+__device__ __forceinline__ void boxplus_others(const float* x, int32_t deg, float* acc) {
+  float F[DC], B[DC];
+  if (REG) {
+    F[0] = x[0] + 0.0f;
+#pragma unroll
+    for (int k = 1; k < DC - 1; ++k) F[k] = boxplus(F[k - 1], x[k]);
+    B[DC - 1] = x[DC - 1] + 0.0f;
+#pragma unroll
+    for (int k = DC - 2; k >= 1; --k) B[k] = boxplus(x[k], B[k + 1]);
+    acc[0] = B[1];
+    acc[DC - 1] = F[DC - 2];
+#pragma unroll
+    for (int j = 1; j < DC - 1; ++j) acc[j] = boxplus(F[j - 1], B[j + 1]);
+  } else {
+    F[0] = x[0] + 0.0f;
+#pragma unroll
+    for (int k = 1; k < DC; ++k) F[k] = (k < deg) ? boxplus(F[k - 1], x[k]) : F[k - 1];
+    B[DC - 1] = (DC - 1 < deg) ? x[DC - 1] + 0.0f : __builtin_inff();
+#pragma unroll
+    for (int k = DC - 2; k >= 0; --k)
+      B[k] = (k >= deg) ? __builtin_inff() : (k == deg - 1 ? x[k] + 0.0f : boxplus(x[k], B[k + 1]));
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+      if (j >= deg) continue;
+      if (j == 0)
+        acc[j] = (deg >= 2) ? B[1] : __builtin_inff();
+      else if (j == deg - 1)
+        acc[j] = F[j - 1];
+      else
+        acc[j] = boxplus(F[j - 1], B[j + 1]);
+    }
+  }
 }
 
 }  // namespace laim

@@ -139,23 +139,10 @@ __device__ __forceinline__ void ctm_check_rule(const CtmParamsDev& P, const floa
       out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[j]) & 0x80000000u));
     }
   } else {
+    float acc[DC];
+    boxplus_others<DC, REG>(x, deg, acc);
 #pragma unroll
-    for (int j = 0; j < DC; ++j) {
-      float acc = __builtin_inff();
-      bool first = true;
-#pragma unroll
-      for (int i = 0; i < DC; ++i) {
-        if (i == j) continue;
-        if (!REG && i >= deg) continue;
-        if (first) {
-          acc = x[i] + 0.0f;
-          first = false;
-        } else {
-          acc = boxplus(acc, x[i]);
-        }
-      }
-      out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
-    }
+    for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
   }
 }
 

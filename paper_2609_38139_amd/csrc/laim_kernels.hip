@@ -423,24 +423,11 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
               out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
             }
           } else {
-            // sum-product: box-plus fold of the other inputs, ascending
+            // sum-product: box-plus of the other inputs (prefix/suffix folds)
+            float acc[DC];
+            boxplus_others<DC, REG>(x[k], deg[k], acc);
 #pragma unroll
-            for (int j = 0; j < DC; ++j) {
-              float acc = __builtin_inff();
-              bool first = true;
-#pragma unroll
-              for (int i = 0; i < DC; ++i) {
-                if (i == j) continue;
-                if (!REG && i >= deg[k]) continue;
-                if (first) {
-                  acc = x[k][i] + 0.0f;  // (+inf) [+] x == x + 0
-                  first = false;
-                } else {
-                  acc = boxplus(acc, x[k][i]);
-                }
-              }
-              out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc : acc, -C, C);
-            }
+            for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
           }
           float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll

@@ -153,22 +153,12 @@ __device__ __forceinline__ void stream_check_rule(const KParams& kp, const float
       out[j] = ng ? -mag : mag;
     }
   } else {
+    float acc[DCT];
+    boxplus_others<DCT, false>(x, d, acc);
 #pragma unroll
     for (int j = 0; j < DCT; ++j) {
       if (j >= d) continue;
-      float acc = __builtin_inff();
-      bool first = true;
-#pragma unroll
-      for (int i2 = 0; i2 < DCT; ++i2) {
-        if (i2 == j || i2 >= d) continue;
-        if (first) {
-          acc = x[i2] + 0.0f;
-          first = false;
-        } else {
-          acc = boxplus(acc, x[i2]);
-        }
-      }
-      out[j] = clampf(sigma_neg ? -acc : acc, C);
+      out[j] = clampf(sigma_neg ? -acc[j] : acc[j], C);
     }
   }
 }
