@@ -16,7 +16,8 @@
  *     printed or normalised min-sum (a reading: the paper uses sum-product),
  *   - the round-discretised check-centric machine of Algorithm 1: BP, then
  *     every active check whose clock rang this round tests Evidence and
- *     flips the argmax qubit (LocalMove), then the syndrome update,
+ *     flips the argmax qubit (LocalMove), then the syndrome update; the
+ *     round's move requests combine by one of three conflict rules,
  *   - the decoding-success test (Preliminaries, conditions (1) and (2)) by an
  *     independent GF(2) rank test,
  *   - the continuous-time machine of Algorithm 1 as stated: Euler-damped
@@ -267,7 +268,19 @@ typedef struct {
   int32_t evidence;      /* 1: apply the Evidence test */
   int32_t retire;        /* 1: stop a shot once its syndrome is clear */
   uint64_t seed;
+  int32_t conflict;      /* how one round's move requests combine: ORC_CONFLICT_* */
 } orc_params;
+
+/* Move requests of one round combine (Algorithm 1 has one clock ring at a
+ * time; a round gathers several, so a rule is needed):
+ *   OR         a qubit requested by at least one check flips once;
+ *   XOR        a qubit flips once per request (two requests cancel);
+ *   SEQUENTIAL the requests are applied one at a time in the order of their
+ *              ring times within the round (word 2 of the check's Philox
+ *              output, ties by ascending check index); a request applies
+ *              only if its check is still active, i.e. its syndrome bit,
+ *              updated by the moves already applied, is 1. */
+enum { ORC_CONFLICT_OR = 0, ORC_CONFLICT_XOR = 1, ORC_CONFLICT_SEQUENTIAL = 2 };
 
 /* Check-to-qubit rule (BP-LLR2) for edge j of check c:
  *   m_{c->v} = (-1)^{s_c + d_c} * CN_{w in N(c)\v}(m_{w->c}), then clamped;
@@ -358,6 +371,63 @@ int32_t orc_bp_sweep(int32_t m, int32_t n, const int32_t* rowptr, const int32_t*
   return 0;
 }
 
+/* Combination of one round's move requests into the flip vector f (n
+ * entries, cleared here). Request i is check req_c[i] asking to flip qubit
+ * req_v[i] at ring time req_key[i]; every check makes at most one request,
+ * and s is the syndrome at the start of the move step. */
+typedef struct { uint32_t key; int32_t c, v; } orc_request;
+
+static int cmp_request(const void* a, const void* b) {
+  const orc_request* x = (const orc_request*)a;
+  const orc_request* y = (const orc_request*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->c > y->c) - (x->c < y->c);
+}
+
+static int32_t resolve_moves(const tanner* T, int32_t conflict, const uint8_t* s, int32_t nreq,
+                             orc_request* req, uint8_t* f) {
+  memset(f, 0, (size_t)T->n);
+  if (conflict == ORC_CONFLICT_OR) {
+    for (int32_t i = 0; i < nreq; ++i) f[req[i].v] = 1;
+  } else if (conflict == ORC_CONFLICT_XOR) {
+    for (int32_t i = 0; i < nreq; ++i) f[req[i].v] ^= 1;
+  } else if (conflict == ORC_CONFLICT_SEQUENTIAL) {
+    qsort(req, (size_t)nreq, sizeof(orc_request), cmp_request);
+    for (int32_t i = 0; i < nreq; ++i) {
+      /* the check's syndrome now: s_c plus the moves applied so far */
+      uint8_t x = s[req[i].c];
+      for (int32_t k = T->rowptr[req[i].c]; k < T->rowptr[req[i].c + 1]; ++k) x ^= f[T->col[k]];
+      if (x & 1) f[req[i].v] ^= 1;
+    }
+  } else {
+    return -1;
+  }
+  return 0;
+}
+
+/* The combination rule on its own, for the pins: requests given as arrays,
+ * f [n] out. Returns 0, -1 for an unknown rule, -2 when out of memory. */
+int32_t orc_resolve_moves(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                          int32_t conflict, const uint8_t* s, int32_t nreq, const int32_t* req_c,
+                          const int32_t* req_v, const uint32_t* req_key, uint8_t* f) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  orc_request* req = (orc_request*)malloc(sizeof(orc_request) * (size_t)(nreq > 0 ? nreq : 1));
+  if (!req) {
+    tanner_free(&T);
+    return -2;
+  }
+  for (int32_t i = 0; i < nreq; ++i) {
+    req[i].key = req_key[i];
+    req[i].c = req_c[i];
+    req[i].v = req_v[i];
+  }
+  int32_t rc = resolve_moves(&T, conflict, s, nreq, req, f);
+  free(req);
+  tanner_free(&T);
+  return rc;
+}
+
 /* ------------------------------------------------------------------------
  * The round-discretised check-centric machine (Algorithm 1).
  *
@@ -372,7 +442,8 @@ int32_t orc_bp_sweep(int32_t m, int32_t n, const int32_t* rowptr, const int32_t*
  *      is sigma(L) >= 1/d_c, i.e. L >= -log(d_c - 1). If it holds, the check
  *      picks its LocalMove: the qubits with L_v == Lmax (in ascending order)
  *      are the ties, and word 1 of the same Philox output picks tie number
- *      floor(w1 * ntie / 2^32). A qubit chosen by several checks flips once;
+ *      floor(w1 * ntie / 2^32). The requests combine by the conflict rule
+ *      (OR by default: a qubit chosen by several checks flips once);
  *   4. z ^= f; s = H (e0 ^ z), which equals s ^ H f (the syndrome update);
  *   5. if s = 0 for the first time, t_clr = r + 1.
  * t_clr = 0 if H e0 = 0 and -1 if the syndrome never clears.
@@ -394,8 +465,9 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
   uint8_t* f = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
   uint8_t* r_err = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
   uint8_t* s_new = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
+  orc_request* req = (orc_request*)malloc(sizeof(orc_request) * (size_t)(m > 0 ? m : 1));
   int32_t rc = 0;
-  if (!mvc || !mcv || !L || !piv || !f || !r_err || !s_new) {
+  if (!mvc || !mcv || !L || !piv || !f || !r_err || !s_new || !req) {
     rc = -2;
     goto done;
   }
@@ -412,7 +484,7 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
       var_phase(T, P, piv, mcv, mvc);
     }
     beliefs(T, P, piv, mcv, L);
-    memset(f, 0, (size_t)n);
+    int32_t nreq = 0;
     for (int32_t c = 0; c < m; ++c) {
       if (!s[c]) continue;
       uint32_t w[4];
@@ -430,12 +502,19 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
       for (int32_t j = 0; j < dc; ++j) {
         if (L[T->col[b + j]] == Lmax) {
           if (pick == 0) {
-            f[T->col[b + j]] = 1;
+            req[nreq].key = w[2];
+            req[nreq].c = c;
+            req[nreq].v = T->col[b + j];
+            nreq++;
             break;
           }
           pick--;
         }
       }
+    }
+    if (resolve_moves(T, P->conflict, s, nreq, req, f)) {
+      rc = -1;
+      goto done;
     }
     for (int32_t v = 0; v < n; ++v) {
       z[v] ^= f[v];
@@ -468,7 +547,7 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
   }
   if (L_out) beliefs(T, P, piv, mcv, L_out);
 done:
-  free(mvc); free(mcv); free(L); free(piv); free(f); free(r_err); free(s_new);
+  free(mvc); free(mcv); free(L); free(piv); free(f); free(r_err); free(s_new); free(req);
   return rc;
 }
 

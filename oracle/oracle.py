@@ -42,7 +42,10 @@ class Params(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
                 ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("conflict", C.c_int32)]
+
+
+CONFLICT_RULES = {"or": 0, "xor": 1, "sequential": 2}
 
 
 @dataclass
@@ -60,11 +63,13 @@ class DecodeParams:
     evidence: bool = True
     retire: bool = True
     seed: int = 0
+    conflict: str = "or"  # how one round's move requests combine: "or", "xor", "sequential"
 
     def c(self) -> Params:
         return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
                       self.iters, self.rounds, self.mask_density, int(self.gauge),
-                      int(self.evidence), int(self.retire), self.seed)
+                      int(self.evidence), int(self.retire), self.seed,
+                      CONFLICT_RULES[self.conflict])
 
 
 class CtmParams(C.Structure):
@@ -147,6 +152,9 @@ def lib():
         L.orc_ctm_decode.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(CtmParams), u8p,
                                      C.c_uint64, C.c_int32, u8p, u8p, f64p, i32p, f64p, C.c_int32,
                                      C.c_int32]
+        L.orc_resolve_moves.restype = C.c_int32
+        L.orc_resolve_moves.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_int32, u8p, C.c_int32,
+                                        i32p, i32p, u32p, u8p]
         L.orc_bitcentric_machine.restype = C.c_int32
         L.orc_bitcentric_machine.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_double, u8p,
                                              C.c_int32, u8p, C.POINTER(C.c_double), i32p]
@@ -221,6 +229,27 @@ def syndrome(code, e) -> np.ndarray:
     lib().orc_syndrome(code.H.rows, code.H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32),
                        _p(e, C.c_uint8), e.shape[0], _p(s, C.c_uint8))
     return s
+
+
+def resolve_moves(code, conflict: str, s, req_c, req_v, req_key) -> np.ndarray:
+    """Flip vector of one round's move requests (check req_c[i] asks for qubit
+    req_v[i] at ring time req_key[i]) under a conflict rule, from the
+    syndrome s at the start of the move step."""
+    m, n = code.H.rows, code.H.cols
+    rp, cl = _csr(code.H)
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    rc_ = np.ascontiguousarray(req_c, dtype=np.int32)
+    rv = np.ascontiguousarray(req_v, dtype=np.int32)
+    rk = np.ascontiguousarray(req_key, dtype=np.uint32)
+    if rc_.size == 0:
+        rc_, rv, rk = np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros(1, np.uint32)
+    f = np.zeros(n, dtype=np.uint8)
+    rc = lib().orc_resolve_moves(m, n, _p(rp, C.c_int32), _p(cl, C.c_int32), CONFLICT_RULES[conflict],
+                                 _p(s, C.c_uint8), len(req_c), _p(rc_, C.c_int32), _p(rv, C.c_int32),
+                                 _p(rk, C.c_uint32), _p(f, C.c_uint8))
+    if rc != 0:
+        raise RuntimeError(f"oracle resolve_moves failed with status {rc}")
+    return f
 
 
 def decode(code, params: DecodeParams, e0, shot0: int = 0, nthreads: int = 1,
