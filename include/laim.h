@@ -149,7 +149,23 @@ typedef struct {
   int32_t evidence;     /* 1: apply the Evidence test; 0: ablation without it */
   int32_t retire;       /* 1: stop a shot at its first clear syndrome (same z, s, t_clr) */
   uint64_t seed;        /* Philox key for the clocks and tie-breaks */
+  int32_t conflict;     /* how one round's move requests combine, LAIM_CONFLICT_* (0: OR) */
 } laim_decode_params;
+
+/* Conflict rules. Algorithm 1 lets one clock ring at a time; a round of the
+ * discretised machine gathers the requests of every check that rang, and
+ * these values say how they combine:
+ *   OR          a qubit requested by one or more checks flips once (default);
+ *   XOR         a qubit flips once per request, so two requests cancel;
+ *   SEQUENTIAL  requests apply one at a time in the order of their ring
+ *               times within the round (word 2 of the check's Philox output
+ *               for the round, ties by ascending check index), each only if
+ *               its check is still active after the requests applied before
+ *               it. Beliefs, Evidence and the chosen qubits are those of the
+ *               round's start under every rule. */
+#define LAIM_CONFLICT_OR 0
+#define LAIM_CONFLICT_XOR 1
+#define LAIM_CONFLICT_SEQUENTIAL 2
 
 /* Execution forms of laim_decode_rounds; all give identical results. */
 #define LAIM_FORM_AUTO 0     /* resident if the code fits in LDS (and, for min-sum,

@@ -62,6 +62,10 @@ laim_status resolve_params(const laim_decode_params* p, KParams* kp) {
     set_error("gauge = 1 (the bit-centric LLR switch) is not part of the check-centric machine");
     return LAIM_EUNSUP;
   }
+  if (p->conflict < LAIM_CONFLICT_OR || p->conflict > LAIM_CONFLICT_SEQUENTIAL) {
+    set_error("conflict must be LAIM_CONFLICT_OR, _XOR or _SEQUENTIAL");
+    return LAIM_EINVAL;
+  }
   kp->bp = p->bp;
   kp->alpha = p->alpha;
   kp->pi = (float)log(p->q / (1.0 - p->q));
@@ -72,6 +76,7 @@ laim_status resolve_params(const laim_decode_params* p, KParams* kp) {
   kp->evidence = p->evidence ? 1 : 0;
   kp->retire = p->retire ? 1 : 0;
   kp->seed = p->seed;
+  kp->conflict = p->conflict;
   return LAIM_OK;
 }
 
@@ -534,10 +539,10 @@ laim_status laim_logical_failure(const laim_code* code, const uint8_t* e0, const
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "failure kernel");
 }
 
-static int resolve_form(const laim_code* code, int bp, int form, ResidentShape* sh) {
+static int resolve_form(const laim_code* code, int bp, bool seq, int form, ResidentShape* sh) {
   const laim_resident_cfg* want = code->has_cfg[bp] ? &code->cfg[bp] : nullptr;
   if (form == LAIM_FORM_STREAM) return LAIM_FORM_STREAM;
-  const bool ok = resident_shape(code->dev, bp, want, sh, code->device);
+  const bool ok = resident_shape(code->dev, bp, want, sh, code->device, seq);
   if (form == LAIM_FORM_RESIDENT) return ok ? LAIM_FORM_RESIDENT : -1;
   return ok ? LAIM_FORM_RESIDENT : LAIM_FORM_STREAM;
 }
@@ -546,10 +551,11 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
                             int32_t nshots, int32_t form) {
   if (!code || !params || nshots < 0) return 0;
   ResidentShape sh;
-  int f = resolve_form(code, params->bp == 1 ? 1 : 0, form, &sh);
+  const bool seq = params->conflict == LAIM_CONFLICT_SEQUENTIAL;
+  int f = resolve_form(code, params->bp == 1 ? 1 : 0, seq, form, &sh);
   if (params->bp == 0 && params->alpha > 1.0f) f = (form == LAIM_FORM_RESIDENT) ? -1 : LAIM_FORM_STREAM;
   if (f == LAIM_FORM_RESIDENT) return resident_workspace_bytes();
-  if (f == LAIM_FORM_STREAM) return stream_workspace_bytes(code->dev, nshots);
+  if (f == LAIM_FORM_STREAM) return stream_workspace_bytes(code->dev, nshots, seq);
   return 0;
 }
 
@@ -570,6 +576,7 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
     return LAIM_EINVAL;
   }
   if (nshots == 0) return LAIM_OK;
+  const bool seq = kp.conflict == kConflictSequential;
   ResidentShape sh;
   int f;
   // The resident min-sum kernel relies on alpha <= 1 (its outputs cannot
@@ -580,7 +587,7 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
       set_error("the resident min-sum form needs alpha <= 1");
       return LAIM_EUNSUP;
     }
-    if (!resident_shape(code->dev, kp.bp, cfg, &sh, code->device)) return LAIM_EINVAL;
+    if (!resident_shape(code->dev, kp.bp, cfg, &sh, code->device, seq)) return LAIM_EINVAL;
     f = LAIM_FORM_RESIDENT;
   } else if (!resident_ok) {
     if (form == LAIM_FORM_RESIDENT) {
@@ -589,11 +596,11 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
     }
     f = LAIM_FORM_STREAM;
   } else {
-    f = resolve_form(code, kp.bp, form, &sh);
+    f = resolve_form(code, kp.bp, seq, form, &sh);
     if (f < 0) return LAIM_EUNSUP;
   }
-  const size_t need =
-      (f == LAIM_FORM_RESIDENT) ? resident_workspace_bytes() : stream_workspace_bytes(code->dev, nshots);
+  const size_t need = (f == LAIM_FORM_RESIDENT) ? resident_workspace_bytes()
+                                                : stream_workspace_bytes(code->dev, nshots, seq);
   if (!ws || ws_bytes < need) {
     set_error("workspace of %zu bytes needed (got %zu)", need, ws_bytes);
     return LAIM_ENOMEM;

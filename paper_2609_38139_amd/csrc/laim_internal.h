@@ -50,7 +50,11 @@ struct KParams {
   int32_t evidence;
   int32_t retire;
   uint64_t seed;
+  int32_t conflict;  // kConflict*
 };
+
+// How one round's move requests combine (values of laim_decode_params.conflict).
+constexpr int32_t kConflictOr = 0, kConflictXor = 1, kConflictSequential = 2;
 
 laim_status resolve_params(const laim_decode_params* p, KParams* kp);
 uint64_t bernoulli_bound(double p);
@@ -69,20 +73,21 @@ struct ResidentShape {
   int32_t vpt;   // qubits per thread
   int32_t spb;   // shots per block
   int32_t mpad;  // nt * cpt rounded up to a multiple of 64 (LDS holds DC * mpad messages)
+  int32_t group_bytes;  // LDS bytes of one shot's group
   size_t lds;    // dynamic LDS bytes per block
 };
 
 // Picks / validates the resident launch shape; returns false (with an
 // error text) if the code cannot run resident with it.
 bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
-                    int device);
+                    int device, bool seq = false);
 size_t resident_workspace_bytes();
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
                            uint8_t* z, uint8_t* s, int32_t* tclr, float* L, uint8_t* fail,
                            hipStream_t st);
 
-size_t stream_workspace_bytes(const DevCode& c, int32_t nshots);
+size_t stream_workspace_bytes(const DevCode& c, int32_t nshots, bool seq);
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
                          int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
                          hipStream_t st);
@@ -136,8 +141,8 @@ struct ServerReqDev {
   uint8_t* fail;      // [1]
 };
 
-bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, UnitCtx* u,
-                   int* variant, size_t* lds, int* block);
+bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, bool seq,
+                   UnitCtx* u, int* variant, size_t* lds, int* block);
 hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
                         int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
                         hipStream_t st);

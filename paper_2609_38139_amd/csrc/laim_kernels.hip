@@ -175,7 +175,10 @@ struct GroupJob {
   int32_t* ev_out;       //   [4] flips and syndrome weight of the last round run, t_clr, failure
 };
 
-constexpr int kCtrlWords = 64;  // [0] queue value, [1 + g] group still working
+constexpr int kCtrlWords = 64;  // [0] queue value, [1 + g] group still working,
+                                // [kCtrlSeq0 .. + 2] sequential-rule pass flags
+constexpr int kCtrlSeq0 = 60;
+constexpr uint8_t kNoRequest = 0x7F;
 constexpr int kMaxShotsPerBlock = 31;
 constexpr int kGroupWords = 16;  // per-group scratch words after msg
 // scratch word indices
@@ -200,6 +203,18 @@ __device__ __forceinline__ GroupJob dead_job() {
   return j;
 }
 
+// Applies a flip of qubit v to the correction and syndrome bitmaps.
+template <int DV, bool REG>
+__device__ __forceinline__ void flip_qubit(const DevCode& c, int32_t v, uint32_t* zw, uint32_t* sw) {
+  atomicXor(&zw[v >> 5], 1u << (v & 31));
+  const int32_t dv = REG ? DV : c.var_deg[v];
+#pragma unroll
+  for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
+    const int32_t c2 = edge_check(c.var_edge[(int64_t)v * c.dvmax + q]);
+    atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
+  }
+}
+
 // Runs the units `src` hands out, one after another, all with the same
 // code and launch shape: the per-thread graph tables are built once and
 // stay in registers. Every thread of the block calls it (threads beyond
@@ -219,6 +234,11 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   uint32_t* flw = reinterpret_cast<uint32_t*>(gw + kGroupWords);  // [nw] flip requests
   uint32_t* zw = flw + nw;                                         // [nw] correction
   uint32_t* sw = zw + nw;                                          // [(m + 31) / 32] syndrome
+  // sequential conflict rule only: ring time and request byte per check
+  // (bits 0-6 the slot of the requested qubit, kNoRequest if none; bit 7
+  // whether the request applies)
+  uint32_t* rkey = sw + ((c.m + 31) >> 5);                         // [m]
+  uint8_t* rq = reinterpret_cast<uint8_t*>(rkey + c.m);            // [m]
   const float C = kp.clamp;
   const float pi = kp.pi;
 
@@ -270,6 +290,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     }
 #pragma unroll 1
     for (int32_t w = t; w < 2 * nw + ((c.m + 31) >> 5); w += u.nt) flw[w] = 0u;
+    if (kp.conflict == kConflictSequential) {
+#pragma unroll 1
+      for (int32_t ch = t; ch < c.m; ch += u.nt) rq[ch] = kNoRequest;
+    }
 #pragma unroll 1
     for (int k = 0; k < CPT; ++k) {
       const int32_t ch = t + k * u.nt;
@@ -441,9 +465,15 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     // ---- feedback: every active check whose clock rang tests Evidence
     // and requests a flip of its LocalMove qubit. A lane visits only its
     // own active checks, so a wavefront runs as many passes as its busiest
-    // lane has defects. Requests combine by OR: the request that sets a
-    // qubit's bit first applies the flip, toggling the qubit's correction
-    // bit and the syndrome bits of its checks (s ^= H f, z ^= f).
+    // lane has defects. Requests combine by the conflict rule:
+    //   OR   the request that sets a qubit's bit first applies the flip;
+    //   XOR  every request applies (two on one qubit cancel);
+    //   SEQUENTIAL  requests are recorded and resolved below.
+    // Applying a flip toggles the qubit's correction bit and the syndrome
+    // bits of its checks (z ^= f, s ^= H f); the flip bitmap is toggled
+    // too, so that its population -- the net count kept in kGwFlips -- is
+    // the number of qubits that changed.
+    uint32_t reqm = 0;  // this thread's checks with a recorded request (sequential rule)
     if (working) {
       uint32_t act = sb;
       int32_t nflip = 0;
@@ -485,29 +515,108 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         for (int j = 0; j < DC; ++j)
           if (j < d && Lv[j] == Lmax) ++ntie;
         uint32_t pick = (uint32_t)(((uint64_t)w.w1 * (uint64_t)ntie) >> 32);
-        int32_t chosen = -1;
+        int32_t slot = -1;
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
-          if (j < d && Lv[j] == Lmax && chosen < 0) {
+          if (j < d && Lv[j] == Lmax && slot < 0) {
             if (pick == 0)
-              chosen = nb[j];
+              slot = j;
             else
               --pick;
           }
         }
-        if (chosen < 0) continue;
-        const uint32_t bit = 1u << (chosen & 31);
-        if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
-        atomicXor(&zw[chosen >> 5], bit);
-        const int32_t dv = REG ? DV : c.var_deg[chosen];
-#pragma unroll
-        for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
-          const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
-          atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
+        if (slot < 0) continue;
+        if (kp.conflict == kConflictSequential) {
+          // provisionally applies: the check is active at the round's start
+          rkey[ch] = w.w2;
+          rq[ch] = (uint8_t)(0x80 | slot);
+          reqm |= 1u << k;
+          continue;
         }
-        ++nflip;
+        const int32_t chosen = nb[slot];
+        const uint32_t bit = 1u << (chosen & 31);
+        uint32_t had;
+        if (kp.conflict == kConflictOr) {
+          if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
+          had = 0;
+        } else {
+          had = atomicXor(&flw[chosen >> 5], bit) & bit;
+        }
+        flip_qubit<DV, REG>(c, chosen, zw, sw);
+        nflip += had ? -1 : 1;
       }
       if (nflip) atomicAdd(&gw[kGwFlips], nflip);
+    }
+    if (kp.conflict == kConflictSequential) {
+      // Sequential rule: request i applies iff its check's start syndrome
+      // (1) toggled by every applied request that rang earlier -- ring
+      // time, then check index -- and asks for a qubit of the check is 1.
+      // The requests form a directed acyclic graph in ring-time order, so
+      // the relaxation below reaches the unique solution after at most
+      // (longest chain + 1) passes; a pass that changes nothing in the
+      // block ends it. Three flags rotate so that a flag is cleared only
+      // after every thread has read it.
+      if (tid == 0) ctrl[kCtrlSeq0] = 0;
+      __syncthreads();
+#pragma unroll 1
+      for (int32_t pass = 0; pass <= c.m + 1; ++pass) {
+        const int32_t fi = kCtrlSeq0 + pass % 3;
+        if (tid == 0) ctrl[kCtrlSeq0 + (pass + 1) % 3] = 0;
+        bool changed = false;
+        uint32_t pend = reqm;
+#pragma unroll 1
+        while (pend) {
+          const int32_t k = __builtin_ctz(pend);
+          pend &= pend - 1u;
+          const int32_t ch = t + k * u.nt;
+          const uint32_t key = rkey[ch];
+          const int32_t d = REG ? DC : c.chk_deg[ch];
+          const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+          uint32_t x = 1u;
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            if (j >= d) continue;
+            const int32_t v = nb[j];
+            const int32_t dv = REG ? DV : c.var_deg[v];
+#pragma unroll
+            for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
+              const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+              const int32_t c2 = edge_check(e);
+              const uint32_t r2 = rq[c2];
+              if (c2 == ch || (r2 & 0x7Fu) != (uint32_t)edge_slot(e)) continue;
+              const uint32_t k2 = rkey[c2];
+              if (k2 < key || (k2 == key && c2 < ch)) x ^= r2 >> 7;
+            }
+          }
+          const uint32_t cur = rq[ch];
+          if ((cur >> 7) != x) {
+            rq[ch] = (uint8_t)((x << 7) | (cur & 0x7Fu));
+            changed = true;
+          }
+        }
+        if (changed) ctrl[fi] = 1;
+        __syncthreads();
+        if (!ctrl[fi]) break;
+      }
+      if (working && reqm) {
+        int32_t nflip = 0;
+        uint32_t pend = reqm;
+#pragma unroll 1
+        while (pend) {
+          const int32_t k = __builtin_ctz(pend);
+          pend &= pend - 1u;
+          const int32_t ch = t + k * u.nt;
+          const uint32_t cur = rq[ch];
+          rq[ch] = kNoRequest;
+          if (!(cur >> 7)) continue;
+          const int32_t chosen = c.chk_var[(int64_t)ch * c.dcmax + (cur & 0x7Fu)];
+          const uint32_t bit = 1u << (chosen & 31);
+          const uint32_t had = atomicXor(&flw[chosen >> 5], bit) & bit;
+          flip_qubit<DV, REG>(c, chosen, zw, sw);
+          nflip += had ? -1 : 1;
+        }
+        if (nflip) atomicAdd(&gw[kGwFlips], nflip);
+      }
     }
     __syncthreads();
     // ---- the new syndrome bits of this thread's checks (unchanged when
@@ -853,14 +962,16 @@ static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) 
 }
 
 // msg, scratch words, flip and correction bitmaps (n bits each), syndrome
-// bitmap (m bits)
-static size_t group_bytes_for(int dc, int mpad, int n, int m) {
-  const size_t b = (size_t)(dc * (mpad / 64) * kSlotStride + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
+// bitmap (m bits); with the sequential conflict rule also a ring time
+// (m words) and a request byte (m bytes) per check
+static size_t group_bytes_for(int dc, int mpad, int n, int m, bool seq) {
+  size_t b = (size_t)(dc * (mpad / 64) * kSlotStride + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
+  if (seq) b += (size_t)m * 5;
   return (b + 15) / 16 * 16;
 }
 
 bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
-                    int device) {
+                    int device, bool seq) {
   int dc, dv, reg;
   if (!pick_degrees(c, &dc, &dv, &reg)) {
     set_error("resident form needs check degree <= 8 and qubit degree <= 4 (have %d, %d)", c.dcmax,
@@ -912,7 +1023,7 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
     return false;
   }
   const int mpad = (nt * cpt + 63) / 64 * 64;
-  const size_t gb = group_bytes_for(dc, mpad, c.n, c.m);
+  const size_t gb = group_bytes_for(dc, mpad, c.n, c.m, seq);
   const size_t lds = kCtrlWords * 4 + gb * (size_t)spb;
   if (lds > (size_t)lds_max) {
     set_error("resident form needs %zu bytes of LDS per block (device limit %d)", lds, lds_max);
@@ -923,6 +1034,7 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
   out->vpt = vpt;
   out->spb = spb;
   out->mpad = mpad;
+  out->group_bytes = (int32_t)gb;
   out->lds = lds;
   return true;
 }
@@ -931,15 +1043,15 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
 // Variant and unit shape of a code inside the multi-code kernels. The
 // launch shape follows the code's resident shape, with checks per thread
 // limited to the compiled variants (at most the shape's value).
-bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, UnitCtx* u,
-                   int* variant, size_t* lds, int* block) {
+bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, bool seq,
+                   UnitCtx* u, int* variant, size_t* lds, int* block) {
   int dc, dv, reg;
   if (!pick_degrees(c, &dc, &dv, &reg)) {
     set_error("the batched form needs check degree <= 8 and qubit degree <= 4");
     return false;
   }
   ResidentShape sh;
-  if (!resident_shape(c, bp, want, &sh, device)) return false;
+  if (!resident_shape(c, bp, want, &sh, device, seq)) return false;
   int best = -1;
   for (int i = 0; i < (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0])); ++i) {
     const int* v = kBatchVariants[i];
@@ -952,12 +1064,12 @@ bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int 
   }
   const int cpt = kBatchVariants[best][2];
   laim_resident_cfg cfg = {0, cpt, want ? want->shots_per_block : 0};
-  if (cpt != sh.cpt && !resident_shape(c, bp, &cfg, &sh, device)) return false;
+  if (cpt != sh.cpt && !resident_shape(c, bp, &cfg, &sh, device, seq)) return false;
   u->nt = sh.nt;
   u->vpt = sh.vpt;
   u->spb = sh.spb;
   u->mpad = sh.mpad;
-  u->group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n, c.m);
+  u->group_bytes = sh.group_bytes;
   u->rounds = 0;
   u->resume = 0;
   u->events = 0;
@@ -1032,7 +1144,7 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.u.vpt = sh.vpt;
   a.u.spb = sh.spb;
   a.u.mpad = sh.mpad;
-  a.u.group_bytes = (int32_t)group_bytes_for(dc, sh.mpad, c.n, c.m);
+  a.u.group_bytes = sh.group_bytes;
   a.u.rounds = kp.rounds;
   a.u.resume = 0;
   a.u.events = 0;

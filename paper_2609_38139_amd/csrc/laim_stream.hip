@@ -33,11 +33,17 @@ struct StreamWS {
   int32_t* tclr;     // [ntile * kStreamTile]
   uint8_t* done;     // [ntile * kStreamTile]: retired shots and the last tile's padding
   uint8_t* newdone;  // [ntile * kStreamTile]
+  // sequential conflict rule only (else null)
+  uint8_t* rq;       // [ntile][m][kStreamTile]: slot of the requested qubit (bits 0-6,
+                     //   kStreamNoRequest if none), bit 7 whether the request applies
+  uint32_t* rkey;    // [ntile][m][kStreamTile]: ring time of the request
 };
+
+constexpr uint8_t kStreamNoRequest = 0x7F;
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t* total) {
+static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t* total, bool seq) {
   const int64_t ntile = ((int64_t)nshots + kStreamTile - 1) / kStreamTile;
   const int64_t ns = ntile * kStreamTile;
   const size_t msg_b = align256((size_t)ns * c.m * c.dcmax * 4);
@@ -66,13 +72,21 @@ static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t*
   off += sh1;
   w.newdone = reinterpret_cast<uint8_t*>(p + off);
   off += sh1;
+  w.rq = nullptr;
+  w.rkey = nullptr;
+  if (seq) {
+    w.rq = reinterpret_cast<uint8_t*>(p + off);
+    off += s_b;
+    w.rkey = reinterpret_cast<uint32_t*>(p + off);
+    off += align256((size_t)ns * c.m * 4);
+  }
   if (total) *total = off;
   return w;
 }
 
-size_t stream_workspace_bytes(const DevCode& c, int32_t nshots) {
+size_t stream_workspace_bytes(const DevCode& c, int32_t nshots, bool seq) {
   size_t t = 0;
-  stream_carve(c, nshots, nullptr, &t);
+  stream_carve(c, nshots, nullptr, &t, seq);
   return t;
 }
 
@@ -121,6 +135,7 @@ __global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, co
     if (x) w.anys[i] = 1u;
   }
   st4b(w.s + stream_at(tile, c.m, ch, lane), x4);
+  if (w.rq) st4b(w.rq + stream_at(tile, c.m, ch, lane), 0x01010101u * kStreamNoRequest);
   for (int32_t j = 0; j < c.dcmax; ++j)
     *reinterpret_cast<float4*>(w.msg[0] + stream_at(tile, c.m * c.dcmax, (int64_t)ch * c.dcmax + j, lane)) =
         make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -273,17 +288,83 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
     for (int j = 0; j < DCT; ++j)
       if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
     uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
-    int32_t chosen = -1;
+    int32_t slot = -1;
 #pragma unroll
     for (int j = 0; j < DCT; ++j) {
-      if (j < d && Lv[j] == Lmax && chosen < 0) {
+      if (j < d && Lv[j] == Lmax && slot < 0) {
         if (pick == 0)
-          chosen = nb[j];
+          slot = j;
         else
           --pick;
       }
     }
-    if (chosen >= 0) w.fl[(tile * c.n + chosen) * kStreamTile + col] = 1;
+    if (slot < 0) continue;
+    if (kp.conflict == kConflictSequential) {
+      // recorded, provisionally applying; resolved by stream_resolve
+      const int64_t o = stream_at(tile, c.m, ch, lane) + q;
+      w.rkey[o] = rw.w2;
+      w.rq[o] = (uint8_t)(0x80 | slot);
+      continue;
+    }
+    const int64_t fo = (tile * c.n + nb[slot]) * kStreamTile + col;
+    if (kp.conflict == kConflictOr)
+      w.fl[fo] = 1;
+    else  // XOR: the byte of this shot in the 4-byte word holding it
+      atomicXor(reinterpret_cast<uint32_t*>(w.fl + (fo & ~(int64_t)3)), 1u << (8 * (fo & 3)));
+  }
+}
+
+// Sequential conflict rule: request i applies iff its check's start
+// syndrome (1), toggled by every applied request that rang earlier (ring
+// time, then check index) and asks for a qubit of the check, is 1. One
+// thread per shot relaxes the requests of its shot in place, pass after
+// pass over the checks; the requests form a directed acyclic graph in
+// ring-time order, so a pass without change comes after at most (longest
+// chain + 2) passes. Then the applied requests become flip requests
+// (f ^= e_v) and the records are cleared.
+__global__ void __launch_bounds__(256) stream_resolve(DevCode c, StreamWS w) {
+  const int32_t col = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+  if (w.done[tile * kStreamTile + col]) return;
+  uint8_t* rq = w.rq + tile * c.m * kStreamTile + col;
+  const uint32_t* rk = w.rkey + tile * c.m * kStreamTile + col;
+#pragma unroll 1
+  for (int32_t pass = 0; pass <= c.m + 1; ++pass) {
+    bool changed = false;
+#pragma unroll 1
+    for (int32_t ch = 0; ch < c.m; ++ch) {
+      const uint32_t cur = rq[(int64_t)ch * kStreamTile];
+      if ((cur & 0x7Fu) == kStreamNoRequest) continue;
+      const uint32_t key = rk[(int64_t)ch * kStreamTile];
+      const int32_t d = c.chk_deg[ch];
+      uint32_t x = 1u;
+      for (int32_t j = 0; j < d; ++j) {
+        const int32_t v = c.chk_var[(int64_t)ch * c.dcmax + j];
+        for (int32_t q = 0; q < c.var_deg[v]; ++q) {
+          const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+          const int32_t c2 = edge_check(e);
+          const uint32_t r2 = rq[(int64_t)c2 * kStreamTile];
+          if (c2 == ch || (r2 & 0x7Fu) != (uint32_t)edge_slot(e)) continue;
+          const uint32_t k2 = rk[(int64_t)c2 * kStreamTile];
+          if (k2 < key || (k2 == key && c2 < ch)) x ^= r2 >> 7;
+        }
+      }
+      if ((cur >> 7) != x) {
+        rq[(int64_t)ch * kStreamTile] = (uint8_t)((x << 7) | (cur & 0x7Fu));
+        changed = true;
+      }
+    }
+    if (!changed) break;
+  }
+#pragma unroll 1
+  for (int32_t ch = 0; ch < c.m; ++ch) {
+    const uint32_t cur = rq[(int64_t)ch * kStreamTile];
+    if ((cur & 0x7Fu) == kStreamNoRequest) continue;
+    rq[(int64_t)ch * kStreamTile] = kStreamNoRequest;
+    if (!(cur >> 7)) continue;
+    const int32_t v = c.chk_var[(int64_t)ch * c.dcmax + (cur & 0x7Fu)];
+    uint8_t* f = w.fl + (tile * c.n + v) * kStreamTile + col;
+    *f = (uint8_t)(*f ^ 1u);
   }
 }
 
@@ -428,7 +509,8 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
   SweepFn sweep_fn;
   MovesFn moves_fn;
   stream_fns(c.dcmax, &sweep_fn, &moves_fn);
-  StreamWS w = stream_carve(c, nshots, ws, nullptr);
+  const bool seq = kp.conflict == kConflictSequential;
+  StreamWS w = stream_carve(c, nshots, ws, nullptr, seq);
   const unsigned ntile = (unsigned)((nshots + kStreamTile - 1) / kStreamTile);
   const int32_t ntot = (int32_t)(ntile * kStreamTile);
   const dim3 gchk((unsigned)((c.m + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
@@ -452,6 +534,7 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
       fresh = false;
     }
     hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0);
+    if (seq) hipLaunchKernelGGL(stream_resolve, dim3(ntile), dim3(kStreamTile), 0, st, c, w);
     hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w);
     hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w);
     hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, r, nshots);

@@ -44,7 +44,11 @@ class Params(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
                 ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("conflict", C.c_int32)]
+
+
+# LAIM_CONFLICT_*: how one round's move requests combine
+CONFLICT_RULES = {"or": 0, "xor": 1, "sequential": 2}
 
 
 class ResidentCfg(C.Structure):
@@ -80,13 +84,16 @@ class DecodeParams:
     evidence: bool = True
     retire: bool = True
     seed: int = 0
+    conflict: str = "or"  # "or", "xor" or "sequential"
 
     def c(self) -> Params:
         if self.bp not in ("minsum", "sumproduct"):
             raise ValueError("bp must be 'minsum' or 'sumproduct'")
+        if self.conflict not in CONFLICT_RULES:
+            raise ValueError("conflict must be 'or', 'xor' or 'sequential'")
         return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
                       self.iters, self.rounds, self.mask_density, int(self.gauge),
-                      int(self.evidence), int(self.retire), self.seed)
+                      int(self.evidence), int(self.retire), self.seed, CONFLICT_RULES[self.conflict])
 
 
 class ContinuousParamsC(C.Structure):

@@ -1,0 +1,188 @@
+"""Parity of the conflict rules (how one round's move requests combine: XOR,
+or sequentially in ring-time order) on the GPU with the oracle, in every
+execution form: the resident and stream kernels, resident launch shapes,
+the batched plan and the serving loop. Corrections, syndromes and clearing
+rounds bit for bit; min-sum beliefs bit for bit."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2609_38139_amd import codes
+
+from test_gpu_parity import _code_cache, compare_decode, dcode, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2609_38139_amd import laim
+    laim.lib()
+    return laim
+
+
+CASES = [  # code, bp, p, q, rounds, clock density
+    ("toric2d:8", "minsum", 0.06, 0.05, 32, 0.5),
+    ("toric2d:8", "sumproduct", 0.06, 0.05, 32, 0.5),
+    ("toric2d:6", "minsum", 0.08, 0.05, 24, 1.0),
+    ("toric3d_point:3", "minsum", 0.04, 0.05, 16, 0.5),
+    ("toric3d_membrane:3", "minsum", 0.06, 0.125, 12, 0.9),
+    ("bb:6x6", "minsum", 0.03, 0.05, 32, 0.5),
+    ("bb:12x6", "sumproduct", 0.02, 0.05, 32, 1.0),
+    ("rep:15", "minsum", 0.2, 0.1, 16, 1.0),
+]
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+@pytest.mark.parametrize("rule", ["xor", "sequential"])
+@pytest.mark.parametrize("name,bp,p,q,R,rho", CASES)
+def test_rules_match_oracle(L, orc, name, bp, p, q, R, rho, rule, form):
+    code, dc = dcode(L, name)
+    e0 = orc.sample_noise(code, p, 5, 300, 211)
+    P = L.DecodeParams(bp=bp, q=q, rounds=R, mask_density=rho, conflict=rule)
+    compare_decode(L, orc, name, P, e0, shot0=300, form=form, tag=rule)
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+@pytest.mark.parametrize("rule", ["xor", "sequential"])
+def test_rules_on_irregular_graphs(L, orc, rule, form):
+    rng = np.random.default_rng(9)
+    H = np.zeros((24, 30), dtype=np.uint8)
+    for r in range(24):
+        H[r, rng.choice(30, size=int(rng.integers(1, 7)), replace=False)] = 1
+    for v in range(30):
+        if not H[:, v].any():
+            H[rng.integers(0, 24), v] = 1
+    for v in range(30):
+        for r in np.nonzero(H[:, v])[0][4:]:
+            H[r, v] = 0
+    mixed = codes.from_dense(H, name="mixed-conflict")
+    if mixed.name not in _code_cache:
+        _code_cache[mixed.name] = (mixed, L.Code(mixed, 0))
+    e0 = orc.sample_noise(mixed, 0.15, 2, 0, 97)
+    for rho in (0.5, 1.0):
+        P = L.DecodeParams(q=0.1, rounds=12, mask_density=rho, conflict=rule, retire=False)
+        compare_decode(L, orc, mixed.name, P, e0, form=form, tag=f"{rule} irregular")
+
+
+def test_sequential_launch_shapes_agree(L, orc):
+    """The sequential rule's block-wide relaxation does not depend on the
+    resident launch shape (toric L=16: 256 checks; several shots per block)."""
+    code, dc = dcode(L, "toric2d:16")
+    e0 = orc.sample_noise(code, 0.07, 0, 0, 150)
+    P = L.DecodeParams(rounds=32, mask_density=0.8, conflict="sequential")
+    for cfg in ({"checks_per_thread": 1}, {"checks_per_thread": 2}, {"checks_per_thread": 4},
+                {"checks_per_thread": 8}, {"checks_per_thread": 1, "shots_per_block": 3},
+                {"checks_per_thread": 2, "shots_per_block": 2}):
+        compare_decode(L, orc, "toric2d:16", P, e0, cfg=cfg, tag="sequential shape")
+
+
+def test_single_edge_errors_at_density_one(L, orc):
+    """Both checks of an erroneous edge ask for it every round: XOR cancels
+    the two requests for ever, OR and the sequential rule clear in round 1."""
+    import torch
+    code, dc = dcode(L, "toric2d:5")
+    n = code.H.cols
+    e0 = np.eye(n, dtype=np.uint8)
+    for form in ("resident", "stream"):
+        for rule, want in (("or", 1), ("sequential", 1), ("xor", -1)):
+            P = L.DecodeParams(rounds=5, mask_density=1.0, conflict=rule, retire=False)
+            g = L.decode_rounds(dc, P, torch.from_numpy(e0).cuda(), form=form)
+            t = g["tclr"].cpu().numpy()
+            assert (t == want).all(), (form, rule)
+            z = g["z"].cpu().numpy()
+            assert np.array_equal(z, e0 if want == 1 else np.zeros_like(e0)), (form, rule)
+
+
+def test_invalid_rule_is_rejected(L):
+    import torch
+    code, dc = dcode(L, "toric2d:4")
+    e0 = torch.zeros((2, code.H.cols), dtype=torch.uint8, device="cuda")
+    import ctypes as C
+    P = L.DecodeParams().c()
+    P.conflict = 3
+    z = torch.empty((2, code.H.cols), dtype=torch.uint8, device="cuda")
+    s = torch.empty((2, code.H.rows), dtype=torch.uint8, device="cuda")
+    t = torch.empty((2,), dtype=torch.int32, device="cuda")
+    ws = torch.empty((1 << 20,), dtype=torch.uint8, device="cuda")
+    st = L.lib().laim_decode_rounds(dc.handle, C.byref(P), e0.data_ptr(), 0, 2, ws.data_ptr(), ws.numel(),
+                                    z.data_ptr(), s.data_ptr(), t.data_ptr(), None, 0, None)
+    assert st == L.EINVAL
+    with pytest.raises(ValueError):
+        L.decode_rounds(dc, L.DecodeParams(conflict="and"), e0)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("rule", ["xor", "sequential"])
+def test_metric_code_full_launch_sampled(L, orc, rule):
+    """2D toric L=32 at p=0.05 on 16,384 shots in one launch (every form's
+    default shape); the oracle recomputes a sample of shots."""
+    import torch
+    code, dc = dcode(L, "toric2d:32")
+    P = L.DecodeParams(rounds=32, conflict=rule)
+    e0 = L.sample_noise(dc, 0.05, 0, 0, 16384)
+    print(f"[conflict] full launch {rule}", flush=True)
+    outs = {f: L.decode_rounds(dc, P, e0, form=f) for f in ("resident", "stream")}
+    torch.cuda.synchronize()
+    for k in ("z", "s", "tclr"):
+        assert torch.equal(outs["resident"][k], outs["stream"][k]), k
+    idx = [0, 1, 4095, 8191, 16383]
+    e0n = e0.cpu().numpy()
+    for i in idx:
+        o = orc.decode(code, oracle_params(orc, P), e0n[i:i + 1], shot0=i)
+        assert np.array_equal(outs["resident"]["z"][i].cpu().numpy(), o["z"][0])
+        assert int(outs["resident"]["tclr"][i]) == o["tclr"][0]
+
+
+def test_batch_plan_and_server_with_mixed_rules(L, orc):
+    """One batched plan and one server holding items of all three rules;
+    every shot gets the result of its own single launch and the oracle's."""
+    import torch
+    mix = []
+    for name, rule, bp, s0 in (("toric2d:8", "or", "minsum", 0), ("toric2d:8", "sequential", "minsum", 0),
+                               ("bb:6x6", "xor", "sumproduct", 50), ("toric2d:16", "sequential", "sumproduct", 7),
+                               ("toric3d_point:3", "xor", "minsum", 3)):
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(bp=bp, rounds=24, mask_density=0.8, conflict=rule)
+        e0 = L.sample_noise(code, 0.06 if "toric2d" in name else 0.03, 1, s0, 120)
+        mix.append({"spec": spec, "code": code, "params": P, "e0": e0, "shot0": s0})
+    torch.cuda.synchronize()
+    singles = [L.decode_rounds(it["code"], it["params"], it["e0"], shot0=it["shot0"]) for it in mix]
+    torch.cuda.synchronize()
+    plan = L.BatchPlan(mix)
+    for replay in range(2):
+        outs = plan.launch()
+        torch.cuda.synchronize()
+        for it, o, ref in zip(mix, outs, singles):
+            for k in ("z", "s", "tclr"):
+                assert torch.equal(o[k], ref[k]), (it["spec"].name, it["params"].conflict, k, replay)
+    for it, ref in zip(mix, singles):
+        e0 = it["e0"][:30].cpu().numpy()
+        o = orc.decode(it["spec"], oracle_params(orc, it["params"]), e0, shot0=it["shot0"], nthreads=NTHREADS)
+        assert np.array_equal(ref["z"][:30].cpu().numpy(), o["z"]), it["params"].conflict
+        assert np.array_equal(ref["tclr"][:30].cpu().numpy(), o["tclr"]), it["params"].conflict
+    # the serving loop, one round per step
+    srv = L.Server(0, 1 << 28, 1024)
+    pending, results = {}, {}
+    for i, it in enumerate(mix):
+        for k in range(0, 120, 11):
+            t = srv.submit(it["code"], it["params"], it["shot0"] + k, it["e0"][k].cpu().numpy())
+            pending[t] = (i, k)
+    print(f"[conflict] serving {len(pending)} requests", flush=True)
+    steps = 0
+    while pending and steps < 10000:
+        steps += 1
+        for ev in srv.step():
+            if ev["done"]:
+                results[pending.pop(ev["ticket"])] = srv.result(ev["ticket"])
+    assert not pending
+    for (i, k), r in results.items():
+        assert np.array_equal(r["z"], singles[i]["z"][k].cpu().numpy()), (i, k)
+        assert r["tclr"] == int(singles[i]["tclr"][k]), (i, k)
