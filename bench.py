@@ -368,7 +368,8 @@ def main():
     #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
     #   2 d_c         scale and sign per output
     # = 23 for d_c = 4, d_v = 2 (2.875 per message update). For sum-product,
-    # d_c (d_c - 2) box-plus steps of BOXPLUS_OPS each plus d_c clamps.
+    # 3 (d_c - 2) box-plus steps (prefix and suffix folds, then one step per
+    # inner output) of BOXPLUS_OPS each plus d_c clamps.
     # Beside it: the rate the stream form's HBM traffic would need for the
     # same sweeps (each check-to-qubit message written once and read once by
     # its partner's gather, 4 B each way, i.e. 4 B per message update
@@ -380,7 +381,7 @@ def main():
     if args.bp == "minsum":
         ops_check = dc * dv + (dc + 1) // 2 + 1 + dc * max(0, (dc - 1) // 2) + 2 * dc
     else:
-        ops_check = dc * dv + BOXPLUS_OPS * dc * (dc - 2) + dc
+        ops_check = dc * dv + BOXPLUS_OPS * 3 * max(0, dc - 2) + dc
     ops_per_update = ops_check / (2.0 * dc)
     bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
     hbm_equiv_gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
@@ -435,6 +436,17 @@ def main():
                          "msg_updates_per_s": 2 * E * args.iters * ro["rounds_exec"] / (ro["ms_per_step"] / 1000),
                          "decode_ms": round(ro["decode_ms"], 2), "failures": ro["failures"],
                          "logical_error_rate": ro["failures"] / ro["shots"]}
+        # conflict rules for the round's move requests (ablation): same
+        # workload and shots, each rule
+        extras["conflict_rules"] = {}
+        for k, rule in enumerate(("or", "xor", "sequential")):
+            P_c = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire,
+                                    conflict=rule)
+            rc_ = timed_steps(laim, code, P_c, args, 1, 0, form, shot_base=5 * 10**9)
+            extras["conflict_rules"][rule] = {
+                "shots_per_s": round(rc_["shots"] / (rc_["ms_per_step"] / 1000), 1),
+                "failures": rc_["failures"], "logical_error_rate": rc_["failures"] / rc_["shots"],
+                "mean_rounds_run": round(rc_["rounds_exec"] / rc_["shots"], 3)}
     if not args.no_batch:
         extras["batched_vs_plain"] = batch_vs_plain(laim, codes)
     if not args.no_serve:
