@@ -25,6 +25,16 @@
  *   - for pins only: the discrete bit-centric machine of the SM ("Setup and
  *     algorithm"), in double precision.
  *
+ * Pins (the test suite checks each part against what the paper and the
+ * mathematics fix: window and tree closed forms, brute-force marginals,
+ * invariants, special cases, the bit-centric theorem). Parity unpinned:
+ *   - min-sum and sum-product dynamics, round and continuous, on loopy codes
+ *     (toric, bivariate-bicycle, membrane) beyond those invariants and
+ *     special cases: only the GPU parity tests compare them;
+ *   - the round machine's logical error rates, which the paper does not
+ *     print (its dynamics is the continuous one);
+ *   - which Philox word gives the sequential conflict rule its ring times.
+ *
  * Precision: the decoder runs in FP32 because its integer decisions (which
  * check moves, which qubit flips) are taken from FP32 messages; every float
  * expression is evaluated left to right, one rounding per operation; the

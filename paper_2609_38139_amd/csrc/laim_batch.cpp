@@ -383,10 +383,25 @@ laim_status laim_server_submit(laim_server* s, const laim_code* code,
     set_error("the code lives on another device than the server");
     return LAIM_EINVAL;
   }
-  // one item per distinct (code, parameters)
+  // one item per distinct (code, parameters); the key is built field by
+  // field so that padding bytes of the caller's struct do not enter it
+  laim_decode_params kp_key;
+  memset(&kp_key, 0, sizeof(kp_key));
+  kp_key.bp = params->bp;
+  kp_key.alpha = params->alpha;
+  kp_key.q = params->q;
+  kp_key.clamp = params->clamp;
+  kp_key.iters = params->iters;
+  kp_key.rounds = params->rounds;
+  kp_key.mask_density = params->mask_density;
+  kp_key.gauge = params->gauge;
+  kp_key.evidence = params->evidence;
+  kp_key.retire = params->retire;
+  kp_key.seed = params->seed;
+  kp_key.conflict = params->conflict;
   std::vector<char> key(sizeof(void*) + sizeof(laim_decode_params));
   memcpy(key.data(), &code, sizeof(void*));
-  memcpy(key.data() + sizeof(void*), params, sizeof(laim_decode_params));
+  memcpy(key.data() + sizeof(void*), &kp_key, sizeof(laim_decode_params));
   int item = -1;
   for (size_t i = 0; i < s->item_keys.size(); ++i)
     if (s->item_keys[i] == key) item = (int)i;

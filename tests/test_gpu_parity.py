@@ -258,18 +258,22 @@ def test_invalid_arguments_are_rejected(L):
 
 # ------------------------------------------------- full-size, sampled shots
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("form,bp", [("resident", "minsum"), ("resident", "sumproduct"),
-                                     ("stream", "minsum")])
-def test_metric_config_full_size_sampled(L, orc, form, bp):
+@pytest.mark.parametrize("form,bp,cfg", [("resident", "minsum", None), ("resident", "minsum", (8, 1)),
+                                         ("resident", "sumproduct", None), ("stream", "minsum", None)])
+def test_metric_config_full_size_sampled(L, orc, form, bp, cfg):
     """2D toric L = 32, p = 0.05, 65536 shots in one launch, 4L = 128 rounds
-    of 20 sweeps: the launch the benchmark times. 96 shots spread over the
-    whole range are recomputed one by one by the oracle."""
+    of 20 sweeps: the launch the benchmark times (also in its tuned resident
+    shape, 128 threads x 8 checks, one shot per block). 96 shots spread over
+    the whole range are recomputed one by one by the oracle."""
     code, dc = dcode(L, "toric2d:32")
     S = 65536
-    print(f"[parity] full size {form} {bp} S={S}", flush=True)
+    print(f"[parity] full size {form} {bp} cfg={cfg} S={S}", flush=True)
     e0 = L.sample_noise(dc, 0.05, 0, 0, S)
     P = L.DecodeParams(bp=bp, rounds=128)
-    g = L.decode_rounds(dc, P, e0, form=form)
+    if cfg is None:
+        g = L.decode_rounds(dc, P, e0, form=form)
+    else:
+        g = L.decode_rounds(dc, P, e0, cfg={"checks_per_thread": cfg[0], "shots_per_block": cfg[1]})
     f = L.logical_failure(dc, e0, g["z"])
     rng = np.random.default_rng(17)
     idx = np.unique(np.concatenate([[0, 1, S - 1], rng.integers(0, S, 93)]))
