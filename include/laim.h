@@ -312,7 +312,11 @@ laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_
  * outputs, laid out as in laim_decode_rounds). The plan precomputes the work
  * list, owns its device workspace and records the launch sequence in a HIP
  * graph that laim_batch_plan_launch replays. Inputs and outputs are read and
- * written at the addresses given at creation.
+ * written at the addresses given at creation. Items whose code cannot run in
+ * the resident form (a shot's state larger than the LDS, degrees beyond the
+ * compiled variants, or min-sum with alpha > 1) run in the stream form,
+ * recorded in the same graph after the persistent launch; the plan owns
+ * their HBM workspace. Results never depend on which form an item takes.
  */
 typedef struct {
   const laim_code* code;

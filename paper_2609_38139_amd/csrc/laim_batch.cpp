@@ -86,6 +86,11 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
     int block = 0;
   } per[2];
   std::vector<int> fallback_fail;  // items whose failure test runs in its own kernel
+  struct StreamItem {
+    int32_t index;
+    KParams kp;
+  };
+  std::vector<StreamItem> stream_items;  // items run in the stream form
   for (int32_t i = 0; i < nitems; ++i) {
     const laim_batch_item& b = items[i];
     if (!b.code || b.nshots < 0 ||
@@ -101,6 +106,15 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
     size_t lds = 0;
     int block = 0;
     laim_status st = make_item(b.code, &b.params, &it, &lds, &block);
+    if (st == LAIM_EUNSUP) {
+      // no resident variant (the shot's state exceeds the LDS, degrees
+      // beyond the compiled variants, or min-sum with alpha > 1): the item
+      // runs in the stream form, recorded in the same graph
+      KParams kp;
+      if (resolve_params(&b.params, &kp) != LAIM_OK) return LAIM_EINVAL;
+      stream_items.push_back({i, kp});
+      continue;
+    }
     if (st != LAIM_OK) return st;
     it.e0 = b.e0;
     it.shot0 = b.shot0;
@@ -149,6 +163,13 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
     off[bp][2] = total;
     total += 256;
   }
+  std::vector<size_t> stream_off;
+  for (const StreamItem& si : stream_items) {
+    const laim_batch_item& b = items[si.index];
+    stream_off.push_back(total);
+    total += al256(stream_workspace_bytes(b.code->dev, b.nshots,
+                                          si.kp.conflict == kConflictSequential));
+  }
   hipError_t e = hipMalloc(&plan->dev_mem, total);
   if (e != hipSuccess) {
     delete plan;
@@ -183,6 +204,14 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
     if (e != hipSuccess) break;
     const laim_batch_item& b = items[i];
     e = launch_failure(b.code->dev, b.e0, b.z_out, b.nshots, b.fail_out, plan->cap);
+  }
+  for (size_t k = 0; k < stream_items.size() && e == hipSuccess; ++k) {
+    const laim_batch_item& b = items[stream_items[k].index];
+    if (b.nshots == 0) continue;
+    e = launch_stream(b.code->dev, stream_items[k].kp, b.e0, b.shot0, b.nshots, base + stream_off[k], b.z_out,
+                      b.s_out, b.tclr_out, nullptr, plan->cap);
+    if (e == hipSuccess && b.fail_out)
+      e = launch_failure(b.code->dev, b.e0, b.z_out, b.nshots, b.fail_out, plan->cap);
   }
   if (plan->cap) {
     hipGraph_t gph = nullptr;

@@ -139,3 +139,71 @@ def test_server_admits_by_memory(L):
         assert r["tclr"] == int(singles[i]["tclr"][k])
     st = srv.stats()
     assert st["resident"] == 0 and st["waiting"] == 0 and st["bytes"] == 0
+
+
+def _plan_sampled(L, orc, spec_list, nsample=4, seed=1):
+    """Builds one batched plan over (name, p, q, rounds, shots) items,
+    launches it twice and checks sampled shots of every item against the
+    oracle and every shot against s = H (e0 ^ z) and t_clr >= 0 <=> s = 0."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    items = []
+    for name, p, q, R, S in spec_list:
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(q=q, rounds=R)
+        e0 = L.sample_noise(code, p, seed, 0, S)
+        items.append({"spec": spec, "code": code, "params": P, "e0": e0, "shot0": 0})
+    torch.cuda.synchronize()
+    plan = L.BatchPlan(items)
+    for replay in range(2):
+        print(f"[batch] {len(items)} items, replay {replay}", flush=True)
+        outs = plan.launch()
+        torch.cuda.synchronize()
+        if replay == 0:
+            first = [{k: o[k].clone() for k in ("z", "s", "tclr", "fail")} for o in outs]
+    for it, o, f0 in zip(items, outs, first):
+        for k in ("z", "s", "tclr", "fail"):
+            assert torch.equal(o[k], f0[k]), (it["spec"].name, k)
+        s_full = L.syndrome(it["code"], it["e0"] ^ o["z"])
+        assert torch.equal(s_full, o["s"]), it["spec"].name
+        assert torch.equal(o["s"].any(1), o["tclr"] < 0), it["spec"].name
+    jobs = []
+    rng = np.random.default_rng(7)
+    for j, (it, o) in enumerate(zip(items, outs)):
+        S = it["e0"].shape[0]
+        for i in sorted(set([0, S - 1] + rng.integers(0, S, nsample - 2).tolist())):
+            jobs.append((j, int(i)))
+    P_or = [orc.DecodeParams(q=it["params"].q, rounds=it["params"].rounds) for it in items]
+    e0s = {(j, i): items[j]["e0"][i:i + 1].cpu().numpy() for j, i in jobs}
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(lambda ji: orc.decode(items[ji[0]]["spec"], P_or[ji[0]], e0s[ji], shot0=ji[1]), jobs))
+    for (j, i), r in zip(jobs, refs):
+        o = outs[j]
+        assert np.array_equal(o["z"][i].cpu().numpy(), r["z"][0]), (items[j]["spec"].name, i)
+        assert int(o["tclr"][i]) == int(r["tclr"][0]), (items[j]["spec"].name, i)
+        fo = orc.logical_failure(items[j]["spec"], e0s[(j, i)], r["z"])
+        assert int(o["fail"][i]) == int(fo[0]), (items[j]["spec"].name, i)
+
+
+@pytest.mark.timeout(900)
+def test_batch_plan_3d_toric_mixed_sizes(L, orc):
+    """Both 3D toric sectors at L = 8, 16, 24 in one plan, 16384 shots each,
+    4L rounds (min-sum). Codes whose shot does not fit the LDS (point L=24,
+    membrane L=16 and 24) run in the stream form inside the same graph."""
+    _plan_sampled(L, orc, [("toric3d_point:8", 0.03, 0.05, 32, 16384),
+                           ("toric3d_point:16", 0.03, 0.05, 64, 16384),
+                           ("toric3d_point:24", 0.03, 0.05, 96, 16384),
+                           ("toric3d_membrane:8", 0.03, 0.125, 32, 16384),
+                           ("toric3d_membrane:16", 0.03, 0.125, 64, 16384),
+                           ("toric3d_membrane:24", 0.03, 0.125, 96, 16384)], nsample=3)
+
+
+@pytest.mark.timeout(900)
+def test_batch_plan_bivariate_bicycle_with_toric(L, orc):
+    """BB (6,6) and (12,6) at 262144 shots each with 2D toric L=16 and 32 in
+    one plan (min-sum, 64 rounds for BB, 4L for toric)."""
+    _plan_sampled(L, orc, [("bb:6x6", 0.005, 0.05, 64, 262144),
+                           ("bb:12x6", 0.008, 0.05, 64, 262144),
+                           ("toric2d:16", 0.05, 0.05, 64, 16384),
+                           ("toric2d:32", 0.05, 0.05, 128, 16384)], nsample=6)
