@@ -207,3 +207,41 @@ def test_batch_plan_bivariate_bicycle_with_toric(L, orc):
                            ("bb:12x6", 0.008, 0.05, 64, 262144),
                            ("toric2d:16", 0.05, 0.05, 64, 16384),
                            ("toric2d:32", 0.05, 0.05, 128, 16384)], nsample=6)
+
+
+@pytest.mark.timeout(600)
+def test_server_serving_mix_equals_alone_and_oracle(L, orc):
+    """The serving workload's code mix (2D toric L=16/32/48, 3D toric point
+    sector L=12, BB (12,6); p = 0.03; 8L rounds, 96 for the 3D and BB codes):
+    requests interleaved in arrival order give each shot exactly the result
+    of its own decode alone, and a sample matches the oracle."""
+    import torch
+    mix = []
+    for name, R in (("toric2d:16", 128), ("toric2d:32", 256), ("toric2d:48", 384),
+                    ("toric3d_point:12", 96), ("bb:12x6", 96)):
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(rounds=R)
+        e0 = L.sample_noise(code, 0.03, 0, 100, 24)
+        mix.append({"spec": spec, "code": code, "params": P, "e0": e0, "shot0": 100})
+    alone = []
+    for it in mix:
+        r = L.decode_rounds(it["code"], it["params"], it["e0"], shot0=it["shot0"])
+        r["fail"] = L.logical_failure(it["code"], it["e0"], r["z"])
+        alone.append({k: v.cpu().numpy() for k, v in r.items() if k != "workspace" and v is not None})
+    torch.cuda.synchronize()
+    order = [(i % 5, i // 5) for i in range(5 * 24)]
+    print(f"[serve] serving mix, {len(order)} requests", flush=True)
+    res, srv = _serve(L, mix, order)
+    assert len(res) == len(order)
+    for (i, k), r in res.items():
+        assert np.array_equal(r["z"], alone[i]["z"][k]), (mix[i]["spec"].name, k)
+        assert np.array_equal(r["s"], alone[i]["s"][k]), (mix[i]["spec"].name, k)
+        assert r["tclr"] == alone[i]["tclr"][k] and r["fail"] == alone[i]["fail"][k], (mix[i]["spec"].name, k)
+    for i, it in enumerate(mix):
+        e0 = it["e0"][:2].cpu().numpy()
+        o = orc.decode(it["spec"], orc.DecodeParams(rounds=it["params"].rounds), e0, shot0=it["shot0"], nthreads=2)
+        assert np.array_equal(alone[i]["z"][:2], o["z"]), it["spec"].name
+        assert np.array_equal(alone[i]["tclr"][:2], o["tclr"]), it["spec"].name
+    st = srv.stats()
+    assert st["resident"] == 0 and st["waiting"] == 0

@@ -304,3 +304,31 @@ def test_large_codes_stream_form(L, orc, name, R):
     e0 = orc.sample_noise(code, 0.02, 0, 0, 24)
     P = L.DecodeParams(q=q, rounds=R)
     compare_decode(L, orc, name, P, e0, form="auto", beliefs=False)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("Lsz,p,bp", [(16, 0.01, "minsum"), (16, 0.10, "minsum"), (16, 0.10, "sumproduct"),
+                                      (64, 0.05, "minsum"), (64, 0.05, "sumproduct")])
+def test_2d_toric_sizes_full_launch_sampled(L, orc, Lsz, p, bp):
+    """2D toric L = 16 and 64 at 65536 shots per launch, 4L rounds of 20
+    sweeps, in the default resident shape: sampled shots recomputed by the
+    oracle; every shot checked against s = H (e0 ^ z)."""
+    from concurrent.futures import ThreadPoolExecutor
+    name = f"toric2d:{Lsz}"
+    code, dc = dcode(L, name)
+    S = 65536
+    print(f"[parity] {name} p={p} {bp} S={S}", flush=True)
+    e0 = L.sample_noise(dc, p, 0, 0, S)
+    P = L.DecodeParams(bp=bp, rounds=4 * Lsz)
+    g = L.decode_rounds(dc, P, e0)
+    idx = np.array([0, 1, 777, 32768, S - 1] + ([12345, 54321, 60000] if Lsz == 16 else []))
+    e0s = to_np(e0[idx])
+    op = oracle_params(orc, P)
+    with ThreadPoolExecutor(NTHREADS) as ex:
+        refs = list(ex.map(lambda k: orc.decode(code, op, e0s[k:k + 1], shot0=int(idx[k])), range(len(idx))))
+    for k, i in enumerate(idx):
+        assert np.array_equal(to_np(g["z"][i]), refs[k]["z"][0]), i
+        assert int(g["tclr"][i]) == int(refs[k]["tclr"][0]), i
+    sfull = to_np(L.syndrome(dc, e0 ^ g["z"]))
+    assert np.array_equal(sfull, to_np(g["s"]))
+    assert np.array_equal(sfull.any(1), to_np(g["tclr"]) < 0)
