@@ -178,6 +178,41 @@ __device__ __forceinline__ void stream_check_rule(const KParams& kp, const float
   }
 }
 
+// m_{v->c} for the d slots of one check and the kSV shots of this lane:
+// pi plus the PW partner messages of each slot in ascending check order.
+// `mine` holds entry `lane` of the check's partner block. Every load is
+// issued before any is used, and without branches: a missing partner reads
+// the tile's first row instead and contributes +0, which leaves the sum
+// unchanged (the sum starts at pi, which is never -0, so it is never -0).
+template <int DCT, int PW>
+__device__ __forceinline__ void stream_gather(const DevCode& c, const float* __restrict__ src, int64_t tile,
+                                              int32_t erows, int32_t lane, int32_t mine, int32_t d,
+                                              int32_t pstride, float4* acc) {
+  int32_t eix[PW][DCT];
+  float4 v[PW][DCT];
+#pragma unroll
+  for (int p = 0; p < PW; ++p) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      const int32_t e = __builtin_amdgcn_readlane(mine, j * pstride + p);
+      eix[p][j] = (j < d) ? e : -1;
+      const int64_t row = (eix[p][j] >= 0) ? (int64_t)edge_check(e) * c.dcmax + edge_slot(e) : 0;
+      v[p][j] = *reinterpret_cast<const float4*>(src + stream_at(tile, erows, row, lane));
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PW; ++p) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      const bool ok = eix[p][j] >= 0;
+      acc[j].x = acc[j].x + (ok ? v[p][j].x : 0.0f);
+      acc[j].y = acc[j].y + (ok ? v[p][j].y : 0.0f);
+      acc[j].z = acc[j].z + (ok ? v[p][j].z : 0.0f);
+      acc[j].w = acc[j].w + (ok ? v[p][j].w : 0.0f);
+    }
+  }
+}
+
 // One BP sweep: m_{c->v} (src) -> m_{c->v} (dst), one wavefront per (tile,
 // check). `fresh` marks the first sweep of every shot (m_{v->c} = 0). A tile
 // whose shots have all retired is skipped; the other tiles are swept whole,
@@ -190,32 +225,56 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
   if (ch >= c.m) return;
-  if (!__any(ld4b(w.done + tile * kStreamTile + kSV * lane) != 0x01010101u)) return;
   const float C = kp.clamp;
-  const int32_t d = c.chk_deg[ch];
-  const int32_t pw = c.dvmax - 1;
+  const int32_t pw = c.dvmax - 1;           // partners per edge
+  const int32_t pstride = pw > 0 ? pw : 1;  // the partner table's row length
   const int32_t erows = c.m * c.dcmax;
+  const int32_t nidx = c.dcmax * pstride;   // partner entries of this check
+  // The check's degree and partner edges are wavefront-uniform: lane l loads
+  // entry l of the check's partner block, and every edge is then broadcast
+  // from its lane, so all table reads cost one memory round trip; they and
+  // the syndrome bytes are requested together with the retirement flags.
+  const int32_t* pblk = c.partner + (int64_t)ch * nidx;
+  const int32_t mine_raw = pblk[lane < nidx ? lane : 0];  // in bounds for every lane
+  const int32_t d_raw = c.chk_deg[ch];
+  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
+  if (!__any(ld4b(w.done + tile * kStreamTile + kSV * lane) != 0x01010101u)) return;
+  const int32_t mine = (lane < nidx) ? mine_raw : -1;
+  const int32_t d = __builtin_amdgcn_readfirstlane(d_raw);
+  float4 acc[DCT];
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) acc[j] = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
+  if (DCT <= 8 && nidx <= 64 && pw == 1)
+    stream_gather<DCT, 1>(c, src, tile, erows, lane, mine, d, pstride, acc);
+  else if (DCT <= 8 && nidx <= 64 && pw == 2)
+    stream_gather<DCT, 2>(c, src, tile, erows, lane, mine, d, pstride, acc);
+  else if (DCT <= 8 && nidx <= 64 && pw == 3)
+    stream_gather<DCT, 3>(c, src, tile, erows, lane, mine, d, pstride, acc);
+  else {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      for (int32_t p = 0; p < pw; ++p) {
+        const int32_t e = pblk[j * pstride + p];
+        if (e < 0) break;
+        const float4 w4 = *reinterpret_cast<const float4*>(
+            src + stream_at(tile, erows, (int64_t)edge_check(e) * c.dcmax + edge_slot(e), lane));
+        acc[j].x = acc[j].x + w4.x;
+        acc[j].y = acc[j].y + w4.y;
+        acc[j].z = acc[j].z + w4.z;
+        acc[j].w = acc[j].w + w4.w;
+      }
+    }
+  }
   float x[kSV][DCT];
 #pragma unroll
   for (int j = 0; j < DCT; ++j) {
     if (j >= d) continue;
-    float4 acc = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
-    for (int32_t p = 0; p < pw; ++p) {
-      const int32_t e = c.partner[((int64_t)ch * c.dcmax + j) * pw + p];
-      if (e < 0) break;
-      const float4 v = *reinterpret_cast<const float4*>(
-          src + stream_at(tile, erows, (int64_t)edge_check(e) * c.dcmax + edge_slot(e), lane));
-      acc.x = acc.x + v.x;
-      acc.y = acc.y + v.y;
-      acc.z = acc.z + v.z;
-      acc.w = acc.w + v.w;
-    }
-    x[0][j] = fresh ? 0.0f : clampf(acc.x, C);
-    x[1][j] = fresh ? 0.0f : clampf(acc.y, C);
-    x[2][j] = fresh ? 0.0f : clampf(acc.z, C);
-    x[3][j] = fresh ? 0.0f : clampf(acc.w, C);
+    x[0][j] = fresh ? 0.0f : clampf(acc[j].x, C);
+    x[1][j] = fresh ? 0.0f : clampf(acc[j].y, C);
+    x[2][j] = fresh ? 0.0f : clampf(acc[j].z, C);
+    x[3][j] = fresh ? 0.0f : clampf(acc[j].w, C);
   }
-  const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
   float out[kSV][DCT];
 #pragma unroll
   for (int q = 0; q < kSV; ++q)
