@@ -103,6 +103,18 @@ __device__ __forceinline__ int64_t stream_at(int64_t tile, int32_t rows, int64_t
 }
 
 __device__ __forceinline__ uint32_t ld4b(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+
+// Messages stream through HBM, each read once per sweep: non-temporal
+// 16-byte accesses.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 nt_load4(const float* p) {
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store4(float* p, float a, float b, float c, float d) {
+  f32x4 v = {a, b, c, d};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+}
 __device__ __forceinline__ void st4b(uint8_t* p, uint32_t v) { *reinterpret_cast<uint32_t*>(p) = v; }
 
 // Shot start: z = 0, no flip requests.
@@ -197,7 +209,7 @@ __device__ __forceinline__ void stream_gather(const DevCode& c, const float* __r
       const int32_t e = __builtin_amdgcn_readlane(mine, j * pstride + p);
       eix[p][j] = (j < d) ? e : -1;
       const int64_t row = (eix[p][j] >= 0) ? (int64_t)edge_check(e) * c.dcmax + edge_slot(e) : 0;
-      v[p][j] = *reinterpret_cast<const float4*>(src + stream_at(tile, erows, row, lane));
+      v[p][j] = nt_load4(src + stream_at(tile, erows, row, lane));
     }
   }
 #pragma unroll
@@ -282,8 +294,9 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
 #pragma unroll
   for (int j = 0; j < DCT; ++j) {
     if (j >= d) continue;
-    *reinterpret_cast<float4*>(dst + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane)) =
-        make_float4(out[0][j], out[1][j], out[2][j], out[3][j]);
+    // streamed out: read once, by the partner gather of the next sweep
+    nt_store4(dst + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane), out[0][j], out[1][j], out[2][j],
+              out[3][j]);
   }
 }
 
