@@ -312,8 +312,95 @@ __device__ __forceinline__ float stream_belief(const DevCode& c, const float* ms
   return clampf(acc, C);
 }
 
+// One shot's move request from the beliefs Lv of the check's d qubits:
+// Evidence first, then the clock, then the tie pick; the request is
+// recorded by the conflict rule.
+template <int DCT>
+__device__ __forceinline__ void stream_request(const DevCode& c, const KParams& kp, StreamWS& w, int32_t ch,
+                                               int32_t d, const int32_t* nb, const float* Lv, int64_t tile,
+                                               int32_t lane, int32_t q, int32_t r, uint64_t shot0) {
+  const int32_t col = kSV * lane + q;
+  const uint64_t shot = shot0 + (uint64_t)(tile * kStreamTile + col);
+  float Lmax = 0.0f;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j)
+    if (j < d && (j == 0 || Lv[j] > Lmax)) Lmax = Lv[j];
+  if (kp.evidence && !(Lmax >= c.thr[d])) return;  // Evidence first, then the clock
+  const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
+                                   ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed, (uint32_t)(kp.seed >> 32));
+  if (!below(rw.w0, kp.mask_bound)) return;
+  uint32_t ntie = 0;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j)
+    if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
+  uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
+  int32_t slot = -1;
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j < d && Lv[j] == Lmax && slot < 0) {
+      if (pick == 0)
+        slot = j;
+      else
+        --pick;
+    }
+  }
+  if (slot < 0) return;
+  if (kp.conflict == kConflictSequential) {
+    // recorded, provisionally applying; resolved by stream_resolve
+    const int64_t o = stream_at(tile, c.m, ch, lane) + q;
+    w.rkey[o] = rw.w2;
+    w.rq[o] = (uint8_t)(0x80 | slot);
+    return;
+  }
+  const int64_t fo = (tile * c.n + nb[slot]) * kStreamTile + col;
+  if (kp.conflict == kConflictOr)
+    w.fl[fo] = 1;
+  else  // XOR: the byte of this shot in the 4-byte word holding it
+    atomicXor(reinterpret_cast<uint32_t*>(w.fl + (fo & ~(int64_t)3)), 1u << (8 * (fo & 3)));
+}
+
+// Adds to L4[j] (pi for 4 shots) the messages m_{c->v} of the DV edges of
+// the qubit in slot j, in ascending check order; `el` holds, in lane
+// j * DV + q, edge q of that qubit (or -1). Every message row is requested
+// before the first add.
+template <int DCT, int DV>
+__device__ __forceinline__ void stream_belief_rows(const DevCode& c, const float* __restrict__ msg, int64_t tile,
+                                                   int32_t erows, int32_t lane, int32_t el, float4* L4) {
+  int32_t eix[DV][DCT];
+  float4 v[DV][DCT];
+#pragma unroll
+  for (int q = 0; q < DV; ++q) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      const int32_t e = __builtin_amdgcn_readlane(el, j * DV + q);
+      eix[q][j] = e;
+      const int64_t row = (e >= 0) ? (int64_t)edge_check(e) * c.dcmax + edge_slot(e) : 0;
+      v[q][j] = *reinterpret_cast<const float4*>(msg + stream_at(tile, erows, row, lane));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DV; ++q) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      const bool ok = eix[q][j] >= 0;
+      L4[j].x = L4[j].x + (ok ? v[q][j].x : 0.0f);
+      L4[j].y = L4[j].y + (ok ? v[q][j].y : 0.0f);
+      L4[j].z = L4[j].z + (ok ? v[q][j].z : 0.0f);
+      L4[j].w = L4[j].w + (ok ? v[q][j].w : 0.0f);
+    }
+  }
+}
+
 // Feedback: active checks whose Evidence holds and whose clock rang request
-// a flip of their LocalMove qubit.
+// a flip of their LocalMove qubit. One wavefront per (tile, check); a
+// wavefront with no active shot leaves at once. For checks of degree <= 8
+// whose qubits have degree <= kMovesMaxDv, the beliefs of the check's
+// qubits are computed for all 4 shots of a lane at once: the check's qubits
+// and their edges are wavefront-uniform (loaded cooperatively, broadcast by
+// readlane), and every message row is requested before the first add. A
+// missing edge reads a valid row and adds +0, exact since the sum starts at
+// pi (never -0).
+constexpr int kMovesMaxDv = 4;
 template <int DCT>
 __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ msg, int32_t r,
@@ -325,17 +412,52 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
   const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
   const uint32_t dn = ld4b(w.done + tile * kStreamTile + kSV * lane);
   const uint32_t act = s4 & ~dn & 0x01010101u;
-  if (!act) return;
-  const int32_t d = c.chk_deg[ch];
+  if (!__any(act != 0u)) return;
+  const int32_t d = __builtin_amdgcn_readfirstlane(c.chk_deg[ch]);
   if (d == 0) return;
   const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+  const int32_t dvm = c.dvmax;
+  if (DCT <= 8 && dvm <= kMovesMaxDv) {
+    // lane l: qubit of slot l, and edge (l mod dvm) of the qubit of slot l / dvm
+    const int32_t nbl = nb[lane < c.dcmax ? lane : 0];
+    const int32_t jl = lane / dvm;
+    const int32_t ql = lane - jl * dvm;
+    // slots j >= d hold no qubit (-1): read slot 0's entries there instead
+    const int32_t vq = __shfl(nbl, jl < d ? jl : 0);
+    const int32_t el_raw = c.var_edge[(int64_t)vq * dvm + ql];
+    const int32_t el = (jl < d) ? el_raw : -1;
+    const int32_t erows = c.m * c.dcmax;
+    float4 L4[DCT];
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) L4[j] = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
+    if (!fresh) {  // on a fresh sweep every message is +0 and L = pi
+      if (dvm == 1)
+        stream_belief_rows<DCT, 1>(c, msg, tile, erows, lane, el, L4);
+      else if (dvm == 2)
+        stream_belief_rows<DCT, 2>(c, msg, tile, erows, lane, el, L4);
+      else if (dvm == 3)
+        stream_belief_rows<DCT, 3>(c, msg, tile, erows, lane, el, L4);
+      else
+        stream_belief_rows<DCT, 4>(c, msg, tile, erows, lane, el, L4);
+    }
+    float Lq[kSV][DCT];
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      Lq[0][j] = clampf(L4[j].x, kp.clamp);
+      Lq[1][j] = clampf(L4[j].y, kp.clamp);
+      Lq[2][j] = clampf(L4[j].z, kp.clamp);
+      Lq[3][j] = clampf(L4[j].w, kp.clamp);
+    }
+#pragma unroll
+    for (int q = 0; q < kSV; ++q)
+      if ((act >> (8 * q)) & 1u) stream_request<DCT>(c, kp, w, ch, d, nb, Lq[q], tile, lane, q, r, shot0);
+    return;
+  }
 #pragma unroll 1
   for (int q = 0; q < kSV; ++q) {
     if (!((act >> (8 * q)) & 1u)) continue;
     const int32_t col = kSV * lane + q;
-    const uint64_t shot = shot0 + (uint64_t)(tile * kStreamTile + col);
     float Lv[DCT];
-    float Lmax = 0.0f;
 #pragma unroll
     for (int j = 0; j < DCT; ++j) {
       if (j >= d) continue;
@@ -348,41 +470,8 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
         L = stream_belief(c, msg, tile, col, nb[j], kp.pi, kp.clamp);
       }
       Lv[j] = L;
-      if (j == 0 || L > Lmax) Lmax = L;
     }
-    if (kp.evidence && !(Lmax >= c.thr[d])) continue;  // Evidence first, then the clock
-    const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
-                                     ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
-                                     (uint32_t)(kp.seed >> 32));
-    if (!below(rw.w0, kp.mask_bound)) continue;
-    uint32_t ntie = 0;
-#pragma unroll
-    for (int j = 0; j < DCT; ++j)
-      if (j < d) ntie += (Lv[j] == Lmax) ? 1u : 0u;
-    uint32_t pick = (uint32_t)(((uint64_t)rw.w1 * (uint64_t)ntie) >> 32);
-    int32_t slot = -1;
-#pragma unroll
-    for (int j = 0; j < DCT; ++j) {
-      if (j < d && Lv[j] == Lmax && slot < 0) {
-        if (pick == 0)
-          slot = j;
-        else
-          --pick;
-      }
-    }
-    if (slot < 0) continue;
-    if (kp.conflict == kConflictSequential) {
-      // recorded, provisionally applying; resolved by stream_resolve
-      const int64_t o = stream_at(tile, c.m, ch, lane) + q;
-      w.rkey[o] = rw.w2;
-      w.rq[o] = (uint8_t)(0x80 | slot);
-      continue;
-    }
-    const int64_t fo = (tile * c.n + nb[slot]) * kStreamTile + col;
-    if (kp.conflict == kConflictOr)
-      w.fl[fo] = 1;
-    else  // XOR: the byte of this shot in the 4-byte word holding it
-      atomicXor(reinterpret_cast<uint32_t*>(w.fl + (fo & ~(int64_t)3)), 1u << (8 * (fo & 3)));
+    stream_request<DCT>(c, kp, w, ch, d, nb, Lv, tile, lane, q, r, shot0);
   }
 }
 
