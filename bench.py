@@ -38,6 +38,29 @@ RESIDENT_SOURCES = ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38
                     "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py")
 
 
+STREAM_SOURCES = ("paper_2609_38139_amd/csrc/laim_stream.hip", "paper_2609_38139_amd/csrc/device_math.h",
+                  "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py")
+
+
+def profile_fields(profile: str, sources):
+    """The machine-readable fields of a committed rocprofv3 summary, or None
+    when the kernel sources (hashed in order) differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ": " in line:
+            k, v = line.strip().split(": ", 1)
+            fields[k] = v
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return fields if fields.get("source_sha256") == h.hexdigest() else None
+
+
 def profiled_traffic(profile: str, shape: str, sources=RESIDENT_SOURCES):
     """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
     WRITE_SIZE, scaled by a plain copy's counts), or None when the kernel
@@ -481,7 +504,20 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 5 * 2 * (1 << 30) / (ca.elapsed_time(cb) / 1000) / 1e9
         del src, dst
+        # the sweep kernel alone, from its committed rocprofv3 summary (only
+        # while the stream sources are the profiled ones)
+        pf = profile_fields("stream_sweep_toric2d_L32_minsum.md", STREAM_SOURCES) if default_workload else None
+        sweep_prof = None
+        if pf is not None:
+            ns = float(pf["avg_launch_ns"])
+            alg = 2 * E * 4.0 + code.m * 1.0  # bytes per shot and sweep: E messages in and out, s
+            gbs = alg * args.shots / (ns * 1e-9) / 1e9
+            sweep_prof = {"kernel": pf.get("kernel"), "avg_launch_ms": round(ns / 1e6, 4),
+                          "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "traffic_bytes_per_launch": float(pf["traffic_bytes_per_launch"]),
+                          "source": "profiles/stream_sweep_toric2d_L32_minsum.md"}
         extras["stream_form"] = {"shots_per_s": round(rs["shots"] / sec_s, 1),
+                                 "sweep_kernel_rocprof": sweep_prof,
                                  "device_copy_GBs": round(copy_gbs, 1),
                                  "msg_updates_per_s": upd / sec_s,
                                  "decode_ms": round(rs["decode_ms"], 2),

@@ -332,3 +332,26 @@ def test_2d_toric_sizes_full_launch_sampled(L, orc, Lsz, p, bp):
     sfull = to_np(L.syndrome(dc, e0 ^ g["z"]))
     assert np.array_equal(sfull, to_np(g["s"]))
     assert np.array_equal(sfull.any(1), to_np(g["tclr"]) < 0)
+
+
+@pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
+def test_stream_generic_paths_high_degrees(L, orc, bp):
+    """Qubit degrees up to 6 and check degrees above 8: beyond the resident
+    variants and the stream kernels' specialised gathers (qubit degree <= 4,
+    check degree <= 8), so the stream form's generic loops run."""
+    rng = np.random.default_rng(21)
+    m, n = 24, 48
+    H = np.zeros((m, n), dtype=np.uint8)
+    for v in range(n):
+        H[rng.choice(m, size=int(rng.integers(1, 7)), replace=False), v] = 1
+    for r in range(m):
+        if not H[r].any():
+            H[r, rng.integers(0, n)] = 1
+    code = codes.from_dense(H, name="high-degree")
+    assert code.H.to_dense().sum(0).max() > 4 and code.H.to_dense().sum(1).max() > 8
+    if code.name not in _code_cache:
+        _code_cache[code.name] = (code, L.Code(code, 0))
+    e0 = orc.sample_noise(code, 0.1, 4, 0, 300)
+    for conflict in ("or", "xor", "sequential"):
+        P = L.DecodeParams(bp=bp, q=0.1, rounds=10, conflict=conflict, retire=False)
+        compare_decode(L, orc, code.name, P, e0, form="auto", tag=f"high-degree {conflict}")
