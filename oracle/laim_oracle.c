@@ -119,14 +119,17 @@ static void philox_for(uint64_t seed, uint64_t shot, uint32_t w2, uint32_t w3, u
  * and then jumps to +-CLAMP). +inf is the identity of the fold (an empty
  * product is 1, whose 2 atanh is +inf).
  *
- * g is built from textbook methods with +, -, *, / and exponent-field
- * manipulation only, so that its result does not depend on the platform:
+ * g is built from textbook methods with IEEE +, -, *, fused multiply-add
+ * (one rounding) and exponent-field manipulation only, so that its result
+ * does not depend on the platform:
  * exp: Cody-Waite argument reduction x = k ln2 + r with ln2 split into a
  *   16-significant-bit head (k*head exact for |k| < 256) and a tail, the
- *   degree-7 Taylor polynomial of e^r (coefficients 1/j!) by Horner, then
- *   scaling by 2^k through the exponent field;
- * log(1 + u), u in [0, 1]: 2 atanh(s) with s = u / (2 + u) in [0, 1/3], by
- *   the atanh power series through s^15 (coefficients 1/(2j+1)).
+ *   degree-7 Taylor polynomial of e^r (coefficients 1/j!) by Horner with a
+ *   fused multiply-add per step, then scaling by 2^k through the exponent
+ *   field;
+ * log(1 + u), u in [0, 1]: u Q(u), Q the degree-9 polynomial interpolating
+ *   log(1 + u)/u at the 10 Chebyshev nodes of [0, 1], by Horner with a
+ *   fused multiply-add per step.
  * ---------------------------------------------------------------------- */
 static float f32_from_bits(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
 
@@ -138,16 +141,16 @@ float orc_exp_neg(float a) {
   const float LN2_TAIL = (float)(0.69314718055994530942 - 0.693145751953125);
   const float INV_LN2 = (float)1.44269504088896340736;
   float x = -a;
-  float kf = floorf(x * INV_LN2 + 0.5f);
-  float r = (x - kf * LN2_HEAD) - kf * LN2_TAIL;
+  float kf = floorf(fmaf(x, INV_LN2, 0.5f));
+  float r = fmaf(-kf, LN2_TAIL, fmaf(-kf, LN2_HEAD, x));
   float p = 1.0f / 5040.0f;
-  p = p * r + 1.0f / 720.0f;
-  p = p * r + 1.0f / 120.0f;
-  p = p * r + 1.0f / 24.0f;
-  p = p * r + 1.0f / 6.0f;
-  p = p * r + 0.5f;
-  p = p * r + 1.0f;
-  p = p * r + 1.0f;
+  p = fmaf(p, r, 1.0f / 720.0f);
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
   int k = (int)kf;
   float scale = f32_from_bits((uint32_t)(k + 127) << 23);
   return p * scale;
@@ -155,19 +158,20 @@ float orc_exp_neg(float a) {
 
 /* log(1 + u) for u in [0, 1] as u Q(u), Q the degree-9 polynomial that
  * interpolates log(1 + u)/u at the 10 Chebyshev nodes of [0, 1] (computed in
- * 40-digit arithmetic, coefficients rounded to FP32), in Horner form. No
- * division; relative error below 3 ulp over [0, 1] in FP32. */
+ * 40-digit arithmetic, coefficients rounded to FP32), in Horner form with a
+ * fused multiply-add per step. No division; relative error below 3 ulp over
+ * [0, 1] in FP32. */
 float orc_log1p_unit(float u) {
   float q = -0x1.a04acap-9f;
-  q = q * u + 0x1.402f4cp-6f;
-  q = q * u + -0x1.cdd008p-5f;
-  q = q * u + 0x1.afdde8p-4f;
-  q = q * u + -0x1.38b908p-3f;
-  q = q * u + 0x1.92b430p-3f;
-  q = q * u + -0x1.ff0254p-3f;
-  q = q * u + 0x1.554bd6p-2f;
-  q = q * u + -0x1.ffffb8p-2f;
-  q = q * u + 1.0f;
+  q = fmaf(q, u, 0x1.402f4cp-6f);
+  q = fmaf(q, u, -0x1.cdd008p-5f);
+  q = fmaf(q, u, 0x1.afdde8p-4f);
+  q = fmaf(q, u, -0x1.38b908p-3f);
+  q = fmaf(q, u, 0x1.92b430p-3f);
+  q = fmaf(q, u, -0x1.ff0254p-3f);
+  q = fmaf(q, u, 0x1.554bd6p-2f);
+  q = fmaf(q, u, -0x1.ffffb8p-2f);
+  q = fmaf(q, u, 1.0f);
   return u * q;
 }
 
