@@ -1,8 +1,9 @@
 // device_math.h -- device-side primitives of the decoder: the counter-based
 // generator behind every random draw, and the FP32 arithmetic of the BP
 // check rule (BP-LLR2). Compiled with -ffp-contract=off: every expression
-// below is one IEEE operation per arithmetic operator, evaluated in the
-// order written, so results are reproducible bit for bit.
+// below is one IEEE operation per arithmetic operator (fmaf one fused
+// operation), evaluated in the order written, so results are reproducible
+// bit for bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -66,43 +67,44 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 // e^{-a} for a >= 0, by Cody-Waite reduction -a = k ln2 + r (ln2 split into
 // a head with 16 significant bits, so k*head is exact, and a tail), the
-// degree-7 Taylor polynomial of e^r in Horner form, and a 2^k scale built in
-// the exponent field. Arguments above 80 (and +inf) give 0.
+// degree-7 Taylor polynomial of e^r in Horner form with one fused
+// multiply-add (v_fma_f32, a single rounding) per step, and a 2^k scale
+// built in the exponent field. Arguments above 80 (and +inf) give 0.
 __device__ __forceinline__ float exp_neg(float a) {
   if (!(a <= 80.0f)) return 0.0f;
   const float ln2_hi = __uint_as_float(0x3F317200u);
   const float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
   const float log2e = (float)1.44269504088896340736;
   const float x = -a;
-  const float kf = floorf(x * log2e + 0.5f);
-  const float r = (x - kf * ln2_hi) - kf * ln2_lo;
+  const float kf = floorf(fmaf(x, log2e, 0.5f));
+  const float r = fmaf(-kf, ln2_lo, fmaf(-kf, ln2_hi, x));
   float p = 1.0f / 5040.0f;
-  p = p * r + 1.0f / 720.0f;
-  p = p * r + 1.0f / 120.0f;
-  p = p * r + 1.0f / 24.0f;
-  p = p * r + 1.0f / 6.0f;
-  p = p * r + 0.5f;
-  p = p * r + 1.0f;
-  p = p * r + 1.0f;
+  p = fmaf(p, r, 1.0f / 720.0f);
+  p = fmaf(p, r, 1.0f / 120.0f);
+  p = fmaf(p, r, 1.0f / 24.0f);
+  p = fmaf(p, r, 1.0f / 6.0f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
   const int k = (int)kf;
   return p * __uint_as_float((uint32_t)(k + 127) << 23);
 }
 
 // log(1 + u) for u in [0, 1] as u Q(u), Q the degree-9 polynomial that
 // interpolates log(1 + u)/u at the 10 Chebyshev nodes of [0, 1] (computed in
-// high precision, coefficients rounded to FP32), in Horner form: no
-// division, under 3 ulp of relative error.
+// high precision, coefficients rounded to FP32), in Horner form with one
+// fused multiply-add per step: no division, under 3 ulp of relative error.
 __device__ __forceinline__ float log1p_unit(float u) {
   float q = -0x1.a04acap-9f;
-  q = q * u + 0x1.402f4cp-6f;
-  q = q * u + -0x1.cdd008p-5f;
-  q = q * u + 0x1.afdde8p-4f;
-  q = q * u + -0x1.38b908p-3f;
-  q = q * u + 0x1.92b430p-3f;
-  q = q * u + -0x1.ff0254p-3f;
-  q = q * u + 0x1.554bd6p-2f;
-  q = q * u + -0x1.ffffb8p-2f;
-  q = q * u + 1.0f;
+  q = fmaf(q, u, 0x1.402f4cp-6f);
+  q = fmaf(q, u, -0x1.cdd008p-5f);
+  q = fmaf(q, u, 0x1.afdde8p-4f);
+  q = fmaf(q, u, -0x1.38b908p-3f);
+  q = fmaf(q, u, 0x1.92b430p-3f);
+  q = fmaf(q, u, -0x1.ff0254p-3f);
+  q = fmaf(q, u, 0x1.554bd6p-2f);
+  q = fmaf(q, u, -0x1.ffffb8p-2f);
+  q = fmaf(q, u, 1.0f);
   return u * q;
 }
 
