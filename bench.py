@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -200,12 +202,15 @@ def per_shot_plain(laim, codes):
     for p, it, o in zip(ps, items, plain):
         f = laim.logical_failure(code, it["e0"], o["z"])
         ler[str(p)] = float(f.float().mean())
-    return {"workload": "2D toric L=8, p in {0.02,0.04,0.06,0.08}, seed 0, 1000 shots each, min-sum, "
-                        "64 rounds, retire on clear",
-            "plain_per_shot_shots_per_s": round(4000 / t_plain, 1),
-            "batched_shots_per_s": round(4000 / t_batch, 1),
-            "speedup": round(t_plain / t_batch, 1), "identical_outputs": bool(same),
-            "logical_error_rate": ler}
+    res = {"workload": "2D toric L=8, p in {0.02,0.04,0.06,0.08}, seed 0, 1000 shots each, min-sum, "
+                       "64 rounds, retire on clear",
+           "plain_per_shot_shots_per_s": round(4000 / t_plain, 1),
+           "batched_shots_per_s": round(4000 / t_batch, 1),
+           "speedup": round(t_plain / t_batch, 1), "identical_outputs": bool(same),
+           "logical_error_rate": ler}
+    gpu = [{"e0": it["e0"].cpu().numpy(), "z": o["z"].cpu().numpy(), "s": o["s"].cpu().numpy(),
+            "tclr": o["tclr"].cpu().numpy()} for it, o in zip(items, outs)]
+    return res, gpu
 
 
 def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
@@ -481,6 +486,7 @@ def main():
               "msg_updates_per_launch": msg_per_launch}
 
     extras = {}
+    small_gpu = None
     if args.no_extras:
         args.no_batch = args.no_serve = True
     if not args.no_extras:
@@ -548,7 +554,7 @@ def main():
                 "mean_rounds_run": round(rc_["rounds_exec"] / rc_["shots"], 3)}
     if not args.no_batch:
         extras["batched_vs_plain"] = batch_vs_plain(laim, codes)
-        extras["per_shot_plain"] = per_shot_plain(laim, codes)
+        extras["per_shot_plain"], small_gpu = per_shot_plain(laim, codes)
     if not args.no_serve:
         extras["serving"] = serving(laim, args.serve_seconds)
     if not args.no_extras:
@@ -568,6 +574,18 @@ def main():
         n1, el1, _, _ = cpu_baseline(args, spec, P_or, min(3.0, args.cpu_seconds), nthreads=1, max_shots=256)
         cpu["single_thread"] = {"value": round(n1 / el1, 2), "unit": "shots/s", "cores": 1,
                                 "sample": f"shot ids 0..{n1 - 1} ({el1:.1f} s wall)"}
+        if small_gpu is not None:
+            # the small configuration whole (4 x 1000 shots of 2D toric L=8), by
+            # the oracle on the host cores, compared bit for bit with the GPU's
+            spec8 = codes.toric_2d(8)
+            P8 = O.DecodeParams(rounds=64)
+            t0 = time.perf_counter()
+            refs = [O.decode(spec8, P8, g["e0"], nthreads=nth) for g in small_gpu]
+            el8 = time.perf_counter() - t0
+            same8 = all(np.array_equal(r[k], g[k]) for r, g in zip(refs, small_gpu) for k in ("z", "s", "tclr"))
+            cpu["small_config"] = {"value": round(4000 / el8, 1), "unit": "shots/s", "cores": nth,
+                                   "sample": "all 4000 shots of 2D toric L=8, p = 0.02..0.08, 64 rounds",
+                                   "identical_to_gpu": bool(same8)}
 
     line = {
         "metric": "shots/s and BP msg-updates/s (2D toric L=32, p=0.05); served p50/p99 latency",
