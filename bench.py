@@ -319,6 +319,16 @@ def serving(laim, seconds):
         r = serve.run(srv, wl, rate, n, rng_seed=1)
         r["fraction_of_saturation"] = frac
         out["open_loop"].append(r)
+    # the same 0.95x arrivals with the arena cut to half of what they used at
+    # their peak: admission by memory binds, requests wait for room (FIFO)
+    last = out["open_loop"][-1]
+    budget = max(1 << 20, last["arena_bytes_peak"] // 2)
+    srv_b = laim.Server(0, mem_budget=budget, max_slots=4096)
+    serve.run(srv_b, wl, None, 64)  # warm-up
+    r = serve.run(srv_b, wl, last["rate_req_per_s"], last["requests"], rng_seed=1)
+    r["fraction_of_saturation"] = 0.95
+    r["arena_budget_bytes"] = budget
+    out["memory_bound"] = r
     return out
 
 

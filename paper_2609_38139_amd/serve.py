@@ -72,6 +72,8 @@ def run(server, wl: Workload, rate: float | None, nreq: int, rng_seed: int = 0,
     nxt = 0
     t0 = time.perf_counter()
     resident_peak = 0
+    bytes_peak = 0
+    waiting_peak = 0
     pending = 0
     while done < nreq:
         now = time.perf_counter() - t0
@@ -88,6 +90,8 @@ def run(server, wl: Workload, rate: float | None, nreq: int, rng_seed: int = 0,
         evs = server.step()
         st = server.stats()
         resident_peak = max(resident_peak, st["resident"])
+        bytes_peak = max(bytes_peak, st["bytes"])
+        waiting_peak = max(waiting_peak, st["waiting"])
         for e in evs:
             lat.append(e["latency_ns"])
             rounds += 1
@@ -101,4 +105,4 @@ def run(server, wl: Workload, rate: float | None, nreq: int, rng_seed: int = 0,
             "requests_per_s": round(done / el, 1), "rounds_per_s": round(rounds / el, 1),
             "p50_round_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
             "p99_round_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
-            "resident_peak": resident_peak}
+            "resident_peak": resident_peak, "arena_bytes_peak": bytes_peak, "waiting_peak": waiting_peak}
