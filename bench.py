@@ -450,11 +450,15 @@ def main():
     # bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is the
     # operation count of the sweeps on this instruction set (three-input min,
     # median and xor exist), per check and sweep:
-    #   d_c d_v       qubit-side sums (d_v - 1 each) and one clamp per input
+    #   d_c (d_v - 1) qubit-side sums, plus d_c clamps -- except for min-sum
+    #                 on qubits of degree 2 with alpha < 1 and |pi|/(1 - alpha)
+    #                 < CLAMP, where the clamp provably cannot bind and the
+    #                 kernel does not execute it
     #   ceil(d_c/2)+1 sign parity by three-input xors, folded into +-alpha
     #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
     #   2 d_c         scale and sign per output
-    # = 23 for d_c = 4, d_v = 2 (2.875 per message update). For sum-product,
+    # = 19 for d_c = 4, d_v = 2 (2.375 per message update; 23 with the
+    # clamps). For sum-product,
     # 3 (d_c - 2) box-plus steps (prefix and suffix folds, then one step per
     # inner output) of BOXPLUS_OPS each plus d_c clamps.
     # Beside it: the rate the stream form's HBM traffic would need for the
@@ -466,7 +470,10 @@ def main():
     dc, dv = code.dc_max, code.dv_max
     BOXPLUS_OPS = 66  # VALU per box-plus step (exp and log1p by fused Horner steps)
     if args.bp == "minsum":
-        ops_check = dc * dv + (dc + 1) // 2 + 1 + dc * max(0, (dc - 1) // 2) + 2 * dc
+        pi = abs(np.log(P.q / (1.0 - P.q)))
+        idle_clamp = dv == 2 and P.alpha < 1.0 and pi < 0.99 * P.clamp * (1.0 - P.alpha)
+        ops_check = (dc * (dv - 1) + (0 if idle_clamp else dc) + (dc + 1) // 2 + 1
+                     + dc * max(0, (dc - 1) // 2) + 2 * dc)
     else:
         ops_check = dc * dv + BOXPLUS_OPS * 3 * max(0, dc - 2) + dc
     ops_per_update = ops_check / (2.0 * dc)

@@ -49,8 +49,8 @@ laim_status make_item(const laim_code* code, const laim_decode_params* params, B
   it->c = code->dev;
   it->kp = kp;
   const laim_resident_cfg* want = code->has_cfg[kp.bp] ? &code->cfg[kp.bp] : nullptr;
-  if (!batch_variant(code->dev, kp.bp, want, code->device, kp.conflict == kConflictSequential, &it->u,
-                     &it->variant, lds, block))
+  if (!batch_variant(code->dev, kp.bp, want, code->device, kp.conflict == kConflictSequential,
+                     reg_dv2_ok(kp), &it->u, &it->variant, lds, block))
     return LAIM_EUNSUP;
   it->u.rounds = kp.rounds;
   return LAIM_OK;

@@ -539,10 +539,10 @@ laim_status laim_logical_failure(const laim_code* code, const uint8_t* e0, const
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "failure kernel");
 }
 
-static int resolve_form(const laim_code* code, int bp, bool seq, int form, ResidentShape* sh) {
+static int resolve_form(const laim_code* code, int bp, bool seq, bool reg2, int form, ResidentShape* sh) {
   const laim_resident_cfg* want = code->has_cfg[bp] ? &code->cfg[bp] : nullptr;
   if (form == LAIM_FORM_STREAM) return LAIM_FORM_STREAM;
-  const bool ok = resident_shape(code->dev, bp, want, sh, code->device, seq);
+  const bool ok = resident_shape(code->dev, bp, want, sh, code->device, seq, reg2);
   if (form == LAIM_FORM_RESIDENT) return ok ? LAIM_FORM_RESIDENT : -1;
   return ok ? LAIM_FORM_RESIDENT : LAIM_FORM_STREAM;
 }
@@ -552,7 +552,9 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
   if (!code || !params || nshots < 0) return 0;
   ResidentShape sh;
   const bool seq = params->conflict == LAIM_CONFLICT_SEQUENTIAL;
-  int f = resolve_form(code, params->bp == 1 ? 1 : 0, seq, form, &sh);
+  KParams kp;
+  if (resolve_params(params, &kp) != LAIM_OK) return 0;
+  int f = resolve_form(code, kp.bp, seq, reg_dv2_ok(kp), form, &sh);
   if (params->bp == 0 && params->alpha > 1.0f) f = (form == LAIM_FORM_RESIDENT) ? -1 : LAIM_FORM_STREAM;
   if (f == LAIM_FORM_RESIDENT) return resident_workspace_bytes();
   if (f == LAIM_FORM_STREAM) return stream_workspace_bytes(code->dev, nshots, seq);
@@ -587,7 +589,7 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
       set_error("the resident min-sum form needs alpha <= 1");
       return LAIM_EUNSUP;
     }
-    if (!resident_shape(code->dev, kp.bp, cfg, &sh, code->device, seq)) return LAIM_EINVAL;
+    if (!resident_shape(code->dev, kp.bp, cfg, &sh, code->device, seq, reg_dv2_ok(kp))) return LAIM_EINVAL;
     f = LAIM_FORM_RESIDENT;
   } else if (!resident_ok) {
     if (form == LAIM_FORM_RESIDENT) {
@@ -596,7 +598,7 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
     }
     f = LAIM_FORM_STREAM;
   } else {
-    f = resolve_form(code, kp.bp, seq, form, &sh);
+    f = resolve_form(code, kp.bp, seq, reg_dv2_ok(kp), form, &sh);
     if (f < 0) return LAIM_EUNSUP;
   }
   const size_t need = (f == LAIM_FORM_RESIDENT) ? resident_workspace_bytes()

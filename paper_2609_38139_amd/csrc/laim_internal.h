@@ -75,12 +75,24 @@ struct ResidentShape {
   int32_t mpad;  // nt * cpt rounded up to a multiple of 64 (LDS holds DC * mpad messages)
   int32_t group_bytes;  // LDS bytes of one shot's group
   size_t lds;    // dynamic LDS bytes per block
+  int32_t dc, dv, reg;  // kernel variant degrees (reg: exact regular variant)
 };
 
+// Whether the exact-degree kernels for qubit degree 2 may run: they skip the
+// clamp of the qubit-side min-sum messages, which cannot bind when alpha < 1
+// and |pi| / (1 - alpha) < CLAMP (then |m_{v->c}| <= |pi| + alpha max|m_{v->c}|
+// keeps every message within |pi| / (1 - alpha); a 1% margin covers the
+// roundings). Sum-product keeps every clamp.
+inline bool reg_dv2_ok(const KParams& kp) {
+  if (kp.bp != 0) return true;
+  return kp.alpha < 1.0f && (kp.pi < 0.0f ? -kp.pi : kp.pi) < 0.99f * kp.clamp * (1.0f - kp.alpha);
+}
+
 // Picks / validates the resident launch shape; returns false (with an
-// error text) if the code cannot run resident with it.
+// error text) if the code cannot run resident with it. With reg2 false the
+// exact variants for qubit degree 2 are not used (the padded one is).
 bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
-                    int device, bool seq = false);
+                    int device, bool seq = false, bool reg2 = true);
 size_t resident_workspace_bytes();
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
@@ -142,7 +154,7 @@ struct ServerReqDev {
 };
 
 bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, bool seq,
-                   UnitCtx* u, int* variant, size_t* lds, int* block);
+                   bool reg2, UnitCtx* u, int* variant, size_t* lds, int* block);
 hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
                         int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
                         hipStream_t st);

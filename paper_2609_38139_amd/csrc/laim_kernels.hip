@@ -387,7 +387,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
             float acc = pi;
 #pragma unroll
             for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
-            acc = __builtin_amdgcn_fmed3f(acc, -C, C);
+            // min-sum on qubits of degree 2 (exact variants, run only when
+            // alpha < 1 and |pi| / (1 - alpha) < CLAMP): |m_{v->c}| stays
+            // below |pi| / (1 - alpha), so the clamp cannot bind
+            if (!(BP == 0 && REG && DV == 2)) acc = __builtin_amdgcn_fmed3f(acc, -C, C);
             if (!REG && j >= deg[k]) acc = __builtin_inff();
             x[k][j] = acc;
           }
@@ -934,12 +937,14 @@ static const ResVariant kResVariants[] = {
 };
 
 // Template degrees for a code: exact ones for the regular families, the
-// padded (8, 4) variant otherwise.
-static bool pick_degrees(const DevCode& c, int* dc, int* dv, int* reg) {
+// padded (8, 4) variant otherwise -- and for qubit degree 2 when reg2 is
+// false (min-sum whose qubit-side clamp could bind; the exact variant skips
+// it).
+static bool pick_degrees(const DevCode& c, bool reg2, int* dc, int* dv, int* reg) {
   static const int exact[][2] = {{2, 2}, {4, 2}, {6, 2}, {4, 4}, {6, 3}};
   if (c.regular) {
     for (auto& e : exact)
-      if (e[0] == c.dcmax && e[1] == c.dvmax) {
+      if (e[0] == c.dcmax && e[1] == c.dvmax && (reg2 || e[1] != 2)) {
         *dc = e[0];
         *dv = e[1];
         *reg = 1;
@@ -971,9 +976,9 @@ static size_t group_bytes_for(int dc, int mpad, int n, int m, bool seq) {
 }
 
 bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
-                    int device, bool seq) {
+                    int device, bool seq, bool reg2) {
   int dc, dv, reg;
-  if (!pick_degrees(c, &dc, &dv, &reg)) {
+  if (!pick_degrees(c, reg2, &dc, &dv, &reg)) {
     set_error("resident form needs check degree <= 8 and qubit degree <= 4 (have %d, %d)", c.dcmax,
               c.dvmax);
     return false;
@@ -1036,6 +1041,9 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
   out->mpad = mpad;
   out->group_bytes = (int32_t)gb;
   out->lds = lds;
+  out->dc = dc;
+  out->dv = dv;
+  out->reg = reg;
   return true;
 }
 
@@ -1044,14 +1052,10 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
 // launch shape follows the code's resident shape, with checks per thread
 // limited to the compiled variants (at most the shape's value).
 bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, bool seq,
-                   UnitCtx* u, int* variant, size_t* lds, int* block) {
-  int dc, dv, reg;
-  if (!pick_degrees(c, &dc, &dv, &reg)) {
-    set_error("the batched form needs check degree <= 8 and qubit degree <= 4");
-    return false;
-  }
+                   bool reg2, UnitCtx* u, int* variant, size_t* lds, int* block) {
   ResidentShape sh;
-  if (!resident_shape(c, bp, want, &sh, device, seq)) return false;
+  if (!resident_shape(c, bp, want, &sh, device, seq, reg2)) return false;
+  const int dc = sh.dc, dv = sh.dv, reg = sh.reg;
   int best = -1;
   for (int i = 0; i < (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0])); ++i) {
     const int* v = kBatchVariants[i];
@@ -1064,7 +1068,7 @@ bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int 
   }
   const int cpt = kBatchVariants[best][2];
   laim_resident_cfg cfg = {0, cpt, want ? want->shots_per_block : 0};
-  if (cpt != sh.cpt && !resident_shape(c, bp, &cfg, &sh, device, seq)) return false;
+  if (cpt != sh.cpt && !resident_shape(c, bp, &cfg, &sh, device, seq, reg2)) return false;
   u->nt = sh.nt;
   u->vpt = sh.vpt;
   u->spb = sh.spb;
@@ -1135,9 +1139,10 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
                            uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
-  int dc, dv, reg;
-  if (!pick_degrees(c, &dc, &dv, &reg)) return hipErrorInvalidValue;
-  const ResVariant* var = find_variant(dc, dv, sh.cpt, kp.bp, reg);
+  // the degrees the shape was sized for; the exact qubit-degree-2 min-sum
+  // variants skip a clamp, so the shape must have allowed them
+  if (sh.reg && sh.dv == 2 && !reg_dv2_ok(kp)) return hipErrorInvalidValue;
+  const ResVariant* var = find_variant(sh.dc, sh.dv, sh.cpt, kp.bp, sh.reg);
   if (!var) return hipErrorInvalidValue;
   ResArgs a;
   a.u.nt = sh.nt;

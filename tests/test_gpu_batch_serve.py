@@ -245,3 +245,29 @@ def test_server_serving_mix_equals_alone_and_oracle(L, orc):
         assert np.array_equal(alone[i]["tclr"][:2], o["tclr"]), it["spec"].name
     st = srv.stats()
     assert st["resident"] == 0 and st["waiting"] == 0
+
+
+def test_batch_plan_clamp_binding_items(L, orc):
+    """Min-sum items whose qubit-side clamp can bind (alpha = 1, or a small
+    CLAMP) run in the padded kernel variant, beside items of the same code
+    that run the exact variant; all match their single launches and the
+    oracle."""
+    import torch
+    spec = codes.by_name("toric2d:8")
+    code = L.Code(spec, 0)
+    e0 = L.sample_noise(code, 0.06, 2, 0, 200)
+    items = [{"spec": spec, "code": code, "params": L.DecodeParams(rounds=24, **kw), "e0": e0, "shot0": 0}
+             for kw in ({}, {"alpha": 1.0}, {"clamp": 4.0}, {"clamp": 4.0, "bp": "sumproduct"})]
+    plan = L.BatchPlan(items)
+    outs = plan.launch()
+    torch.cuda.synchronize()
+    e0n = e0.cpu().numpy()
+    for it, o in zip(items, outs):
+        ref = L.decode_rounds(code, it["params"], e0)
+        for k in ("z", "s", "tclr"):
+            assert torch.equal(o[k], ref[k]), (it["params"], k)
+        P = it["params"]
+        od = orc.decode(spec, orc.DecodeParams(bp=P.bp, alpha=P.alpha, clamp=P.clamp, rounds=P.rounds),
+                        e0n[:40], nthreads=8)
+        assert np.array_equal(o["z"][:40].cpu().numpy(), od["z"]), P
+        assert np.array_equal(o["tclr"][:40].cpu().numpy(), od["tclr"]), P

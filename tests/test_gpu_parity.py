@@ -355,3 +355,15 @@ def test_stream_generic_paths_high_degrees(L, orc, bp):
     for conflict in ("or", "xor", "sequential"):
         P = L.DecodeParams(bp=bp, q=0.1, rounds=10, conflict=conflict, retire=False)
         compare_decode(L, orc, code.name, P, e0, form="auto", tag=f"high-degree {conflict}")
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+def test_large_shot_ids_and_seed(L, orc, form):
+    """Shot ids past 2^32 and a seed past 2^32 (the high words of the Philox
+    counter and key) reach every random draw identically on both sides."""
+    code, dc = dcode(L, "toric2d:8")
+    shot0 = (1 << 33) + 123
+    e0 = orc.sample_noise(code, 0.06, (1 << 40) + 7, shot0, 150)
+    for conflict in ("or", "sequential"):
+        P = L.DecodeParams(rounds=32, seed=(1 << 36) + 99, conflict=conflict)
+        compare_decode(L, orc, "toric2d:8", P, e0, shot0=shot0, form=form, tag=f"large ids {conflict}")
