@@ -218,9 +218,11 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
     Table S1's dt = 0.001 and tau = 0.1, a shot failing if not clear by
     t_max. Reports shots/s, Euler shot-steps/s and the VALU roofline of the
     kernel. Work per check and Euler step: the check update of the round
-    machine (23 operations for a degree-4 check, gather included) plus, for
-    each of the 2 d_c messages, the Euler update (subtract, multiply, add)
-    and its clamp: 23 + 8 d_c = 55."""
+    machine (19 operations for a degree-4 check, gather included) plus, for
+    each of the 2 d_c messages, the Euler update (subtract, multiply, add):
+    19 + 6 d_c = 43. Every clamp is idle here (alpha < 1, dt/tau <= 1 and
+    |pi|/(1 - alpha) < CLAMP: the Euler update is a convex combination) and
+    is not executed; with the clamps it would be 23 + 8 d_c."""
     import math
 
     import torch
@@ -258,7 +260,9 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
                 k += 1
             steps += min(k, K)
     m = code.m
-    ops_check = 23 + 8 * code.dc_max if bp == "minsum" else None
+    dc = code.dc_max
+    ops_check = (dc * (code.dv_max - 1) + (dc + 1) // 2 + 1 + dc * max(0, (dc - 1) // 2) + 2 * dc
+                 + 6 * dc) if bp == "minsum" else None
     res = {"workload": f"2D toric L={L}, p={p}, {bp}, dt={dt}, tau=0.1, t_max={t_max}, {nshots} shots",
            "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
            "euler_shot_steps_per_s": steps / sec, "msg_updates_per_s": 2 * code.E * steps / sec,

@@ -247,6 +247,9 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
 
 template <int DC, int DV, int CPT, int BP, bool REG>
 __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, CtmArgs a) {
+  // min-sum on qubits of degree 2 (exact variants, run only when
+  // ctm_reg_dv2_ok holds): no clamp can bind
+  constexpr bool kNoClamp = (BP == 0 && REG && DV == 2);
   extern __shared__ __align__(16) unsigned char smem[];
   const int32_t t = threadIdx.x;
   const int32_t nt = a.nt;
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
           float acc = P.pi;
 #pragma unroll
           for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[kk][j][p]];
-          Fv[kk][j] = __builtin_amdgcn_fmed3f(acc, -C, C);
+          Fv[kk][j] = kNoClamp ? acc : __builtin_amdgcn_fmed3f(acc, -C, C);
         }
         float x[DC];
 #pragma unroll
@@ -377,8 +380,10 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
           if (!REG && j >= deg[kk]) continue;
-          mvc[kk][j] = __builtin_amdgcn_fmed3f(mvc[kk][j] + lam * (Fv[kk][j] - mvc[kk][j]), -C, C);
-          mcv[kk][j] = __builtin_amdgcn_fmed3f(mcv[kk][j] + lam * (Fc[kk][j] - mcv[kk][j]), -C, C);
+          const float nv = mvc[kk][j] + lam * (Fv[kk][j] - mvc[kk][j]);
+          const float nc = mcv[kk][j] + lam * (Fc[kk][j] - mcv[kk][j]);
+          mvc[kk][j] = kNoClamp ? nv : __builtin_amdgcn_fmed3f(nv, -C, C);
+          mcv[kk][j] = kNoClamp ? nc : __builtin_amdgcn_fmed3f(nc, -C, C);
           mk[j * kCtmStride] = mcv[kk][j];
         }
       }
@@ -446,13 +451,15 @@ const CtmVariant kCtmVariants[] = {
     LAIM_CTM_IRR(8, 4, 1), LAIM_CTM_IRR(8, 4, 2), LAIM_CTM_IRR(8, 4, 4),
 };
 
-// Template degrees: exact ones for regular codes, else (and for min-sum
-// with alpha > 1, whose outputs need the clamp) the padded (8, 4) variant.
-bool ctm_degrees(const DevCode& c, bool allow_reg, int* dc, int* dv, int* reg) {
+// Template degrees: exact ones for regular codes, else the padded (8, 4)
+// variant -- also for min-sum with alpha > 1 (its outputs need the clamp)
+// and, for qubit degree 2, when reg2 is false (the exact degree-2 min-sum
+// kernels skip the clamps, see ctm_reg_dv2_ok).
+bool ctm_degrees(const DevCode& c, bool allow_reg, bool reg2, int* dc, int* dv, int* reg) {
   static const int exact[][2] = {{2, 2}, {4, 2}, {6, 2}, {4, 4}, {6, 3}};
   if (c.regular && allow_reg)
     for (auto& e : exact)
-      if (e[0] == c.dcmax && e[1] == c.dvmax) {
+      if (e[0] == c.dcmax && e[1] == c.dvmax && (reg2 || e[1] != 2)) {
         *dc = e[0];
         *dv = e[1];
         *reg = 1;
@@ -475,9 +482,10 @@ const CtmVariant* ctm_find(int dc, int dv, int cpt, int bp, int reg) {
 
 }  // namespace
 
-bool ctm_shape(const DevCode& c, int bp, float alpha, int32_t cpt_want, int device, CtmShape* out) {
+bool ctm_shape(const DevCode& c, const CtmParamsDev& P, int32_t cpt_want, int device, CtmShape* out) {
+  const int bp = P.bp;
   int dc, dv, reg;
-  if (!ctm_degrees(c, !(bp == 0 && alpha > 1.0f), &dc, &dv, &reg)) {
+  if (!ctm_degrees(c, !(bp == 0 && P.alpha > 1.0f), ctm_reg_dv2_ok(P), &dc, &dv, &reg)) {
     set_error("the continuous machine needs check degree <= 8 and qubit degree <= 4 (have %d, %d)",
               c.dcmax, c.dvmax);
     return false;
@@ -515,6 +523,9 @@ bool ctm_shape(const DevCode& c, int bp, float alpha, int32_t cpt_want, int devi
   out->cpt = cpt;
   out->mpad = mpad;
   out->lds = (lds + 15) / 16 * 16;
+  out->dc = dc;
+  out->dv = dv;
+  out->reg = reg;
   return true;
 }
 
@@ -522,8 +533,10 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
                       int32_t* counts, uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
-  int dc, dv, reg;
-  if (!ctm_degrees(c, !(P.bp == 0 && P.alpha > 1.0f), &dc, &dv, &reg)) return hipErrorInvalidValue;
+  // the degrees the shape was sized for; the exact degree-2 min-sum kernels
+  // skip the clamps, so the parameters must allow them
+  if (sh.reg && sh.dv == 2 && !ctm_reg_dv2_ok(P)) return hipErrorInvalidValue;
+  const int dc = sh.dc, dv = sh.dv, reg = sh.reg;
   const CtmVariant* var = ctm_find(dc, dv, sh.cpt, P.bp, reg);
   if (!var) return hipErrorInvalidValue;
   CtmArgs a;

@@ -679,8 +679,6 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
     set_error("more than 2048 logicals are not supported");
     return LAIM_EUNSUP;
   }
-  CtmShape sh;
-  if (!ctm_shape(code->dev, p.bp, p.alpha, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
   CtmParamsDev P;
   P.bp = p.bp;
   P.alpha = p.alpha;
@@ -691,6 +689,8 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
   P.max_steps = (int32_t)floor(p.t_max / p.dt + 0.5);
   P.evidence = p.evidence ? 1 : 0;
   P.seed = p.seed;
+  CtmShape sh;
+  if (!ctm_shape(code->dev, P, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
   DeviceGuard g(code->device);
   hipError_t er = launch_ctm(code->dev, P, sh, e0, shot0, nshots, workspace, z_out, s_out, tclr_out,
                              counts_out, fail_out, (hipStream_t)stream);

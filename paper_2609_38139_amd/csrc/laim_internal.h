@@ -181,6 +181,7 @@ struct CtmShape {
   int32_t cpt;   // checks per thread
   int32_t mpad;  // nt * cpt rounded up to a multiple of 64
   size_t lds;    // dynamic LDS bytes per block
+  int32_t dc, dv, reg;  // kernel variant degrees
 };
 
 struct CtmArgs {
@@ -196,7 +197,18 @@ struct CtmArgs {
   int32_t nt, mpad;
 };
 
-bool ctm_shape(const DevCode& c, int bp, float alpha, int32_t cpt_want, int device, CtmShape* out);
+// Whether the continuous machine's exact kernels for qubit degree 2 may run:
+// their min-sum path skips every clamp. The Euler update m + lam (F - m) with
+// 0 < lam <= 1 is a convex combination of m and F, so every message stays
+// within |pi| / (1 - alpha) (as for the round machine) when alpha < 1, and
+// that is below CLAMP with a 1% margin for roundings.
+inline bool ctm_reg_dv2_ok(const CtmParamsDev& P) {
+  if (P.bp != 0) return true;
+  return P.alpha < 1.0f && P.lam <= 1.0f &&
+         (P.pi < 0.0f ? -P.pi : P.pi) < 0.99f * P.clamp * (1.0f - P.alpha);
+}
+
+bool ctm_shape(const DevCode& c, const CtmParamsDev& P, int32_t cpt_want, int device, CtmShape* out);
 hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& sh, const uint8_t* e0,
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
                       int32_t* counts, uint8_t* fail, hipStream_t st);

@@ -172,3 +172,13 @@ def test_full_size_sampled_shots(L, orc):
     s = orc.syndrome(code, e0 ^ g["z"].cpu().numpy())
     assert np.array_equal(s, g["s"].cpu().numpy())
     assert np.array_equal(g["tclr"].cpu().numpy() >= 0, s.sum(axis=1) == 0)
+
+
+def test_clamp_binding_settings(L, orc):
+    """Settings where a clamp of the degree-2 min-sum dynamics can bind (a
+    small CLAMP, or an Euler factor dt/tau > 1 that overshoots) run in the
+    padded kernel variant, which clamps every message; both match the
+    oracle, as does the default setting next to them."""
+    for kw in ({"clamp": 3.0}, {"dt": 0.2, "tau": 0.1}, {}):
+        run_both(L, orc, "toric2d:6", 0.08, 80, bp="minsum", t_max=12.0,
+                 **({"dt": 0.01} | kw), tag=f"clamp {kw}")
