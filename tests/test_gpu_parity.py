@@ -367,3 +367,28 @@ def test_large_shot_ids_and_seed(L, orc, form):
     for conflict in ("or", "sequential"):
         P = L.DecodeParams(rounds=32, seed=(1 << 36) + 99, conflict=conflict)
         compare_decode(L, orc, "toric2d:8", P, e0, shot0=shot0, form=form, tag=f"large ids {conflict}")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
+def test_2d_toric_l16_noise_sweep(L, orc, bp):
+    """2D toric L = 16 over the whole noise range p = 0.01 .. 0.10 (4L = 64
+    rounds, 8192 shots per p in one launch each): sampled shots against the
+    oracle, and s = H (e0 ^ z) for every shot."""
+    from concurrent.futures import ThreadPoolExecutor
+    code, dc = dcode(L, "toric2d:16")
+    P = L.DecodeParams(bp=bp, rounds=64)
+    op = oracle_params(orc, P)
+    idx = np.array([0, 4095, 8191])
+    for k in range(1, 11):
+        p = k / 100.0
+        print(f"[parity] toric2d:16 {bp} p={p}", flush=True)
+        e0 = L.sample_noise(dc, p, 0, 0, 8192)
+        g = L.decode_rounds(dc, P, e0)
+        e0s = to_np(e0[idx])
+        with ThreadPoolExecutor(NTHREADS) as ex:
+            refs = list(ex.map(lambda j: orc.decode(code, op, e0s[j:j + 1], shot0=int(idx[j])), range(len(idx))))
+        for j, i in enumerate(idx):
+            assert np.array_equal(to_np(g["z"][i]), refs[j]["z"][0]), (p, i)
+            assert int(g["tclr"][i]) == int(refs[j]["tclr"][0]), (p, i)
+        assert np.array_equal(to_np(L.syndrome(dc, e0 ^ g["z"])), to_np(g["s"])), p
