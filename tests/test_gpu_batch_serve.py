@@ -271,3 +271,32 @@ def test_batch_plan_clamp_binding_items(L, orc):
                         e0n[:40], nthreads=8)
         assert np.array_equal(o["z"][:40].cpu().numpy(), od["z"]), P
         assert np.array_equal(o["tclr"][:40].cpu().numpy(), od["tclr"]), P
+
+
+def test_batch_plan_with_empty_and_single_items(L, orc):
+    """Items with no shots and with one shot, in both the persistent kernel
+    and the stream form (membrane L=16 does not fit the LDS), next to a
+    normal item."""
+    import torch
+    specs = [codes.by_name("toric2d:8"), codes.by_name("toric3d_membrane:16")]
+    cds = [L.Code(s, 0) for s in specs]
+    items = []
+    for spec, code, S in ((specs[0], cds[0], 0), (specs[1], cds[1], 0), (specs[0], cds[0], 1),
+                          (specs[1], cds[1], 1), (specs[0], cds[0], 77)):
+        q = 0.125 if "membrane" in spec.name else 0.05
+        e0 = L.sample_noise(code, 0.03, 5, 11, S) if S else torch.zeros((0, code.n), dtype=torch.uint8,
+                                                                           device="cuda")
+        items.append({"spec": spec, "code": code, "params": L.DecodeParams(q=q, rounds=8), "e0": e0, "shot0": 11})
+    plan = L.BatchPlan(items)
+    outs = plan.launch()
+    torch.cuda.synchronize()
+    for it, o in zip(items, outs):
+        S = it["e0"].shape[0]
+        assert o["z"].shape[0] == S
+        if S == 0:
+            continue
+        P = it["params"]
+        od = orc.decode(it["spec"], orc.DecodeParams(q=P.q, rounds=P.rounds), it["e0"][:1].cpu().numpy(),
+                        shot0=11)
+        assert np.array_equal(o["z"][:1].cpu().numpy(), od["z"]), it["spec"].name
+        assert int(o["tclr"][0]) == int(od["tclr"][0]), it["spec"].name
