@@ -300,7 +300,7 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
  *             (0 if H e0 = 0, -1 if never within iters)
  *   L_out     device [nshots][n] double or NULL: beliefs of the last iteration
  * Errors: LAIM_EUNSUP unless every check has degree 2 and every bit degree
- * <= 4, n <= 32768 and the state fits in LDS; LAIM_EINVAL for bad arguments.
+ * <= 4, n and m <= 3072 and the state fits in LDS; LAIM_EINVAL for bad arguments.
  */
 laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_t* e0,
                                    int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,

@@ -13,8 +13,9 @@
 // where every operation above is exact up to the additions' rounding.
 //
 // One block per shot; thread t owns bits t + k nt and writes the new
-// messages on their edges. LDS: old and new messages by edge (check-major
-// edge order, double-buffered), pi, f and s.
+// messages on their edges, with its edge indices and its checks' bits kept
+// in registers. LDS: old and new messages by edge (check-major edge order,
+// double-buffered), pi, f and s.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,6 +23,11 @@
 #include "laim_internal.h"
 
 namespace laim {
+
+// Bits (and checks) per thread: the thread's edge indices and its checks'
+// bits stay in registers for all iterations.
+constexpr int kBcMaxBits = 3;
+constexpr int kBcMaxDv = 4;
 
 __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0, const uint8_t* e0,
                                                           int32_t iters, uint8_t* z_out,
@@ -39,16 +45,40 @@ __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0,
   uint8_t* s = f + c.n;                                // [m]
   __shared__ int32_t any_s;
 
+  // per-thread tables: for bit v = t + k nt its degree and the LDS index
+  // 2 ch + j of each of its edges (ascending check); for check t + k nt its
+  // two bits
+  int32_t bdv[kBcMaxBits];
+  int32_t bix[kBcMaxBits][kBcMaxDv];
+  int32_t cb0[kBcMaxBits], cb1[kBcMaxBits];
+#pragma unroll
+  for (int k = 0; k < kBcMaxBits; ++k) {
+    const int32_t v = t + k * nt;
+    bdv[k] = (v < c.n) ? c.var_deg[v] : 0;
+#pragma unroll
+    for (int q = 0; q < kBcMaxDv; ++q) {
+      int32_t ix = 0;
+      if (q < bdv[k]) {
+        const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+        ix = edge_check(e) * 2 + edge_slot(e);
+      }
+      bix[k][q] = ix;
+    }
+    const int32_t ch = t + k * nt;
+    cb0[k] = (ch < c.m) ? c.chk_var[(int64_t)ch * c.dcmax] : 0;
+    cb1[k] = (ch < c.m) ? c.chk_var[(int64_t)ch * c.dcmax + 1] : 0;
+  }
+
   const uint8_t* e0row = e0 + shot * c.n;
   for (int32_t e = t; e < E; e += nt) {
     cv[0][e] = 0.0;
     vc[0][e] = 0.0;
   }
   for (int32_t v = t; v < c.n; v += nt) piv[v] = pi0;
-  for (int32_t ch = t; ch < c.m; ch += nt) {
-    uint32_t x = 0;
-    for (int32_t j = 0; j < c.chk_deg[ch]; ++j) x ^= e0row[c.chk_var[ch * c.dcmax + j]];
-    s[ch] = (uint8_t)(x & 1u);
+#pragma unroll
+  for (int k = 0; k < kBcMaxBits; ++k) {
+    const int32_t ch = t + k * nt;
+    if (ch < c.m) s[ch] = (uint8_t)((e0row[cb0[k]] ^ e0row[cb1[k]]) & 1u);
   }
   if (t == 0) any_s = 0;
   __syncthreads();
@@ -56,7 +86,7 @@ __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0,
     if (s[ch]) any_s = 1;
   __syncthreads();
   int32_t iclr = any_s ? -1 : 0;
-  uint32_t zbits = 0;  // correction of this thread's bits t + k nt (the host keeps k < 32)
+  uint32_t zbits = 0;  // correction of this thread's bits t + k nt
   int cur = 0;
 
   for (int32_t it = 1; it <= iters; ++it) {
@@ -66,46 +96,60 @@ __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0,
     double* nvc = vc[cur ^ 1];
     // new messages and beliefs of the owned bits from the old state; the LLR
     // switch of a flipped bit negates its prior and its new messages
-#pragma unroll 1
-    for (int32_t k = 0, v = t; v < c.n; ++k, v += nt) {
-      const int32_t dv = c.var_deg[v];
-      const int32_t* ve = c.var_edge + v * c.dvmax;
-      double L = piv[v];
-      for (int32_t q = 0; q < dv; ++q) L = L + mcv[edge_check(ve[q]) * 2 + edge_slot(ve[q])];
+#pragma unroll
+    for (int k = 0; k < kBcMaxBits; ++k) {
+      const int32_t v = t + k * nt;
+      if (v >= c.n) continue;
+      const int32_t dv = bdv[k];
+      const double pv = piv[v];
+      double m_in[kBcMaxDv];
+#pragma unroll
+      for (int q = 0; q < kBcMaxDv; ++q) m_in[q] = (q < dv) ? mcv[bix[k][q]] : 0.0;
+      double L = pv;
+#pragma unroll
+      for (int q = 0; q < kBcMaxDv; ++q)
+        if (q < dv) L = L + m_in[q];
       const bool flip = L > 0.0;
       if (L_out && it == iters) L_out[shot * c.n + v] = L;
-      for (int32_t q = 0; q < dv; ++q) {
-        const int32_t ch = edge_check(ve[q]);
-        const int32_t j = edge_slot(ve[q]);
-        const double other = mvc[ch * 2 + (1 - j)];
-        const double mc = s[ch] ? -other : other;
-        double acc = piv[v];
-        for (int32_t q2 = 0; q2 < dv; ++q2)
-          if (q2 != q) acc = acc + mcv[edge_check(ve[q2]) * 2 + edge_slot(ve[q2])];
-        ncv[ch * 2 + j] = flip ? -mc : mc;
-        nvc[ch * 2 + j] = flip ? -acc : acc;
+#pragma unroll
+      for (int q = 0; q < kBcMaxDv; ++q) {
+        if (q >= dv) continue;
+        const int32_t ix = bix[k][q];
+        const double other = mvc[ix ^ 1];          // the check's other edge
+        const double mc = s[ix >> 1] ? -other : other;
+        double acc = pv;
+#pragma unroll
+        for (int q2 = 0; q2 < kBcMaxDv; ++q2)
+          if (q2 < dv && q2 != q) acc = acc + m_in[q2];
+        ncv[ix] = flip ? -mc : mc;
+        nvc[ix] = flip ? -acc : acc;
       }
       f[v] = flip ? 1 : 0;
       if (flip) {
-        piv[v] = -piv[v];
+        piv[v] = -pv;
         zbits ^= 1u << k;
       }
     }
     if (t == 0) any_s = 0;
     __syncthreads();
     // syndrome update s_c ^= XOR over N(c) of f
-    for (int32_t ch = t; ch < c.m; ch += nt) {
-      uint32_t x = s[ch];
-      for (int32_t j = 0; j < c.chk_deg[ch]; ++j) x ^= f[c.chk_var[ch * c.dcmax + j]];
-      s[ch] = (uint8_t)(x & 1u);
-      if (x & 1u) any_s = 1;
+#pragma unroll
+    for (int k = 0; k < kBcMaxBits; ++k) {
+      const int32_t ch = t + k * nt;
+      if (ch >= c.m) continue;
+      const uint32_t x = (uint32_t)(s[ch] ^ f[cb0[k]] ^ f[cb1[k]]) & 1u;
+      s[ch] = (uint8_t)x;
+      if (x) any_s = 1;
     }
     __syncthreads();
     if (!any_s && iclr < 0) iclr = it;
     cur ^= 1;
   }
-#pragma unroll 1
-  for (int32_t k = 0, v = t; v < c.n; ++k, v += nt) z_out[shot * c.n + v] = (uint8_t)((zbits >> k) & 1u);
+#pragma unroll
+  for (int k = 0; k < kBcMaxBits; ++k) {
+    const int32_t v = t + k * nt;
+    if (v < c.n) z_out[shot * c.n + v] = (uint8_t)((zbits >> k) & 1u);
+  }
   if (t == 0) iclr_out[shot] = iclr;
 }
 
@@ -115,8 +159,8 @@ bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds) {
     return false;
   }
   *nt = (c.n < 1024) ? ((c.n + 63) / 64) * 64 : 1024;
-  if ((int64_t)c.n > 32LL * *nt) {
-    set_error("the bit-centric machine supports at most 32768 bits");
+  if ((int64_t)c.n > (int64_t)kBcMaxBits * *nt || (int64_t)c.m > (int64_t)kBcMaxBits * *nt) {
+    set_error("the bit-centric machine supports at most %d bits and checks", kBcMaxBits * 1024);
     return false;
   }
   int lds_max = 0;
