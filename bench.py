@@ -462,9 +462,11 @@ def main():
     #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
     #   2 d_c         scale and sign per output
     # = 19 for d_c = 4, d_v = 2 (2.375 per message update; 23 with the
-    # clamps). For sum-product,
-    # 3 (d_c - 2) box-plus steps (prefix and suffix folds, then one step per
-    # inner output) of BOXPLUS_OPS each plus d_c clamps.
+    # clamps). Sum-product has no fixed count: each of its 3 (d_c - 2)
+    # box-plus steps evaluates exp only for arguments up to 80 (a larger one
+    # gives 0 at once), so its work depends on the message magnitudes --
+    # about 66 VALU per step for small ones, little more than half of that
+    # once |m| is large. Its roofline therefore reports no fraction.
     # Beside it: the rate the stream form's HBM traffic would need for the
     # same sweeps (each check-to-qubit message written once and read once by
     # its partner's gather, 4 B each way, i.e. 4 B per message update
@@ -472,15 +474,13 @@ def main():
     # In the stream form the sweeps themselves stream through HBM and the
     # roofline is that traffic against the 8 TB/s peak.
     dc, dv = code.dc_max, code.dv_max
-    BOXPLUS_OPS = 66  # VALU per box-plus step (exp and log1p by fused Horner steps)
+    ops_check = None
     if args.bp == "minsum":
         pi = abs(np.log(P.q / (1.0 - P.q)))
         idle_clamp = dv == 2 and P.alpha < 1.0 and pi < 0.99 * P.clamp * (1.0 - P.alpha)
         ops_check = (dc * (dv - 1) + (0 if idle_clamp else dc) + (dc + 1) // 2 + 1
                      + dc * max(0, (dc - 1) // 2) + 2 * dc)
-    else:
-        ops_check = dc * dv + BOXPLUS_OPS * 3 * max(0, dc - 2) + dc
-    ops_per_update = ops_check / (2.0 * dc)
+    ops_per_update = ops_check / (2.0 * dc) if ops_check is not None else None
     bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
     hbm_equiv_gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
     default_workload = (L == 32 and args.p == 0.05 and args.shots == 65536 and R == 128
@@ -491,9 +491,10 @@ def main():
         if default_workload:
             traffic = profiled_traffic("resident_kernel_toric2d_L32_minsum.md",
                                        f"{shape['checks_per_thread']},{shape['shots_per_block']}")
-        achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12
-        rl = {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 1),
-              "unit": "Tops/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+        achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12 if ops_per_update else None
+        rl = {"bound": "alu", "achieved": round(achieved_tops, 3) if achieved_tops else None,
+              "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
+              "frac": round(achieved_tops / VALU_PEAK_TOPS, 4) if achieved_tops else None, "traffic": traffic,
               "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
               "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
               "msg_updates_per_launch": msg_per_launch,
