@@ -211,3 +211,56 @@ def test_sum_product_clears_every_2d_toric_shot(orc):
         out = orc.ctm_decode(code, CP(bp="sumproduct", t_max=50), e0, nthreads=8)
         assert np.all(out["tclr"] >= 0)
         assert orc.logical_failure(code, e0, out["z"]).mean() <= 0.05
+
+
+@pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
+def test_clock_decisions_follow_the_pinned_euler_state(orc, bp):
+    """Until the first flip the syndrome is the initial one, so the BP state
+    that event j sees is that of k Euler steps from zero, k the first step
+    count with k dt >= T_j; the affine-recursion and tree pins above fix
+    those steps. From that state, written out here: beliefs pi + sum of
+    m_{c->v} (ascending c, clamped), Evidence max_{v in N(c)} L_v >=
+    -log(d_c - 1), LocalMove the arg-max with ties split by word w2. Every
+    traced decision up to and including the first flip must agree, which
+    pins the decode path's own damping, step count and Evidence test."""
+    checked = ev_yes = ev_no = 0
+    for name, p in (("toric2d:6", 0.06), ("toric3d_point:3", 0.05), ("bb:6x6", 0.03)):
+        code = codes.by_name(name)
+        H = code.H.to_dense()
+        rp, cl = code.H.rowptr, code.H.col
+        params = CP(bp=bp, dt=0.01, tau=0.1, t_max=40, seed=3)
+        thr = orc.evidence_thresholds(int(np.diff(rp).max()))
+        pi = np.float32(math.log(params.q / (1 - params.q)))
+        for shot in range(6):
+            e0 = orc.sample_noise(code, p, 0, shot, 1)
+            out = orc.ctm_decode(code, params, e0, shot0=shot, trace_cap=100000)
+            s0 = (H @ e0[0]) % 2
+            for j, (t_ev, _, c, v) in enumerate(out["trace"]):
+                k = 0
+                while k * params.dt < t_ev:
+                    k += 1
+                mcv, _ = orc.ctm_bp_steps(code, params, s0, k)
+                c = int(c)
+                nb = cl[rp[c]:rp[c + 1]]
+                L = []
+                for u in nb:
+                    acc = pi
+                    for c2 in np.nonzero(H[:, u])[0]:
+                        e = rp[c2] + int(np.nonzero(cl[rp[c2]:rp[c2 + 1]] == u)[0][0])
+                        acc = np.float32(acc + mcv[e])
+                    L.append(np.float32(min(max(acc, -params.clamp), params.clamp)))
+                Lmax = max(L)
+                if Lmax >= thr[len(nb)]:
+                    ev_yes += 1
+                    ties = [u for u, x in zip(nb, L) if x == Lmax]
+                    w2 = int(orc.philox([shot & 0xFFFFFFFF, shot >> 32, j, 2],
+                                        [params.seed & 0xFFFFFFFF, params.seed >> 32])[0][2])
+                    want = int(ties[(w2 * len(ties)) >> 32])
+                else:
+                    ev_no += 1
+                    want = -1
+                assert int(v) == want, (name, shot, j, k, L)
+                checked += 1
+                if want >= 0:
+                    break
+    assert checked >= 20 and ev_yes >= 5 and ev_no >= 5, (checked, ev_yes, ev_no)

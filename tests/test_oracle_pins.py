@@ -420,6 +420,54 @@ def test_special_cases(orc, bp):
         assert r["tclr"][0] == 1 and np.array_equal(r["z"], one)
 
 
+@pytest.mark.parametrize("conflict", ["or", "xor"])
+@pytest.mark.parametrize("bp,rho", [("minsum", 0.5), ("sumproduct", 1.0), ("minsum", 0.125)])
+def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict):
+    """The feedback step of every round, re-derived here (Algorithm 1 with one
+    Philox draw per check and round): check c rings when word 0 of
+    Philox(seed, (shot_lo, shot_hi, c, 16 r + 1)) is below floor(rho 2^32);
+    an active ringing check has Evidence when max_{v in N(c)} L_v >=
+    -log(d_c - 1) and then asks for the arg-max qubit, ties split by word 1;
+    the requests combine by OR or XOR. The beliefs L of round r come from a
+    run stopped after r + 1 rounds (without the gauge option the state is
+    not touched after the feedback), the window and tree pins above fix BP
+    itself, and the traced z of successive rounds give the flips f."""
+    checked = asked = 0
+    for name, p in (("toric2d:6", 0.08), ("bb:6x6", 0.04), ("toric3d_point:3", 0.04)):
+        c = codes.by_name(name)
+        H = c.H.to_dense()
+        rp, cl = c.H.rowptr, c.H.col
+        thr = orc.evidence_thresholds(int(np.diff(rp).max()))
+        bound = orc.bernoulli_bound(rho)
+        prm = dict(bp=bp, mask_density=rho, conflict=conflict, retire=False, seed=11, iters=6)
+        R = 6
+        for shot in range(3):
+            e0 = orc.sample_noise(c, p, 0, shot, 1)
+            tr = orc.decode(c, P(rounds=R, **prm), e0, shot0=shot, trace=True)
+            s_r = (H @ e0[0]) % 2
+            z_prev = np.zeros(c.n, dtype=np.uint8)
+            for r in range(R):
+                L = orc.decode(c, P(rounds=r + 1, **prm), e0, shot0=shot, want_beliefs=True)["L"][0]
+                cnt = np.zeros(c.n, dtype=np.int64)
+                for ch in np.nonzero(s_r)[0]:
+                    w = orc.philox([shot, 0, int(ch), 16 * r + 1], [prm["seed"], 0])[0]
+                    if int(w[0]) >= bound:
+                        continue
+                    nb = cl[rp[ch]:rp[ch + 1]]
+                    Lmax = L[nb].max()
+                    if not Lmax >= thr[len(nb)]:
+                        continue
+                    ties = nb[L[nb] == Lmax]
+                    cnt[ties[(int(w[1]) * len(ties)) >> 32]] += 1
+                    asked += 1
+                f = (cnt > 0) if conflict == "or" else (cnt % 2 == 1)
+                assert np.array_equal(tr["z_trace"][r] ^ z_prev, f.astype(np.uint8)), (name, shot, r)
+                z_prev = tr["z_trace"][r]
+                s_r = tr["s_trace"][r]
+                checked += 1
+    assert checked == 3 * 3 * 6 and asked >= 20, asked
+
+
 @pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
 def test_retire_equals_fixed_rounds(orc, bp):
     """Once s = 0 no check is active, so stopping a shot early changes none
