@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--bp", default="minsum", choices=["minsum", "sumproduct"])
     ap.add_argument("--form", default="resident", choices=["resident", "stream", "auto"])
     ap.add_argument("--no-retire", action="store_true")
+    ap.add_argument("--no-skip", action="store_true",
+                    help="run every BP sweep (no skipping at a fixed point of the messages)")
     ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -339,17 +341,19 @@ def serving(laim, seconds):
 def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
     """Runs warmup + steps passes; returns per-step and per-decode times (ms)
     from HIP events on the stream every kernel is launched on, plus the
-    executed rounds of the last step."""
+    rounds run and BP sweeps computed over the timed steps."""
     import torch
     S = args.shots
     st = torch.cuda.current_stream()
     e0 = torch.empty((S, code.n), dtype=torch.uint8, device="cuda")
     out = {"z": torch.empty((S, code.n), dtype=torch.uint8, device="cuda"),
            "s": torch.empty((S, code.m), dtype=torch.uint8, device="cuda"),
-           "tclr": torch.empty((S,), dtype=torch.int32, device="cuda"), "L": None}
+           "tclr": torch.empty((S,), dtype=torch.int32, device="cuda"), "L": None,
+           "sweeps": torch.empty((S,), dtype=torch.int32, device="cuda")}
     ws = torch.empty((max(laim.workspace_bytes(code, P, S, form), 256),), dtype=torch.uint8, device="cuda")
     fails = torch.zeros((), dtype=torch.int64, device="cuda")
     rounds_exec = torch.zeros((), dtype=torch.int64, device="cuda")
+    sweeps_exec = torch.zeros((), dtype=torch.int64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
@@ -367,12 +371,14 @@ def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
         fails.add_(f.sum())
         t = out["tclr"]
         rounds_exec.add_(torch.where(t >= 0, t, torch.full_like(t, P.rounds)).sum())
+        sweeps_exec.add_(out["sweeps"].sum())
 
     for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
     fails.zero_()
     rounds_exec.zero_()
+    sweeps_exec.zero_()
     t0.record(st)
     for i in range(steps):
         step(warmup + i, ev[i])
@@ -382,7 +388,7 @@ def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
     dec_ms = [a.elapsed_time(b) for a, b in ev]
     return {"ms_per_step": total_ms / steps, "decode_ms": sum(dec_ms) / steps,
             "failures": int(fails.item()), "rounds_exec": int(rounds_exec.item()),
-            "shots": S * steps}
+            "sweeps_exec": int(sweeps_exec.item()), "shots": S * steps}
 
 
 def cpu_baseline(args, spec, P_or, seconds, nthreads=None, max_shots=4096):
@@ -422,7 +428,8 @@ def main():
     spec = codes.toric_2d(L)
     code = laim.Code(spec, 0)
     E = code.E
-    P = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire)
+    skip = not args.no_skip
+    P = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire, skip_fixed=skip)
     form = args.form
     if args.calibrate_copy_mb:
         src = torch.ones((args.calibrate_copy_mb << 20,), dtype=torch.uint8, device="cuda")
@@ -444,10 +451,14 @@ def main():
     S_total = main_run["shots"]
     sec = main_run["ms_per_step"] * args.steps / 1000.0
     shots_per_s = S_total / sec
+    # message updates of the method (every sweep of every round run) and
+    # those the kernels computed (sweeps at a fixed point are skipped)
     msg_updates = 2 * E * args.iters * main_run["rounds_exec"]
-    msg_per_s = msg_updates / sec
+    msg_computed = 2 * E * main_run["sweeps_exec"]
+    msg_per_s = msg_computed / sec
     dec_s = main_run["decode_ms"] / 1000.0
-    msg_per_launch = msg_updates / args.steps
+    msg_per_launch = msg_computed / args.steps
+    sweeps_frac = main_run["sweeps_exec"] / max(1, args.iters * main_run["rounds_exec"])
 
     # Roofline of the dominant kernel. The resident decode launch keeps every
     # message on chip, so HBM carries only e0 in and z, s, t_clr out; its
@@ -473,6 +484,9 @@ def main():
     # counting both directions, plus 1 B of syndrome per check and sweep).
     # In the stream form the sweeps themselves stream through HBM and the
     # roofline is that traffic against the 8 TB/s peak.
+    # Only computed sweeps count as work: with the fixed-point skip the
+    # kernel also spends time comparing each new message with the one it
+    # replaces, and the feedback phase is a larger share of the launch.
     dc, dv = code.dc_max, code.dv_max
     ops_check = None
     if args.bp == "minsum":
@@ -497,7 +511,7 @@ def main():
               "frac": round(achieved_tops / VALU_PEAK_TOPS, 4) if achieved_tops else None, "traffic": traffic,
               "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
               "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
-              "msg_updates_per_launch": msg_per_launch,
+              "msg_updates_per_launch": msg_per_launch, "sweeps_computed_frac": round(sweeps_frac, 4),
               "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
               "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
     else:
@@ -551,6 +565,23 @@ def main():
                                  "decode_ms": round(rs["decode_ms"], 2),
                                  "algorithmic_hbm_GBs": round(sweeps_bytes / (rs["decode_ms"] / 1000) / 1e9, 1),
                                  "failures": rs["failures"]}
+        if skip:
+            # the same launch running every sweep: identical results
+            rn = timed_steps(laim, code, laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters,
+                                                           retire=not args.no_retire, skip_fixed=False),
+                             args, 2, 1, form)
+            sec_n = rn["ms_per_step"] * 2 / 1000  # two timed steps
+            extras["every_sweep"] = {
+                "shots_per_s": round(rn["shots"] / sec_n, 1),
+                "decode_ms": round(rn["decode_ms"], 3),
+                "msg_updates_per_s": 2 * E * rn["sweeps_exec"] / sec_n,
+                "failures_per_shot": rn["failures"] / rn["shots"],
+                "what": "skip_fixed = 0: every BP sweep computed; same z, s, t_clr as the value"}
+            if ops_per_update and form != "stream":
+                upd_launch = 2 * E * rn["sweeps_exec"] / 2  # two timed launches
+                ach = upd_launch * ops_per_update / (rn["decode_ms"] / 1000) / 1e12
+                extras["every_sweep"]["roofline"] = {"achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 1),
+                                                     "unit": "Tops/s", "frac": round(ach / VALU_PEAK_TOPS, 4)}
         P_fix = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=False)
         rf = timed_steps(laim, code, P_fix, args, 1, 0, form, shot_base=2 * 10**9)
         extras["fixed_rounds"] = {"shots_per_s": round(rf["shots"] / (rf["ms_per_step"] / 1000), 1),
@@ -629,9 +660,11 @@ def main():
                                f"{form} form",
                    "code": f"toric2d:{L}", "p": args.p, "shots_per_step": args.shots, "rounds": R,
                    "iters": args.iters, "bp": args.bp, "form": form, "retire": not args.no_retire,
+                   "skip_fixed": skip and form != "stream",
                    "resident_shape": code.resident_cfg(args.bp) if form != "stream" else None,
                    "autotuned": tuned is not None},
         "msg_updates_per_s": msg_per_s,
+        "msg_updates_of_the_method_per_s": msg_updates / sec,
         "logical_error_rate": main_run["failures"] / S_total,
         "served_latency": (
             {"p50_round_ms": extras["serving"]["open_loop"][1]["p50_round_ms"],

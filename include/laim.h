@@ -150,7 +150,19 @@ typedef struct {
   int32_t retire;       /* 1: stop a shot at its first clear syndrome (same z, s, t_clr) */
   uint64_t seed;        /* Philox key for the clocks and tie-breaks */
   int32_t conflict;     /* how one round's move requests combine, LAIM_CONFLICT_* (0: OR) */
+  int32_t skip_fixed;   /* 1: skip sweeps that cannot change anything (see below); 0: run all */
 } laim_decode_params;
+
+/* skip_fixed. Within a round the sweep is a fixed map of the messages (the
+ * syndrome, prior and parameters do not change), so once a sweep writes
+ * every message of a shot back bit for bit, every later sweep does the same
+ * until a flip changes the syndrome. With skip_fixed = 1 the resident form
+ * detects such a sweep (comparing each new message with the one it
+ * replaces) and leaves the shot's messages as they are for the rest of the
+ * round and for following rounds without a flip. A shot's first sweep
+ * (v->c messages 0) is a different map and never counts. z, s, t_clr and
+ * the beliefs are bit-identical to running every sweep; only the sweeps
+ * computed (sweeps_out) differ. The stream form always runs every sweep. */
 
 /* Conflict rules. Algorithm 1 lets one clock ring at a time; a round of the
  * discretised machine gathers the requests of every check that rang, and
@@ -188,13 +200,16 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
  *   L_out      device [nshots][n] float or NULL: beliefs of the final message
  *              state, clamp(pi + sum over N(v) of m_{c->v}) (for a retired
  *              shot, the state at retirement)
+ *   sweeps_out device [nshots] int32 or NULL: BP sweeps computed for each
+ *              shot; iters x (rounds the shot ran) unless skip_fixed skipped
+ *              some (saturates at 2^31 - 1)
  * Concurrent calls on different streams may share a laim_code but not a
  * workspace.
  */
 laim_status laim_decode_rounds(const laim_code* code, const laim_decode_params* params,
                                const uint8_t* e0, uint64_t shot0, int32_t nshots, void* workspace,
                                size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
-                               float* L_out, int32_t form, laim_stream stream);
+                               float* L_out, int32_t* sweeps_out, int32_t form, laim_stream stream);
 
 /* Launch shape of the resident form (0 in a field means: choose). */
 typedef struct {
@@ -209,7 +224,8 @@ laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_para
                                    const uint8_t* e0, uint64_t shot0, int32_t nshots,
                                    void* workspace, size_t ws_bytes, uint8_t* z_out,
                                    uint8_t* s_out, int32_t* tclr_out, float* L_out,
-                                   const laim_resident_cfg* cfg, laim_stream stream);
+                                   int32_t* sweeps_out, const laim_resident_cfg* cfg,
+                                   laim_stream stream);
 
 /* Sets the resident launch shape used from now on for this code and BP
  * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */

@@ -51,6 +51,8 @@ struct KParams {
   int32_t retire;
   uint64_t seed;
   int32_t conflict;  // kConflict*
+  int32_t skip;      // 1: a group whose messages are a fixed point of the sweep skips the
+                     // round's remaining (identity) sweeps
 };
 
 // How one round's move requests combine (values of laim_decode_params.conflict).
@@ -94,10 +96,13 @@ inline bool reg_dv2_ok(const KParams& kp) {
 bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, ResidentShape* out,
                     int device, bool seq = false, bool reg2 = true);
 size_t resident_workspace_bytes();
+// sweeps[i] = iters x (rounds shot i ran), for the forms that run every sweep
+hipError_t launch_sweep_count(const KParams& kp, const int32_t* tclr, int32_t nshots, int32_t* sweeps,
+                              hipStream_t st);
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
                            uint8_t* z, uint8_t* s, int32_t* tclr, float* L, uint8_t* fail,
-                           hipStream_t st);
+                           int32_t* sweeps, hipStream_t st);
 
 size_t stream_workspace_bytes(const DevCode& c, int32_t nshots, bool seq);
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
@@ -148,7 +153,7 @@ struct ServerReqDev {
   float* msg;         // [m * dcmax]
   uint8_t* z;         // [n]
   uint8_t* s;         // [m]
-  int32_t* hdr;       // [4]: t_clr
+  int32_t* hdr;       // [4]: t_clr, messages at a fixed point (0/1)
   int32_t* ev;        // [2]: flips, syndrome weight
   uint8_t* fail;      // [1]
 };

@@ -166,25 +166,34 @@ struct GroupJob {
   float* st_msg;         // resumable state or null: [m * dcmax] m_{c->v} in ELL order,
   uint8_t* st_z;         //   [n] correction, [m] syndrome,
   uint8_t* st_s;
-  int32_t* st_hdr;       //   [0] t_clr
+  int32_t* st_hdr;       //   [0] t_clr, [1] messages at a fixed point
   uint8_t* z_out;        // results or null: [n] z, [m] s, t_clr, [n] beliefs,
   uint8_t* s_out;
   int32_t* t_out;
   float* L_out;
   uint8_t* f_out;        //   logical failure (0/1)
   int32_t* ev_out;       //   [4] flips and syndrome weight of the last round run, t_clr, failure
+  int32_t* sw_out;       //   BP sweeps computed
 };
 
-constexpr int kCtrlWords = 64;  // [0] queue value, [1 + g] group still working,
+constexpr int kCtrlWords = 64;  // [0] queue value, [1 + g] group still working (bit 0)
+                                // and needing sweeps (bit 1), [kCtrlChg0, kCtrlChg1]
+                                // "a message changed" in even / odd sweeps,
                                 // [kCtrlSeq0 .. + 2] sequential-rule pass flags
+constexpr int kCtrlChg0 = 56, kCtrlChg1 = 57;
 constexpr int kCtrlSeq0 = 60;
 constexpr uint8_t kNoRequest = 0x7F;
 constexpr int kMaxShotsPerBlock = 31;
 constexpr int kGroupWords = 16;  // per-group scratch words after msg
 // scratch word indices
 constexpr int kGwZero = 0, kGwLpar = 1 /* 4 words */, kGwFlips = 5, kGwDefects = 6, kGwInit = 7,
-              kGwAct0 = 8, kGwAct1 = 9;
+              kGwAct0 = 8, kGwAct1 = 9, kGwChg0 = 10, kGwChg1 = 11;
 constexpr int kFusedMaxWords = 4;  // logicals folded in LDS by the fused failure test
+
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
 
 __device__ __forceinline__ GroupJob dead_job() {
   GroupJob j;
@@ -200,6 +209,7 @@ __device__ __forceinline__ GroupJob dead_job() {
   j.L_out = nullptr;
   j.f_out = nullptr;
   j.ev_out = nullptr;
+  j.sw_out = nullptr;
   return j;
 }
 
@@ -241,6 +251,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   uint8_t* rq = reinterpret_cast<uint8_t*>(rkey + c.m);            // [m]
   const float C = kp.clamp;
   const float pi = kp.pi;
+  const float thr_reg = REG ? c.thr[DC] : 0.0f;  // Evidence bound of the one check degree
 
   // ---- per-thread graph tables
   int32_t cidx[CPT];
@@ -339,130 +350,184 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   bool working = alive && !(kp.retire && tclr >= 0);
   bool fresh = !u.resume;
   int32_t flips_last = 0;
+  // conv: the group's messages are a fixed point of the sweep for its
+  // current syndrome -- a sweep wrote every message back bit for bit. The
+  // sweep is a deterministic map of (messages, syndrome), so every further
+  // sweep is the identity until a flip changes the syndrome, and the group
+  // skips them (with kp.skip; the results are those of all the sweeps).
+  bool conv = kp.skip && member && u.resume && alive && job_at(g).st_hdr[1] != 0;
+  int32_t nsweeps = 0;
 
   for (int32_t rr = 0; rr < u.rounds; ++rr) {
     const int32_t r = r0 + rr;
     __syncthreads();
     if (member && t == 0) {
-      ctrl[1 + g] = working ? 1 : 0;
+      ctrl[1 + g] = working ? (conv ? 1 : 3) : 0;
       gw[((rr + 1) & 1) ? kGwAct1 : kGwAct0] = 0;
       gw[kGwFlips] = 0;
+      gw[kGwChg0] = 0;
+      gw[kGwChg1] = 0;
+    }
+    if (tid == 0) {
+      ctrl[kCtrlChg0] = 0;
+      ctrl[kCtrlChg1] = 0;
     }
     __syncthreads();
     int32_t anyw = 0;
     for (int32_t h = 0; h < spb; ++h) anyw |= ctrl[1 + h];
     if (!anyw) break;
 
-    // ---- BP sweeps
-    int32_t it0 = 0;
-    if (fresh && REG && kp.iters > 0) {
-      // First sweep of a shot: every m_{v->c} is 0, so each check sends
-      // (-1)^{s_c + d_c} * 0 (min-sum: alpha * 0; sum-product: 0 [+] 0 = +0).
-      if (working) {
+    // ---- BP sweeps, only while some working group is not at a fixed point
+    bool sweep = working && !conv;
+    if (anyw & 2) {
+      int32_t it0 = 0;
+      if (fresh && REG && kp.iters > 0) {
+        // First sweep of a shot: every m_{v->c} is 0, so each check sends
+        // (-1)^{s_c + d_c} * 0 (min-sum: alpha * 0; sum-product: 0 [+] 0 = +0).
+        if (sweep) {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-          if (cidx[k] < 0) continue;
-          const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
-          float* mk = msg + msg_word<DC>(cidx[k], 0);
+          for (int k = 0; k < CPT; ++k) {
+            if (cidx[k] < 0) continue;
+            const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
+            float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
-          for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = z0;
-        }
-      }
-      fresh = false;
-      it0 = 1;
-      __syncthreads();
-    }
-    for (int32_t it = it0; it < kp.iters; ++it) {
-      float x[CPT][DC];
-      if (!REG && fresh) {
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-#pragma unroll
-          for (int j = 0; j < DC; ++j) x[k][j] = (j >= deg[k]) ? __builtin_inff() : 0.0f;
-      } else {
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-#pragma unroll
-          for (int j = 0; j < DC; ++j) {
-            float acc = pi;
-#pragma unroll
-            for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
-            // min-sum on qubits of degree 2 (exact variants, run only when
-            // alpha < 1 and |pi| / (1 - alpha) < CLAMP): |m_{v->c}| stays
-            // below |pi| / (1 - alpha), so the clamp cannot bind
-            if (!(BP == 0 && REG && DV == 2)) acc = __builtin_amdgcn_fmed3f(acc, -C, C);
-            if (!REG && j >= deg[k]) acc = __builtin_inff();
-            x[k][j] = acc;
+            for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = z0;
           }
         }
+        fresh = false;
+        it0 = 1;
+        nsweeps += sweep ? 1 : 0;
+        __syncthreads();
       }
-      __syncthreads();
-      if (working) {
+      // CMP: compare each new message with the one it replaces; the flags
+      // of even and odd sweeps alternate, so that a flag is cleared only
+      // after every thread has read it. A shot's first sweep (m_{v->c} = 0
+      // rather than pi + sum m_{c->v}) is another map and never counts as
+      // a fixed point.
+      auto sweeps = [&](auto cmp_tag) {
+        constexpr bool CMP = decltype(cmp_tag)::value;
+        for (int32_t it = it0; it < kp.iters; ++it) {
+          const bool first = fresh;
+          float x[CPT][DC];
+          if (sweep) {
+            if (!REG && fresh) {
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-          if (cidx[k] < 0) continue;
-          const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
-          float out[DC];
-          if (BP == 0) {
-            // normalised min-sum: alpha * (smallest other |m|) with the
-            // sign product. No input is -0 (pi + messages with pi != -0,
-            // or +0 on a fresh sweep), so the sign bit is sg(). The sign
-            // product of all inputs goes into the scale (alpha * min
-            // rounds the same for either sign); each output then removes
-            // its own input's sign with one bit operation.
-            uint32_t par = sigma_neg << 31;
+              for (int k = 0; k < CPT; ++k)
 #pragma unroll
-            for (int j = 0; j + 1 < DC; j += 2)
-              par = xor3(par, __float_as_uint(x[k][j]), __float_as_uint(x[k][j + 1]));
-            if (DC & 1) par ^= __float_as_uint(x[k][DC - 1]);
-            const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
-            float ex[DC];  // smallest |m| over the other inputs
-            if (DC == 2) {
-              ex[0] = fabsf(x[k][1]);
-              ex[1] = fabsf(x[k][0]);
-            } else if (DC == 4) {
-              ex[0] = min3_abs(x[k][1], x[k][2], x[k][3]);
-              ex[1] = min3_abs(x[k][0], x[k][2], x[k][3]);
-              ex[2] = min3_abs(x[k][0], x[k][1], x[k][3]);
-              ex[3] = min3_abs(x[k][0], x[k][1], x[k][2]);
+                for (int j = 0; j < DC; ++j) x[k][j] = (j >= deg[k]) ? __builtin_inff() : 0.0f;
             } else {
-              float pre[DC], suf[DC];
-              pre[1] = fabsf(x[k][0]);
 #pragma unroll
-              for (int j = 2; j < DC; ++j) pre[j] = fminf(pre[j - 1], fabsf(x[k][j - 1]));
-              suf[DC - 2] = fabsf(x[k][DC - 1]);
+              for (int k = 0; k < CPT; ++k) {
 #pragma unroll
-              for (int j = DC - 3; j >= 0; --j) suf[j] = fminf(suf[j + 1], fabsf(x[k][j + 1]));
-              ex[0] = suf[0];
-              ex[DC - 1] = pre[DC - 1];
+                for (int j = 0; j < DC; ++j) {
+                  float acc = pi;
 #pragma unroll
-              for (int j = 1; j < DC - 1; ++j) ex[j] = fminf(pre[j], suf[j]);
+                  for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
+                  // min-sum on qubits of degree 2 (exact variants, run only when
+                  // alpha < 1 and |pi| / (1 - alpha) < CLAMP): |m_{v->c}| stays
+                  // below |pi| / (1 - alpha), so the clamp cannot bind
+                  if (!(BP == 0 && REG && DV == 2)) acc = __builtin_amdgcn_fmed3f(acc, -C, C);
+                  if (!REG && j >= deg[k]) acc = __builtin_inff();
+                  x[k][j] = acc;
+                }
+              }
             }
-#pragma unroll
-            for (int j = 0; j < DC; ++j) {
-              // With degree >= 2 there is an input to take the minimum of,
-              // so |v| <= alpha * clamp <= clamp (the resident min-sum path
-              // runs only with alpha <= 1) and the output clamp cannot bind;
-              // a degree-1 check of an irregular code has an empty minimum
-              // (+inf) and is clamped.
-              float v = alpha_s * ex[j];
-              if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
-              out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
-            }
-          } else {
-            // sum-product: box-plus of the other inputs (prefix/suffix folds)
-            float acc[DC];
-            boxplus_others<DC, REG>(x[k], deg[k], acc);
-#pragma unroll
-            for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
           }
-          float* mk = msg + msg_word<DC>(cidx[k], 0);
+          __syncthreads();
+          if (CMP) {
+            if (member && t == 0) gw[(it & 1) ? kGwChg0 : kGwChg1] = 0;
+            if (tid == 0) ctrl[(it & 1) ? kCtrlChg0 : kCtrlChg1] = 0;
+          }
+          uint32_t diff = 0u;
+          if (sweep) {
 #pragma unroll
-          for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = out[j];
+            for (int k = 0; k < CPT; ++k) {
+              if (cidx[k] < 0) continue;
+              const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
+              float out[DC];
+              if (BP == 0) {
+                // normalised min-sum: alpha * (smallest other |m|) with the
+                // sign product. No input is -0 (pi + messages with pi != -0,
+                // or +0 on a fresh sweep), so the sign bit is sg(). The sign
+                // product of all inputs goes into the scale (alpha * min
+                // rounds the same for either sign); each output then removes
+                // its own input's sign with one bit operation.
+                uint32_t par = sigma_neg << 31;
+#pragma unroll
+                for (int j = 0; j + 1 < DC; j += 2)
+                  par = xor3(par, __float_as_uint(x[k][j]), __float_as_uint(x[k][j + 1]));
+                if (DC & 1) par ^= __float_as_uint(x[k][DC - 1]);
+                const float alpha_s = __uint_as_float(__float_as_uint(kp.alpha) ^ (par & 0x80000000u));
+                float ex[DC];  // smallest |m| over the other inputs
+                if (DC == 2) {
+                  ex[0] = fabsf(x[k][1]);
+                  ex[1] = fabsf(x[k][0]);
+                } else if (DC == 4) {
+                  ex[0] = min3_abs(x[k][1], x[k][2], x[k][3]);
+                  ex[1] = min3_abs(x[k][0], x[k][2], x[k][3]);
+                  ex[2] = min3_abs(x[k][0], x[k][1], x[k][3]);
+                  ex[3] = min3_abs(x[k][0], x[k][1], x[k][2]);
+                } else {
+                  float pre[DC], suf[DC];
+                  pre[1] = fabsf(x[k][0]);
+#pragma unroll
+                  for (int j = 2; j < DC; ++j) pre[j] = fminf(pre[j - 1], fabsf(x[k][j - 1]));
+                  suf[DC - 2] = fabsf(x[k][DC - 1]);
+#pragma unroll
+                  for (int j = DC - 3; j >= 0; --j) suf[j] = fminf(suf[j + 1], fabsf(x[k][j + 1]));
+                  ex[0] = suf[0];
+                  ex[DC - 1] = pre[DC - 1];
+#pragma unroll
+                  for (int j = 1; j < DC - 1; ++j) ex[j] = fminf(pre[j], suf[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                  // With degree >= 2 there is an input to take the minimum of,
+                  // so |v| <= alpha * clamp <= clamp (the resident min-sum path
+                  // runs only with alpha <= 1) and the output clamp cannot bind;
+                  // a degree-1 check of an irregular code has an empty minimum
+                  // (+inf) and is clamped.
+                  float v = alpha_s * ex[j];
+                  if (!REG) v = __builtin_amdgcn_fmed3f(v, -C, C);
+                  out[j] = __uint_as_float(__float_as_uint(v) ^ (__float_as_uint(x[k][j]) & 0x80000000u));
+                }
+              } else {
+                // sum-product: box-plus of the other inputs (prefix/suffix folds)
+                float acc[DC];
+                boxplus_others<DC, REG>(x[k], deg[k], acc);
+#pragma unroll
+                for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
+              }
+              float* mk = msg + msg_word<DC>(cidx[k], 0);
+              if (CMP) {  // the padding slots of irregular checks are never read
+#pragma unroll
+                for (int j = 0; j < DC; ++j)
+                  if (REG || j < deg[k]) diff |= __float_as_uint(mk[j * kSlotStride]) ^ __float_as_uint(out[j]);
+              }
+#pragma unroll
+              for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = out[j];
+            }
+          }
+          if (CMP && sweep && (diff || first)) {
+            gw[(it & 1) ? kGwChg1 : kGwChg0] = 1;
+            ctrl[(it & 1) ? kCtrlChg1 : kCtrlChg0] = 1;
+          }
+          fresh = false;
+          __syncthreads();
+          nsweeps += sweep ? 1 : 0;
+          if (CMP) {
+            if (sweep && gw[(it & 1) ? kGwChg1 : kGwChg0] == 0) {
+              sweep = false;
+              conv = true;
+            }
+            if (ctrl[(it & 1) ? kCtrlChg1 : kCtrlChg0] == 0) break;  // no group changed
+          }
         }
-      }
-      fresh = false;
-      __syncthreads();
+      };
+      if (kp.skip)
+        sweeps(BoolTag<true>());
+      else
+        sweeps(BoolTag<false>());
     }
 
     // ---- feedback: every active check whose clock rang tests Evidence
@@ -489,26 +554,47 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
         float Lmax = -__builtin_inff();
+        if (REG && DV == 2) {
+          // Qubit j has two messages: the check's own and the one of the
+          // other check of the qubit (one read of the partner table for
+          // all j), added to pi in ascending check order as everywhere.
+          // (a regular variant runs only on codes whose every check has degree
+          // DC and every qubit degree DV, so a row holds DC entries)
+          const int32_t* prow = c.partner + (int64_t)ch * DC;
+          int32_t pe[DC];
 #pragma unroll
-        for (int j = 0; j < DC; ++j) {
-          if (j >= d) continue;
-          const int32_t v = nb[j];
-          const int32_t dv = REG ? DV : c.var_deg[v];
-          float acc = pi;
+          for (int j = 0; j < DC; ++j) pe[j] = prow[j];
 #pragma unroll
-          for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
-            const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-            acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
+          for (int j = 0; j < DC; ++j) {
+            const int32_t c2 = edge_check(pe[j]);
+            const float own = msg[msg_word<DC>(ch, j)];
+            const float oth = msg[msg_word<DC>(c2, edge_slot(pe[j]))];
+            const float acc = clampf(c2 < ch ? (pi + oth) + own : (pi + own) + oth, C);
+            Lv[j] = acc;
+            if (j == 0 || acc > Lmax) Lmax = acc;
           }
-          acc = clampf(acc, C);
-          Lv[j] = acc;
-          if (j == 0 || acc > Lmax) Lmax = acc;
+        } else {
+#pragma unroll
+          for (int j = 0; j < DC; ++j) {
+            if (j >= d) continue;
+            const int32_t v = nb[j];
+            const int32_t dv = REG ? DV : c.var_deg[v];
+            float acc = pi;
+#pragma unroll
+            for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
+              const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+              acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
+            }
+            acc = clampf(acc, C);
+            Lv[j] = acc;
+            if (j == 0 || acc > Lmax) Lmax = acc;
+          }
         }
         if (d == 0) continue;
         // The move needs both the Evidence bound and the check's clock; the
         // bound is tested first, so the random words are drawn only when
         // it holds.
-        if (kp.evidence && !(Lmax >= c.thr[d])) continue;
+        if (kp.evidence && !(Lmax >= (REG ? thr_reg : c.thr[d]))) continue;
         const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
                                         ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
                                         (uint32_t)(kp.seed >> 32));
@@ -644,6 +730,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       const bool any = gw[(rr & 1) ? kGwAct1 : kGwAct0] != 0;
       if (!any && tclr < 0) tclr = r + 1;
       flips_last = nfl;
+      if (nfl) conv = false;  // the syndrome changed
       if (kp.retire && tclr >= 0) working = false;
     }
   }
@@ -667,6 +754,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       }
     }
     if (job.t_out && t == 0) job.t_out[0] = tclr;
+    if (job.sw_out && t == 0) job.sw_out[0] = nsweeps;
     if (job.L_out) {
 #pragma unroll 1
       for (int32_t v = t; v < c.n; v += u.nt) {
@@ -690,7 +778,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       }
 #pragma unroll 1
       for (int32_t v = t; v < c.n; v += u.nt) job.st_z[v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
-      if (t == 0) job.st_hdr[0] = tclr;
+      if (t == 0) {
+        job.st_hdr[0] = tclr;
+        job.st_hdr[1] = conv ? 1 : 0;
+      }
     }
     // fused success test: odd overlap of e0 ^ z with a logical, or s != 0
     if (job.f_out || job.ev_out) {
@@ -736,6 +827,7 @@ struct ResArgs {
   int32_t* tclr;
   float* L;
   uint8_t* fail;
+  int32_t* sweeps;
 };
 
 struct ResJobs {
@@ -749,6 +841,7 @@ struct ResJobs {
   int32_t* tclr;
   float* L;
   uint8_t* fail;
+  int32_t* sweeps;
   uint32_t* counter;
   int32_t spb;
   // Takes the next spb shots from the launch's queue; false once it is empty.
@@ -772,6 +865,7 @@ struct ResJobs {
     j.t_out = tclr + idx;
     j.L_out = L ? L + (int64_t)idx * n : nullptr;
     j.f_out = fail ? fail + idx : nullptr;
+    j.sw_out = sweeps ? sweeps + idx : nullptr;
     return j;
   }
 };
@@ -782,7 +876,8 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
   // control words after the groups, so that group 0's messages start at
   // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
-  ResJobs jobs{a.e0, a.shot0, a.nshots, c.n, c.m, 0, a.z, a.s, a.tclr, a.L, a.fail, a.counter, a.u.spb};
+  ResJobs jobs{a.e0,   a.shot0, a.nshots, c.n,      c.m,      0,        a.z,
+               a.s,    a.tclr,  a.L,      a.fail,   a.sweeps, a.counter, a.u.spb};
   run_units<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
 }
 
@@ -1133,11 +1228,32 @@ hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev*
   return hipGetLastError();
 }
 
+// A shot runs every round until it retires: t_clr rounds if it cleared and
+// retires, else all of them (a shot clear from the start runs none).
+__global__ void __launch_bounds__(256) sweep_count_kernel(int32_t iters, int32_t rounds, int32_t retire,
+                                                          const int32_t* __restrict__ tclr,
+                                                          int32_t nshots, int32_t* __restrict__ sweeps) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nshots) return;
+  const int32_t t = tclr[i];
+  const int64_t k = (int64_t)iters * ((retire && t >= 0) ? t : rounds);
+  sweeps[i] = (int32_t)(k < 2147483647 ? k : 2147483647);
+}
+
+hipError_t launch_sweep_count(const KParams& kp, const int32_t* tclr, int32_t nshots, int32_t* sweeps,
+                              hipStream_t st) {
+  if (nshots <= 0 || !sweeps) return hipSuccess;
+  hipLaunchKernelGGL(sweep_count_kernel, dim3((unsigned)((nshots + 255) / 256)), dim3(256), 0, st,
+                     kp.iters, kp.rounds, kp.retire, tclr, nshots, sweeps);
+  return hipGetLastError();
+}
+
 size_t resident_workspace_bytes() { return 256; }
 
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
-                           uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, hipStream_t st) {
+                           uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, int32_t* sweeps,
+                           hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   // the degrees the shape was sized for; the exact qubit-degree-2 min-sum
   // variants skip a clamp, so the shape must have allowed them
@@ -1162,6 +1278,7 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.tclr = tclr;
   a.L = L;
   a.fail = fail;
+  a.sweeps = sweeps;
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, a.counter, 1);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;

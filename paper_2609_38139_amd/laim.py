@@ -44,7 +44,7 @@ class Params(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
                 ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
-                ("seed", C.c_uint64), ("conflict", C.c_int32)]
+                ("seed", C.c_uint64), ("conflict", C.c_int32), ("skip_fixed", C.c_int32)]
 
 
 # LAIM_CONFLICT_*: how one round's move requests combine
@@ -85,6 +85,7 @@ class DecodeParams:
     retire: bool = True
     seed: int = 0
     conflict: str = "or"  # "or", "xor" or "sequential"
+    skip_fixed: bool = True  # skip sweeps once a shot's messages are a fixed point (same results)
 
     def c(self) -> Params:
         if self.bp not in ("minsum", "sumproduct"):
@@ -93,7 +94,8 @@ class DecodeParams:
             raise ValueError("conflict must be 'or', 'xor' or 'sequential'")
         return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
                       self.iters, self.rounds, self.mask_density, int(self.gauge),
-                      int(self.evidence), int(self.retire), self.seed, CONFLICT_RULES[self.conflict])
+                      int(self.evidence), int(self.retire), self.seed, CONFLICT_RULES[self.conflict],
+                      int(self.skip_fixed))
 
 
 class ContinuousParamsC(C.Structure):
@@ -154,9 +156,9 @@ def lib():
         L.laim_workspace_bytes.argtypes = [vp, C.POINTER(Params), i32, i32]
         L.laim_workspace_bytes.restype = sz
         L.laim_decode_rounds.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp, vp,
-                                         i32, vp]
+                                         vp, i32, vp]
         L.laim_decode_rounds_cfg.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp,
-                                             vp, C.POINTER(ResidentCfg), vp]
+                                             vp, vp, C.POINTER(ResidentCfg), vp]
         L.laim_set_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
         L.laim_get_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
         L.laim_logical_failure.argtypes = [vp, vp, vp, i32, vp, vp]
@@ -300,8 +302,9 @@ def workspace_bytes(code: Code, params: DecodeParams, nshots: int, form: str = "
 
 def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: str = "auto",
                   want_beliefs: bool = False, cfg: dict | None = None, workspace=None, out=None,
-                  stream=None) -> dict:
-    """``laim_decode_rounds``: returns device tensors z, s, tclr (and L)."""
+                  stream=None, want_sweeps: bool = False) -> dict:
+    """``laim_decode_rounds``: returns device tensors z, s, tclr (and L, and
+    with want_sweeps the BP sweeps computed per shot)."""
     import torch
     ns = e0.shape[0]
     _dev(e0, torch.uint8, (ns, code.n), "e0")
@@ -312,6 +315,8 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
                "s": torch.empty((ns, code.m), dtype=torch.uint8, device=dev),
                "tclr": torch.empty((ns,), dtype=torch.int32, device=dev),
                "L": torch.empty((ns, code.n), dtype=torch.float32, device=dev) if want_beliefs else None}
+    if want_sweeps and out.get("sweeps") is None:
+        out["sweeps"] = torch.empty((ns,), dtype=torch.int32, device=dev)
     f = FORM_RESIDENT if cfg is not None else FORMS[form]
     need = int(lib().laim_workspace_bytes(code.handle, C.byref(P), ns, f))
     if workspace is None or workspace.numel() < need:
@@ -319,14 +324,15 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
     if cfg is None:
         st = lib().laim_decode_rounds(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
                                       workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
-                                      _ptr(out["tclr"]), _ptr(out.get("L")), f, _stream(stream))
+                                      _ptr(out["tclr"]), _ptr(out.get("L")), _ptr(out.get("sweeps")), f,
+                                      _stream(stream))
     else:
         rc = ResidentCfg(cfg.get("threads_per_shot", 0), cfg.get("checks_per_thread", 0),
                          cfg.get("shots_per_block", 0))
         st = lib().laim_decode_rounds_cfg(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
                                           workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
-                                          _ptr(out["tclr"]), _ptr(out.get("L")), C.byref(rc),
-                                          _stream(stream))
+                                          _ptr(out["tclr"]), _ptr(out.get("L")), _ptr(out.get("sweeps")),
+                                          C.byref(rc), _stream(stream))
     check(st, "laim_decode_rounds")
     out["workspace"] = workspace
     return out

@@ -1,0 +1,207 @@
+"""Skipping sweeps at a fixed point of BP changes no result.
+
+Within a round the BP sweep is one fixed map of the messages (the syndrome,
+prior and parameters stay put), so once a sweep writes every message of a
+shot back bit for bit, the rest of the round's sweeps -- and those of later
+rounds without a flip -- are the identity. The resident form skips them when
+skip_fixed is set. These tests check that z, s, t_clr and the beliefs are
+bit-identical with and without the skip and equal to the oracle (which
+always runs every sweep), and that the number of sweeps each shot computed
+is exactly what the rule gives when it is replayed on the oracle's own
+sweep."""
+import numpy as np
+import pytest
+
+from paper_2609_38139_amd import codes
+from test_gpu_parity import compare_decode, dcode, gpu_e0, oracle_params, to_np, _code_cache
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2609_38139_amd import laim
+    laim.lib()
+    return laim
+
+
+def mixed_code():
+    """Check degrees 1..6, qubit degrees 1..4: the irregular (padded) kernel."""
+    rng = np.random.default_rng(5)
+    H = np.zeros((20, 30), dtype=np.uint8)
+    for r in range(20):
+        H[r, rng.choice(30, size=int(rng.integers(1, 7)), replace=False)] = 1
+    for v in range(30):
+        if not H[:, v].any():
+            H[rng.integers(0, 20), v] = 1
+    for v in range(30):
+        for r in np.nonzero(H[:, v])[0][4:]:
+            H[r, v] = 0
+    return codes.from_dense(H, name="mixed-fp")
+
+
+def run(L, dc, P, e0, cfg=None, form="resident"):
+    g = L.decode_rounds(dc, P, e0, form=form, want_beliefs=True, want_sweeps=True, cfg=cfg)
+    return {k: to_np(g[k]) for k in ("z", "s", "tclr", "L", "sweeps")}
+
+
+def rounds_run(P, tclr):
+    return np.where(P.retire & (tclr >= 0), tclr, P.rounds)
+
+
+CASES = [
+    ("toric2d:8", dict(), 0.06),
+    ("toric2d:16", dict(rounds=64), 0.05),
+    ("toric2d:16", dict(rounds=64, conflict="xor"), 0.05),
+    ("toric2d:16", dict(rounds=64, conflict="sequential"), 0.05),
+    ("toric2d:12", dict(bp="sumproduct", rounds=48), 0.05),
+    ("toric2d:12", dict(rounds=48, retire=False), 0.04),
+    ("toric2d:12", dict(rounds=48, evidence=False, mask_density=0.25), 0.04),
+    ("bb:6x6", dict(rounds=32), 0.04),
+    ("toric3d_point:3", dict(rounds=24), 0.05),
+    ("toric3d_membrane:3", dict(rounds=24, q=0.125), 0.06),
+    ("toric2d:8", dict(alpha=1.0, rounds=32), 0.06),   # clamp-binding: the padded variant
+    ("toric2d:8", dict(iters=1, rounds=40), 0.06),
+    ("toric2d:8", dict(iters=0, rounds=8), 0.06),
+    ("mixed", dict(rounds=16, q=0.1), 0.15),
+    ("mixed", dict(rounds=16, q=0.1, bp="sumproduct"), 0.15),
+]
+
+
+@pytest.mark.parametrize("name,kw,p", CASES, ids=[f"{c[0]}-{'-'.join(f'{k}={v}' for k, v in c[1].items())}"
+                                                  for c in CASES])
+def test_skip_is_exact(L, orc, name, kw, p):
+    if name == "mixed":
+        code = mixed_code()
+        _code_cache[code.name] = (code, L.Code(code, 0))
+        name = code.name
+    code, dc = dcode(L, name)
+    e0_np = orc.sample_noise(code, p, 2, 0, 150)
+    P = L.DecodeParams(skip_fixed=True, **kw)
+    # against the oracle (which runs every sweep) ...
+    compare_decode(L, orc, name, P, e0_np, form="resident", tag="skip")
+    # ... and against the kernel without the skip, bit for bit
+    e0 = gpu_e0(L, dc, e0_np)
+    on = run(L, dc, P, e0)
+    off = run(L, dc, L.DecodeParams(skip_fixed=False, **kw), e0)
+    for k in ("z", "s", "tclr"):
+        assert np.array_equal(on[k], off[k]), k
+    assert np.array_equal(on["L"].view(np.uint32), off["L"].view(np.uint32))
+    full = P.iters * rounds_run(P, off["tclr"])
+    assert np.array_equal(off["sweeps"], full)
+    assert np.all(on["sweeps"] <= full)
+    assert np.all(on["sweeps"] >= np.minimum(full, 1))  # a shot that runs a round sweeps at least once
+
+
+@pytest.mark.parametrize("cfg", [{"checks_per_thread": 1}, {"checks_per_thread": 2, "shots_per_block": 2},
+                                 {"checks_per_thread": 4, "shots_per_block": 3},
+                                 {"checks_per_thread": 8, "shots_per_block": 1}])
+def test_skip_in_every_launch_shape(L, orc, cfg):
+    """Several shots per block: a group at a fixed point stops sweeping while
+    the others go on; the counts do not depend on the shape."""
+    code, dc = dcode(L, "toric2d:16")
+    e0_np = orc.sample_noise(code, 0.05, 4, 0, 131)
+    P = L.DecodeParams(rounds=64)
+    compare_decode(L, orc, "toric2d:16", P, e0_np, cfg=cfg, tag="skip-shape")
+    e0 = gpu_e0(L, dc, e0_np)
+    a = run(L, dc, P, e0, cfg=cfg)
+    b = run(L, dc, P, e0)
+    assert np.array_equal(a["sweeps"], b["sweeps"])
+
+
+def replay_sweeps(orc, code, P, e0, shot):
+    """The skip rule replayed with the oracle's sweep: a round of a shot at a
+    fixed point computes no sweep; otherwise sweeps run until one leaves
+    every check-to-qubit message bit for bit as it was (that sweep counts)
+    or the round's sweeps are used up. The first sweep of a shot never
+    counts as a fixed point; a round with a flip ends the fixed point."""
+    H = code.H.to_dense()
+    op = oracle_params(orc, P)
+    tr = orc.decode(code, orc.DecodeParams(**{**op.__dict__, "retire": False}), e0[None], shot0=shot,
+                    trace=True)
+    s = (H @ e0) % 2
+    tclr = 0 if not s.any() else -1
+    pi_v = np.full(code.n, np.float32(np.log(P.q / (1 - P.q))), dtype=np.float32)
+    mvc = np.zeros(code.H.nnz, np.float32)
+    mcv = np.zeros(code.H.nnz, np.float32)
+    conv, fresh, n = False, True, 0
+    zprev = np.zeros(code.n, np.uint8)
+    for r in range(P.rounds):
+        if P.retire and tclr >= 0:
+            break
+        if not conv:
+            for _ in range(P.iters):
+                mcv2, mvc2 = orc.bp_sweep(code, op, pi_v, s, mvc)
+                n += 1
+                same = not fresh and np.array_equal(mcv2.view(np.uint32), mcv.view(np.uint32))
+                mcv, mvc, fresh = mcv2, mvc2, False
+                if same:
+                    conv = True
+                    break
+        if (tr["z_trace"][r] != zprev).any():
+            conv = False
+        zprev = tr["z_trace"][r]
+        s = tr["s_trace"][r]
+        if tclr < 0 and not s.any():
+            tclr = r + 1
+    return n
+
+
+@pytest.mark.parametrize("name,kw,p", [("toric2d:8", dict(rounds=32), 0.06),
+                                       ("toric2d:8", dict(rounds=32, bp="sumproduct"), 0.08),
+                                       ("bb:6x6", dict(rounds=24), 0.05),
+                                       ("mixed", dict(rounds=16, q=0.1), 0.15)])
+def test_sweep_counts_follow_the_rule(L, orc, name, kw, p):
+    if name == "mixed":
+        code = mixed_code()
+        _code_cache[code.name] = (code, L.Code(code, 0))
+        name = code.name
+    code, dc = dcode(L, name)
+    e0_np = orc.sample_noise(code, p, 6, 0, 24)
+    P = L.DecodeParams(**kw)
+    got = run(L, dc, P, gpu_e0(L, dc, e0_np))
+    want = np.array([replay_sweeps(orc, code, P, e0_np[i], i) for i in range(e0_np.shape[0])])
+    assert np.array_equal(got["sweeps"], want), (got["sweeps"], want)
+
+
+def test_stream_form_reports_every_sweep(L, orc):
+    code, dc = dcode(L, "toric2d:8")
+    e0_np = orc.sample_noise(code, 0.06, 1, 0, 70)
+    for retire in (True, False):
+        P = L.DecodeParams(rounds=24, retire=retire)
+        g = run(L, dc, P, gpu_e0(L, dc, e0_np), form="stream")
+        assert np.array_equal(g["sweeps"], P.iters * rounds_run(P, g["tclr"]))
+
+
+@pytest.mark.timeout(600)
+def test_metric_workload_full_size_with_skip(L, orc):
+    """The benchmark's launch (2D toric L = 32, p = 0.05, 65536 shots, 128
+    rounds of 20 sweeps, min-sum) with the skip: sampled shots equal the
+    oracle, every shot equals the launch without the skip, and most sweeps
+    are skipped on this workload."""
+    code, dc = dcode(L, "toric2d:32")
+    S = 65536
+    e0 = L.sample_noise(dc, 0.05, 0, 0, S)
+    P = L.DecodeParams(rounds=128)
+    on = L.decode_rounds(dc, P, e0, form="resident", want_sweeps=True)
+    off = L.decode_rounds(dc, L.DecodeParams(rounds=128, skip_fixed=False), e0, form="resident",
+                          want_sweeps=True)
+    for k in ("z", "s", "tclr"):
+        assert bool((on[k] == off[k]).all()), k
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([[0, S - 1], rng.integers(0, S, 30)]))
+    op = oracle_params(orc, P)
+    from concurrent.futures import ThreadPoolExecutor
+    e0s = to_np(e0[idx])
+    with ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(lambda k: orc.decode(code, op, e0s[k:k + 1], shot0=int(idx[k])), range(len(idx))))
+    z, t = to_np(on["z"][idx]), to_np(on["tclr"][idx])
+    for k in range(len(idx)):
+        assert np.array_equal(z[k], refs[k]["z"][0]) and t[k] == refs[k]["tclr"][0], idx[k]
+    sw_on = int(on["sweeps"].sum().item())
+    sw_off = int(off["sweeps"].sum().item())
+    print(f"[skip] sweeps computed {sw_on} of {sw_off} ({sw_on / sw_off:.3f})", flush=True)
+    assert sw_on < 0.5 * sw_off
