@@ -157,9 +157,10 @@ typedef struct {
  * syndrome, prior and parameters do not change), so once a sweep writes
  * every message of a shot back bit for bit, every later sweep does the same
  * until a flip changes the syndrome. With skip_fixed = 1 the resident form
- * detects such a sweep (comparing each new message with the one it
- * replaces) and leaves the shot's messages as they are for the rest of the
- * round and for following rounds without a flip. A shot's first sweep
+ * detects such a sweep -- sweep i of a round with i = 3 mod 4, and the
+ * round's last, compare each new message with the one it replaces -- and
+ * leaves the shot's messages as they are for the rest of the round and for
+ * following rounds without a flip. A shot's first sweep
  * (v->c messages 0) is a different map and never counts. z, s, t_clr and
  * the beliefs are bit-identical to running every sweep; only the sweeps
  * computed (sweeps_out) differ. The stream form always runs every sweep. */

@@ -254,14 +254,20 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   const float thr_reg = REG ? c.thr[DC] : 0.0f;  // Evidence bound of the one check degree
 
   // ---- per-thread graph tables
+  // A member owns checks t + k nt, k < CPT; those from m on pad the last
+  // tile. Their LDS slots exist (mpad >= nt CPT) and they are swept like
+  // the others -- inputs from the zero word, syndrome 0 -- so that the
+  // sweep needs no per-check condition; nothing reads what they write.
   int32_t cidx[CPT];
   int32_t deg[CPT];
   int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
+  uint32_t vmask = 0u;  // bit k: check k of this thread is one of the code's checks
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int32_t ch = t + k * u.nt;
     const bool valid = member && ch < c.m;
-    cidx[k] = valid ? ch : -1;
+    cidx[k] = member ? ch : -1;
+    vmask |= (valid ? 1u : 0u) << k;
     deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
@@ -308,7 +314,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll 1
     for (int k = 0; k < CPT; ++k) {
       const int32_t ch = t + k * u.nt;
-      if (ch >= c.m) continue;
+      if (ch >= c.m) {  // a padding check
+        for (int j = 0; j < DC; ++j) msg[msg_word<DC>(ch, j)] = 0.0f;
+        continue;
+      }
       uint32_t x = 0;
       if (u.resume) {
         for (int j = 0; j < DC; ++j)
@@ -357,6 +366,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   // skips them (with kp.skip; the results are those of all the sweeps).
   bool conv = kp.skip && member && u.resume && alive && job_at(g).st_hdr[1] != 0;
   int32_t nsweeps = 0;
+  // this thread's active checks that failed the Evidence test in the last
+  // feedback (valid while the group stays at a fixed point: same beliefs,
+  // same syndrome, so the same outcome)
+  uint32_t noev = 0u;
 
   for (int32_t rr = 0; rr < u.rounds; ++rr) {
     const int32_t r = r0 + rr;
@@ -378,6 +391,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     if (!anyw) break;
 
     // ---- BP sweeps, only while some working group is not at a fixed point
+    const bool same_state = conv;  // nothing changed since the last feedback
     bool sweep = working && !conv;
     if (anyw & 2) {
       int32_t it0 = 0;
@@ -387,7 +401,6 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         if (sweep) {
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
-            if (cidx[k] < 0) continue;
             const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
             float* mk = msg + msg_word<DC>(cidx[k], 0);
 #pragma unroll
@@ -399,14 +412,20 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         nsweeps += sweep ? 1 : 0;
         __syncthreads();
       }
-      // CMP: compare each new message with the one it replaces; the flags
-      // of even and odd sweeps alternate, so that a flag is cleared only
-      // after every thread has read it. A shot's first sweep (m_{v->c} = 0
-      // rather than pi + sum m_{c->v}) is another map and never counts as
-      // a fixed point.
+      // With CMP, a sweep may also compare each new message with the one
+      // it replaces; comparing costs a fifth of a sweep, so it is done
+      // every fourth sweep and at the last of the round, and a fixed point
+      // is found at most three sweeps late (those sweeps are identities).
+      // The flags of successive compared sweeps alternate, so that a flag
+      // is cleared only after every thread has read it. A shot's first
+      // sweep (m_{v->c} = 0 rather than pi + sum m_{c->v}) is another map
+      // and never counts as a fixed point.
       auto sweeps = [&](auto cmp_tag) {
-        constexpr bool CMP = decltype(cmp_tag)::value;
+        constexpr bool CMP_ON = decltype(cmp_tag)::value;
+        int32_t ncmp = 0;  // compared sweeps so far in this round
         for (int32_t it = it0; it < kp.iters; ++it) {
+          const bool CMP = CMP_ON && ((it & 3) == 3 || it == kp.iters - 1);
+          const int32_t f = ncmp & 1;
           const bool first = fresh;
           float x[CPT][DC];
           if (sweep) {
@@ -435,14 +454,13 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           }
           __syncthreads();
           if (CMP) {
-            if (member && t == 0) gw[(it & 1) ? kGwChg0 : kGwChg1] = 0;
-            if (tid == 0) ctrl[(it & 1) ? kCtrlChg0 : kCtrlChg1] = 0;
+            if (member && t == 0) gw[f ? kGwChg0 : kGwChg1] = 0;
+            if (tid == 0) ctrl[f ? kCtrlChg0 : kCtrlChg1] = 0;
           }
           uint32_t diff = 0u;
           if (sweep) {
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-              if (cidx[k] < 0) continue;
               const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
               float out[DC];
               if (BP == 0) {
@@ -499,28 +517,31 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
                 for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
               }
               float* mk = msg + msg_word<DC>(cidx[k], 0);
-              if (CMP) {  // the padding slots of irregular checks are never read
+              if (CMP) {  // padding checks and the padding slots of irregular checks are never read
+                uint32_t dk = 0u;
 #pragma unroll
                 for (int j = 0; j < DC; ++j)
-                  if (REG || j < deg[k]) diff |= __float_as_uint(mk[j * kSlotStride]) ^ __float_as_uint(out[j]);
+                  if (REG || j < deg[k]) dk |= __float_as_uint(mk[j * kSlotStride]) ^ __float_as_uint(out[j]);
+                diff |= ((vmask >> k) & 1u) ? dk : 0u;
               }
 #pragma unroll
               for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = out[j];
             }
           }
           if (CMP && sweep && (diff || first)) {
-            gw[(it & 1) ? kGwChg1 : kGwChg0] = 1;
-            ctrl[(it & 1) ? kCtrlChg1 : kCtrlChg0] = 1;
+            gw[f ? kGwChg1 : kGwChg0] = 1;
+            ctrl[f ? kCtrlChg1 : kCtrlChg0] = 1;
           }
           fresh = false;
           __syncthreads();
           nsweeps += sweep ? 1 : 0;
           if (CMP) {
-            if (sweep && gw[(it & 1) ? kGwChg1 : kGwChg0] == 0) {
+            ++ncmp;
+            if (sweep && gw[f ? kGwChg1 : kGwChg0] == 0) {
               sweep = false;
               conv = true;
             }
-            if (ctrl[(it & 1) ? kCtrlChg1 : kCtrlChg0] == 0) break;  // no group changed
+            if (ctrl[f ? kCtrlChg1 : kCtrlChg0] == 0) break;  // no group changed
           }
         }
       };
@@ -543,7 +564,8 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     // the number of qubits that changed.
     uint32_t reqm = 0;  // this thread's checks with a recorded request (sequential rule)
     if (working) {
-      uint32_t act = sb;
+      if (!same_state) noev = 0u;
+      uint32_t act = sb & ~noev;
       int32_t nflip = 0;
 #pragma unroll 1
       while (act) {
@@ -594,7 +616,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         // The move needs both the Evidence bound and the check's clock; the
         // bound is tested first, so the random words are drawn only when
         // it holds.
-        if (kp.evidence && !(Lmax >= (REG ? thr_reg : c.thr[d]))) continue;
+        if (kp.evidence && !(Lmax >= (REG ? thr_reg : c.thr[d]))) {
+          noev |= 1u << k;
+          continue;
+        }
         const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
                                         ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed,
                                         (uint32_t)(kp.seed >> 32));
@@ -716,7 +741,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         uint32_t nsb = 0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-          if (cidx[k] >= 0) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+          if ((vmask >> k) & 1u) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
         sb = nsb;
       }
       if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
