@@ -349,7 +349,8 @@ def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
     out = {"z": torch.empty((S, code.n), dtype=torch.uint8, device="cuda"),
            "s": torch.empty((S, code.m), dtype=torch.uint8, device="cuda"),
            "tclr": torch.empty((S,), dtype=torch.int32, device="cuda"), "L": None,
-           "sweeps": torch.empty((S,), dtype=torch.int32, device="cuda")}
+           "sweeps": torch.empty((S,), dtype=torch.int32, device="cuda"),
+           "fail": torch.empty((S,), dtype=torch.uint8, device="cuda")}
     ws = torch.empty((max(laim.workspace_bytes(code, P, S, form), 256),), dtype=torch.uint8, device="cuda")
     fails = torch.zeros((), dtype=torch.int64, device="cuda")
     rounds_exec = torch.zeros((), dtype=torch.int64, device="cuda")
@@ -364,11 +365,11 @@ def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
         laim.sample_noise(code, args.p, 0, shot0, S, out=e0)
         if evs:
             evs[0].record(st)
+        # the decoder failure test runs inside the decode launch (fail_out)
         laim.decode_rounds(code, P, e0, shot0=shot0, form=form, workspace=ws, out=out)
         if evs:
             evs[1].record(st)
-        f = laim.logical_failure(code, e0, out["z"])
-        fails.add_(f.sum())
+        fails.add_(out["fail"].sum())
         t = out["tclr"]
         rounds_exec.add_(torch.where(t >= 0, t, torch.full_like(t, P.rounds)).sum())
         sweeps_exec.add_(out["sweeps"].sum())

@@ -204,13 +204,18 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
  *   sweeps_out device [nshots] int32 or NULL: BP sweeps computed for each
  *              shot; iters x (rounds the shot ran) unless skip_fixed skipped
  *              some (saturates at 2^31 - 1)
+ *   fail_out   device [nshots] uint8 or NULL: the decoder failure of each
+ *              shot, exactly as laim_logical_failure(e0, z_out) gives it; the
+ *              resident form computes it inside the launch (codes with at
+ *              most 128 logicals), otherwise a failure kernel follows
  * Concurrent calls on different streams may share a laim_code but not a
  * workspace.
  */
 laim_status laim_decode_rounds(const laim_code* code, const laim_decode_params* params,
                                const uint8_t* e0, uint64_t shot0, int32_t nshots, void* workspace,
                                size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
-                               float* L_out, int32_t* sweeps_out, int32_t form, laim_stream stream);
+                               float* L_out, int32_t* sweeps_out, uint8_t* fail_out, int32_t form,
+                               laim_stream stream);
 
 /* Launch shape of the resident form (0 in a field means: choose). */
 typedef struct {
@@ -225,8 +230,8 @@ laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_para
                                    const uint8_t* e0, uint64_t shot0, int32_t nshots,
                                    void* workspace, size_t ws_bytes, uint8_t* z_out,
                                    uint8_t* s_out, int32_t* tclr_out, float* L_out,
-                                   int32_t* sweeps_out, const laim_resident_cfg* cfg,
-                                   laim_stream stream);
+                                   int32_t* sweeps_out, uint8_t* fail_out,
+                                   const laim_resident_cfg* cfg, laim_stream stream);
 
 /* Sets the resident launch shape used from now on for this code and BP
  * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */

@@ -565,7 +565,7 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
 static laim_status decode_common(const laim_code* code, const laim_decode_params* params,
                                  const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
                                  size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
-                                 float* L_out, int32_t* sweeps_out, int32_t form,
+                                 float* L_out, int32_t* sweeps_out, uint8_t* fail_out, int32_t form,
                                  const laim_resident_cfg* cfg, laim_stream stream) {
   if (!code || nshots < 0 || (nshots > 0 && (!e0 || !z_out || !s_out || !tclr_out))) {
     set_error("laim_decode_rounds: bad arguments");
@@ -577,6 +577,10 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
   if (form < LAIM_FORM_AUTO || form > LAIM_FORM_STREAM) {
     set_error("unknown form %d", form);
     return LAIM_EINVAL;
+  }
+  if (fail_out && code->dev.kw > 64) {
+    set_error("more than 2048 logicals are not supported");
+    return LAIM_EUNSUP;
   }
   if (nshots == 0) return LAIM_OK;
   const bool seq = kp.conflict == kConflictSequential;
@@ -614,36 +618,43 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
   }
   DeviceGuard g(code->device);
   hipError_t er;
+  // the resident kernel folds the failure test into the launch for codes
+  // with at most 128 logicals; otherwise it runs as its own kernel after
+  const bool fused_fail = f == LAIM_FORM_RESIDENT && code->dev.kw <= 4;
   if (f == LAIM_FORM_RESIDENT) {
     er = launch_resident(code->dev, kp, sh, e0, shot0, nshots, ws, z_out, s_out, tclr_out, L_out,
-                         nullptr, sweeps_out, (hipStream_t)stream);
+                         fused_fail ? fail_out : nullptr, sweeps_out, (hipStream_t)stream);
   } else {
     er = launch_stream(code->dev, kp, e0, shot0, nshots, ws, z_out, s_out, tclr_out, L_out,
                        (hipStream_t)stream);
     if (er == hipSuccess) er = launch_sweep_count(kp, tclr_out, nshots, sweeps_out, (hipStream_t)stream);
   }
+  if (er == hipSuccess && fail_out && !fused_fail)
+    er = launch_failure(code->dev, e0, z_out, nshots, fail_out, (hipStream_t)stream);
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "decode kernels");
 }
 
 laim_status laim_decode_rounds(const laim_code* code, const laim_decode_params* params,
                                const uint8_t* e0, uint64_t shot0, int32_t nshots, void* workspace,
                                size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
-                               float* L_out, int32_t* sweeps_out, int32_t form, laim_stream stream) {
+                               float* L_out, int32_t* sweeps_out, uint8_t* fail_out, int32_t form,
+                               laim_stream stream) {
   return decode_common(code, params, e0, shot0, nshots, workspace, ws_bytes, z_out, s_out, tclr_out,
-                       L_out, sweeps_out, form, nullptr, stream);
+                       L_out, sweeps_out, fail_out, form, nullptr, stream);
 }
 
 laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_params* params,
                                    const uint8_t* e0, uint64_t shot0, int32_t nshots,
                                    void* workspace, size_t ws_bytes, uint8_t* z_out, uint8_t* s_out,
                                    int32_t* tclr_out, float* L_out, int32_t* sweeps_out,
-                                   const laim_resident_cfg* cfg, laim_stream stream) {
+                                   uint8_t* fail_out, const laim_resident_cfg* cfg,
+                                   laim_stream stream) {
   if (!cfg) {
     set_error("cfg is NULL");
     return LAIM_EINVAL;
   }
   return decode_common(code, params, e0, shot0, nshots, workspace, ws_bytes, z_out, s_out, tclr_out,
-                       L_out, sweeps_out, LAIM_FORM_RESIDENT, cfg, stream);
+                       L_out, sweeps_out, fail_out, LAIM_FORM_RESIDENT, cfg, stream);
 }
 
 laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_params* params,

@@ -20,33 +20,40 @@ namespace laim {
 
 // ---------------------------------------------------------------- noise
 // One thread per (shot, block of 4 qubits): one Philox call gives the four
-// uniform words of qubits 4b .. 4b+3.
+// uniform words of qubits 4b .. 4b+3. Block (x, y) covers shot x, qubit
+// blocks 256 y .. 256 y + 255; rows of a multiple of 4 qubits on a 4-byte
+// aligned buffer take one 32-bit store per thread.
 __global__ void __launch_bounds__(256) noise_kernel(int32_t n, int32_t nb4, uint64_t bound,
-                                                    uint64_t seed, uint64_t shot0, int64_t total,
+                                                    uint64_t seed, uint64_t shot0, int32_t word_rows,
                                                     uint8_t* __restrict__ e) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t i = idx / nb4;
-  const int32_t b = (int32_t)(idx - i * nb4);
+  const int64_t i = blockIdx.x;
+  const int32_t b = (int32_t)blockIdx.y * 256 + (int32_t)threadIdx.x;
+  if (b >= nb4) return;
   const uint64_t shot = shot0 + (uint64_t)i;
   const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)b, 0u,
                                   (uint32_t)seed, (uint32_t)(seed >> 32));
   uint8_t* row = e + i * (int64_t)n;
   const int32_t v = 4 * b;
-  if (v + 0 < n) row[v + 0] = below(w.w0, bound) ? 1 : 0;
-  if (v + 1 < n) row[v + 1] = below(w.w1, bound) ? 1 : 0;
-  if (v + 2 < n) row[v + 2] = below(w.w2, bound) ? 1 : 0;
-  if (v + 3 < n) row[v + 3] = below(w.w3, bound) ? 1 : 0;
+  const uint32_t q0 = below(w.w0, bound) ? 1u : 0u, q1 = below(w.w1, bound) ? 1u : 0u;
+  const uint32_t q2 = below(w.w2, bound) ? 1u : 0u, q3 = below(w.w3, bound) ? 1u : 0u;
+  if (word_rows) {
+    *reinterpret_cast<uint32_t*>(row + v) = q0 | (q1 << 8) | (q2 << 16) | (q3 << 24);
+  } else {
+    if (v + 0 < n) row[v + 0] = (uint8_t)q0;
+    if (v + 1 < n) row[v + 1] = (uint8_t)q1;
+    if (v + 2 < n) row[v + 2] = (uint8_t)q2;
+    if (v + 3 < n) row[v + 3] = (uint8_t)q3;
+  }
 }
 
 hipError_t launch_noise(const DevCode& c, uint64_t bound, uint64_t seed, uint64_t shot0,
                         int32_t nshots, uint8_t* e, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   const int32_t nb4 = (c.n + 3) / 4;
-  const int64_t total = (int64_t)nb4 * nshots;
-  const int64_t blocks = (total + 255) / 256;
-  hipLaunchKernelGGL(noise_kernel, dim3((unsigned)blocks), dim3(256), 0, st, c.n, nb4, bound, seed,
-                     shot0, total, e);
+  const int32_t word_rows = (c.n % 4 == 0 && ((uintptr_t)e % 4) == 0) ? 1 : 0;
+  if ((nb4 + 255) / 256 > 65535) return hipErrorInvalidValue;  // grid y limit: n <= 2^26
+  const dim3 grid((unsigned)nshots, (unsigned)((nb4 + 255) / 256));
+  hipLaunchKernelGGL(noise_kernel, grid, dim3(256), 0, st, c.n, nb4, bound, seed, shot0, word_rows, e);
   return hipGetLastError();
 }
 
@@ -122,11 +129,122 @@ __global__ void __launch_bounds__(256) failure_kernel(DevCode c, const uint8_t* 
   }
 }
 
+// The same test with r packed into an LDS bitmap first: lane l packs
+// qubits 32 l .. 32 l + 31 from 16-byte loads of both rows (bit 0 of each
+// byte, gathered four at a time by one multiply), then the checks and the
+// logical parities read bits. Needs rows of a multiple of 32 bytes and
+// 16-byte aligned e0 and z; the bitmap takes n / 8 bytes of LDS.
+constexpr int kFailPackedMaxN = 1 << 18;
+
+__device__ __forceinline__ uint32_t pack_bit0(uint4 x) {
+  // (b0 + b1 2^8 + b2 2^16 + b3 2^24) * (2^28 + 2^21 + 2^14 + 2^7) puts
+  // b0..b3 at bits 28..31 with no carries from the other products
+  const uint32_t m = 0x01010101u, k = 0x10204080u;
+  return (((x.x & m) * k) >> 28) | ((((x.y & m) * k) >> 28) << 4) | ((((x.z & m) * k) >> 28) << 8) |
+         ((((x.w & m) * k) >> 28) << 12);
+}
+
+__global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const uint8_t* __restrict__ e0,
+                                                             const uint8_t* __restrict__ z,
+                                                             uint8_t* __restrict__ fail) {
+  extern __shared__ uint32_t rb[];  // [n / 32] bits of r, then [kw] logical parities
+  __shared__ int32_t anys;
+  const int32_t nw = c.n >> 5;
+  uint32_t* par = rb + nw;
+  const int64_t i = blockIdx.x;
+  const uint4* a = reinterpret_cast<const uint4*>(e0 + i * (int64_t)c.n);
+  const uint4* b = reinterpret_cast<const uint4*>(z + i * (int64_t)c.n);
+  for (int32_t w = threadIdx.x; w < c.kw; w += blockDim.x) par[w] = 0u;
+  if (threadIdx.x == 0) anys = 0;
+  for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+    const uint4 a0 = a[2 * w], a1 = a[2 * w + 1], b0 = b[2 * w], b1 = b[2 * w + 1];
+    const uint4 r0 = make_uint4(a0.x ^ b0.x, a0.y ^ b0.y, a0.z ^ b0.z, a0.w ^ b0.w);
+    const uint4 r1 = make_uint4(a1.x ^ b1.x, a1.y ^ b1.y, a1.z ^ b1.z, a1.w ^ b1.w);
+    rb[w] = pack_bit0(r0) | (pack_bit0(r1) << 16);
+  }
+  __syncthreads();
+  // logical parities: the rows of lcol of the qubits in r. With one word
+  // per qubit (at most 32 logicals) a lane reads the rows of its 32 qubits
+  // as eight independent 16-byte loads and keeps those whose bit is set.
+  uint32_t local[4] = {0u, 0u, 0u, 0u};
+  for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+    uint32_t bits = rb[w];
+    if (!bits) continue;
+    if (c.kw == 1) {
+      const uint4* lc = reinterpret_cast<const uint4*>(c.lcol + ((int64_t)w << 5));
+      uint32_t acc = 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint4 q = lc[u];
+        const uint32_t nib = bits >> (4 * u);
+        acc ^= ((nib & 1u) ? q.x : 0u) ^ ((nib & 2u) ? q.y : 0u) ^ ((nib & 4u) ? q.z : 0u) ^
+               ((nib & 8u) ? q.w : 0u);
+      }
+      local[0] ^= acc;
+      continue;
+    }
+    while (bits) {
+      const int32_t v = (w << 5) + __builtin_ctz(bits);
+      bits &= bits - 1u;
+      for (int32_t q = 0; q < c.kw; ++q) {
+        const uint32_t lb = c.lcol[(int64_t)v * c.kw + q];
+        if (q < 4)
+          local[q] ^= lb;
+        else if (lb)
+          atomicXor(&par[q], lb);
+      }
+    }
+  }
+  for (int32_t q = 0; q < c.kw && q < 4; ++q)
+    if (local[q]) atomicXor(&par[q], local[q]);
+  // syndrome: every entry of a check's row at once (padding entries are -1)
+  int32_t mine = 0;
+  if (c.dcmax <= 8) {
+#pragma unroll 2
+    for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+      const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+      int32_t vv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) vv[j] = (j < c.dcmax) ? nb[j] : -1;
+      uint32_t x = 0u;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (vv[j] >= 0) x ^= rb[vv[j] >> 5] >> (vv[j] & 31);
+      mine |= (int32_t)(x & 1u);
+    }
+  } else {
+    for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+      const int32_t d = c.chk_deg[ch];
+      const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
+      uint32_t x = 0u;
+      for (int32_t j = 0; j < d; ++j) {
+        const int32_t v = nb[j];
+        x ^= rb[v >> 5] >> (v & 31);
+      }
+      mine |= (int32_t)(x & 1u);
+    }
+  }
+  if (mine) anys = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t f = (uint32_t)anys;
+    for (int32_t q = 0; q < c.kw; ++q) f |= par[q];
+    fail[i] = f ? 1 : 0;
+  }
+}
+
 hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z, int32_t nshots,
                           uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   if (c.kw > kFailMaxWords) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(failure_kernel, dim3((unsigned)nshots), dim3(256), 0, st, c, e0, z, fail);
+  const bool packed = c.n % 32 == 0 && c.n <= kFailPackedMaxN && ((uintptr_t)e0 % 16) == 0 &&
+                      ((uintptr_t)z % 16) == 0;
+  if (packed) {
+    const size_t lds = (size_t)(c.n / 32 + c.kw) * 4;
+    hipLaunchKernelGGL(failure_packed_kernel, dim3((unsigned)nshots), dim3(256), lds, st, c, e0, z, fail);
+  } else {
+    hipLaunchKernelGGL(failure_kernel, dim3((unsigned)nshots), dim3(256), 0, st, c, e0, z, fail);
+  }
   return hipGetLastError();
 }
 

@@ -156,9 +156,9 @@ def lib():
         L.laim_workspace_bytes.argtypes = [vp, C.POINTER(Params), i32, i32]
         L.laim_workspace_bytes.restype = sz
         L.laim_decode_rounds.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp, vp,
-                                         vp, i32, vp]
+                                         vp, vp, i32, vp]
         L.laim_decode_rounds_cfg.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, sz, vp, vp, vp,
-                                             vp, vp, C.POINTER(ResidentCfg), vp]
+                                             vp, vp, vp, C.POINTER(ResidentCfg), vp]
         L.laim_set_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
         L.laim_get_resident_cfg.argtypes = [vp, i32, C.POINTER(ResidentCfg)]
         L.laim_logical_failure.argtypes = [vp, vp, vp, i32, vp, vp]
@@ -302,9 +302,10 @@ def workspace_bytes(code: Code, params: DecodeParams, nshots: int, form: str = "
 
 def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: str = "auto",
                   want_beliefs: bool = False, cfg: dict | None = None, workspace=None, out=None,
-                  stream=None, want_sweeps: bool = False) -> dict:
-    """``laim_decode_rounds``: returns device tensors z, s, tclr (and L, and
-    with want_sweeps the BP sweeps computed per shot)."""
+                  stream=None, want_sweeps: bool = False, want_fail: bool = False) -> dict:
+    """``laim_decode_rounds``: returns device tensors z, s, tclr (and L; with
+    want_sweeps the BP sweeps computed per shot; with want_fail the decoder
+    failure of each shot)."""
     import torch
     ns = e0.shape[0]
     _dev(e0, torch.uint8, (ns, code.n), "e0")
@@ -317,6 +318,8 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
                "L": torch.empty((ns, code.n), dtype=torch.float32, device=dev) if want_beliefs else None}
     if want_sweeps and out.get("sweeps") is None:
         out["sweeps"] = torch.empty((ns,), dtype=torch.int32, device=dev)
+    if want_fail and out.get("fail") is None:
+        out["fail"] = torch.empty((ns,), dtype=torch.uint8, device=dev)
     f = FORM_RESIDENT if cfg is not None else FORMS[form]
     need = int(lib().laim_workspace_bytes(code.handle, C.byref(P), ns, f))
     if workspace is None or workspace.numel() < need:
@@ -324,15 +327,15 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
     if cfg is None:
         st = lib().laim_decode_rounds(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
                                       workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
-                                      _ptr(out["tclr"]), _ptr(out.get("L")), _ptr(out.get("sweeps")), f,
-                                      _stream(stream))
+                                      _ptr(out["tclr"]), _ptr(out.get("L")), _ptr(out.get("sweeps")),
+                                      _ptr(out.get("fail")), f, _stream(stream))
     else:
         rc = ResidentCfg(cfg.get("threads_per_shot", 0), cfg.get("checks_per_thread", 0),
                          cfg.get("shots_per_block", 0))
         st = lib().laim_decode_rounds_cfg(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
                                           workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
                                           _ptr(out["tclr"]), _ptr(out.get("L")), _ptr(out.get("sweeps")),
-                                          C.byref(rc), _stream(stream))
+                                          _ptr(out.get("fail")), C.byref(rc), _stream(stream))
     check(st, "laim_decode_rounds")
     out["workspace"] = workspace
     return out

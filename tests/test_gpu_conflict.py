@@ -112,7 +112,7 @@ def test_invalid_rule_is_rejected(L):
     t = torch.empty((2,), dtype=torch.int32, device="cuda")
     ws = torch.empty((1 << 20,), dtype=torch.uint8, device="cuda")
     st = L.lib().laim_decode_rounds(dc.handle, C.byref(P), e0.data_ptr(), 0, 2, ws.data_ptr(), ws.numel(),
-                                    z.data_ptr(), s.data_ptr(), t.data_ptr(), None, None, 0, None)
+                                    z.data_ptr(), s.data_ptr(), t.data_ptr(), None, None, None, 0, None)
     assert st == L.EINVAL
     with pytest.raises(ValueError):
         L.decode_rounds(dc, L.DecodeParams(conflict="and"), e0)

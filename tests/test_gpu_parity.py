@@ -76,14 +76,28 @@ def compare_decode(L, orc, name, P, e0_np, shot0=0, form="auto", cfg=None, belie
 
 
 # ------------------------------------------------------------ primitives
-@pytest.mark.parametrize("name", ["toric2d:8", "toric3d_point:3", "bb:6x6", "rep:7"])
+@pytest.mark.parametrize("name", ["toric2d:8", "toric3d_point:3", "bb:6x6", "rep:7", "toric2d:32",
+                                  "toric3d_point:7"])
 def test_noise_parity(L, orc, name):
+    """Rows of 4k qubits are written a word at a time, others bytewise;
+    rows over 1024 qubits span two blocks of the launch."""
     code, dc = dcode(L, name)
     for p in (0.0, 0.02, 0.37, 1.0):
         for seed in (0, 123456789012345):
             for shot0 in (0, (1 << 33) + 5):
                 e = to_np(L.sample_noise(dc, p, seed, shot0, 257))
                 assert np.array_equal(e, orc.sample_noise(code, p, seed, shot0, 257)), (p, seed, shot0)
+
+
+def test_noise_into_a_misaligned_buffer(L, orc):
+    import torch
+    code, dc = dcode(L, "toric2d:8")
+    S = 100
+    flat = torch.full((S * code.n + 1,), 7, dtype=torch.uint8, device="cuda")
+    out = flat[1:].view(S, code.n)
+    L.sample_noise(dc, 0.1, 5, 9, S, out=out)
+    assert np.array_equal(to_np(out), orc.sample_noise(code, 0.1, 5, 9, S))
+    assert int(flat[0].item()) == 7
 
 
 @pytest.mark.parametrize("name", ["toric2d:8", "toric3d_membrane:3", "bb:12x6", "rep:7"])
@@ -96,7 +110,8 @@ def test_syndrome_parity(L, orc, name):
 
 
 @pytest.mark.parametrize("name", ["toric2d:3", "toric2d:8", "bb:6x6", "bb:12x6", "toric3d_point:3",
-                                  "toric3d_membrane:3", "rep:9"])
+                                  "toric3d_membrane:3", "rep:9", "toric2d:16", "toric2d:32",
+                                  "toric3d_point:4"])
 def test_failure_parity(L, orc, name):
     """Homology test by logicals (GPU) against the oracle's rank test, on
     random residuals and on residuals in ker H (mostly trivial or logical)."""
@@ -121,6 +136,43 @@ def test_failure_parity(L, orc, name):
     f = to_np(L.logical_failure(dc, gpu_e0(L, dc, e0), gpu_e0(L, dc, z)))
     assert np.array_equal(f, orc.logical_failure(code, e0, z))
     assert f[400:].sum() > 0 and f[400:].sum() < 200
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+@pytest.mark.parametrize("name,p", [("toric2d:16", 0.06), ("bb:12x6", 0.06), ("toric3d_point:3", 0.05)])
+def test_decode_reports_failures(L, orc, name, p, form):
+    """fail_out of the decode call (inside the resident launch, after it in
+    the stream form) equals the standalone failure test and the oracle."""
+    code, dc = dcode(L, name)
+    e0_np = orc.sample_noise(code, p, 3, 0, 211)
+    e0 = gpu_e0(L, dc, e0_np)
+    g = L.decode_rounds(dc, L.DecodeParams(rounds=24), e0, form=form, want_fail=True)
+    f = to_np(g["fail"])
+    assert np.array_equal(f, to_np(L.logical_failure(dc, e0, g["z"])))
+    assert np.array_equal(f, orc.logical_failure(code, e0_np, to_np(g["z"])))
+    assert 0 < f.sum() < len(f)
+
+
+def test_failure_packed_and_direct_paths_agree(L, orc):
+    """Rows whose length is a multiple of 32 on 16-byte aligned buffers take
+    the bit-packed kernel; the same rows seen through buffers one byte off
+    take the direct one. Both equal the oracle."""
+    import torch
+    code, dc = dcode(L, "toric2d:16")
+    rng = np.random.default_rng(8)
+    S = 333
+    e0 = (rng.random((S, code.n)) < 0.08).astype(np.uint8)
+    z = (rng.random((S, code.n)) < 0.08).astype(np.uint8)
+    z[::3] = e0[::3]  # residual 0: success
+    want = orc.logical_failure(code, e0, z)
+    fa = to_np(L.logical_failure(dc, gpu_e0(L, dc, e0), gpu_e0(L, dc, z)))
+    flat_e = torch.zeros(S * code.n + 1, dtype=torch.uint8, device="cuda")
+    flat_z = torch.zeros(S * code.n + 1, dtype=torch.uint8, device="cuda")
+    flat_e[1:] = torch.from_numpy(e0.ravel()).cuda()
+    flat_z[1:] = torch.from_numpy(z.ravel()).cuda()
+    fb = to_np(L.logical_failure(dc, flat_e[1:].view(S, code.n), flat_z[1:].view(S, code.n)))
+    assert np.array_equal(fa, want) and np.array_equal(fb, want)
+    assert 0 < want.sum() < S
 
 
 # -------------------------------------------------------------- decode
