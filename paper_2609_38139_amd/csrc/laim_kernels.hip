@@ -305,7 +305,7 @@ constexpr int kMaxShotsPerBlock = 31;
 constexpr int kGroupWords = 16;  // per-group scratch words after msg
 // scratch word indices
 constexpr int kGwZero = 0, kGwLpar = 1 /* 4 words */, kGwFlips = 5, kGwDefects = 6, kGwInit = 7,
-              kGwAct0 = 8, kGwAct1 = 9, kGwChg0 = 10, kGwChg1 = 11;
+              kGwAct0 = 8, kGwAct1 = 9, kGwChg0 = 10, kGwChg1 = 11, kGwLive = 12;
 constexpr int kFusedMaxWords = 4;  // logicals folded in LDS by the fused failure test
 
 template <bool B>
@@ -498,6 +498,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       gw[kGwFlips] = 0;
       gw[kGwChg0] = 0;
       gw[kGwChg1] = 0;
+      gw[kGwLive] = 0;
     }
     if (tid == 0) {
       ctrl[kCtrlChg0] = 0;
@@ -778,6 +779,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         nflip += had ? -1 : 1;
       }
       if (nflip) atomicAdd(&gw[kGwFlips], nflip);
+      if (sb & ~noev) gw[kGwLive] = 1;  // an active check passed the Evidence test
     }
     if (kp.conflict == kConflictSequential) {
       // Sequential rule: request i applies iff its check's start syndrome
@@ -875,6 +877,12 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       flips_last = nfl;
       if (nfl) conv = false;  // the syndrome changed
       if (kp.retire && tclr >= 0) working = false;
+      // Frozen: at a fixed point, no flip, and no active check passes the
+      // Evidence test. The next round then repeats this one exactly -- no
+      // sweep changes anything, the same checks fail the test, nothing
+      // flips -- and so does every round after it: the shot's z, s, t_clr
+      // and beliefs are final and it stops here.
+      if (conv && !gw[kGwLive]) working = false;
     }
   }
 
