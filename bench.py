@@ -592,9 +592,11 @@ def main():
         P_o = laim.DecodeParams(bp=other, rounds=R, iters=args.iters, retire=not args.no_retire)
         ro = timed_steps(laim, code, P_o, args, 1, 1, form, shot_base=3 * 10**9)
         extras[other] = {"shots_per_s": round(ro["shots"] / (ro["ms_per_step"] / 1000), 1),
-                         "msg_updates_per_s": 2 * E * args.iters * ro["rounds_exec"] / (ro["ms_per_step"] / 1000),
+                         "msg_updates_per_s": 2 * E * ro["sweeps_exec"] / (ro["ms_per_step"] / 1000),
+                         "sweeps_computed_frac": round(ro["sweeps_exec"] / max(1, args.iters * ro["rounds_exec"]), 4),
                          "decode_ms": round(ro["decode_ms"], 2), "failures": ro["failures"],
-                         "logical_error_rate": ro["failures"] / ro["shots"]}
+                         "logical_error_rate": ro["failures"] / ro["shots"],
+                         "resident_shape": code.resident_cfg(other) if form != "stream" else None}
         # conflict rules for the round's move requests (ablation): same
         # workload and shots, each rule
         extras["conflict_rules"] = {}
