@@ -445,7 +445,7 @@ def main():
     elif not args.no_tune and form != "stream":
         from paper_2609_38139_amd import autotune
         for bp in ("minsum", "sumproduct"):
-            t = autotune.tune(code, bp, use_cache=False)
+            t = autotune.tune(code, bp, rounds=R, use_cache=False)
             if bp == args.bp:
                 tuned = t
     main_run = timed_steps(laim, code, P, args, args.steps, args.warmup, form)

@@ -60,9 +60,14 @@ def candidates(code, bp: str):
     return out
 
 
-def tune(code, bp: str = "minsum", nshots: int = 16384, rounds: int = 4, iters: int = 20,
+def tune(code, bp: str = "minsum", nshots: int = 16384, rounds: int = 64, iters: int = 20,
          p: float = 0.05, q: float = 0.05, use_cache: bool = True, verbose: bool = False) -> dict:
-    """Returns {'cfg': best shape, 'ms': {shape: time}} and installs the best shape."""
+    """Returns {'cfg': best shape, 'ms': {shape: time}} and installs the best shape.
+
+    Each shape decodes the same batch for `rounds` rounds with shots retiring
+    at clear, as decoding runs: a block of several shots waits for its
+    slowest, and shots that clear or freeze early end their work, so fewer
+    or shorter runs would rank the shapes differently."""
     import torch
 
     from . import laim
@@ -72,7 +77,7 @@ def tune(code, bp: str = "minsum", nshots: int = 16384, rounds: int = 4, iters: 
         cfg = cache[key]["cfg"]
         code.set_resident_cfg(bp, cfg)
         return cache[key]
-    P = laim.DecodeParams(bp=bp, rounds=rounds, iters=iters, q=q, retire=False)
+    P = laim.DecodeParams(bp=bp, rounds=rounds, iters=iters, q=q, retire=True)
     e0 = laim.sample_noise(code, p, 0, 0, nshots)
     results = {}
     ref = None
