@@ -243,11 +243,20 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
     ms = []
     for _ in range(reps):
         ev0.record(st)
-        out = laim.decode_continuous(code, P, e0, shot0=7 * 10**9, want_fail=True, workspace=ws)
+        out = laim.decode_continuous(code, P, e0, shot0=7 * 10**9, want_fail=True, workspace=ws,
+                                     want_steps=True)
         ev1.record(st)
         torch.cuda.synchronize()
         ms.append(ev0.elapsed_time(ev1))
     sec = min(ms) / 1000.0
+    computed = int(out["steps"].sum().item())
+    # the same launch computing every Euler step (identical outputs)
+    P_all = laim.ContinuousParams(bp=bp, dt=dt, tau=0.1, t_max=t_max, skip_fixed=False)
+    ev0.record(st)
+    laim.decode_continuous(code, P_all, e0, shot0=7 * 10**9, workspace=ws)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    sec_all = ev0.elapsed_time(ev1) / 1000.0
     tclr = out["tclr"].cpu().numpy()
     K = int(math.floor(t_max / dt + 0.5))
     # Euler steps run by each shot: up to the step whose time first reaches the
@@ -267,14 +276,21 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
                  + 6 * dc) if bp == "minsum" else None
     res = {"workload": f"2D toric L={L}, p={p}, {bp}, dt={dt}, tau=0.1, t_max={t_max}, {nshots} shots",
            "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
-           "euler_shot_steps_per_s": steps / sec, "msg_updates_per_s": 2 * code.E * steps / sec,
+           "euler_steps_computed_frac": round(computed / max(1, steps), 4),
+           "euler_shot_steps_per_s": computed / sec, "msg_updates_per_s": 2 * code.E * computed / sec,
+           "euler_shot_steps_of_the_method_per_s": steps / sec,
+           "every_step": {"shots_per_s": round(nshots / sec_all, 1), "decode_ms": round(sec_all * 1e3, 3),
+                          "what": "skip_fixed = 0: every Euler step computed; identical outputs"},
            "cleared": int((tclr >= 0).sum()), "logical_error_rate": float(out["fail"].float().mean().item()),
            "mean_tclr_cleared": float(tclr[tclr >= 0].mean()) if (tclr >= 0).any() else None}
     if ops_check is not None:
-        ach = steps * m * ops_check / sec / 1e12
+        # only the computed steps count as work
+        ach = computed * m * ops_check / sec / 1e12
         res["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 1),
                            "unit": "Tops/s", "frac": round(ach / VALU_PEAK_TOPS, 4),
                            "ops_per_check_step": ops_check}
+        ach_all = steps * m * ops_check / sec_all / 1e12
+        res["every_step"]["roofline"] = {"achieved": round(ach_all, 3), "frac": round(ach_all / VALU_PEAK_TOPS, 4)}
     return res
 
 

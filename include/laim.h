@@ -275,6 +275,12 @@ typedef struct {
                        Euler steps at most (t_max / dt <= 2^31 - 1) */
   int32_t evidence; /* 1: apply the Evidence test */
   uint64_t seed;    /* Philox key for the clocks and tie-breaks */
+  int32_t skip_fixed; /* 1: skip Euler steps that cannot change the messages. Between
+                         moves the step is a fixed map of the messages; once one
+                         leaves every message bit for bit as it was (tested on steps
+                         7, 15, 23, ...), the steps up to the next event are skipped.
+                         Events are still handled one by one: all outputs, counts
+                         included, equal those of every step. 0: run every step. */
 } laim_continuous_params;
 
 /* Workspace of laim_decode_continuous (the shot queue), in bytes. */
@@ -290,6 +296,8 @@ typedef struct {
  *              syndrome (0 if H e0 = 0), or -1 if it did not clear by t_max
  *   counts_out device [nshots][2] int32 or NULL: events (clock rings of
  *              active checks) and moves (flips) of each shot
+ *   steps_out  device [nshots] int32 or NULL: Euler steps computed for each
+ *              shot; every step of the run unless skip_fixed skipped some
  *   fail_out   device [nshots] uint8 or NULL: logical failure, as
  *              laim_logical_failure
  *   checks_per_thread  0 to choose, else 1, 2, 4 or 8 (a launch shape;
@@ -301,8 +309,8 @@ typedef struct {
 laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_params* params,
                                    const uint8_t* e0, uint64_t shot0, int32_t nshots,
                                    void* workspace, size_t ws_bytes, uint8_t* z_out, uint8_t* s_out,
-                                   double* tclr_out, int32_t* counts_out, uint8_t* fail_out,
-                                   int32_t checks_per_thread, laim_stream stream);
+                                   double* tclr_out, int32_t* counts_out, int32_t* steps_out,
+                                   uint8_t* fail_out, int32_t checks_per_thread, laim_stream stream);
 
 /* --------------------------------------------------- bit-centric machine
  * The discrete bit-centric machine of the SM ("Setup and algorithm") for
@@ -372,7 +380,10 @@ typedef struct laim_server laim_server;
 typedef struct {
   uint64_t ticket;     /* from laim_server_submit */
   int32_t round;       /* rounds completed by this request after this step */
-  int32_t done;        /* 1 when the request finished (cleared and retired, or rounds exhausted) */
+  int32_t done;        /* 1 when the request finished: cleared and retired, rounds exhausted, or
+                          frozen (with skip_fixed: its messages at a fixed point, nothing flipped
+                          and no active check passing Evidence, so no later round can change
+                          its result) */
   int32_t tclr;        /* as in laim_decode_rounds (-1 while not cleared) */
   int32_t flips;       /* qubits flipped in this round */
   int32_t defects;     /* syndrome weight after this round */

@@ -576,8 +576,11 @@ laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t 
     Request& r = s->reqs.at(order[i]);
     r.round += 1;
     r.tclr = s->ev_h[4 * i + 2];
-    r.fail = s->ev_h[4 * i + 3];
-    r.done = (r.retire && r.tclr >= 0) || r.round >= r.rounds_total;
+    r.fail = s->ev_h[4 * i + 3] & 1;
+    // a frozen request (its state can no longer change) is finished: the
+    // remaining rounds would leave z, s, t_clr and the failure as they are
+    const bool frozen = (s->ev_h[4 * i + 3] >> 1) & 1;
+    r.done = (r.retire && r.tclr >= 0) || r.round >= r.rounds_total || frozen;
     if (ne < max_events) {
       laim_server_event& ev = events[ne++];
       ev.ticket = r.ticket;

@@ -30,13 +30,18 @@ namespace laim {
 namespace {
 
 constexpr int kCtmStride = 65;
-constexpr int kCtmWords = 16;  // scratch words after the messages
+constexpr int kCtmWords = 18;  // scratch words after the messages
 // scratch word indices
 // (the words start 8-byte aligned; the FP64 ones sit at even indices)
 constexpr int kCwZero = 0, kCwLpar = 1 /* 4 words */, kCwNs = 5, kCwMoved = 6, kCwJ = 7,
               kCwTev = 8 /* 2 words */, kCwEvents = 10, kCwMoves = 11, kCwClear = 12 /* 2 words */,
-              kCwQueue = 15;
+              kCwChg = 15, kCwSkipped = 16, kCwQueue = 17;
 constexpr int kCtmFusedWords = 4;
+
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
 
 template <int DC>
 __device__ __forceinline__ int32_t ctm_word(int32_t c, int32_t j) {
@@ -263,15 +268,20 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
   const float C = P.clamp;
   const float lam = P.lam;
 
-  // ---- per-thread graph tables (for the whole launch)
+  // ---- per-thread graph tables (for the whole launch). Checks t + k nt
+  // from m on pad the last tile: their LDS slots exist (mpad >= nt CPT) and
+  // they are stepped like the others -- inputs from the zero word, syndrome
+  // 0 -- so that the step needs no per-check condition; nothing reads them.
   int32_t cidx[CPT];
   int32_t deg[CPT];
   int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
+  uint32_t vmask = 0u;  // bit k: check k of this thread is one of the code's checks
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int32_t ch = t + k * nt;
     const bool valid = ch < c.m;
-    cidx[k] = valid ? ch : -1;
+    cidx[k] = ch;
+    vmask |= (valid ? 1u : 0u) << k;
     deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
@@ -304,10 +314,10 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         mvc[k][j] = 0.0f;
         mcv[k][j] = 0.0f;
       }
-      if (cidx[k] < 0) continue;
       float* mk = msg + ctm_word<DC>(cidx[k], 0);
 #pragma unroll
       for (int j = 0; j < DC; ++j) mk[j * kCtmStride] = 0.0f;
+      if (!((vmask >> k) & 1u)) continue;
       uint32_t x = 0;
       for (int32_t j = 0; j < deg[k]; ++j) x ^= e0row[c.chk_var[(int64_t)cidx[k] * c.dcmax + j]];
       sb |= (x & 1u) << k;
@@ -337,7 +347,19 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
     if (t == 0) *reinterpret_cast<double*>(gw + kCwTev) = Tev;
 
     int32_t kev = (nS > 0) ? ctm_step_of(Tev, P.dt, P.max_steps) : 0;
-    for (int32_t k = 0;; ++k) {
+    // conv: the messages are a fixed point of the Euler step for the current
+    // syndrome -- a step left every message bit for bit as it was. The step
+    // is a fixed map of (messages, syndrome), so every step up to the next
+    // move is the identity and the loop goes straight to the next event
+    // step (thread 0 adds the skipped steps to kCwSkipped); events are still
+    // handled one by one. Steps 7, 15, 23, ... compare (with P.skip) and
+    // raise kCwChg if a message changed; the step before each of them
+    // clears it, after every thread has read the last one. A jump happens
+    // only on a clear flag, and nothing raises it until the next compared
+    // step, so the steps after a jump find it clear as well.
+    bool conv = false;
+    int32_t k = 0;
+    for (;; ++k) {
       if (nS > 0 && k >= kev) {
         if (t == 0) ctm_events<DC, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw);
         __syncthreads();
@@ -349,11 +371,19 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
           uint32_t nsb = 0;
 #pragma unroll
           for (int kk = 0; kk < CPT; ++kk)
-            if (cidx[kk] >= 0) nsb |= ((sw[cidx[kk] >> 5] >> (cidx[kk] & 31)) & 1u) << kk;
+            if ((vmask >> kk) & 1u) nsb |= ((sw[cidx[kk] >> 5] >> (cidx[kk] & 31)) & 1u) << kk;
           sb = nsb;
+          conv = false;
         }
       }
       if (nS == 0 || k >= P.max_steps) break;
+      if (conv) {
+        const int32_t next = (nS > 0 && kev < P.max_steps) ? kev : P.max_steps;  // > k here
+        if (t == 0) gw[kCwSkipped] += next - k;
+        k = next - 1;
+        continue;
+      }
+      const bool cmp = P.skip && (k & 7) == 7;
 
       // ---- one Euler step: both directions from the state before it
       float Fv[CPT][DC], Fc[CPT][DC];
@@ -373,21 +403,40 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         ctm_check_rule<DC, BP, REG>(P, x, deg[kk], sigma_neg, Fc[kk]);
       }
       __syncthreads();
+      if (!cmp && t == 0) gw[kCwChg] = 0;
+      uint32_t diff = 0u;
+      // the update, written twice so that the compare costs nothing on the
+      // steps that do not compare
+      auto update = [&](auto cmp_tag) {
+        constexpr bool CMP = decltype(cmp_tag)::value;
 #pragma unroll
-      for (int kk = 0; kk < CPT; ++kk) {
-        if (cidx[kk] < 0) continue;
-        float* mk = msg + ctm_word<DC>(cidx[kk], 0);
+        for (int kk = 0; kk < CPT; ++kk) {
+          float* mk = msg + ctm_word<DC>(cidx[kk], 0);
+          uint32_t dk = 0u;
 #pragma unroll
-        for (int j = 0; j < DC; ++j) {
-          if (!REG && j >= deg[kk]) continue;
-          const float nv = mvc[kk][j] + lam * (Fv[kk][j] - mvc[kk][j]);
-          const float nc = mcv[kk][j] + lam * (Fc[kk][j] - mcv[kk][j]);
-          mvc[kk][j] = kNoClamp ? nv : __builtin_amdgcn_fmed3f(nv, -C, C);
-          mcv[kk][j] = kNoClamp ? nc : __builtin_amdgcn_fmed3f(nc, -C, C);
-          mk[j * kCtmStride] = mcv[kk][j];
+          for (int j = 0; j < DC; ++j) {
+            if (!REG && j >= deg[kk]) continue;
+            const float nv = mvc[kk][j] + lam * (Fv[kk][j] - mvc[kk][j]);
+            const float nc = mcv[kk][j] + lam * (Fc[kk][j] - mcv[kk][j]);
+            const float v2 = kNoClamp ? nv : __builtin_amdgcn_fmed3f(nv, -C, C);
+            const float c2 = kNoClamp ? nc : __builtin_amdgcn_fmed3f(nc, -C, C);
+            if (CMP)
+              dk |= (__float_as_uint(v2) ^ __float_as_uint(mvc[kk][j])) |
+                    (__float_as_uint(c2) ^ __float_as_uint(mcv[kk][j]));
+            mvc[kk][j] = v2;
+            mcv[kk][j] = c2;
+            mk[j * kCtmStride] = c2;
+          }
+          if (CMP) diff |= ((vmask >> kk) & 1u) ? dk : 0u;  // padding checks are not compared
         }
-      }
+      };
+      if (cmp)
+        update(BoolTag<true>());
+      else
+        update(BoolTag<false>());
+      if (cmp && diff) gw[kCwChg] = 1;
       __syncthreads();
+      if (cmp) conv = gw[kCwChg] == 0;
     }
 
     // ---- results
@@ -395,7 +444,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
       a.z[(int64_t)si * c.n + v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
 #pragma unroll
     for (int k = 0; k < CPT; ++k)
-      if (cidx[k] >= 0) a.s[(int64_t)si * c.m + cidx[k]] = (uint8_t)((sb >> k) & 1u);
+      if ((vmask >> k) & 1u) a.s[(int64_t)si * c.m + cidx[k]] = (uint8_t)((sb >> k) & 1u);
     if (a.fail && c.kw <= kCtmFusedWords) {
       uint32_t lp[kCtmFusedWords] = {0u, 0u, 0u, 0u};
 #pragma unroll 1
@@ -416,6 +465,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         a.counts[2 * (int64_t)si] = gw[kCwEvents];
         a.counts[2 * (int64_t)si + 1] = gw[kCwMoves];
       }
+      if (a.steps) a.steps[si] = k - gw[kCwSkipped];  // the loop ended at step k
       if (a.fail && c.kw <= kCtmFusedWords) {
         uint32_t f = (tclr < 0.0) ? 1u : 0u;
         for (int w = 0; w < kCtmFusedWords; ++w) f |= (uint32_t)gw[kCwLpar + w];
@@ -531,7 +581,7 @@ bool ctm_shape(const DevCode& c, const CtmParamsDev& P, int32_t cpt_want, int de
 
 hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& sh, const uint8_t* e0,
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
-                      int32_t* counts, uint8_t* fail, hipStream_t st) {
+                      int32_t* counts, int32_t* steps, uint8_t* fail, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
   // the degrees the shape was sized for; the exact degree-2 min-sum kernels
   // skip the clamps, so the parameters must allow them
@@ -548,6 +598,7 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
   a.s = s;
   a.tclr = tclr;
   a.counts = counts;
+  a.steps = steps;
   a.fail = (c.kw <= kCtmFusedWords) ? fail : nullptr;
   a.nt = sh.nt;
   a.mpad = sh.mpad;

@@ -660,8 +660,8 @@ laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_para
 laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_params* params,
                                    const uint8_t* e0, uint64_t shot0, int32_t nshots,
                                    void* workspace, size_t ws_bytes, uint8_t* z_out, uint8_t* s_out,
-                                   double* tclr_out, int32_t* counts_out, uint8_t* fail_out,
-                                   int32_t checks_per_thread, laim_stream stream) {
+                                   double* tclr_out, int32_t* counts_out, int32_t* steps_out,
+                                   uint8_t* fail_out, int32_t checks_per_thread, laim_stream stream) {
   if (!code || !params || nshots < 0 || (nshots > 0 && (!e0 || !z_out || !s_out || !tclr_out))) {
     set_error("laim_decode_continuous: bad arguments");
     return LAIM_EINVAL;
@@ -703,11 +703,12 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
   P.max_steps = (int32_t)floor(p.t_max / p.dt + 0.5);
   P.evidence = p.evidence ? 1 : 0;
   P.seed = p.seed;
+  P.skip = p.skip_fixed ? 1 : 0;
   CtmShape sh;
   if (!ctm_shape(code->dev, P, checks_per_thread, code->device, &sh)) return LAIM_EUNSUP;
   DeviceGuard g(code->device);
   hipError_t er = launch_ctm(code->dev, P, sh, e0, shot0, nshots, workspace, z_out, s_out, tclr_out,
-                             counts_out, fail_out, (hipStream_t)stream);
+                             counts_out, steps_out, fail_out, (hipStream_t)stream);
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "continuous-machine kernel");
 }
 

@@ -179,6 +179,7 @@ struct CtmParamsDev {
   int32_t max_steps;
   int32_t evidence;
   uint64_t seed;
+  int32_t skip;  // 1: steps at a fixed point of the messages are skipped
 };
 
 struct CtmShape {
@@ -198,6 +199,7 @@ struct CtmArgs {
   uint8_t* s;
   double* tclr;
   int32_t* counts;  // [nshots][2]: events, moves (or null)
+  int32_t* steps;   // [nshots]: Euler steps computed (or null)
   uint8_t* fail;    // or null
   int32_t nt, mpad;
 };
@@ -216,7 +218,7 @@ inline bool ctm_reg_dv2_ok(const CtmParamsDev& P) {
 bool ctm_shape(const DevCode& c, const CtmParamsDev& P, int32_t cpt_want, int device, CtmShape* out);
 hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& sh, const uint8_t* e0,
                       uint64_t shot0, int32_t nshots, void* ws, uint8_t* z, uint8_t* s, double* tclr,
-                      int32_t* counts, uint8_t* fail, hipStream_t st);
+                      int32_t* counts, int32_t* steps, uint8_t* fail, hipStream_t st);
 
 // ---- bit-centric machine (laim_bitcentric.hip)
 bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds);

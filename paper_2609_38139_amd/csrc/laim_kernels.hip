@@ -291,6 +291,7 @@ struct GroupJob {
   float* L_out;
   uint8_t* f_out;        //   logical failure (0/1)
   int32_t* ev_out;       //   [4] flips and syndrome weight of the last round run, t_clr, failure
+                         //   (bit 0) and frozen (bit 1)
   int32_t* sw_out;       //   BP sweeps computed
 };
 
@@ -483,6 +484,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   // sweep is the identity until a flip changes the syndrome, and the group
   // skips them (with kp.skip; the results are those of all the sweeps).
   bool conv = kp.skip && member && u.resume && alive && job_at(g).st_hdr[1] != 0;
+  bool frozen = false;
   int32_t nsweeps = 0;
   // this thread's active checks that failed the Evidence test in the last
   // feedback (valid while the group stays at a fixed point: same beliefs,
@@ -882,7 +884,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       // sweep changes anything, the same checks fail the test, nothing
       // flips -- and so does every round after it: the shot's z, s, t_clr
       // and beliefs are final and it stops here.
-      if (conv && !gw[kGwLive]) working = false;
+      if (conv && !gw[kGwLive]) {
+        working = false;
+        frozen = true;
+      }
     }
   }
 
@@ -960,7 +965,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       job.ev_out[0] = flips_last;
       job.ev_out[1] = gw[kGwDefects];
       job.ev_out[2] = tclr;
-      job.ev_out[3] = f ? 1 : 0;
+      job.ev_out[3] = (f ? 1 : 0) | (frozen ? 2 : 0);
     }
   }
   }  // units

@@ -101,7 +101,7 @@ class DecodeParams:
 class ContinuousParamsC(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("dt", C.c_double), ("tau", C.c_double), ("t_max", C.c_double),
-                ("evidence", C.c_int32), ("seed", C.c_uint64)]
+                ("evidence", C.c_int32), ("seed", C.c_uint64), ("skip_fixed", C.c_int32)]
 
 
 @dataclass
@@ -118,12 +118,14 @@ class ContinuousParams:
     t_max: float = 100.0
     evidence: bool = True
     seed: int = 0
+    skip_fixed: bool = True  # skip Euler steps at a fixed point of the messages (same results)
 
     def c(self) -> ContinuousParamsC:
         if self.bp not in ("minsum", "sumproduct"):
             raise ValueError("bp must be 'minsum' or 'sumproduct'")
         return ContinuousParamsC(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
-                                 self.dt, self.tau, self.t_max, int(self.evidence), self.seed)
+                                 self.dt, self.tau, self.t_max, int(self.evidence), self.seed,
+                                 int(self.skip_fixed))
 
 
 CONTINUOUS_WORKSPACE_BYTES = 256
@@ -173,7 +175,7 @@ def lib():
         L.laim_server_stats.argtypes = [vp, i32p, i32p, C.POINTER(sz)]
         L.laim_server_destroy.argtypes = [vp]
         L.laim_decode_continuous.argtypes = [vp, C.POINTER(ContinuousParamsC), vp, u64, i32, vp, sz,
-                                             vp, vp, vp, vp, vp, i32, vp]
+                                             vp, vp, vp, vp, vp, vp, i32, vp]
         L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
         L.laim_server_destroy.restype = None
         _lib = L
@@ -343,9 +345,10 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
 
 def decode_continuous(code: Code, params: ContinuousParams, e0, shot0: int = 0,
                       checks_per_thread: int = 0, want_fail: bool = False, workspace=None,
-                      stream=None) -> dict:
+                      stream=None, want_steps: bool = False) -> dict:
     """``laim_decode_continuous``: returns device tensors z, s, tclr (float64),
-    counts ([nshots, 2] int32: events, moves) and, with want_fail, fail."""
+    counts ([nshots, 2] int32: events, moves) and, with want_fail, fail; with
+    want_steps the Euler steps computed per shot."""
     import torch
     ns = e0.shape[0]
     _dev(e0, torch.uint8, (ns, code.n), "e0")
@@ -354,14 +357,15 @@ def decode_continuous(code: Code, params: ContinuousParams, e0, shot0: int = 0,
            "s": torch.empty((ns, code.m), dtype=torch.uint8, device=dev),
            "tclr": torch.empty((ns,), dtype=torch.float64, device=dev),
            "counts": torch.empty((ns, 2), dtype=torch.int32, device=dev),
-           "fail": torch.empty((ns,), dtype=torch.uint8, device=dev) if want_fail else None}
+           "fail": torch.empty((ns,), dtype=torch.uint8, device=dev) if want_fail else None,
+           "steps": torch.empty((ns,), dtype=torch.int32, device=dev) if want_steps else None}
     if workspace is None:
         workspace = torch.empty((CONTINUOUS_WORKSPACE_BYTES,), dtype=torch.uint8, device=dev)
     P = params.c()
     check(lib().laim_decode_continuous(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(workspace),
                                        workspace.numel(), _ptr(out["z"]), _ptr(out["s"]),
-                                       _ptr(out["tclr"]), _ptr(out["counts"]), _ptr(out["fail"]),
-                                       checks_per_thread, _stream(stream)),
+                                       _ptr(out["tclr"]), _ptr(out["counts"]), _ptr(out["steps"]),
+                                       _ptr(out["fail"]), checks_per_thread, _stream(stream)),
           "laim_decode_continuous")
     return out
 

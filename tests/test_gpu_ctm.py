@@ -182,3 +182,38 @@ def test_clamp_binding_settings(L, orc):
     for kw in ({"clamp": 3.0}, {"dt": 0.2, "tau": 0.1}, {}):
         run_both(L, orc, "toric2d:6", 0.08, 80, bp="minsum", t_max=12.0,
                  **({"dt": 0.01} | kw), tag=f"clamp {kw}")
+
+
+@pytest.mark.parametrize("bp,name,p,t_max", [("minsum", "toric2d:8", 0.06, 20.0), ("sumproduct", "toric2d:8", 0.06, 20.0),
+                                             ("minsum", "bb:6x6", 0.04, 10.0), ("minsum", "toric3d_point:3", 0.05, 10.0),
+                                             ("minsum", "toric2d:16", 0.05, 30.0)])
+def test_skipping_fixed_steps_is_exact(L, orc, bp, name, p, t_max):
+    """Steps at a fixed point of the messages are skipped up to the next
+    event (skip_fixed, the default): every output -- corrections,
+    syndromes, clearing times, event and move counts, failures -- equals
+    the same launch computing every step, and the oracle."""
+    import torch
+    kw = dict(bp=bp, dt=0.001, t_max=t_max)
+    got, _ = run_both(L, orc, name, p, 77, tag="skip", **kw)
+    code, dc = dcode(L, name)
+    e0 = orc.sample_noise(code, p, 0, 0, 77)
+    e0d = torch.from_numpy(e0).cuda()
+    g = L.decode_continuous(dc, L.ContinuousParams(skip_fixed=False, **kw), e0d, want_fail=True,
+                            want_steps=True)
+    for k in ("z", "s", "tclr", "counts", "fail"):
+        assert np.array_equal(g[k].cpu().numpy(), got[k]), k
+    # steps computed: without the skip, those up to the step at which the
+    # clearing event acts (the first k with k dt >= t_clr), or all K
+    K = int(np.floor(t_max / 0.001 + 0.5))
+    want = []
+    for T in got["tclr"]:
+        if T < 0:
+            want.append(K)
+        else:
+            k = 0
+            while k * 0.001 < T:
+                k += 1
+            want.append(min(k, K))
+    assert np.array_equal(g["steps"].cpu().numpy(), np.array(want))
+    on = L.decode_continuous(dc, L.ContinuousParams(**kw), e0d, want_steps=True)["steps"].cpu().numpy()
+    assert np.all(on <= np.array(want))
