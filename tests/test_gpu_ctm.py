@@ -217,3 +217,17 @@ def test_skipping_fixed_steps_is_exact(L, orc, bp, name, p, t_max):
     assert np.array_equal(g["steps"].cpu().numpy(), np.array(want))
     on = L.decode_continuous(dc, L.ContinuousParams(**kw), e0d, want_steps=True)["steps"].cpu().numpy()
     assert np.all(on <= np.array(want))
+
+
+@pytest.mark.parametrize("name,cpt", [("toric3d_point:3", 2), ("toric3d_point:3", 4), ("toric2d:5", 8)])
+def test_padding_checks_continuous(L, orc, name, cpt):
+    """Launch shapes whose last tile is padded (more checks per block than
+    the code has): results equal the oracle, with and without the skip."""
+    import torch
+    got, _ = run_both(L, orc, name, 0.05, 41, cpt=cpt, tag="padding", dt=0.01, t_max=10.0)
+    code, dc = dcode(L, name)
+    e0 = orc.sample_noise(code, 0.05, 0, 0, 41)
+    g = L.decode_continuous(dc, L.ContinuousParams(dt=0.01, t_max=10.0, skip_fixed=False),
+                            torch.from_numpy(e0).cuda(), checks_per_thread=cpt, want_fail=True)
+    for k in ("z", "s", "tclr", "counts", "fail"):
+        assert np.array_equal(g[k].cpu().numpy(), got[k]), k

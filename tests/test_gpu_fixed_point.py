@@ -209,3 +209,26 @@ def test_metric_workload_full_size_with_skip(L, orc):
     sw_off = int(off["sweeps"].sum().item())
     print(f"[skip] sweeps computed {sw_on} of {sw_off} ({sw_on / sw_off:.3f})", flush=True)
     assert sw_on < 0.5 * sw_off
+
+
+@pytest.mark.parametrize("name,cfg", [("bb:6x6", {"checks_per_thread": 4, "threads_per_shot": 10}),
+                                      ("toric3d_point:3", {"checks_per_thread": 2}),
+                                      ("toric3d_point:3", {"checks_per_thread": 4}),
+                                      ("toric3d_point:3", {"checks_per_thread": 8, "shots_per_block": 3}),
+                                      ("toric2d:6", {"checks_per_thread": 4, "threads_per_shot": 11})])
+def test_padding_checks(L, orc, name, cfg):
+    """Shapes whose threads own more checks than the code has (the last tile
+    is padded): the padding checks are swept like the others and must
+    change nothing -- results equal the oracle and the default shape, with
+    and without the skip, and the sweep counts do not depend on the shape."""
+    code, dc = dcode(L, name)
+    e0_np = orc.sample_noise(code, 0.05, 9, 0, 97)
+    e0 = gpu_e0(L, dc, e0_np)
+    for skip in (True, False):
+        P = L.DecodeParams(rounds=40, skip_fixed=skip)
+        compare_decode(L, orc, name, P, e0_np, cfg=cfg, tag=f"padding skip={skip}")
+        a = run(L, dc, P, e0, cfg=cfg)
+        b = run(L, dc, P, e0)
+        for k in ("z", "s", "tclr", "sweeps"):
+            assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a["L"].view(np.uint32), b["L"].view(np.uint32))
