@@ -300,3 +300,28 @@ def test_batch_plan_with_empty_and_single_items(L, orc):
                         shot0=11)
         assert np.array_equal(o["z"][:1].cpu().numpy(), od["z"]), it["spec"].name
         assert int(o["tclr"][0]) == int(od["tclr"][0]), it["spec"].name
+
+
+def test_batch_plan_and_server_skip_equals_every_sweep(L):
+    """The exact shortcuts (skip_fixed, the default) inside the batched plan
+    and the server: the same items with every sweep computed give the same
+    z, s, t_clr and failures; in the server, requests that freeze finish
+    early with the result of all their rounds."""
+    import dataclasses
+
+    import torch
+    mix_on = _mix(L)
+    mix_off = [dict(it, params=dataclasses.replace(it["params"], skip_fixed=False)) for it in mix_on]
+    outs_on = L.BatchPlan(mix_on).launch()
+    outs_off = L.BatchPlan(mix_off).launch()
+    torch.cuda.synchronize()
+    for it, a, b in zip(mix_on, outs_on, outs_off):
+        for k in ("z", "s", "tclr", "fail"):
+            assert torch.equal(a[k], b[k]), (it["spec"].name, k)
+    order = [(i, k) for i, it in enumerate(mix_on) for k in range(0, it["e0"].shape[0], 13)]
+    ra, _ = _serve(L, mix_on, order)
+    rb, _ = _serve(L, mix_off, order)
+    assert ra.keys() == rb.keys()
+    for key in ra:
+        for k in ("z", "s", "tclr", "fail"):
+            assert np.array_equal(np.asarray(ra[key][k]), np.asarray(rb[key][k])), (key, k)
