@@ -530,7 +530,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         }
         fresh = false;
         it0 = 1;
-        nsweeps += sweep ? 1 : 0;
+        nsweeps += (sweep && nsweeps != 0x7fffffff) ? 1 : 0;  // saturating
         __syncthreads();
       }
       // With CMP, a sweep may also compare each new message with the one
@@ -655,7 +655,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           }
           fresh = false;
           __syncthreads();
-          nsweeps += sweep ? 1 : 0;
+          nsweeps += (sweep && nsweeps != 0x7fffffff) ? 1 : 0;  // saturating
           if (CMP) {
             ++ncmp;
             if (sweep && gw[f ? kGwChg1 : kGwChg0] == 0) {
