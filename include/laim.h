@@ -157,7 +157,7 @@ typedef struct {
  * syndrome, prior and parameters do not change), so once a sweep writes
  * every message of a shot back bit for bit, every later sweep does the same
  * until a flip changes the syndrome. With skip_fixed = 1 the resident form
- * detects such a sweep -- sweep i of a round with i = 3 mod 4, and the
+ * detects such a sweep -- sweep i of a round with i = 7 mod 8, and the
  * round's last, compare each new message with the one it replaces -- and
  * leaves the shot's messages as they are for the rest of the round and for
  * following rounds without a flip. A shot's first sweep

@@ -534,9 +534,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         __syncthreads();
       }
       // With CMP, a sweep may also compare each new message with the one
-      // it replaces; comparing costs a fifth of a sweep, so it is done
-      // every fourth sweep and at the last of the round, and a fixed point
-      // is found at most three sweeps late (those sweeps are identities).
+      // it replaces; comparing costs half a sweep's worth of extra VALU per
+      // check, so it is done every eighth sweep and at the last of the
+      // round, and a fixed point is found at most seven sweeps late (those
+      // sweeps are identities).
       // The flags of successive compared sweeps alternate, so that a flag
       // is cleared only after every thread has read it. A shot's first
       // sweep (m_{v->c} = 0 rather than pi + sum m_{c->v}) is another map
@@ -545,7 +546,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         constexpr bool CMP_ON = decltype(cmp_tag)::value;
         int32_t ncmp = 0;  // compared sweeps so far in this round
         for (int32_t it = it0; it < kp.iters; ++it) {
-          const bool CMP = CMP_ON && ((it & 3) == 3 || it == kp.iters - 1);
+          const bool CMP = CMP_ON && ((it & 7) == 7 || it == kp.iters - 1);
           const int32_t f = ncmp & 1;
           const bool first = fresh;
           float x[CPT][DC];

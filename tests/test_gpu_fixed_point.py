@@ -115,7 +115,7 @@ def test_skip_in_every_launch_shape(L, orc, cfg):
 def replay_sweeps(orc, code, P, e0, shot):
     """The skip rule replayed with the oracle's sweep: a round of a shot at a
     fixed point computes no sweep; otherwise sweeps run until a compared
-    one -- sweep i of the round with i = 3 mod 4, or its last -- leaves
+    one -- sweep i of the round with i = 7 mod 8, or its last -- leaves
     every check-to-qubit message bit for bit as it was (that sweep counts)
     or the round's sweeps are used up. The first sweep of a shot never
     counts as a fixed point; a round with a flip ends the fixed point."""
@@ -137,7 +137,7 @@ def replay_sweeps(orc, code, P, e0, shot):
             for it in range(P.iters):
                 mcv2, mvc2 = orc.bp_sweep(code, op, pi_v, s, mvc)
                 n += 1
-                compared = it % 4 == 3 or it == P.iters - 1
+                compared = it % 8 == 7 or it == P.iters - 1
                 same = compared and not fresh and np.array_equal(mcv2.view(np.uint32), mcv.view(np.uint32))
                 mcv, mvc, fresh = mcv2, mvc2, False
                 if same:
@@ -154,6 +154,7 @@ def replay_sweeps(orc, code, P, e0, shot):
 
 @pytest.mark.parametrize("name,kw,p", [("toric2d:8", dict(rounds=32), 0.06),
                                        ("toric2d:8", dict(rounds=32, iters=6), 0.06),
+                                       ("toric2d:8", dict(rounds=32, iters=11), 0.06),
                                        ("toric2d:8", dict(rounds=32, iters=1), 0.06),
                                        ("toric2d:8", dict(rounds=32, bp="sumproduct"), 0.08),
                                        ("bb:6x6", dict(rounds=24), 0.05),
