@@ -432,7 +432,7 @@ def cpu_baseline(args, spec, P_or, seconds, nthreads=None, max_shots=4096):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(shots are independent: N GPUs would each take a disjoint range of shot ids)",
               file=sys.stderr)
         return 2
