@@ -39,7 +39,7 @@ typedef int32_t laim_status;
 #define LAIM_EINVAL (-1) /* bad argument or shape */
 #define LAIM_ENOMEM (-2) /* allocation failed or workspace too small */
 #define LAIM_EHIP (-3)   /* a HIP runtime call failed */
-#define LAIM_EUNSUP (-4) /* valid, but not supported by this build */
+#define LAIM_EUNSUP (-4) /* valid, but not supported by this library */
 #define LAIM_EBUSY (-5)  /* resource exhausted (server slots, budget) */
 
 typedef void* laim_stream; /* hipStream_t */
