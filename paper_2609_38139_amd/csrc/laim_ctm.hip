@@ -250,7 +250,9 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
 
 }  // namespace
 
-template <int DC, int DV, int CPT, int BP, bool REG>
+// SKIP: the kernel skips steps at a fixed point (P.skip); the instance
+// without it carries none of that bookkeeping.
+template <int DC, int DV, int CPT, int BP, bool REG, bool SKIP>
 __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, CtmArgs a) {
   // min-sum on qubits of degree 2 (exact variants, run only when
   // ctm_reg_dv2_ok holds): no clamp can bind
@@ -377,13 +379,13 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         }
       }
       if (nS == 0 || k >= P.max_steps) break;
-      if (conv) {
+      if (SKIP && conv) {
         const int32_t next = (nS > 0 && kev < P.max_steps) ? kev : P.max_steps;  // > k here
         if (t == 0) gw[kCwSkipped] += next - k;
         k = next - 1;
         continue;
       }
-      const bool cmp = P.skip && (k & 7) == 7;
+      const bool cmp = SKIP && (k & 7) == 7;
 
       // ---- one Euler step: both directions from the state before it
       float Fv[CPT][DC], Fc[CPT][DC];
@@ -403,7 +405,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         ctm_check_rule<DC, BP, REG>(P, x, deg[kk], sigma_neg, Fc[kk]);
       }
       __syncthreads();
-      if (!cmp && t == 0) gw[kCwChg] = 0;
+      if (SKIP && !cmp && t == 0) gw[kCwChg] = 0;
       uint32_t diff = 0u;
       // the update, written twice so that the compare costs nothing on the
       // steps that do not compare
@@ -430,7 +432,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
           if (CMP) diff |= ((vmask >> kk) & 1u) ? dk : 0u;  // padding checks are not compared
         }
       };
-      if (cmp)
+      if (SKIP && cmp)
         update(BoolTag<true>());
       else
         update(BoolTag<false>());
@@ -482,15 +484,16 @@ typedef void (*CtmKernel)(DevCode, CtmParamsDev, CtmArgs);
 
 struct CtmVariant {
   int dc, dv, cpt, bp, reg;
-  CtmKernel fn;
+  CtmKernel fn;       // every Euler step
+  CtmKernel fn_skip;  // steps at a fixed point skipped
 };
 
-#define LAIM_CTM(DC, DV, CPT)                                                  \
-  {DC, DV, CPT, 0, 1, ctm_kernel<DC, DV, CPT, 0, true>},                      \
-      {DC, DV, CPT, 1, 1, ctm_kernel<DC, DV, CPT, 1, true>}
-#define LAIM_CTM_IRR(DC, DV, CPT)                                              \
-  {DC, DV, CPT, 0, 0, ctm_kernel<DC, DV, CPT, 0, false>},                     \
-      {DC, DV, CPT, 1, 0, ctm_kernel<DC, DV, CPT, 1, false>}
+#define LAIM_CTM(DC, DV, CPT)                                                                        \
+  {DC, DV, CPT, 0, 1, ctm_kernel<DC, DV, CPT, 0, true, false>, ctm_kernel<DC, DV, CPT, 0, true, true>}, \
+      {DC, DV, CPT, 1, 1, ctm_kernel<DC, DV, CPT, 1, true, false>, ctm_kernel<DC, DV, CPT, 1, true, true>}
+#define LAIM_CTM_IRR(DC, DV, CPT)                                                                       \
+  {DC, DV, CPT, 0, 0, ctm_kernel<DC, DV, CPT, 0, false, false>, ctm_kernel<DC, DV, CPT, 0, false, true>}, \
+      {DC, DV, CPT, 1, 0, ctm_kernel<DC, DV, CPT, 1, false, false>, ctm_kernel<DC, DV, CPT, 1, false, true>}
 
 const CtmVariant kCtmVariants[] = {
     LAIM_CTM(2, 2, 1), LAIM_CTM(2, 2, 2), LAIM_CTM(2, 2, 4),
@@ -602,7 +605,8 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
   a.fail = (c.kw <= kCtmFusedWords) ? fail : nullptr;
   a.nt = sh.nt;
   a.mpad = sh.mpad;
-  const void* fn = reinterpret_cast<const void*>(var->fn);
+  const CtmKernel kfn = P.skip ? var->fn_skip : var->fn;
+  const void* fn = reinterpret_cast<const void*>(kfn);
   if (sh.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
     if (e != hipSuccess) return e;
@@ -618,7 +622,7 @@ hipError_t launch_ctm(const DevCode& c, const CtmParamsDev& P, const CtmShape& s
   const int64_t want = (int64_t)per_cu * cus;
   const unsigned blocks = (unsigned)(want < nshots ? want : nshots);
   hipLaunchKernelGGL(ctm_zero_counter, dim3(1), dim3(64), 0, st, a.counter);
-  hipLaunchKernelGGL(var->fn, dim3(blocks), dim3(sh.nt), sh.lds, st, c, P, a);
+  hipLaunchKernelGGL(kfn, dim3(blocks), dim3(sh.nt), sh.lds, st, c, P, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (fail && c.kw > kCtmFusedWords) return launch_failure(c, e0, z, nshots, fail, st);
