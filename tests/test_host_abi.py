@@ -1,6 +1,7 @@
 """CPU-side checks of the library: it loads, exports every symbol the header
-declares, rejects malformed input before touching a device, and its host
-GF(2) code finds a correct logical basis."""
+declares, the binding's structs have the header's layout, it rejects
+malformed input before touching a device, and its host GF(2) code finds a
+correct logical basis."""
 import os
 import re
 
@@ -28,6 +29,42 @@ def test_exports_every_declared_symbol(laim):
     lib = laim.lib()
     for name in declared:
         assert hasattr(lib, name), name
+
+
+STRUCTS = {"laim_decode_params": "Params", "laim_resident_cfg": "ResidentCfg",
+           "laim_continuous_params": "ContinuousParamsC", "laim_batch_item": "BatchItem",
+           "laim_server_event": "ServerEvent"}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every parameter struct the binding passes by pointer has the size and
+    field offsets that a C compiler gives the header's struct."""
+    import ctypes as C
+    import subprocess
+    from paper_2609_38139_amd import laim as L
+    hdr = open(os.path.join(ROOT, "include", "laim.h")).read()
+    lines = []
+    for cname, pyname in STRUCTS.items():
+        body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + r"\s*;", hdr).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        cfields = re.findall(r"([A-Za-z_][A-Za-z_0-9]*)\s*;", body)
+        pyfields = [f[0] for f in getattr(L, pyname)._fields_]
+        assert cfields == pyfields, cname
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        lines += [f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));' for f in cfields]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"laim.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\n  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict((" ".join(w[:2]), int(w[2])) for w in (ln.split() for ln in out) if w)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(L, pyname)
+        assert got[f"{cname} size"] == C.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[f"{cname} {f[0]}"] == getattr(cls, f[0]).offset, (cname, f[0])
 
 
 def test_rejects_malformed_csr_without_a_device(laim):
