@@ -1,5 +1,5 @@
 """CPU-side checks of the library: it loads, exports every symbol the header
-declares, the binding's structs have the header's layout, it rejects
+declares, the binding's structs and prototypes agree with the header, it rejects
 malformed input before touching a device, and its host GF(2) code finds a
 correct logical basis."""
 import os
@@ -65,6 +65,42 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[f"{cname} size"] == C.sizeof(cls), cname
         for f in cls._fields_:
             assert got[f"{cname} {f[0]}"] == getattr(cls, f[0]).offset, (cname, f[0])
+
+
+def _c_kind(decl):
+    """('ptr', 8) for pointers and the stream handle, else ('int'|'float', size)."""
+    decl = decl.strip()
+    if "*" in decl or decl.split()[0] == "laim_stream":
+        return ("ptr", 8)
+    t = " ".join(decl.replace("const ", "").split()[:-1] or decl.split())
+    return {"int32_t": ("int", 4), "laim_status": ("int", 4), "int": ("int", 4), "uint64_t": ("int", 8),
+            "int64_t": ("int", 8), "size_t": ("int", 8), "double": ("float", 8), "float": ("float", 4),
+            "void": None}[t]
+
+
+def _ctypes_kind(t):
+    import ctypes as C
+    if t is None:
+        return None
+    if t in (C.c_void_p, C.c_char_p) or issubclass(t, C._Pointer):
+        return ("ptr", 8)
+    return ("float" if t in (C.c_float, C.c_double) else "int", C.sizeof(t))
+
+
+def test_binding_prototypes_match_the_header(laim):
+    """Each exported function's argument list and return type, as the
+    binding declares them, agree with the header's prototype in count, kind
+    (pointer, integer, floating) and width."""
+    hdr = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "laim.h")).read(), flags=re.S)
+    lib = laim.lib()
+    for name in laim.SYMBOLS:
+        m = re.search(r"^([A-Za-z_][\w \*]*?)\s*\b" + name + r"\s*\(([^)]*)\)\s*;", hdr, re.M)
+        assert m, name
+        ret, args = m.group(1), m.group(2).strip()
+        cargs = [] if args in ("", "void") else [_c_kind(a) for a in args.split(",")]
+        fn = getattr(lib, name)
+        assert [_ctypes_kind(t) for t in (fn.argtypes or [])] == cargs, name
+        assert _ctypes_kind(fn.restype) == _c_kind(ret + " r"), name
 
 
 def test_rejects_malformed_csr_without_a_device(laim):
