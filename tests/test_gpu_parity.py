@@ -294,6 +294,40 @@ def test_single_and_empty_batches(L, orc):
     assert out["z"].shape == (0, code.n)
 
 
+def test_every_call_accepts_an_empty_batch(L):
+    """Zero shots: every shot-batched call returns at once with empty outputs,
+    whatever optional outputs are asked for, and an idle server step reports
+    no event."""
+    import torch
+    code, dc = dcode(L, "toric2d:6")
+    print("empty batch: noise, syndrome, failure", flush=True)
+    e0 = L.sample_noise(dc, 0.05, 1, 0, 0)
+    assert e0.shape == (0, code.n)
+    assert L.syndrome(dc, e0).shape == (0, code.m)
+    assert L.logical_failure(dc, e0, e0).shape == (0,)
+    for form in ("resident", "stream"):
+        for bp in ("minsum", "sumproduct"):
+            print(f"empty batch: decode_rounds {form} {bp}", flush=True)
+            out = L.decode_rounds(dc, L.DecodeParams(bp=bp, rounds=4), e0, form=form, want_beliefs=True,
+                                  want_sweeps=True, want_fail=True)
+            for k, shape in (("z", (0, code.n)), ("s", (0, code.m)), ("tclr", (0,)), ("L", (0, code.n)),
+                             ("sweeps", (0,)), ("fail", (0,))):
+                assert out[k].shape == shape, (form, bp, k)
+    print("empty batch: decode_continuous", flush=True)
+    out = L.decode_continuous(dc, L.ContinuousParams(dt=0.01, t_max=1.0), e0, want_fail=True,
+                              want_steps=True)
+    assert out["counts"].shape == (0, 2) and out["steps"].shape == (0,) and out["fail"].shape == (0,)
+    print("empty batch: decode_bitcentric", flush=True)
+    rc, rdc = dcode(L, "rep:7")
+    e1 = torch.zeros((0, rc.n), dtype=torch.uint8, device="cuda")
+    out = L.decode_bitcentric(rdc, 0.05, e1, 8, want_beliefs=True)
+    assert out["z"].shape == (0, rc.n) and out["iclr"].shape == (0,) and out["L"].shape == (0, rc.n)
+    print("empty batch: idle server step", flush=True)
+    srv = L.Server(device=0, mem_budget=1 << 20, max_slots=4)
+    assert srv.step() == []
+    torch.cuda.synchronize()
+
+
 def test_invalid_arguments_are_rejected(L):
     import torch
     code, dc = dcode(L, "toric2d:8")
