@@ -186,7 +186,8 @@ typedef struct {
 #define LAIM_FORM_RESIDENT 1 /* one persistent launch, per-shot state in LDS/registers */
 #define LAIM_FORM_STREAM 2   /* messages in HBM, one launch per BP sweep and per phase */
 
-/* Workspace needed by laim_decode_rounds for nshots shots in `form`. */
+/* Workspace needed by laim_decode_rounds for nshots shots in `form`; 0 for
+ * bad arguments or a form the code cannot run in. */
 size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* params,
                             int32_t nshots, int32_t form);
 
@@ -208,6 +209,12 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
  *              shot, exactly as laim_logical_failure(e0, z_out) gives it; the
  *              resident form computes it inside the launch (codes with at
  *              most 128 logicals), otherwise a failure kernel follows
+ * Errors: LAIM_EINVAL for bad arguments or an unknown form; LAIM_EUNSUP for
+ * form = LAIM_FORM_RESIDENT when the code cannot run in it (a shot's state
+ * larger than the LDS, degrees beyond the compiled variants, or min-sum with
+ * alpha > 1), and for fail_out on codes with more than 2048 logicals;
+ * LAIM_ENOMEM for a workspace smaller than laim_workspace_bytes gives. All
+ * are reported before anything is launched.
  * Concurrent calls on different streams may share a laim_code but not a
  * workspace.
  */

@@ -604,7 +604,11 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
     f = LAIM_FORM_STREAM;
   } else {
     f = resolve_form(code, kp.bp, seq, reg_dv2_ok(kp), form, &sh);
-    if (f < 0) return LAIM_EUNSUP;
+    if (f < 0) {
+      set_error("the code cannot run in the resident form (a shot's state exceeds the LDS or its "
+                "degrees have no compiled variant)");
+      return LAIM_EUNSUP;
+    }
   }
   const size_t need = (f == LAIM_FORM_RESIDENT) ? resident_workspace_bytes()
                                                 : stream_workspace_bytes(code->dev, nshots, seq);

@@ -342,6 +342,28 @@ def test_invalid_arguments_are_rejected(L):
         L.decode_rounds(dc, L.DecodeParams(), e0[:, :10].contiguous())
 
 
+def test_explicit_resident_form_it_cannot_take(L, orc):
+    """Asking for the resident form where it cannot run is an error, with no
+    workspace size, while the automatic choice runs the stream form."""
+    import torch
+    for name, P in (("toric3d_membrane:16", L.DecodeParams(q=0.125, rounds=2)),
+                    ("toric2d:8", L.DecodeParams(alpha=1.25, rounds=6))):
+        code, dc = dcode(L, name)
+        print(f"[resident refused] {name} alpha={P.alpha}", flush=True)
+        assert L.workspace_bytes(dc, P, 8, form="resident") == 0
+        assert L.workspace_bytes(dc, P, 8, form="auto") == L.workspace_bytes(dc, P, 8, form="stream") > 0
+        e0_np = orc.sample_noise(code, 0.03, 4, 0, 8)
+        e0 = gpu_e0(L, dc, e0_np)
+        with pytest.raises(L.LaimError) as ei:
+            L.decode_rounds(dc, P, e0, form="resident")
+        assert ei.value.status == L.EUNSUP
+        assert b"resident" in L.lib().laim_last_error()
+        a = L.decode_rounds(dc, P, e0, form="auto")
+        b = L.decode_rounds(dc, P, e0, form="stream")
+        for k in ("z", "s", "tclr"):
+            assert torch.equal(a[k], b[k]), (name, k)
+
+
 # ------------------------------------------------- full-size, sampled shots
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("form,bp,cfg", [("resident", "minsum", None), ("resident", "minsum", (8, 1)),
