@@ -137,7 +137,10 @@ laim_status laim_syndrome(const laim_code* code, const uint8_t* e, int32_t nshot
  */
 typedef struct {
   int32_t bp;           /* 0: normalised min-sum (alpha * min, sign product); 1: sum-product
-                           (BP-LLR2, evaluated as an ascending box-plus fold) */
+                           (BP-LLR2 in box-plus form: output j of a check is F_{j-1} [+] B_{j+1},
+                           with the ascending prefix folds F_k = F_{k-1} [+] m_k and the
+                           descending suffix folds B_k = m_k [+] B_{k+1}; an empty side is
+                           dropped) */
   float alpha;          /* min-sum scale, > 0 (0.75) */
   double q;             /* decoder prior in (0, 1): pi = log(q / (1 - q)) (Table S1: 0.05) */
   float clamp;          /* CLAMP > 0 (Table S1: 1000) */

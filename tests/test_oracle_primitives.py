@@ -178,3 +178,64 @@ def test_evidence_thresholds(orc):
         assert abs(sig - 1 / d) < 1e-7
     assert t[4] == np.float32(-np.log(3.0))
     assert t[6] == np.float32(-np.log(5.0))
+
+
+def _star(dc):
+    """One check on dc qubits, each qubit in no other check."""
+    from paper_2609_38139_amd import codes
+    return codes.from_dense(np.ones((1, dc), dtype=np.uint8))
+
+
+def _check_inputs(rng, dc, trial):
+    kind = trial % 4
+    if kind == 0:
+        x = rng.standard_normal(dc) * 8
+    elif kind == 1:
+        x = rng.uniform(-40, 40, dc)
+    elif kind == 2:
+        x = rng.standard_normal(dc) * 0.5
+    else:
+        x = rng.uniform(-3, 3, dc) * rng.choice([1, 10], dc)
+    return x.astype(np.float32)
+
+
+def test_sum_product_order_against_definition_and_ascending_fold(orc):
+    """The sum-product check rule (BP-LLR2) of the oracle evaluates output j
+    as F_{j-1} [+] B_{j+1} (ascending prefix and descending suffix box-plus
+    folds). Box-plus is the tanh product written in the log domain, so every
+    order computes the same real number; this pins how far the FP32 order
+    may move the result, for check degrees 2..8:
+      - from the definition 2 atanh(prod_{i != j} tanh(m_i / 2)), evaluated
+        with 50 significant digits: at most 1e-6 of max(1, |m|);
+      - from the plain ascending fold ((m_0 [+] m_1) [+] m_2) ... of the
+        other inputs (same FP32 box-plus): at most 8 ulp of max(1, |m|), and
+        bit-identical for d_c <= 3, where the two orders coincide.
+    Both include the sign (-1)^{s_c + d_c} and the clamp."""
+    import mpmath
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(11)
+    P = orc.DecodeParams(bp="sumproduct")
+    ulp1 = 2.0 ** -23
+    for dc in range(2, 9):
+        spec = _star(dc)
+        sig = (-1) ** dc  # s_c = 0
+        for trial in range(240):
+            x = _check_inputs(rng, dc, trial)
+            mcv, _ = orc.bp_sweep(spec, P, np.zeros(dc, np.float32), np.zeros(1, np.uint8), x)
+            for j in range(dc):
+                others = [float(x[i]) for i in range(dc) if i != j]
+                prod = mpmath.mpf(1)
+                for o in others:
+                    prod *= mpmath.tanh(mpmath.mpf(o) / 2)
+                ref = float(sig * 2 * mpmath.atanh(prod)) if abs(prod) < 1 else sig * np.inf
+                ref = min(1000.0, max(-1000.0, ref))
+                got = float(mcv[j])
+                assert abs(got - ref) <= 1e-6 * max(1.0, abs(ref)), (dc, trial, j, got, ref)
+                acc = np.float32(others[0]) + np.float32(0.0)
+                for o in others[1:]:
+                    acc = orc.boxplus([acc], [o])[0]
+                fold = float(np.float32(min(1000.0, max(-1000.0, sig * float(acc)))))
+                if dc <= 3:
+                    assert got == fold and np.signbit(got) == np.signbit(fold), (dc, j, got, fold)
+                else:
+                    assert abs(got - fold) <= 8 * ulp1 * max(1.0, abs(fold)), (dc, trial, j, got, fold)
