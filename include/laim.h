@@ -137,10 +137,10 @@ laim_status laim_syndrome(const laim_code* code, const uint8_t* e, int32_t nshot
  */
 typedef struct {
   int32_t bp;           /* 0: normalised min-sum (alpha * min, sign product); 1: sum-product
-                           (BP-LLR2 in box-plus form: output j of a check is F_{j-1} [+] B_{j+1},
-                           with the ascending prefix folds F_k = F_{k-1} [+] m_k and the
-                           descending suffix folds B_k = m_k [+] B_{k+1}; an empty side is
-                           dropped) */
+                           (BP-LLR2 in box-plus form: output j of a check is F(j-1) [+] B(j+1),
+                           with the ascending prefix folds F(k) = F(k-1) [+] m(k) and the
+                           descending suffix folds B(k) = m(k) [+] B(k+1) of its inputs m(0..d-1);
+                           an empty side is dropped) */
   float alpha;          /* min-sum scale, > 0 (0.75) */
   double q;             /* decoder prior in (0, 1): pi = log(q / (1 - q)) (Table S1: 0.05) */
   float clamp;          /* CLAMP > 0 (Table S1: 1000) */
@@ -409,13 +409,28 @@ typedef struct {
  * alpha <= 1). */
 laim_status laim_server_create(int32_t device, size_t mem_budget_bytes, int32_t max_slots,
                                laim_server** out);
-/* Queues one request; e0_host [n] (0/1) is copied. Returns a ticket. */
+/* Queues one request for shot `shot_id` and returns a ticket. The request's
+ * initial error (the hidden error of the problem statement, Preliminaries)
+ * is either given or drawn on the device:
+ *   e0_host  [n] host 0/1 values, copied before the call returns; or NULL:
+ *            the error is sampled on the device at admission from (key =
+ *            params->seed, shot id, p), exactly as laim_sample_noise(code, p,
+ *            params->seed, shot_id, 1) draws it (i.i.d. Bernoulli(p) Z errors).
+ *   p        noise rate of a sampled error, used only when e0_host is NULL
+ *            (values outside [0, 1] are clamped to it; NaN is an error).
+ * A request with params->rounds = 0 runs no round: its first step reports the
+ * start state (t_clr 0 if H e0 = 0, else -1) and finishes it.
+ * Errors: LAIM_EINVAL for bad arguments, LAIM_EUNSUP for a code the server
+ * cannot run, LAIM_ENOMEM when one request of this code needs more device
+ * state than the server's whole budget (it could never be admitted). */
 laim_status laim_server_submit(laim_server* srv, const laim_code* code,
                                const laim_decode_params* params, uint64_t shot_id,
-                               const uint8_t* e0_host, uint64_t* ticket);
-/* Admits waiting requests that fit, advances every resident request by one
- * round, and returns one event per advanced request (blocking until the
- * round's results are on the host). events_host has room for max_events. */
+                               const uint8_t* e0_host, double p, uint64_t* ticket);
+/* Admits waiting requests that fit, advances resident requests by one round
+ * -- at most max_events of them, the oldest first -- and returns one event per
+ * advanced request (blocking until the round's results are on the host).
+ * events_host has room for max_events; requests beyond it wait for a later
+ * step, so that every finished request reports its done event. */
 laim_status laim_server_step(laim_server* srv, laim_server_event* events_host, int32_t max_events,
                              int32_t* n_events);
 /* Final z [n], s [m] and t_clr of a finished request (host copies); the

@@ -308,13 +308,32 @@ struct Request {
   int32_t rounds_total;
   int32_t round = 0;
   int32_t retire = 1;
-  std::vector<uint8_t> e0;
+  std::vector<uint8_t> e0;  // the caller's error, or empty when it is sampled on the device
+  uint64_t noise_bound = 0;  // floor(p 2^32) of a sampled error
+  uint64_t noise_seed = 0;
   bool resident = false, done = false;
   size_t off = 0, bytes = 0;  // arena block
   size_t o_e0, o_msg, o_z, o_s, o_hdr;
   int32_t tclr = -1, fail = 0;
   int64_t t_ready = 0;
 };
+
+// Arena bytes of one request: e0 [n], messages [m][dcmax], z [n], s [m] and
+// a 256-byte header, each part 256-byte aligned.
+struct RequestLayout {
+  size_t b_e0, b_msg, b_z, b_s, b_hdr, total;
+};
+
+RequestLayout request_layout(const laim_code* c) {
+  RequestLayout l;
+  l.b_e0 = al256(c->n);
+  l.b_msg = al256((size_t)c->m * c->dcmax * 4);
+  l.b_z = al256(c->n);
+  l.b_s = al256(c->m);
+  l.b_hdr = 256;
+  l.total = l.b_e0 + l.b_msg + l.b_z + l.b_s + l.b_hdr;
+  return l;
+}
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -403,14 +422,26 @@ void laim_server_destroy(laim_server* s) {
 
 laim_status laim_server_submit(laim_server* s, const laim_code* code,
                                const laim_decode_params* params, uint64_t shot_id,
-                               const uint8_t* e0_host, uint64_t* ticket) {
-  if (!s || !code || !params || !e0_host || !ticket) {
+                               const uint8_t* e0_host, double p, uint64_t* ticket) {
+  if (!s || !code || !params || !ticket) {
     set_error("laim_server_submit: bad arguments");
+    return LAIM_EINVAL;
+  }
+  if (!e0_host && p != p) {
+    set_error("p is NaN");
     return LAIM_EINVAL;
   }
   if (code->device != s->device) {
     set_error("the code lives on another device than the server");
     return LAIM_EINVAL;
+  }
+  // a request larger than the whole arena could never be admitted and would
+  // hold up the FIFO for good
+  const size_t need = request_layout(code).total;
+  if (need > s->arena.size) {
+    set_error("a request of this code needs %zu bytes of device state; the server's budget is %zu",
+              need, s->arena.size);
+    return LAIM_ENOMEM;
   }
   // one item per distinct (code, parameters); the key is built field by
   // field so that padding bytes of the caller's struct do not enter it
@@ -456,8 +487,13 @@ laim_status laim_server_submit(laim_server* s, const laim_code* code,
   r.shot = shot_id;
   r.rounds_total = params->rounds;
   r.retire = params->retire ? 1 : 0;
-  r.e0.assign(e0_host, e0_host + code->n);
-  for (auto& b : r.e0) b &= 1u;
+  if (e0_host) {
+    r.e0.assign(e0_host, e0_host + code->n);
+    for (auto& b : r.e0) b &= 1u;
+  } else {
+    r.noise_bound = bernoulli_bound(p);
+    r.noise_seed = params->seed;
+  }
   r.t_ready = now_ns();
   *ticket = r.ticket;
   s->waiting.push_back(r.ticket);
@@ -481,20 +517,25 @@ laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t 
   while (!s->waiting.empty() && resident < s->max_slots) {
     Request& r = s->reqs.at(s->waiting.front());
     const laim_code* c = r.code;
-    const size_t b_e0 = al256(c->n), b_msg = al256((size_t)c->m * c->dcmax * 4),
-                 b_z = al256(c->n), b_s = al256(c->m), b_hdr = 256;
-    const size_t bytes = b_e0 + b_msg + b_z + b_s + b_hdr;
+    const RequestLayout lay = request_layout(c);
     size_t off;
-    if (!s->arena.alloc(bytes, &off)) break;
+    if (!s->arena.alloc(lay.total, &off)) break;
     r.off = off;
-    r.bytes = bytes;
+    r.bytes = lay.total;
     r.o_e0 = off;
-    r.o_msg = r.o_e0 + b_e0;
-    r.o_z = r.o_msg + b_msg;
-    r.o_s = r.o_z + b_z;
-    r.o_hdr = r.o_s + b_s;
-    e = hipMemcpyAsync((char*)s->arena_mem + r.o_e0, r.e0.data(), c->n, hipMemcpyHostToDevice, s->st);
-    if (e != hipSuccess) return hip_fail(e, "admitting a request");
+    r.o_msg = r.o_e0 + lay.b_e0;
+    r.o_z = r.o_msg + lay.b_msg;
+    r.o_s = r.o_z + lay.b_z;
+    r.o_hdr = r.o_s + lay.b_s;
+    uint8_t* e0_dev = (uint8_t*)s->arena_mem + r.o_e0;
+    if (r.e0.empty())  // sampled from (seed, shot id, p), as laim_sample_noise draws it
+      e = launch_noise(c->dev, r.noise_bound, r.noise_seed, r.shot, 1, e0_dev, s->st);
+    else
+      e = hipMemcpyAsync(e0_dev, r.e0.data(), c->n, hipMemcpyHostToDevice, s->st);
+    if (e != hipSuccess) {
+      s->arena.release(r.off, r.bytes);
+      return hip_fail(e, "admitting a request");
+    }
     r.resident = true;
     s->waiting.pop_front();
     ++resident;
@@ -515,14 +556,20 @@ laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t 
     s->items_dirty = false;
   }
   // ---- units: resident requests grouped by (BP, item, first round or not)
+  // At most max_events requests advance, the oldest first, so that every
+  // advanced request reports its event (and a finished one its done flag).
   std::vector<uint64_t> order;
   for (auto& kv : s->reqs)
-    if (kv.second.resident && !kv.second.done) order.push_back(kv.first);
+    if (kv.second.resident && !kv.second.done && (int32_t)order.size() < std::max(max_events, 0))
+      order.push_back(kv.first);
   if (order.empty()) return LAIM_OK;
+  // a unit holds requests of one item in the same phase: first round, later
+  // round, or no round at all (rounds = 0: only the start state and result)
+  auto phase = [](const Request& r) { return r.rounds_total == 0 ? 2 : (r.round > 0 ? 1 : 0); };
   std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
     const Request &x = s->reqs.at(a), &y = s->reqs.at(b);
-    const int kx = x.bp * 1000000 + x.item * 2 + (x.round > 0);
-    const int ky = y.bp * 1000000 + y.item * 2 + (y.round > 0);
+    const int kx = x.bp * 1000000 + x.item * 3 + phase(x);
+    const int ky = y.bp * 1000000 + y.item * 3 + phase(y);
     return kx < ky;
   });
   int nreq = 0, nunit = 0;
@@ -546,13 +593,15 @@ laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t 
     s->reqs_h[nreq] = q;
     const BatchItemDev& it = s->items[r.item];
     const bool resume = r.round > 0;
+    const int32_t nround = r.rounds_total > 0 ? 1 : 0;
     const bool new_unit = nunit == 0 || s->units_h[nunit - 1].item != r.item ||
                           s->units_h[nunit - 1].resume != (resume ? 1 : 0) ||
+                          s->units_h[nunit - 1].rounds != nround ||
                           s->units_h[nunit - 1].count >= it.u.spb;
     if (new_unit) {
       if (unit_first[r.bp] < 0) unit_first[r.bp] = nunit;
       ++unit_count[r.bp];
-      s->units_h[nunit++] = ServerUnitDev{r.item, nreq, 0, resume ? 1 : 0};
+      s->units_h[nunit++] = ServerUnitDev{r.item, nreq, 0, resume ? 1 : 0, nround};
       lds[r.bp] = std::max(lds[r.bp], s->item_lds[r.item]);
       block[r.bp] = std::max(block[r.bp], s->item_block[r.item]);
     }
@@ -574,14 +623,14 @@ laim_status laim_server_step(laim_server* s, laim_server_event* events, int32_t 
   int32_t ne = 0;
   for (int i = 0; i < nreq; ++i) {
     Request& r = s->reqs.at(order[i]);
-    r.round += 1;
+    if (r.rounds_total > 0) r.round += 1;
     r.tclr = s->ev_h[4 * i + 2];
     r.fail = s->ev_h[4 * i + 3] & 1;
     // a frozen request (its state can no longer change) is finished: the
     // remaining rounds would leave z, s, t_clr and the failure as they are
     const bool frozen = (s->ev_h[4 * i + 3] >> 1) & 1;
     r.done = (r.retire && r.tclr >= 0) || r.round >= r.rounds_total || frozen;
-    if (ne < max_events) {
+    {
       laim_server_event& ev = events[ne++];
       ev.ticket = r.ticket;
       ev.round = r.round;

@@ -263,7 +263,7 @@ using namespace laim;
 extern "C" {
 
 const char* laim_last_error(void) { return g_last_error.c_str(); }
-int32_t laim_version(void) { return 1; }
+int32_t laim_version(void) { return 2; }
 
 laim_status laim_host_logicals(int32_t m, int32_t n, const int32_t* h_rowptr, const int32_t* h_col,
                                int32_t mg, const int32_t* g_rowptr, const int32_t* g_col,

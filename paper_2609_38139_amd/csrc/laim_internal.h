@@ -143,6 +143,7 @@ struct ServerUnitDev {
   int32_t first;   // first request of the unit in the request table
   int32_t count;   // requests in the unit (<= spb)
   int32_t resume;  // 0 on a request's first round
+  int32_t rounds;  // rounds run: 1, or 0 for requests with a budget of no rounds
 };
 
 struct ServerReqDev {

@@ -1155,7 +1155,7 @@ __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
   const DevCode c = I->c;
   const KParams kp = I->kp;
   UnitCtx ctx = I->u;
-  ctx.rounds = 1;
+  ctx.rounds = U.rounds;
   ctx.resume = U.resume;
   ctx.events = 1;
   ServerJobs jobs{reqs, U.first, U.count, false};

@@ -169,7 +169,7 @@ def lib():
         L.laim_batch_plan_destroy.argtypes = [vp]
         L.laim_batch_plan_destroy.restype = None
         L.laim_server_create.argtypes = [i32, sz, i32, C.POINTER(vp)]
-        L.laim_server_submit.argtypes = [vp, vp, C.POINTER(Params), u64, vp, C.POINTER(u64)]
+        L.laim_server_submit.argtypes = [vp, vp, C.POINTER(Params), u64, vp, C.c_double, C.POINTER(u64)]
         L.laim_server_step.argtypes = [vp, C.POINTER(ServerEvent), i32, i32p]
         L.laim_server_result.argtypes = [vp, u64, vp, vp, i32p]
         L.laim_server_stats.argtypes = [vp, i32p, i32p, C.POINTER(sz)]
@@ -452,20 +452,29 @@ class Server:
         self._ev = (ServerEvent * max_slots)()
         self._codes = {}
 
-    def submit(self, code: Code, params: DecodeParams, shot_id: int, e0) -> int:
-        e0 = np.ascontiguousarray(e0, dtype=np.uint8).ravel()
-        if e0.size != code.n:
-            raise ValueError("e0 must hold n bits")
+    def submit(self, code: Code, params: DecodeParams, shot_id: int, e0=None, p: float = 0.0) -> int:
+        """Queues one shot. With e0 given (n host bits) it is copied; with
+        e0 None the server samples the error on the device from
+        (params.seed, shot_id, p)."""
+        ptr = None
+        if e0 is not None:
+            e0 = np.ascontiguousarray(e0, dtype=np.uint8).ravel()
+            if e0.size != code.n:
+                raise ValueError("e0 must hold n bits")
+            ptr = e0.ctypes.data_as(C.c_void_p)
         P = params.c()
         t = C.c_uint64()
-        check(lib().laim_server_submit(self.handle, code.handle, C.byref(P), shot_id,
-                                       e0.ctypes.data_as(C.c_void_p), C.byref(t)), "laim_server_submit")
+        check(lib().laim_server_submit(self.handle, code.handle, C.byref(P), shot_id, ptr, float(p),
+                                       C.byref(t)), "laim_server_submit")
         self._codes[t.value] = code
         return t.value
 
-    def step(self) -> list:
+    def step(self, max_events: int | None = None) -> list:
+        """One server step; at most max_events requests (default: every
+        slot) advance."""
+        k = self.max_slots if max_events is None else min(int(max_events), self.max_slots)
         n = C.c_int32()
-        check(lib().laim_server_step(self.handle, self._ev, self.max_slots, C.byref(n)), "laim_server_step")
+        check(lib().laim_server_step(self.handle, self._ev, k, C.byref(n)), "laim_server_step")
         out = []
         for i in range(n.value):
             e = self._ev[i]

@@ -1,7 +1,8 @@
 """Load generator and statistics for the continuous-batching server.
 
 Requests are single shots of a mix of codes, each decoded for up to its own
-number of rounds (a shot retires once its syndrome clears). Arrivals form a
+number of rounds (a shot retires once its syndrome clears); the server draws
+each request's error on the device when it admits it. Arrivals form a
 Poisson process; every step the server admits what fits and advances each
 resident request by one round. Reported: requests/s, shots/s, rounds/s and
 the p50/p99 of the per-round latency (from a round's input being ready --
@@ -21,12 +22,11 @@ DEFAULT_MIX = [("toric2d:16", 128), ("toric2d:32", 256), ("toric2d:48", 384),
 
 
 class Workload:
-    """Pre-sampled requests: request i uses code i mod len(mix) (the codes
-    take equal shares) and shot id i; its error is drawn on the device."""
+    """Request i uses code i mod len(mix) (the codes take equal shares) and
+    shot id i; its error is drawn by the server on the device from (seed,
+    shot id, p) when the request is admitted."""
 
     def __init__(self, laim, mix=DEFAULT_MIX, p=0.03, nreq=2048, bp="minsum", seed=0):
-        import torch
-
         from . import codes
         self.laim = laim
         self.codes = []
@@ -34,27 +34,15 @@ class Workload:
         for name, rounds in mix:
             spec = codes.by_name(name)
             self.codes.append(laim.Code(spec, 0))
-            self.params.append(laim.DecodeParams(bp=bp, rounds=rounds,
+            self.params.append(laim.DecodeParams(bp=bp, rounds=rounds, seed=seed,
                                                  q=0.125 if "membrane" in name else 0.05))
         self.nreq = nreq
-        self.e0 = []
-        for i in range(nreq):
-            k = i % len(mix)
-            self.e0.append(None)
-        # sample per code in batches: request i of code k has shot id i
-        for k, code in enumerate(self.codes):
-            ids = np.arange(k, nreq, len(mix))
-            if ids.size == 0:
-                continue
-            rows = laim.sample_noise(code, p, seed, 0, int(ids[-1]) + 1)
-            rows = rows[torch.from_numpy(ids).cuda()].cpu().numpy()
-            for j, i in enumerate(ids):
-                self.e0[i] = rows[j]
+        self.p = p
         self.seed = seed
 
     def request(self, i):
         k = i % len(self.codes)
-        return self.codes[k], self.params[k], i, self.e0[i]
+        return self.codes[k], self.params[k], i
 
 
 def run(server, wl: Workload, rate: float | None, nreq: int, rng_seed: int = 0,
@@ -80,8 +68,8 @@ def run(server, wl: Workload, rate: float | None, nreq: int, rng_seed: int = 0,
         if now > time_limit:
             break
         while nxt < nreq and arrivals[nxt] <= now:
-            code, P, shot, e0 = wl.request(nxt)
-            server.submit(code, P, shot, e0)
+            code, P, shot = wl.request(nxt)
+            server.submit(code, P, shot, None, wl.p)
             nxt += 1
             pending += 1
         if pending == 0:

@@ -325,3 +325,119 @@ def test_batch_plan_and_server_skip_equals_every_sweep(L):
     for key in ra:
         for k in ("z", "s", "tclr", "fail"):
             assert np.array_equal(np.asarray(ra[key][k]), np.asarray(rb[key][k])), (key, k)
+
+
+def test_server_samples_the_error_on_the_device_when_e0_is_null(L):
+    """laim_server_submit with e0_host NULL draws the request's error on the
+    device from (params.seed, shot id, p), as laim_sample_noise does: the
+    results equal those of the same request with that error given, and of a
+    plain decode of it."""
+    import torch
+    for name, p, bp, R in (("toric2d:16", 0.05, "minsum", 64), ("bb:12x6", 0.01, "sumproduct", 64),
+                           ("toric3d_point:6", 0.03, "minsum", 24)):
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(bp=bp, rounds=R, seed=9)
+        shots = [0, 1, 5, 2**33 + 17, 123456]
+        e0 = torch.stack([L.sample_noise(code, p, 9, s, 1)[0] for s in shots])
+        torch.cuda.synchronize()
+        ref = [L.decode_rounds(code, P, e0[i:i + 1], shot0=s) for i, s in enumerate(shots)]
+        srv = L.Server(0, 1 << 26, 64)
+        tickets = {}
+        for i, s in enumerate(shots):
+            tickets[srv.submit(code, P, s, None, p)] = ("null", i)
+            tickets[srv.submit(code, P, s, e0[i].cpu().numpy())] = ("given", i)
+        res = {}
+        while len(res) < len(tickets):
+            evs = srv.step()
+            assert evs, "a step with resident requests reported nothing"
+            for ev in evs:
+                if ev["done"]:
+                    r = srv.result(ev["ticket"])
+                    r["fail"] = ev["fail"]
+                    res[tickets[ev["ticket"]]] = r
+        for i, s in enumerate(shots):
+            a, b = res[("null", i)], res[("given", i)]
+            assert np.array_equal(a["z"], b["z"]) and np.array_equal(a["s"], b["s"]), (name, s)
+            assert a["tclr"] == b["tclr"] and a["fail"] == b["fail"], (name, s)
+            assert np.array_equal(a["z"], ref[i]["z"][0].cpu().numpy()), (name, s)
+            assert a["tclr"] == int(ref[i]["tclr"][0]), (name, s)
+
+
+def test_server_rejects_a_request_larger_than_its_budget(L):
+    """A request whose state exceeds the server's whole budget could never be
+    admitted: submit refuses it with LAIM_ENOMEM instead of queueing it in
+    front of the others, and smaller requests still run."""
+    small = L.Code(codes.by_name("toric2d:4"), 0)
+    big = L.Code(codes.by_name("toric2d:48"), 0)
+    srv = L.Server(0, 16 * 1024, 8)
+    P = L.DecodeParams(rounds=8)
+    with pytest.raises(L.LaimError) as ei:
+        srv.submit(big, P, 0, None, 0.05)
+    assert ei.value.status == L.ENOMEM
+    t = srv.submit(small, P, 3, None, 0.1)
+    done = False
+    for _ in range(20):
+        for ev in srv.step():
+            assert ev["ticket"] == t
+            if ev["done"]:
+                srv.result(t)
+                done = True
+        if done:
+            break
+    assert done
+    st = srv.stats()
+    assert st["resident"] == 0 and st["waiting"] == 0 and st["bytes"] == 0
+
+
+def test_server_request_with_no_rounds_finishes_at_its_first_step(L, orc):
+    """rounds = 0: no round runs; the first step reports the start state
+    (t_clr 0 for a clear syndrome, else -1 and a failure) with round 0, and
+    the result is z = 0, s = H e0 -- as laim_decode_rounds gives it."""
+    spec = codes.by_name("toric2d:8")
+    code = L.Code(spec, 0)
+    P = L.DecodeParams(rounds=0)
+    srv = L.Server(0, 1 << 24, 16)
+    e_clear = np.zeros(code.n, dtype=np.uint8)
+    e_one = np.zeros(code.n, dtype=np.uint8)
+    e_one[5] = 1
+    ta = srv.submit(code, P, 0, e_clear)
+    tb = srv.submit(code, P, 1, e_one)
+    tc = srv.submit(code, L.DecodeParams(rounds=4), 2, e_one)
+    evs = {ev["ticket"]: ev for ev in srv.step()}
+    assert evs[ta]["done"] and evs[ta]["round"] == 0 and evs[ta]["tclr"] == 0 and evs[ta]["fail"] == 0
+    assert evs[tb]["done"] and evs[tb]["round"] == 0 and evs[tb]["tclr"] == -1 and evs[tb]["fail"] == 1
+    assert evs[tb]["flips"] == 0 and evs[tb]["defects"] == 2
+    assert evs[tc]["round"] == 1
+    rb = srv.result(tb)
+    assert rb["z"].sum() == 0 and np.array_equal(rb["s"], orc.syndrome(spec, e_one)[0])
+    srv.result(ta)
+
+
+def test_server_step_advances_at_most_max_events(L):
+    """With fewer event slots than resident requests, a step advances only
+    that many (the oldest first); every request still reports each of its
+    rounds and its done event, and results equal the plain decode."""
+    import torch
+    spec = codes.by_name("toric2d:8")
+    code = L.Code(spec, 0)
+    P = L.DecodeParams(rounds=16)
+    e0 = L.sample_noise(code, 0.06, 0, 0, 10)
+    ref = L.decode_rounds(code, P, e0)
+    torch.cuda.synchronize()
+    srv = L.Server(0, 1 << 24, 32)
+    tk = {srv.submit(code, P, i, e0[i].cpu().numpy()): i for i in range(10)}
+    seen = {}
+    res = {}
+    while len(res) < 10:
+        evs = srv.step(max_events=3)
+        assert 1 <= len(evs) <= 3
+        for ev in evs:
+            assert ev["round"] == seen.get(ev["ticket"], 0) + 1
+            seen[ev["ticket"]] = ev["round"]
+            if ev["done"]:
+                res[tk[ev["ticket"]]] = srv.result(ev["ticket"])
+    for i in range(10):
+        assert np.array_equal(res[i]["z"], ref["z"][i].cpu().numpy()), i
+        assert res[i]["tclr"] == int(ref["tclr"][i]), i
+    assert srv.stats()["bytes"] == 0
