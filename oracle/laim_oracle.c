@@ -16,8 +16,10 @@
  *     printed or normalised min-sum (a reading: the paper uses sum-product),
  *   - the round-discretised check-centric machine of Algorithm 1: BP, then
  *     every active check whose clock rang this round tests Evidence and
- *     flips the argmax qubit (LocalMove), then the syndrome update; the
- *     round's move requests combine by one of three conflict rules,
+ *     flips the argmax qubit (LocalMove) -- or, as the multi-qubit move the
+ *     LDPC-codes section mentions, every qubit of the check whose belief is
+ *     positive -- then the syndrome update; the round's move requests
+ *     combine by one of three conflict rules,
  *   - the decoding-success test (Preliminaries, conditions (1) and (2)) by an
  *     independent GF(2) rank test,
  *   - the continuous-time machine of Algorithm 1 as stated: Euler-damped
@@ -33,7 +35,10 @@
  *     special cases: only the GPU parity tests compare them;
  *   - the round machine's logical error rates, which the paper does not
  *     print (its dynamics is the continuous one);
- *   - which Philox word gives the sequential conflict rule its ring times.
+ *   - which Philox word gives the sequential conflict rule its ring times;
+ *   - the rule of the multi-qubit move (a reading; the paper names such moves
+ *     without specifying them): beyond its reduction to LocalMove and the
+ *     replay of its decisions, only the GPU parity tests compare it.
  *
  * Precision: the decoder runs in FP32 because its integer decisions (which
  * check moves, which qubit flips) are taken from FP32 messages; every float
@@ -48,7 +53,7 @@
 #include <omp.h>
 #endif
 
-#define ORC_VERSION 1
+#define ORC_VERSION 2
 
 int orc_version(void) { return ORC_VERSION; }
 
@@ -283,7 +288,20 @@ typedef struct {
   int32_t retire;        /* 1: stop a shot once its syndrome is clear */
   uint64_t seed;
   int32_t conflict;      /* how one round's move requests combine: ORC_CONFLICT_* */
+  int32_t move;          /* ORC_MOVE_SINGLE (LocalMove) or ORC_MOVE_MULTI */
 } orc_params;
+
+/* Local moves of an acting check (LDPC-codes section: besides the one-qubit
+ * LocalMove of Algorithm 1, a multi-qubit flip akin to small-set flip,
+ * guided by the local beliefs). The paper gives no rule for the multi-qubit
+ * move; the reading here:
+ *   SINGLE  the LocalMove qubit: the largest belief in N(c), ties broken at
+ *           random (Algorithm 1);
+ *   MULTI   every qubit v of N(c) whose belief says it more likely flipped
+ *           than not, Pr_BP(e_v = 1 | s) > 1/2, i.e. L_v > 0; if there is
+ *           none, the LocalMove qubit. With exactly one such qubit the two
+ *           coincide (it is then the unique largest belief). */
+enum { ORC_MOVE_SINGLE = 0, ORC_MOVE_MULTI = 1 };
 
 /* Move requests of one round combine (Algorithm 1 has one clock ring at a
  * time; a round gathers several, so a rule is needed):
@@ -407,10 +425,16 @@ static int32_t resolve_moves(const tanner* T, int32_t conflict, const uint8_t* s
     for (int32_t i = 0; i < nreq; ++i) f[req[i].v] ^= 1;
   } else if (conflict == ORC_CONFLICT_SEQUENTIAL) {
     qsort(req, (size_t)nreq, sizeof(orc_request), cmp_request);
+    /* a check's requests (one per qubit of a multi-qubit move) are adjacent
+     * after the sort and apply together: all of them if the check is active
+     * before the first, none otherwise */
+    uint8_t x = 0;
     for (int32_t i = 0; i < nreq; ++i) {
-      /* the check's syndrome now: s_c plus the moves applied so far */
-      uint8_t x = s[req[i].c];
-      for (int32_t k = T->rowptr[req[i].c]; k < T->rowptr[req[i].c + 1]; ++k) x ^= f[T->col[k]];
+      if (i == 0 || req[i].c != req[i - 1].c || req[i].key != req[i - 1].key) {
+        /* the check's syndrome now: s_c plus the moves applied so far */
+        x = s[req[i].c];
+        for (int32_t k = T->rowptr[req[i].c]; k < T->rowptr[req[i].c + 1]; ++k) x ^= f[T->col[k]];
+      }
       if (x & 1) f[req[i].v] ^= 1;
     }
   } else {
@@ -479,7 +503,8 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
   uint8_t* f = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
   uint8_t* r_err = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
   uint8_t* s_new = (uint8_t*)malloc((size_t)(m > 0 ? m : 1));
-  orc_request* req = (orc_request*)malloc(sizeof(orc_request) * (size_t)(m > 0 ? m : 1));
+  /* at most one request per edge (a multi-qubit move requests each qubit) */
+  orc_request* req = (orc_request*)malloc(sizeof(orc_request) * (size_t)(E > m ? E : (m > 0 ? m : 1)));
   int32_t rc = 0;
   if (!mvc || !mcv || !L || !piv || !f || !r_err || !s_new || !req) {
     rc = -2;
@@ -510,6 +535,20 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
       for (int32_t j = 1; j < dc; ++j)
         if (L[T->col[b + j]] > Lmax) Lmax = L[T->col[b + j]];
       if (P->evidence && !(Lmax >= thr[dc])) continue;
+      if (P->move == ORC_MOVE_MULTI) {
+        /* every qubit of N(c) with L_v > 0, else the LocalMove qubit */
+        int32_t npos = 0;
+        for (int32_t j = 0; j < dc; ++j) {
+          if (L[T->col[b + j]] > 0.0f) {
+            req[nreq].key = w[2];
+            req[nreq].c = c;
+            req[nreq].v = T->col[b + j];
+            nreq++;
+            npos++;
+          }
+        }
+        if (npos > 0) continue;
+      }
       uint32_t ntie = 0;
       for (int32_t j = 0; j < dc; ++j) ntie += (L[T->col[b + j]] == Lmax) ? 1u : 0u;
       uint32_t pick = (uint32_t)(((uint64_t)w[1] * (uint64_t)ntie) >> 32);

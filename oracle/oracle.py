@@ -42,10 +42,11 @@ class Params(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
                 ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
-                ("seed", C.c_uint64), ("conflict", C.c_int32)]
+                ("seed", C.c_uint64), ("conflict", C.c_int32), ("move", C.c_int32)]
 
 
 CONFLICT_RULES = {"or": 0, "xor": 1, "sequential": 2}
+MOVES = {"single": 0, "multi": 1}
 
 
 @dataclass
@@ -64,12 +65,13 @@ class DecodeParams:
     retire: bool = True
     seed: int = 0
     conflict: str = "or"  # how one round's move requests combine: "or", "xor", "sequential"
+    move: str = "single"  # "single": LocalMove; "multi": every qubit of N(c) with L_v > 0
 
     def c(self) -> Params:
         return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
                       self.iters, self.rounds, self.mask_density, int(self.gauge),
                       int(self.evidence), int(self.retire), self.seed,
-                      CONFLICT_RULES[self.conflict])
+                      CONFLICT_RULES[self.conflict], MOVES[self.move])
 
 
 class CtmParams(C.Structure):

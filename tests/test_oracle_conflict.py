@@ -77,6 +77,64 @@ def test_sequential_is_the_unique_consistent_history(orc, seed):
     assert np.array_equal(f, hist[0])
 
 
+def consistent_group_histories(H, s, groups):
+    """As consistent_histories, for multi-qubit moves: groups[i] = (check,
+    ring time, qubits); a group acts as a whole, exactly when its check's
+    syndrome, changed by the acting groups before it in (ring time, check)
+    order, is 1."""
+    K = len(groups)
+    out = []
+    for act in itertools.product((0, 1), repeat=K):
+        ok = True
+        for i, (ci, ki, _) in enumerate(groups):
+            x = int(s[ci])
+            for j, (cj, kj, vj) in enumerate(groups):
+                if act[j] and (kj, cj) < (ki, ci):
+                    x ^= int(H[ci, vj].sum() % 2)
+            if x != act[i]:
+                ok = False
+                break
+        if ok:
+            f = np.zeros(H.shape[1], dtype=np.uint8)
+            for i, (_, _, vi) in enumerate(groups):
+                if act[i]:
+                    f[vi] ^= 1
+            out.append(f)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_sequential_multi_qubit_moves_apply_as_a_whole(orc, seed):
+    """A multi-qubit move is one request per qubit, all with the check's
+    ring time; under the sequential rule they apply together, exactly when
+    the check is active before the first of them (brute force over every
+    act/skip assignment of the moves: the history is unique)."""
+    rng = np.random.default_rng(500 + seed)
+    m, n = int(rng.integers(3, 7)), int(rng.integers(5, 9))
+    code = random_code(rng, m, n, 2, 4)
+    H = code.H.to_dense()
+    s = rng.integers(0, 2, size=m).astype(np.uint8)
+    if seed % 3 == 0:
+        s[:] = 1
+    groups, req_c, req_v, req_key = [], [], [], []
+    for c in range(m):
+        if rng.random() < 0.8:
+            nb = np.nonzero(H[c])[0]
+            vs = np.sort(rng.choice(nb, size=int(rng.integers(1, len(nb) + 1)), replace=False))
+            key = int(rng.integers(0, 3 if seed % 2 else 2**32))
+            groups.append((c, key, vs))
+            for v in vs:
+                req_c.append(c)
+                req_v.append(int(v))
+                req_key.append(key)
+    hist = consistent_group_histories(H, s, groups)
+    assert len(hist) == 1
+    order = rng.permutation(len(req_c))  # the input order of the requests does not matter
+    f = orc.resolve_moves(code, "sequential", s, [req_c[i] for i in order], [req_v[i] for i in order],
+                          [req_key[i] for i in order])
+    assert np.array_equal(f, hist[0])
+
+
 @pytest.mark.parametrize("seed", range(10))
 def test_or_and_xor_count_requests(orc, seed):
     rng = np.random.default_rng(100 + seed)
@@ -163,16 +221,18 @@ def test_single_edge_error_at_density_one(orc, L):
     assert not r["z"].any()
 
 
-@pytest.mark.parametrize("rule", ["xor", "sequential"])
+@pytest.mark.parametrize("rule,move", [("xor", "single"), ("sequential", "single"), ("or", "multi"),
+                                       ("xor", "multi"), ("sequential", "multi")])
 @pytest.mark.parametrize("name,p", [("toric2d:6", 0.08), ("bb:6x6", 0.04), ("toric3d_membrane:3", 0.06)])
-def test_round_invariants_hold_under_every_rule(orc, rule, name, p):
+def test_round_invariants_hold_under_every_rule(orc, rule, move, name, p):
     """Per round s == H (e0 ^ z) (the oracle also asserts s_new == s ^ H f
     and fails otherwise) and every left-kernel vector y of H keeps
-    y^T s = 0."""
+    y^T s = 0, under every conflict rule and both kinds of move."""
     code = codes.by_name(name)
     H = code.H.to_dense().astype(np.int64)
     e0 = orc.sample_noise(code, p, 0, 0, 12)
-    P = orc.DecodeParams(conflict=rule, rounds=12, retire=False, q=0.125 if "membrane" in name else 0.05)
+    P = orc.DecodeParams(conflict=rule, rounds=12, retire=False, q=0.125 if "membrane" in name else 0.05,
+                         bp="sumproduct" if move == "multi" else "minsum", move=move)
     # left kernel of H over GF(2) from a reduced basis of H^T
     Y = _left_kernel(H)
     for i in range(e0.shape[0]):
@@ -218,3 +278,15 @@ def test_rules_differ_on_the_paper_workload(orc):
            for rule in ("or", "xor", "sequential")}
     assert (out["or"]["z"] != out["xor"]["z"]).any(axis=1).sum() > 0
     assert (out["or"]["z"] != out["sequential"]["z"]).any(axis=1).sum() > 0
+
+
+def test_multi_qubit_moves_change_the_dynamics(orc):
+    """Multi-qubit moves are a different dynamics from LocalMove on the 2D
+    toric workload (sum-product, where positive beliefs are common): some
+    shots end differently, and every shot still satisfies s = H (e0 ^ z)."""
+    code = codes.toric_2d(8)
+    e0 = orc.sample_noise(code, 0.06, 0, 0, 200)
+    a = orc.decode(code, orc.DecodeParams(bp="sumproduct", rounds=32), e0, nthreads=4)
+    b = orc.decode(code, orc.DecodeParams(bp="sumproduct", rounds=32, move="multi"), e0, nthreads=4)
+    assert (a["z"] != b["z"]).any(axis=1).sum() > 0
+    assert np.array_equal(b["s"], orc.syndrome(code, e0 ^ b["z"]))

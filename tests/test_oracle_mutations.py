@@ -80,6 +80,16 @@ MUTATIONS = {
         "for (int32_t k = rowptr[c]; k < rowptr[c + 1]; ++k) x ^= e[(size_t)i * n + col[k]] & 1u;",
         "for (int32_t k = rowptr[c] + 1; k < rowptr[c + 1]; ++k) x ^= e[(size_t)i * n + col[k]] & 1u;",
         ["test_oracle_pins.py"], "special or homology or parity"),
+    "multi-qubit move takes non-negative beliefs": (
+        "          if (L[T->col[b + j]] > 0.0f) {", "          if (L[T->col[b + j]] >= 0.0f) {",
+        ["test_oracle_pins.py"], "feedback_replays or positive_beliefs"),
+    "multi-qubit move without the LocalMove fallback": (
+        "        if (npos > 0) continue;", "        continue;",
+        ["test_oracle_pins.py"], "feedback_replays"),
+    "sequential rule re-tests the check within a multi-qubit move": (
+        "      if (i == 0 || req[i].c != req[i - 1].c || req[i].key != req[i - 1].key) {",
+        "      if (1) {",
+        ["test_oracle_conflict.py"], "multi_qubit"),
     "sequential rule with a stale syndrome": (
         "      for (int32_t k = T->rowptr[req[i].c]; k < T->rowptr[req[i].c + 1]; ++k) x ^= f[T->col[k]];\n", "",
         ["test_oracle_conflict.py"], "sequential"),

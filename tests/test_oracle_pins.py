@@ -420,9 +420,10 @@ def test_special_cases(orc, bp):
         assert r["tclr"][0] == 1 and np.array_equal(r["z"], one)
 
 
+@pytest.mark.parametrize("move", ["single", "multi"])
 @pytest.mark.parametrize("conflict", ["or", "xor"])
 @pytest.mark.parametrize("bp,rho", [("minsum", 0.5), ("sumproduct", 1.0), ("minsum", 0.125)])
-def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict):
+def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict, move):
     """The feedback step of every round, re-derived here (Algorithm 1 with one
     Philox draw per check and round): check c rings when word 0 of
     Philox(seed, (shot_lo, shot_hi, c, 16 r + 1)) is below floor(rho 2^32);
@@ -431,15 +432,18 @@ def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict):
     the requests combine by OR or XOR. The beliefs L of round r come from a
     run stopped after r + 1 rounds (without the gauge option the state is
     not touched after the feedback), the window and tree pins above fix BP
-    itself, and the traced z of successive rounds give the flips f."""
-    checked = asked = 0
+    itself, and the traced z of successive rounds give the flips f.
+    With multi-qubit moves an acting check asks instead for every qubit of
+    N(c) with L_v > 0 (Pr_BP(e_v = 1 | s) > 1/2), or for the arg-max qubit
+    when there is none."""
+    checked = asked = multi = 0
     for name, p in (("toric2d:6", 0.08), ("bb:6x6", 0.04), ("toric3d_point:3", 0.04)):
         c = codes.by_name(name)
         H = c.H.to_dense()
         rp, cl = c.H.rowptr, c.H.col
         thr = orc.evidence_thresholds(int(np.diff(rp).max()))
         bound = orc.bernoulli_bound(rho)
-        prm = dict(bp=bp, mask_density=rho, conflict=conflict, retire=False, seed=11, iters=6)
+        prm = dict(bp=bp, mask_density=rho, conflict=conflict, retire=False, seed=11, iters=6, move=move)
         R = 6
         for shot in range(3):
             e0 = orc.sample_noise(c, p, 0, shot, 1)
@@ -457,8 +461,13 @@ def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict):
                     Lmax = L[nb].max()
                     if not Lmax >= thr[len(nb)]:
                         continue
-                    ties = nb[L[nb] == Lmax]
-                    cnt[ties[(int(w[1]) * len(ties)) >> 32]] += 1
+                    pos = nb[L[nb] > 0]
+                    if move == "multi" and len(pos):
+                        cnt[pos] += 1
+                        multi += len(pos) > 1
+                    else:
+                        ties = nb[L[nb] == Lmax]
+                        cnt[ties[(int(w[1]) * len(ties)) >> 32]] += 1
                     asked += 1
                 f = (cnt > 0) if conflict == "or" else (cnt % 2 == 1)
                 assert np.array_equal(tr["z_trace"][r] ^ z_prev, f.astype(np.uint8)), (name, shot, r)
@@ -466,6 +475,25 @@ def test_feedback_replays_from_beliefs_and_random_words(orc, bp, rho, conflict):
                 s_r = tr["s_trace"][r]
                 checked += 1
     assert checked == 3 * 3 * 6 and asked >= 20, asked
+    if move == "multi" and bp == "sumproduct":  # min-sum beliefs are rarely positive here
+        assert multi >= 1, "no check asked for more than one qubit"
+
+
+@pytest.mark.parametrize("name", ["toric2d:6", "bb:6x6", "toric3d_point:3"])
+def test_multi_qubit_move_without_positive_beliefs_is_localmove(orc, name):
+    """A multi-qubit move asks for the qubits of N(c) with L_v > 0 and falls
+    back to LocalMove when there is none. With prior q = 1/2 (pi = 0) and no
+    BP sweep every belief is exactly +0, so every move is the LocalMove:
+    the two kinds of move give identical runs, which still correct."""
+    c = codes.by_name(name)
+    e0 = orc.sample_noise(c, 0.05, 0, 0, 60)
+    kw = dict(q=0.5, iters=0, rounds=12, retire=False)
+    a = orc.decode(c, P(move="single", **kw), e0, nthreads=4, want_beliefs=True)
+    b = orc.decode(c, P(move="multi", **kw), e0, nthreads=4)
+    assert not a["L"].any() and not np.signbit(a["L"]).any()
+    for k in ("z", "s", "tclr"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["z"].any()
 
 
 @pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
