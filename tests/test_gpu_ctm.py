@@ -99,11 +99,12 @@ def test_irregular_graphs(L, orc):
             run_both(L, orc, code, 0.15, 97, bp=bp, q=0.1, dt=0.01, t_max=20.0, tag="irregular")
 
 
+@pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
 @pytest.mark.parametrize("cpt", [1, 2, 4])
-def test_launch_shapes_agree(L, orc, cpt):
+def test_launch_shapes_agree(L, orc, cpt, bp):
     """Results do not depend on checks per thread (toric L=12: 144 checks,
-    several 64-check tiles and a ragged one)."""
-    run_both(L, orc, "toric2d:12", 0.05, 64, shot0=1000, cpt=cpt, bp="minsum", dt=0.005, t_max=20.0,
+    several 64-check tiles and a ragged one), for both BP rules."""
+    run_both(L, orc, "toric2d:12", 0.05, 64, shot0=1000, cpt=cpt, bp=bp, dt=0.005, t_max=20.0,
              tag="shape")
 
 
