@@ -243,6 +243,30 @@ laim_status laim_decode_rounds_cfg(const laim_code* code, const laim_decode_para
                                    int32_t* sweeps_out, uint8_t* fail_out,
                                    const laim_resident_cfg* cfg, laim_stream stream);
 
+/* Size of the static scratch of laim_decode_rounds_static, per device. */
+#define LAIM_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* laim_decode_rounds_static -- laim_decode_rounds without a workspace, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation. The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the scratch
+ * the chosen form needs -- 256 bytes for the resident form's shot queue, or
+ * laim_workspace_bytes(code, params, nshots, LAIM_FORM_STREAM) for the stream
+ * form -- comes from a static device array of LAIM_STATIC_SCRATCH_BYTES
+ * that each device the library runs on holds until the process ends.
+ * Arguments, outputs and results are those of laim_decode_rounds.
+ * Errors: as laim_decode_rounds; LAIM_ENOMEM (before anything is launched)
+ * when the form needs more scratch than LAIM_STATIC_SCRATCH_BYTES.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one device -- on different streams or from different threads
+ * -- race and must be serialised by the caller. */
+laim_status laim_decode_rounds_static(const laim_code* code, const laim_decode_params* params,
+                                      const uint8_t* e0, uint64_t shot0, int32_t nshots,
+                                      uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
+                                      float* L_out, int32_t* sweeps_out, uint8_t* fail_out,
+                                      int32_t form, laim_stream stream);
+
 /* Sets the resident launch shape used from now on for this code and BP
  * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg);

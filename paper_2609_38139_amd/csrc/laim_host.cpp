@@ -562,7 +562,11 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
   return 0;
 }
 
-static laim_status decode_common(const laim_code* code, const laim_decode_params* params,
+}  // extern "C"
+
+namespace laim {
+
+laim_status decode_common(const laim_code* code, const laim_decode_params* params,
                                  const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
                                  size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
                                  float* L_out, int32_t* sweeps_out, uint8_t* fail_out, int32_t form,
@@ -637,6 +641,10 @@ static laim_status decode_common(const laim_code* code, const laim_decode_params
     er = launch_failure(code->dev, e0, z_out, nshots, fail_out, (hipStream_t)stream);
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "decode kernels");
 }
+
+}  // namespace laim
+
+extern "C" {
 
 laim_status laim_decode_rounds(const laim_code* code, const laim_decode_params* params,
                                const uint8_t* e0, uint64_t shot0, int32_t nshots, void* workspace,

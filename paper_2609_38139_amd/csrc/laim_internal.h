@@ -104,6 +104,14 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
                            uint8_t* z, uint8_t* s, int32_t* tclr, float* L, uint8_t* fail,
                            int32_t* sweeps, hipStream_t st);
 
+// laim_decode_rounds and its variants: validation, form choice and launch
+// (cfg non-null: the resident form with that launch shape).
+laim_status decode_common(const laim_code* code, const laim_decode_params* params,
+                          const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
+                          size_t ws_bytes, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out,
+                          float* L_out, int32_t* sweeps_out, uint8_t* fail_out, int32_t form,
+                          const laim_resident_cfg* cfg, laim_stream stream);
+
 size_t stream_workspace_bytes(const DevCode& c, int32_t nshots, bool seq);
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
                          int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,

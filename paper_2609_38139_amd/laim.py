@@ -30,8 +30,10 @@ SYMBOLS = [
     "laim_logical_failure", "laim_batch_plan_create", "laim_batch_plan_launch",
     "laim_batch_plan_destroy", "laim_server_create", "laim_server_submit", "laim_server_step",
     "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
-    "laim_decode_bitcentric",
+    "laim_decode_bitcentric", "laim_decode_rounds_static",
 ]
+
+STATIC_SCRATCH_BYTES = 32 << 20  # LAIM_STATIC_SCRATCH_BYTES
 
 
 class LaimError(RuntimeError):
@@ -177,6 +179,8 @@ def lib():
         L.laim_decode_continuous.argtypes = [vp, C.POINTER(ContinuousParamsC), vp, u64, i32, vp, sz,
                                              vp, vp, vp, vp, vp, vp, i32, vp]
         L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
+        L.laim_decode_rounds_static.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, vp, vp, vp,
+                                                vp, vp, i32, vp]
         L.laim_server_destroy.restype = None
         _lib = L
     return _lib
@@ -340,6 +344,31 @@ def decode_rounds(code: Code, params: DecodeParams, e0, shot0: int = 0, form: st
                                           _ptr(out.get("fail")), C.byref(rc), _stream(stream))
     check(st, "laim_decode_rounds")
     out["workspace"] = workspace
+    return out
+
+
+def decode_rounds_static(code: Code, params: DecodeParams, e0, shot0: int = 0, form: str = "auto",
+                         want_beliefs: bool = False, want_sweeps: bool = False,
+                         want_fail: bool = False, out=None, stream=None) -> dict:
+    """``laim_decode_rounds_static``: as decode_rounds, with the library's
+    static device scratch instead of a workspace (the call allocates no
+    device memory; ``out`` may hold preallocated outputs)."""
+    import torch
+    ns = e0.shape[0]
+    _dev(e0, torch.uint8, (ns, code.n), "e0")
+    dev = e0.device
+    if out is None:
+        out = {"z": torch.empty((ns, code.n), dtype=torch.uint8, device=dev),
+               "s": torch.empty((ns, code.m), dtype=torch.uint8, device=dev),
+               "tclr": torch.empty((ns,), dtype=torch.int32, device=dev),
+               "L": torch.empty((ns, code.n), dtype=torch.float32, device=dev) if want_beliefs else None,
+               "sweeps": torch.empty((ns,), dtype=torch.int32, device=dev) if want_sweeps else None,
+               "fail": torch.empty((ns,), dtype=torch.uint8, device=dev) if want_fail else None}
+    P = params.c()
+    check(lib().laim_decode_rounds_static(code.handle, C.byref(P), _ptr(e0), shot0, ns, _ptr(out["z"]),
+                                          _ptr(out["s"]), _ptr(out["tclr"]), _ptr(out.get("L")),
+                                          _ptr(out.get("sweeps")), _ptr(out.get("fail")), FORMS[form],
+                                          _stream(stream)), "laim_decode_rounds_static")
     return out
 
 
