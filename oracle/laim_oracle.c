@@ -491,10 +491,12 @@ int32_t orc_resolve_moves(int32_t m, int32_t n, const int32_t* rowptr, const int
  * corrections can be traced (s_trace [rounds][m], z_trace [rounds][n]).
  * Returns 0, or -3 if the internal syndrome-update identity check fails.
  * ---------------------------------------------------------------------- */
-static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr,
-                          uint64_t R_bound, float pi, const uint8_t* e0, uint64_t shot,
-                          uint8_t* z, uint8_t* s, int32_t* tclr, float* L_out, uint8_t* s_trace,
-                          uint8_t* z_trace) {
+/* The machine from a given start syndrome s0 (s0 = H e0 for a decode of
+ * e0), its rounds numbered r0, r0 + 1, ... for the clock words. */
+static int32_t decode_core(const tanner* T, const orc_params* P, const float* thr,
+                           uint64_t R_bound, float pi, const uint8_t* s0, uint64_t shot, int32_t r0,
+                           uint8_t* z, uint8_t* s, int32_t* tclr, float* L_out, uint8_t* s_trace,
+                           uint8_t* z_trace) {
   const int32_t m = T->m, n = T->n, E = T->E;
   float* mvc = (float*)calloc((size_t)(E > 0 ? E : 1), sizeof(float));
   float* mcv = (float*)calloc((size_t)(E > 0 ? E : 1), sizeof(float));
@@ -511,12 +513,15 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
     goto done;
   }
   for (int32_t v = 0; v < n; ++v) { piv[v] = pi; z[v] = 0; }
-  orc_syndrome(m, n, T->rowptr, T->col, e0, 1, s);
   int any = 0;
-  for (int32_t c = 0; c < m; ++c) any |= s[c];
+  for (int32_t c = 0; c < m; ++c) {
+    s[c] = s0[c] & 1u;
+    any |= s[c];
+  }
   *tclr = any ? -1 : 0;
 
-  for (int32_t r = 0; r < P->rounds; ++r) {
+  for (int32_t rr = 0; rr < P->rounds; ++rr) {
+    const int32_t r = r0 + rr;
     if (P->retire && *tclr >= 0) break;
     for (int32_t it = 0; it < P->iters; ++it) {
       check_phase(T, P, mvc, s, mcv);
@@ -569,10 +574,7 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
       rc = -1;
       goto done;
     }
-    for (int32_t v = 0; v < n; ++v) {
-      z[v] ^= f[v];
-      r_err[v] = (uint8_t)(e0[v] ^ z[v]);
-    }
+    for (int32_t v = 0; v < n; ++v) z[v] ^= f[v];
     if (P->gauge) {
       for (int32_t v = 0; v < n; ++v) {
         if (!f[v]) continue;
@@ -584,25 +586,46 @@ static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr
         }
       }
     }
-    /* re-measure and check it against the incremental update s ^ H f */
-    orc_syndrome(m, n, T->rowptr, T->col, r_err, 1, s_new);
+    /* re-measure, s = s0 ^ H z (= H (e0 ^ z)), and check it against the
+     * incremental update s ^ H f */
+    orc_syndrome(m, n, T->rowptr, T->col, z, 1, s_new);
     any = 0;
     for (int32_t c = 0; c < m; ++c) {
+      s_new[c] ^= s0[c] & 1u;
       uint8_t x = s[c];
       for (int32_t k = T->rowptr[c]; k < T->rowptr[c + 1]; ++k) x ^= f[T->col[k]];
       if (x != s_new[c]) rc = -3;
       s[c] = s_new[c];
       any |= s[c];
     }
-    if (!any && *tclr < 0) *tclr = r + 1;
-    if (s_trace) memcpy(s_trace + (size_t)r * m, s, (size_t)m);
-    if (z_trace) memcpy(z_trace + (size_t)r * n, z, (size_t)n);
+    if (!any && *tclr < 0) *tclr = rr + 1;
+    if (s_trace) memcpy(s_trace + (size_t)rr * m, s, (size_t)m);
+    if (z_trace) memcpy(z_trace + (size_t)rr * n, z, (size_t)n);
   }
   if (L_out) beliefs(T, P, piv, mcv, L_out);
 done:
   free(mvc); free(mcv); free(L); free(piv); free(f); free(r_err); free(s_new); free(req);
   return rc;
 }
+
+/* The machine on the initial error e0 (rounds numbered from 0). */
+static int32_t decode_one(const tanner* T, const orc_params* P, const float* thr,
+                          uint64_t R_bound, float pi, const uint8_t* e0, uint64_t shot,
+                          uint8_t* z, uint8_t* s, int32_t* tclr, float* L_out, uint8_t* s_trace,
+                          uint8_t* z_trace) {
+  uint8_t* s0 = (uint8_t*)malloc((size_t)(T->m > 0 ? T->m : 1));
+  if (!s0) return -2;
+  orc_syndrome(T->m, T->n, T->rowptr, T->col, e0, 1, s0);
+  int32_t rc = decode_core(T, P, thr, R_bound, pi, s0, shot, 0, z, s, tclr, L_out, s_trace, z_trace);
+  free(s0);
+  return rc;
+}
+
+/* The machine from given start syndromes (s0 [nshots][m]), rounds numbered
+ * from r0: the building block of the online decoder, exposed for its pins. */
+int32_t orc_decode_syndrome(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                            const orc_params* P, const uint8_t* s0, uint64_t shot0, int32_t r0,
+                            int32_t nshots, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out);
 
 /* thr[d] = -log(d - 1) rounded to float, the Evidence bound for degree d
  * (thr[1] = +inf: a degree-1 check never has evidence; thr[2] = -0). */
@@ -991,6 +1014,269 @@ int32_t orc_logical_failure(int32_t m, int32_t n, const int32_t* h_rowptr, const
   free(r); free(s); free(work);
   gf2_basis_free(&B);
   return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Online decoding in overlapping spacetime windows (Discussion: new faults
+ * and syndrome information keep arriving; the Tanner graph is promoted to a
+ * spacetime decoding graph and the local dynamics runs inside overlapping
+ * spacetime windows). The paper fixes neither the noise model nor the window
+ * rule; the reading:
+ *   noise      N syndrome rounds t = 1..N. Before round t every qubit gets a
+ *              new Z error e_t[v] ~ Bernoulli(p); round t measures
+ *              m_t = H E_t ^ eps_t with E_t = e_1 ^ ... ^ e_t and
+ *              measurement errors eps_t[c] ~ Bernoulli(p_meas), except that
+ *              the last round is perfect (eps_N = 0). Words: e_t[v] is word
+ *              (v mod 4) of Philox(seed, (shot_lo, shot_hi, floor(v/4),
+ *              16 t + 3)), eps_t[c] word (c mod 4) of Philox(seed, (shot_lo,
+ *              shot_hi, floor(c/4), 16 t + 4)), each below floor(rate 2^32).
+ *   detectors  D_t = m_t ^ m_{t-1} (m_0 = 0) = H e_t ^ eps_t ^ eps_{t-1}.
+ *   graph      one variable per e_t[v] and per eps_t[c] (t < N), one check
+ *              per detector (t, c) holding e_t[v] for v in N(c), eps_{t-1}[c]
+ *              and eps_t[c] where they exist; one prior q for all variables.
+ *   windows    window k covers rounds k C + 1 .. min(k C + W, N); the last
+ *              window is the first that reaches round N. Its check (tau, c)
+ *              (round k C + 1 + tau) gets the syndrome D, with the committed
+ *              correction of eps_{kC}[c] added on tau = 0. The round machine
+ *              decodes it from fresh messages, its rounds numbered from k R
+ *              (R rounds per window), so every window draws its own clock
+ *              words. The window's variables of its first C rounds (all of
+ *              them in the last window) are committed: their data
+ *              corrections add to the running correction z, and the
+ *              measurement corrections of the last committed round carry into
+ *              the next window.
+ *   result     z, and the failure of the offline test applied to the final
+ *              error E_N: H (E_N ^ z) != 0 or E_N ^ z not in row(G).
+ * Window variables (w rounds, local round tau, measurement variables for the
+ * first w_eps rounds: w_eps = w, or w - 1 when the window ends with the
+ * perfect round): data (tau, v) is tau n + v, measurement (tau, c) is
+ * w n + tau m + c; check (tau, c) is tau m + c.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t rounds_total; /* N syndrome rounds, the last one perfect */
+  int32_t window;       /* W rounds per window */
+  int32_t commit;       /* C rounds committed per window, 1 <= C <= W */
+  double p;             /* data error rate per qubit and round */
+  double p_meas;        /* measurement error rate per check and round */
+} orc_online_params;
+
+/* Spacetime errors of one shot: e [N][n], eps [N][m] (the last row 0). */
+static void online_noise_one(int32_t n, int32_t m, const orc_online_params* O, uint64_t seed,
+                             uint64_t shot, uint8_t* e, uint8_t* eps) {
+  const uint64_t bd = orc_bernoulli_bound(O->p), bm = orc_bernoulli_bound(O->p_meas);
+  const int32_t N = O->rounds_total;
+  uint32_t w[4];
+  for (int32_t t = 1; t <= N; ++t) {
+    for (int32_t v = 0; v < n; ++v) {
+      philox_for(seed, shot, (uint32_t)(v >> 2), ((uint32_t)t << 4) | 3u, w);
+      e[(size_t)(t - 1) * n + v] = (uint8_t)((uint64_t)w[v & 3] < bd);
+    }
+    for (int32_t c = 0; c < m; ++c) {
+      uint8_t x = 0;
+      if (t < N) {
+        philox_for(seed, shot, (uint32_t)(c >> 2), ((uint32_t)t << 4) | 4u, w);
+        x = (uint8_t)((uint64_t)w[c & 3] < bm);
+      }
+      eps[(size_t)(t - 1) * m + c] = x;
+    }
+  }
+}
+
+void orc_online_noise(int32_t n, int32_t m, const orc_online_params* O, uint64_t seed,
+                      uint64_t shot0, int32_t nshots, uint8_t* e_out, uint8_t* eps_out) {
+  const size_t N = (size_t)O->rounds_total;
+  for (int32_t i = 0; i < nshots; ++i)
+    online_noise_one(n, m, O, seed, shot0 + (uint64_t)i, e_out + (size_t)i * N * n,
+                     eps_out + (size_t)i * N * m);
+}
+
+/* The CSR of a window of w rounds with measurement variables for its first
+ * w_eps rounds. Returns the number of variables, or -2 without memory. */
+static int32_t window_csr(const tanner* T, int32_t w, int32_t w_eps, int32_t** rowptr, int32_t** col) {
+  const int32_t m = T->m, n = T->n;
+  int32_t* rp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)w * m + 1));
+  int32_t* cl = (int32_t*)malloc(sizeof(int32_t) * ((size_t)w * (T->E + 2 * m) + 1));
+  if (!rp || !cl) {
+    free(rp);
+    free(cl);
+    return -2;
+  }
+  int32_t k = 0;
+  rp[0] = 0;
+  for (int32_t tau = 0; tau < w; ++tau) {
+    for (int32_t c = 0; c < m; ++c) {
+      for (int32_t e = T->rowptr[c]; e < T->rowptr[c + 1]; ++e) cl[k++] = tau * n + T->col[e];
+      if (tau >= 1 && tau - 1 < w_eps) cl[k++] = w * n + (tau - 1) * m + c;
+      if (tau < w_eps) cl[k++] = w * n + tau * m + c;
+      rp[tau * m + c + 1] = k;
+    }
+  }
+  *rowptr = rp;
+  *col = cl;
+  return w * n + w_eps * m;
+}
+
+/* The window layout of a run: nwin windows, window k starting at round
+ * k C + 1; the last has w_last rounds. */
+static void window_layout(const orc_online_params* O, int32_t* nwin, int32_t* w_last) {
+  const int32_t N = O->rounds_total, W = O->window, C = O->commit;
+  int32_t k = 0;
+  while (k * C + W < N) ++k;
+  *nwin = k + 1;
+  *w_last = N - k * C;
+}
+
+/* Online decode of nshots shots (ids shot0 + i). With e_in / eps_in
+ * ([nshots][N][n], [nshots][N][m]; both or neither) the given errors are
+ * used instead of sampled ones. Outputs: z [nshots][n], E [nshots][n] (the
+ * final error), fail [nshots], cleared [nshots] (windows whose syndrome
+ * cleared); with one shot, trace_s [nwin][W m] and trace_z [nwin][W (n + m)]
+ * record each window's syndrome and correction (rows zero-padded).
+ * Returns 0, -1 for bad parameters, -2 without memory, -3 if a window's
+ * syndrome update identity fails. */
+int32_t orc_online_decode(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col, int32_t mg,
+                          const int32_t* g_rowptr, const int32_t* g_col, const orc_params* P,
+                          const orc_online_params* O, uint64_t shot0, int32_t nshots,
+                          const uint8_t* e_in, const uint8_t* eps_in, uint8_t* z_out, uint8_t* E_out,
+                          uint8_t* fail_out, int32_t* cleared_out, uint8_t* trace_s, uint8_t* trace_z,
+                          int32_t nthreads) {
+  const int32_t N = O->rounds_total, W = O->window, C = O->commit;
+  if (N < 1 || W < 1 || C < 1 || C > W || P->rounds < 0) return -1;
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  int32_t nwin, w_last;
+  window_layout(O, &nwin, &w_last);
+  /* the two window shapes: full windows (W rounds, every round with its
+   * measurement variables) and the last window (ending with the perfect round) */
+  int32_t *rp_full = NULL, *cl_full = NULL, *rp_last = NULL, *cl_last = NULL;
+  int32_t nv_full = 0, nv_last = window_csr(&T, w_last, w_last - 1, &rp_last, &cl_last);
+  if (nwin > 1) nv_full = window_csr(&T, W, W, &rp_full, &cl_full);
+  if (nv_last < 0 || nv_full < 0) {
+    tanner_free(&T);
+    return -2;
+  }
+  tanner Tf, Tl;
+  int init_f = (nwin > 1) ? tanner_init(&Tf, W * m, nv_full, rp_full, cl_full) : 0;
+  int init_l = tanner_init(&Tl, w_last * m, nv_last, rp_last, cl_last);
+  const int32_t dmax = T.E > 0 ? 32 : 2;
+  float* thr = (float*)malloc(sizeof(float) * (size_t)(dmax + 1));
+  orc_evidence_thresholds(dmax, thr);
+  const float pi = (float)log(P->q / (1.0 - P->q));
+  const uint64_t R_bound = orc_bernoulli_bound(P->mask_density);
+  int32_t rc = (init_f || init_l || !thr) ? -2 : 0;
+  if (nthreads < 1) nthreads = 1;
+  if (rc == 0) {
+#pragma omp parallel for schedule(static) num_threads(nthreads) reduction(min : rc)
+    for (int32_t i = 0; i < nshots; ++i) {
+      const uint64_t shot = shot0 + (uint64_t)i;
+      const int32_t nvm = W * (n + m) > n ? W * (n + m) : n;
+      uint8_t* e = (uint8_t*)malloc((size_t)N * n);
+      uint8_t* eps = (uint8_t*)malloc((size_t)N * m);
+      uint8_t* D = (uint8_t*)malloc((size_t)N * m);
+      uint8_t* sw = (uint8_t*)malloc((size_t)W * m);
+      uint8_t* sout = (uint8_t*)malloc((size_t)W * m);
+      uint8_t* zw = (uint8_t*)malloc((size_t)nvm);
+      uint8_t* bnd = (uint8_t*)calloc((size_t)m, 1);
+      uint8_t* z = z_out + (size_t)i * n;
+      uint8_t* E = E_out + (size_t)i * n;
+      int32_t r1 = 0;
+      if (!e || !eps || !D || !sw || !sout || !zw || !bnd) r1 = -2;
+      if (r1 == 0) {
+        if (e_in) {
+          memcpy(e, e_in + (size_t)i * N * n, (size_t)N * n);
+          memcpy(eps, eps_in + (size_t)i * N * m, (size_t)N * m);
+          for (int32_t c = 0; c < m; ++c) eps[(size_t)(N - 1) * m + c] = 0; /* perfect last round */
+        } else {
+          online_noise_one(n, m, O, P->seed, shot, e, eps);
+        }
+        /* detectors D_t = H e_t ^ eps_t ^ eps_{t-1}; final error E_N */
+        for (int32_t t = 0; t < N; ++t) {
+          orc_syndrome(m, n, rowptr, col, e + (size_t)t * n, 1, D + (size_t)t * m);
+          for (int32_t c = 0; c < m; ++c) {
+            D[(size_t)t * m + c] ^= eps[(size_t)t * m + c];
+            if (t > 0) D[(size_t)t * m + c] ^= eps[(size_t)(t - 1) * m + c];
+          }
+        }
+        for (int32_t v = 0; v < n; ++v) {
+          uint8_t x = 0;
+          for (int32_t t = 0; t < N; ++t) x ^= e[(size_t)t * n + v];
+          E[v] = x & 1u;
+          z[v] = 0;
+        }
+        int32_t cleared = 0;
+        for (int32_t k = 0; k < nwin && r1 == 0; ++k) {
+          const int last = (k == nwin - 1);
+          const int32_t a = k * C; /* first round of the window, 0-based */
+          const int32_t w = last ? w_last : W;
+          const tanner* Tw = last ? &Tl : &Tf;
+          for (int32_t tau = 0; tau < w; ++tau)
+            for (int32_t c = 0; c < m; ++c)
+              sw[tau * m + c] = (uint8_t)(D[(size_t)(a + tau) * m + c] ^ (tau == 0 ? bnd[c] : 0));
+          int32_t tclr;
+          r1 = decode_core(Tw, P, thr, R_bound, pi, sw, shot, k * P->rounds, zw, sout, &tclr, NULL,
+                           NULL, NULL);
+          cleared += (tclr >= 0);
+          const int32_t cr = last ? w : C; /* rounds committed */
+          for (int32_t tau = 0; tau < cr; ++tau)
+            for (int32_t v = 0; v < n; ++v) z[v] ^= zw[tau * n + v];
+          if (!last)
+            for (int32_t c = 0; c < m; ++c) bnd[c] = zw[w * n + (cr - 1) * m + c];
+          if (trace_s && nshots == 1) {
+            memset(trace_s + (size_t)k * W * m, 0, (size_t)W * m);
+            memcpy(trace_s + (size_t)k * W * m, sw, (size_t)w * m);
+            memset(trace_z + (size_t)k * W * (n + m), 0, (size_t)W * (n + m));
+            memcpy(trace_z + (size_t)k * W * (n + m), zw, (size_t)Tw->n);
+          }
+        }
+        if (cleared_out) cleared_out[i] = cleared;
+      }
+      free(e); free(eps); free(D); free(sw); free(sout); free(zw); free(bnd);
+      if (r1 < rc) rc = r1;
+    }
+  }
+  if (rc == 0) rc = orc_logical_failure(m, n, rowptr, col, mg, g_rowptr, g_col, E_out, z_out, nshots, fail_out);
+  free(thr);
+  if (nwin > 1) tanner_free(&Tf);
+  tanner_free(&Tl);
+  tanner_free(&T);
+  free(rp_full); free(cl_full); free(rp_last); free(cl_last);
+  return rc;
+}
+
+int32_t orc_decode_syndrome(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col,
+                            const orc_params* P, const uint8_t* s0, uint64_t shot0, int32_t r0,
+                            int32_t nshots, uint8_t* z_out, uint8_t* s_out, int32_t* tclr_out) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  float thr[33];
+  orc_evidence_thresholds(32, thr);
+  const float pi = (float)log(P->q / (1.0 - P->q));
+  const uint64_t R_bound = orc_bernoulli_bound(P->mask_density);
+  int32_t rc = 0;
+  for (int32_t i = 0; i < nshots && rc == 0; ++i)
+    rc = decode_core(&T, P, thr, R_bound, pi, s0 + (size_t)i * m, shot0 + (uint64_t)i, r0,
+                     z_out + (size_t)i * n, s_out + (size_t)i * m, tclr_out + i, NULL, NULL, NULL);
+  tanner_free(&T);
+  return rc;
+}
+
+/* The CSR of a window code, for the pins: w rounds, measurement variables
+ * for the first w_eps. rowptr_out [w m + 1], col_out [w (E + 2 m)]; returns
+ * the number of variables. */
+int32_t orc_window_code(int32_t m, int32_t n, const int32_t* rowptr, const int32_t* col, int32_t w,
+                        int32_t w_eps, int32_t* rowptr_out, int32_t* col_out) {
+  tanner T;
+  if (tanner_init(&T, m, n, rowptr, col)) return -2;
+  int32_t *rp, *cl;
+  int32_t nv = window_csr(&T, w, w_eps, &rp, &cl);
+  if (nv >= 0) {
+    memcpy(rowptr_out, rp, sizeof(int32_t) * ((size_t)w * m + 1));
+    memcpy(col_out, cl, sizeof(int32_t) * (size_t)rp[w * m]);
+    free(rp);
+    free(cl);
+  }
+  tanner_free(&T);
+  return nv;
 }
 
 /* ------------------------------------------------------------------------

@@ -74,6 +74,34 @@ class DecodeParams:
                       CONFLICT_RULES[self.conflict], MOVES[self.move])
 
 
+class OnlineParamsC(C.Structure):
+    _fields_ = [("rounds_total", C.c_int32), ("window", C.c_int32), ("commit", C.c_int32),
+                ("p", C.c_double), ("p_meas", C.c_double)]
+
+
+@dataclass
+class OnlineParams:
+    """Online decoding: N syndrome rounds (the last perfect), windows of W
+    rounds of which the first C are committed, data and measurement error
+    rates."""
+
+    rounds_total: int = 8
+    window: int = 4
+    commit: int = 2
+    p: float = 0.01
+    p_meas: float = 0.01
+
+    def c(self) -> OnlineParamsC:
+        return OnlineParamsC(self.rounds_total, self.window, self.commit, self.p, self.p_meas)
+
+    def layout(self):
+        """(number of windows, rounds of the last window)."""
+        k = 0
+        while k * self.commit + self.window < self.rounds_total:
+            k += 1
+        return k + 1, self.rounds_total - k * self.commit
+
+
 class CtmParams(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("dt", C.c_double), ("tau", C.c_double), ("max_steps", C.c_int32),
@@ -160,6 +188,17 @@ def lib():
         L.orc_bitcentric_machine.restype = C.c_int32
         L.orc_bitcentric_machine.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_double, u8p,
                                              C.c_int32, u8p, C.POINTER(C.c_double), i32p]
+        L.orc_online_noise.argtypes = [C.c_int32, C.c_int32, C.POINTER(OnlineParamsC), C.c_uint64, C.c_uint64,
+                                       C.c_int32, u8p, u8p]
+        L.orc_online_decode.restype = C.c_int32
+        L.orc_online_decode.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_int32, i32p, i32p,
+                                        C.POINTER(Params), C.POINTER(OnlineParamsC), C.c_uint64, C.c_int32,
+                                        u8p, u8p, u8p, u8p, u8p, i32p, u8p, u8p, C.c_int32]
+        L.orc_decode_syndrome.restype = C.c_int32
+        L.orc_decode_syndrome.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.POINTER(Params), u8p, C.c_uint64,
+                                          C.c_int32, C.c_int32, u8p, u8p, i32p]
+        L.orc_window_code.restype = C.c_int32
+        L.orc_window_code.argtypes = [C.c_int32, C.c_int32, i32p, i32p, C.c_int32, C.c_int32, i32p, i32p]
         _lib = L
     return _lib
 
@@ -385,3 +424,84 @@ def ctm_decode(code, params: ContinuousParams, e0, shot0: int = 0, nthreads: int
         k = min(int(cnt[0, 0]), trace_cap)
         out["trace"] = tr[:k].copy()
     return out
+
+
+# ---------------------------------------------------------------- online decoding
+def online_noise(code, params: OnlineParams, seed: int, shot0: int, nshots: int):
+    """Spacetime errors: e [nshots, N, n] (new data errors of each round) and
+    eps [nshots, N, m] (measurement errors; the last round's are 0)."""
+    n, m, N = code.H.cols, code.H.rows, params.rounds_total
+    e = np.zeros((nshots, N, n), dtype=np.uint8)
+    eps = np.zeros((nshots, N, m), dtype=np.uint8)
+    O = params.c()
+    lib().orc_online_noise(n, m, C.byref(O), seed, shot0, nshots, _p(e, C.c_uint8), _p(eps, C.c_uint8))
+    return e, eps
+
+
+def window_code(code, w: int, w_eps: int):
+    """CSR (rowptr, col, number of variables) of a window of w rounds with
+    measurement variables for its first w_eps rounds."""
+    rp, cl = _csr(code.H)
+    m = code.H.rows
+    rpo = np.zeros(w * m + 1, dtype=np.int32)
+    clo = np.zeros(max(1, w * (code.H.nnz + 2 * m)), dtype=np.int32)
+    nv = lib().orc_window_code(m, code.H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32), w, w_eps,
+                               _p(rpo, C.c_int32), _p(clo, C.c_int32))
+    assert nv >= 0
+    return rpo, clo[:rpo[-1]].copy(), int(nv)
+
+
+def online_decode(code, params: DecodeParams, online: OnlineParams, shot0: int = 0, nshots: int = 1,
+                  e_in=None, eps_in=None, nthreads: int = 1, trace: bool = False) -> dict:
+    """The online (spacetime-window) decoder on nshots shots; with e_in and
+    eps_in ([nshots, N, n], [nshots, N, m]) the given errors replace the
+    sampled ones."""
+    n, m, N = code.H.cols, code.H.rows, online.rounds_total
+    hr, hc = _csr(code.H)
+    gr, gc = _csr(code.G)
+    if e_in is not None:
+        e_in = np.ascontiguousarray(e_in, dtype=np.uint8).reshape(nshots, N, n)
+        eps_in = np.ascontiguousarray(eps_in, dtype=np.uint8).reshape(nshots, N, m)
+    z = np.zeros((nshots, n), dtype=np.uint8)
+    E = np.zeros((nshots, n), dtype=np.uint8)
+    f = np.zeros(nshots, dtype=np.uint8)
+    cl = np.zeros(nshots, dtype=np.int32)
+    nwin, _ = online.layout()
+    W = online.window
+    ts = tz = None
+    if trace:
+        assert nshots == 1
+        ts = np.zeros((nwin, W * m), dtype=np.uint8)
+        tz = np.zeros((nwin, W * (n + m)), dtype=np.uint8)
+    P = params.c()
+    O = online.c()
+    rc = lib().orc_online_decode(m, n, _p(hr, C.c_int32), _p(hc, C.c_int32), code.G.rows, _p(gr, C.c_int32),
+                                 _p(gc, C.c_int32), C.byref(P), C.byref(O), shot0, nshots,
+                                 _p(e_in, C.c_uint8) if e_in is not None else None,
+                                 _p(eps_in, C.c_uint8) if eps_in is not None else None,
+                                 _p(z, C.c_uint8), _p(E, C.c_uint8), _p(f, C.c_uint8), _p(cl, C.c_int32),
+                                 _p(ts, C.c_uint8) if ts is not None else None,
+                                 _p(tz, C.c_uint8) if tz is not None else None, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"oracle online_decode failed with status {rc}")
+    return {"z": z, "E": E, "fail": f, "cleared": cl, "windows": nwin, "trace_s": ts, "trace_z": tz}
+
+
+def decode_syndrome(H, params: DecodeParams, s0, shot0: int = 0, r0: int = 0) -> dict:
+    """The round machine on the Tanner graph of H (a CSR with rows, cols,
+    rowptr, col) from start syndromes s0 [nshots, m], its rounds numbered
+    from r0."""
+    s0 = np.ascontiguousarray(np.atleast_2d(s0), dtype=np.uint8)
+    ns = s0.shape[0]
+    rp = np.ascontiguousarray(H.rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(H.col if len(H.col) else np.zeros(1), dtype=np.int32)
+    z = np.zeros((ns, H.cols), dtype=np.uint8)
+    s = np.zeros((ns, H.rows), dtype=np.uint8)
+    t = np.zeros(ns, dtype=np.int32)
+    P = params.c()
+    rc = lib().orc_decode_syndrome(H.rows, H.cols, _p(rp, C.c_int32), _p(cl, C.c_int32), C.byref(P),
+                                   _p(s0, C.c_uint8), shot0, r0, ns, _p(z, C.c_uint8), _p(s, C.c_uint8),
+                                   _p(t, C.c_int32))
+    if rc != 0:
+        raise RuntimeError(f"oracle decode_syndrome failed with status {rc}")
+    return {"z": z, "s": s, "tclr": t}

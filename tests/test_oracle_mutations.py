@@ -58,7 +58,7 @@ MUTATIONS = {
         "(float)(-log((double)(d - 1)))", "(float)(-log((double)d))",
         ["test_oracle_primitives.py", "test_oracle_pins.py"], "evidence"),
     "t_clr counted from zero": (
-        "if (!any && *tclr < 0) *tclr = r + 1;", "if (!any && *tclr < 0) *tclr = r;",
+        "if (!any && *tclr < 0) *tclr = rr + 1;", "if (!any && *tclr < 0) *tclr = rr;",
         ["test_oracle_pins.py"], "special"),
     "failure test without the row-space condition": (
         "fail_out[i] = (uint8_t)(any || !in_row_space(&B, n, r, work));", "fail_out[i] = (uint8_t)(any);",
@@ -90,6 +90,30 @@ MUTATIONS = {
         "      if (i == 0 || req[i].c != req[i - 1].c || req[i].key != req[i - 1].key) {",
         "      if (1) {",
         ["test_oracle_conflict.py"], "multi_qubit"),
+    "online: the carried measurement correction is dropped": (
+        "sw[tau * m + c] = (uint8_t)(D[(size_t)(a + tau) * m + c] ^ (tau == 0 ? bnd[c] : 0));",
+        "sw[tau * m + c] = (uint8_t)(D[(size_t)(a + tau) * m + c]);",
+        ["test_oracle_online.py"], "replay"),
+    "online: every window numbers its rounds from 0": (
+        "r1 = decode_core(Tw, P, thr, R_bound, pi, sw, shot, k * P->rounds, zw,",
+        "r1 = decode_core(Tw, P, thr, R_bound, pi, sw, shot, 0, zw,",
+        ["test_oracle_online.py"], "replay"),
+    "online: the last round is not perfect": (
+        "      if (t < N) {\n        philox_for", "      if (t <= N) {\n        philox_for",
+        ["test_oracle_online.py"], "noise"),
+    "online: data errors from the measurement counter": (
+        "philox_for(seed, shot, (uint32_t)(v >> 2), ((uint32_t)t << 4) | 3u, w);",
+        "philox_for(seed, shot, (uint32_t)(v >> 2), ((uint32_t)t << 4) | 4u, w);",
+        ["test_oracle_online.py"], "noise"),
+    "online: detectors without the previous measurement error": (
+        "            if (t > 0) D[(size_t)t * m + c] ^= eps[(size_t)(t - 1) * m + c];\n", "",
+        ["test_oracle_online.py"], "replay"),
+    "online: a window commits all its rounds": (
+        "const int32_t cr = last ? w : C; /* rounds committed */", "const int32_t cr = w;",
+        ["test_oracle_online.py"], "replay"),
+    "online: window graph without the previous round's measurement variable": (
+        "      if (tau >= 1 && tau - 1 < w_eps) cl[k++] = w * n + (tau - 1) * m + c;\n", "",
+        ["test_oracle_online.py"], "spacetime_graph"),
     "sequential rule with a stale syndrome": (
         "      for (int32_t k = T->rowptr[req[i].c]; k < T->rowptr[req[i].c + 1]; ++k) x ^= f[T->col[k]];\n", "",
         ["test_oracle_conflict.py"], "sequential"),
