@@ -154,7 +154,19 @@ typedef struct {
   uint64_t seed;        /* Philox key for the clocks and tie-breaks */
   int32_t conflict;     /* how one round's move requests combine, LAIM_CONFLICT_* (0: OR) */
   int32_t skip_fixed;   /* 1: skip sweeps that cannot change anything (see below); 0: run all */
+  int32_t move;         /* the local move of an acting check, LAIM_MOVE_* (0: LocalMove) */
 } laim_decode_params;
+
+/* Local moves. Algorithm 1's LocalMove flips one qubit of an acting check;
+ * the LDPC-codes section also names a multi-qubit flip akin to small-set
+ * flip, guided by the local beliefs, without a rule for it. The rule here:
+ *   SINGLE  the LocalMove qubit (largest belief, random tie-break);
+ *   MULTI   every qubit v of N(c) with L_v > 0, i.e. Pr_BP(e_v = 1 | s) > 1/2;
+ *           the LocalMove qubit when there is none.
+ * Every qubit of a multi-qubit move is one request under the conflict rule
+ * (OR or XOR; the sequential rule takes single moves only: LAIM_EUNSUP). */
+#define LAIM_MOVE_SINGLE 0
+#define LAIM_MOVE_MULTI 1
 
 /* skip_fixed. Within a round the sweep is a fixed map of the messages (the
  * syndrome, prior and parameters do not change), so once a sweep writes

@@ -460,6 +460,7 @@ laim_status laim_server_submit(laim_server* s, const laim_code* code,
   kp_key.seed = params->seed;
   kp_key.conflict = params->conflict;
   kp_key.skip_fixed = params->skip_fixed;
+  kp_key.move = params->move;
   std::vector<char> key(sizeof(void*) + sizeof(laim_decode_params));
   memcpy(key.data(), &code, sizeof(void*));
   memcpy(key.data() + sizeof(void*), &kp_key, sizeof(laim_decode_params));

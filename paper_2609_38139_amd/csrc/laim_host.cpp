@@ -66,6 +66,14 @@ laim_status resolve_params(const laim_decode_params* p, KParams* kp) {
     set_error("conflict must be LAIM_CONFLICT_OR, _XOR or _SEQUENTIAL");
     return LAIM_EINVAL;
   }
+  if (p->move != LAIM_MOVE_SINGLE && p->move != LAIM_MOVE_MULTI) {
+    set_error("move must be LAIM_MOVE_SINGLE or LAIM_MOVE_MULTI");
+    return LAIM_EINVAL;
+  }
+  if (p->move == LAIM_MOVE_MULTI && p->conflict == LAIM_CONFLICT_SEQUENTIAL) {
+    set_error("multi-qubit moves combine by OR or XOR only");
+    return LAIM_EUNSUP;
+  }
   kp->bp = p->bp;
   kp->alpha = p->alpha;
   kp->pi = (float)log(p->q / (1.0 - p->q));
@@ -78,6 +86,7 @@ laim_status resolve_params(const laim_decode_params* p, KParams* kp) {
   kp->seed = p->seed;
   kp->conflict = p->conflict;
   kp->skip = p->skip_fixed ? 1 : 0;
+  kp->move = p->move;
   return LAIM_OK;
 }
 

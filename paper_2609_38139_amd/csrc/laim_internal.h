@@ -53,6 +53,7 @@ struct KParams {
   int32_t conflict;  // kConflict*
   int32_t skip;      // 1: a group whose messages are a fixed point of the sweep skips the
                      // round's remaining (identity) sweeps
+  int32_t move;      // 0: LocalMove; 1: multi-qubit move (every qubit with a positive belief)
 };
 
 // How one round's move requests combine (values of laim_decode_params.conflict).

@@ -764,22 +764,39 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         if (slot < 0) continue;
         if (kp.conflict == kConflictSequential) {
           // provisionally applies: the check is active at the round's start
+          // (single-qubit moves only: the host refuses multi-qubit ones here)
           rkey[ch] = w.w2;
           rq[ch] = (uint8_t)(0x80 | slot);
           reqm |= 1u << k;
           continue;
         }
-        const int32_t chosen = nb[slot];
-        const uint32_t bit = 1u << (chosen & 31);
-        uint32_t had;
-        if (kp.conflict == kConflictOr) {
-          if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
-          had = 0;
-        } else {
-          had = atomicXor(&flw[chosen >> 5], bit) & bit;
+        // The slots the check asks to flip: its LocalMove qubit, or for a
+        // multi-qubit move every qubit of the check with a positive belief
+        // (Pr_BP(e_v = 1 | s) > 1/2), falling back to the LocalMove qubit.
+        uint32_t fmask = 1u << slot;
+        if (kp.move) {
+          uint32_t pos = 0u;
+#pragma unroll
+          for (int j = 0; j < DC; ++j)
+            if (j < d && Lv[j] > 0.0f) pos |= 1u << j;
+          if (pos) fmask = pos;
         }
-        flip_qubit<DV, REG>(c, chosen, zw, sw);
-        nflip += had ? -1 : 1;
+#pragma unroll 1
+        while (fmask) {
+          const int32_t jj = __builtin_ctz(fmask);
+          fmask &= fmask - 1u;
+          const int32_t chosen = nb[jj];
+          const uint32_t bit = 1u << (chosen & 31);
+          uint32_t had;
+          if (kp.conflict == kConflictOr) {
+            if (atomicOr(&flw[chosen >> 5], bit) & bit) continue;  // already requested
+            had = 0;
+          } else {
+            had = atomicXor(&flw[chosen >> 5], bit) & bit;
+          }
+          flip_qubit<DV, REG>(c, chosen, zw, sw);
+          nflip += had ? -1 : 1;
+        }
       }
       if (nflip) atomicAdd(&gw[kGwFlips], nflip);
       if (sb & ~noev) gw[kGwLive] = 1;  // an active check passed the Evidence test

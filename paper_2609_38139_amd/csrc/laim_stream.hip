@@ -347,16 +347,28 @@ __device__ __forceinline__ void stream_request(const DevCode& c, const KParams& 
   if (slot < 0) return;
   if (kp.conflict == kConflictSequential) {
     // recorded, provisionally applying; resolved by stream_resolve
+    // (single-qubit moves only: the host refuses multi-qubit ones here)
     const int64_t o = stream_at(tile, c.m, ch, lane) + q;
     w.rkey[o] = rw.w2;
     w.rq[o] = (uint8_t)(0x80 | slot);
     return;
   }
-  const int64_t fo = (tile * c.n + nb[slot]) * kStreamTile + col;
-  if (kp.conflict == kConflictOr)
-    w.fl[fo] = 1;
-  else  // XOR: the byte of this shot in the 4-byte word holding it
-    atomicXor(reinterpret_cast<uint32_t*>(w.fl + (fo & ~(int64_t)3)), 1u << (8 * (fo & 3)));
+  // the LocalMove qubit, or for a multi-qubit move every qubit of the check
+  // with a positive belief (if any)
+  bool multi = false;
+  if (kp.move) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) multi |= (j < d && Lv[j] > 0.0f);
+  }
+#pragma unroll
+  for (int j = 0; j < DCT; ++j) {
+    if (j >= d || !(multi ? (Lv[j] > 0.0f) : (j == slot))) continue;
+    const int64_t fo = (tile * c.n + nb[j]) * kStreamTile + col;
+    if (kp.conflict == kConflictOr)
+      w.fl[fo] = 1;
+    else  // XOR: the byte of this shot in the 4-byte word holding it
+      atomicXor(reinterpret_cast<uint32_t*>(w.fl + (fo & ~(int64_t)3)), 1u << (8 * (fo & 3)));
+  }
 }
 
 // Adds to L4[j] (pi for 4 shots) the messages m_{c->v} of the DV edges of

@@ -46,11 +46,14 @@ class Params(C.Structure):
     _fields_ = [("bp", C.c_int32), ("alpha", C.c_float), ("q", C.c_double), ("clamp", C.c_float),
                 ("iters", C.c_int32), ("rounds", C.c_int32), ("mask_density", C.c_double),
                 ("gauge", C.c_int32), ("evidence", C.c_int32), ("retire", C.c_int32),
-                ("seed", C.c_uint64), ("conflict", C.c_int32), ("skip_fixed", C.c_int32)]
+                ("seed", C.c_uint64), ("conflict", C.c_int32), ("skip_fixed", C.c_int32),
+                ("move", C.c_int32)]
 
 
 # LAIM_CONFLICT_*: how one round's move requests combine
 CONFLICT_RULES = {"or": 0, "xor": 1, "sequential": 2}
+# LAIM_MOVE_*: the local move of an acting check
+MOVES = {"single": 0, "multi": 1}
 
 
 class ResidentCfg(C.Structure):
@@ -88,16 +91,19 @@ class DecodeParams:
     seed: int = 0
     conflict: str = "or"  # "or", "xor" or "sequential"
     skip_fixed: bool = True  # skip sweeps once a shot's messages are a fixed point (same results)
+    move: str = "single"  # "single": LocalMove; "multi": every qubit of the check with L_v > 0
 
     def c(self) -> Params:
         if self.bp not in ("minsum", "sumproduct"):
             raise ValueError("bp must be 'minsum' or 'sumproduct'")
         if self.conflict not in CONFLICT_RULES:
             raise ValueError("conflict must be 'or', 'xor' or 'sequential'")
+        if self.move not in MOVES:
+            raise ValueError("move must be 'single' or 'multi'")
         return Params(1 if self.bp == "sumproduct" else 0, self.alpha, self.q, self.clamp,
                       self.iters, self.rounds, self.mask_density, int(self.gauge),
                       int(self.evidence), int(self.retire), self.seed, CONFLICT_RULES[self.conflict],
-                      int(self.skip_fixed))
+                      int(self.skip_fixed), MOVES[self.move])
 
 
 class ContinuousParamsC(C.Structure):

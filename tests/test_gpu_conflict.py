@@ -186,3 +186,86 @@ def test_batch_plan_and_server_with_mixed_rules(L, orc):
     for (i, k), r in results.items():
         assert np.array_equal(r["z"], singles[i]["z"][k].cpu().numpy()), (i, k)
         assert r["tclr"] == int(singles[i]["tclr"][k]), (i, k)
+
+
+MULTI_CASES = [  # code, bp, p, q, rounds, clock density
+    ("toric2d:8", "sumproduct", 0.06, 0.05, 32, 0.5),
+    ("toric2d:8", "minsum", 0.06, 0.05, 32, 1.0),
+    ("toric3d_point:3", "sumproduct", 0.04, 0.05, 16, 0.5),
+    ("toric3d_membrane:3", "sumproduct", 0.06, 0.125, 12, 0.9),
+    ("bb:6x6", "sumproduct", 0.03, 0.05, 32, 0.5),
+    ("bb:12x6", "minsum", 0.02, 0.05, 32, 1.0),
+    ("rep:15", "sumproduct", 0.2, 0.1, 16, 1.0),
+]
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+@pytest.mark.parametrize("rule", ["or", "xor"])
+@pytest.mark.parametrize("name,bp,p,q,R,rho", MULTI_CASES)
+def test_multi_qubit_moves_match_oracle(L, orc, name, bp, p, q, R, rho, rule, form):
+    """Multi-qubit moves (every qubit of an acting check with a positive
+    belief, else the LocalMove qubit), under OR and XOR, in both forms."""
+    code, dc = dcode(L, name)
+    e0 = orc.sample_noise(code, p, 6, 40, 211)
+    P = L.DecodeParams(bp=bp, q=q, rounds=R, mask_density=rho, conflict=rule, move="multi")
+    compare_decode(L, orc, name, P, e0, shot0=40, form=form, tag=f"multi {rule}")
+
+
+@pytest.mark.parametrize("form", ["resident", "stream"])
+def test_multi_qubit_moves_on_irregular_graphs(L, orc, form):
+    rng = np.random.default_rng(19)
+    H = np.zeros((24, 30), dtype=np.uint8)
+    for r in range(24):
+        H[r, rng.choice(30, size=int(rng.integers(1, 8)), replace=False)] = 1
+    for v in range(30):
+        if not H[:, v].any():
+            H[rng.integers(0, 24), v] = 1
+    for v in range(30):
+        for r in np.nonzero(H[:, v])[0][4:]:
+            H[r, v] = 0
+    mixed = codes.from_dense(H, name="mixed-multi")
+    if mixed.name not in _code_cache:
+        _code_cache[mixed.name] = (mixed, L.Code(mixed, 0))
+    e0 = orc.sample_noise(mixed, 0.15, 2, 0, 97)
+    for bp in ("minsum", "sumproduct"):
+        P = L.DecodeParams(bp=bp, q=0.1, rounds=12, mask_density=0.8, move="multi", retire=False)
+        compare_decode(L, orc, mixed.name, P, e0, form=form, tag="multi irregular")
+
+
+def test_multi_qubit_moves_in_plan_and_server_and_refused_sequentially(L, orc):
+    """The batched plan and the server run multi-qubit moves with the same
+    results as single launches; the sequential rule refuses them."""
+    import torch
+    items = []
+    for name, bp, p, q, R, rho in MULTI_CASES[:4]:
+        spec = codes.by_name(name)
+        code = L.Code(spec, 0)
+        P = L.DecodeParams(bp=bp, q=q, rounds=R, mask_density=rho, move="multi")
+        e0 = L.sample_noise(code, p, 3, 0, 120)
+        items.append({"spec": spec, "code": code, "params": P, "e0": e0, "shot0": 0})
+    outs = L.BatchPlan(items).launch()
+    torch.cuda.synchronize()
+    srv = L.Server(0, 1 << 26, 256)
+    tickets = {}
+    for j, it in enumerate(items):
+        ref = L.decode_rounds(it["code"], it["params"], it["e0"])
+        for k in ("z", "s", "tclr"):
+            assert torch.equal(outs[j][k], ref[k]), (it["spec"].name, k)
+        o = orc.decode(it["spec"], oracle_params(orc, it["params"]), it["e0"][:24].cpu().numpy(), nthreads=8)
+        assert np.array_equal(outs[j]["z"][:24].cpu().numpy(), o["z"]), it["spec"].name
+        for i in range(0, 120, 7):
+            tickets[srv.submit(it["code"], it["params"], i, it["e0"][i].cpu().numpy())] = (j, i)
+    done = 0
+    while done < len(tickets):
+        for ev in srv.step():
+            if ev["done"]:
+                j, i = tickets[ev["ticket"]]
+                r = srv.result(ev["ticket"])
+                assert np.array_equal(r["z"], outs[j]["z"][i].cpu().numpy()), (j, i)
+                assert r["tclr"] == int(outs[j]["tclr"][i]), (j, i)
+                done += 1
+    code, dc = dcode(L, "toric2d:6")
+    with pytest.raises(L.LaimError) as ei:
+        L.decode_rounds(dc, L.DecodeParams(move="multi", conflict="sequential"),
+                        torch.zeros((2, code.n), dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == L.EUNSUP

@@ -66,7 +66,8 @@ def pick_shots(tclr, fail, k=36, seed=0):
 def oracle_params(orc, P):
     return orc.DecodeParams(bp=P.bp, alpha=P.alpha, q=P.q, clamp=P.clamp, iters=P.iters,
                             rounds=P.rounds, mask_density=P.mask_density, gauge=P.gauge,
-                            evidence=P.evidence, retire=P.retire, seed=P.seed, conflict=P.conflict)
+                            evidence=P.evidence, retire=P.retire, seed=P.seed, conflict=P.conflict,
+                            move=P.move)
 
 
 def check_sampled(L, orc, spec, dc, P, e0, out, tag, shot0=0):

@@ -52,7 +52,8 @@ def gpu_e0(L, dc, e0_np):
 def oracle_params(orc, P):
     return orc.DecodeParams(bp=P.bp, alpha=P.alpha, q=P.q, clamp=P.clamp, iters=P.iters,
                             rounds=P.rounds, mask_density=P.mask_density, gauge=P.gauge,
-                            evidence=P.evidence, retire=P.retire, seed=P.seed, conflict=P.conflict)
+                            evidence=P.evidence, retire=P.retire, seed=P.seed, conflict=P.conflict,
+                            move=P.move)
 
 
 def compare_decode(L, orc, name, P, e0_np, shot0=0, form="auto", cfg=None, beliefs=True, tag=""):
