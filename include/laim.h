@@ -382,6 +382,69 @@ laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_
                                    int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
                                    double* L_out, laim_stream stream);
 
+/* -------------------------------------------------------- online decoding
+ * Online decoding (Discussion: faults and syndrome rounds keep arriving; the
+ * Tanner graph is promoted to a spacetime decoding graph and the local
+ * dynamics runs in overlapping spacetime windows). The paper fixes neither
+ * the noise nor the window rule; this library's:
+ *  - N syndrome rounds t = 1..N. Before round t each qubit gets a new Z
+ *    error e_t[v] ~ Bernoulli(p): word (v mod 4) of Philox(key = seed,
+ *    counter = (shot_lo, shot_hi, floor(v / 4), 16 t + 3)) below
+ *    floor(p 2^32). Round t measures H E_t ^ eps_t, E_t = e_1 ^ ... ^ e_t,
+ *    with measurement errors eps_t[c] ~ Bernoulli(p_meas) (word (c mod 4)
+ *    of Philox(seed, (shot_lo, shot_hi, floor(c / 4), 16 t + 4))); the last
+ *    round is perfect (eps_N = 0). seed is the decode parameters' seed.
+ *  - Detectors D_t = H e_t ^ eps_t ^ eps_{t-1} (eps_0 = 0).
+ *  - A window of w rounds is the code whose variables are the data errors
+ *    (tau, v) -> tau n + v and the measurement errors (tau, c) ->
+ *    w n + tau m + c of its rounds (not of a final perfect round), and whose
+ *    check tau m + c is detector (tau, c).
+ *  - Window k covers rounds k C + 1 .. min(k C + W, N); the last window is
+ *    the first that reaches N. Its syndrome is its rounds' detectors, with
+ *    the measurement corrections committed for round k C added to its
+ *    first round; the round machine (laim_decode_params, R = rounds per
+ *    window) decodes it from fresh messages, its rounds numbered from k R
+ *    for the clocks. Its first C rounds (every round, in the last window)
+ *    are committed: their data corrections add to z, and the measurement
+ *    corrections of its last committed round carry into the next window.
+ *  - Failure is the offline test (laim_logical_failure) on E_N and z.
+ */
+typedef struct {
+  int32_t rounds_total; /* N syndrome rounds (>= 1), the last one perfect */
+  int32_t window;       /* W rounds per window (>= 1) */
+  int32_t commit;       /* C rounds committed per window, 1 <= C <= W */
+  double p;             /* data error rate per qubit and round */
+  double p_meas;        /* measurement error rate per check and round */
+} laim_online_params;
+
+typedef struct laim_online_plan laim_online_plan;
+
+/* Builds the window codes of `code` for these parameters on the code's
+ * device (the plan keeps a pointer to code, which must outlive it). */
+laim_status laim_online_plan_create(const laim_code* code, const laim_online_params* op,
+                                    laim_online_plan** out);
+void laim_online_plan_destroy(laim_online_plan* plan);
+/* Workspace of laim_decode_online for nshots shots (0 for bad arguments). */
+size_t laim_online_workspace_bytes(const laim_online_plan* plan, const laim_decode_params* params,
+                                   int32_t nshots);
+/* laim_decode_online -- online decode of nshots shots (ids shot0 + i), all
+ * shots advancing window by window.
+ *   e_in, eps_in  device [nshots][N][n] and [nshots][N][m] uint8, or both
+ *                 NULL: the errors to use instead of sampled ones (the last
+ *                 round's eps_in is ignored: that round is perfect)
+ *   workspace     device, >= laim_online_workspace_bytes, 256-byte aligned
+ *   z_out         device [nshots][n]: the committed data correction
+ *   E_out         device [nshots][n] or NULL: the final error E_N
+ *   fail_out      device [nshots] or NULL: failure of (E_N, z)
+ *   cleared_out   device [nshots] int32 or NULL: windows whose syndrome cleared
+ * Errors: LAIM_EINVAL for bad arguments, LAIM_ENOMEM for a short workspace,
+ * as laim_decode_rounds for the parameters; nothing is launched then. */
+laim_status laim_decode_online(const laim_online_plan* plan, const laim_decode_params* params,
+                               uint64_t shot0, int32_t nshots, const uint8_t* e_in,
+                               const uint8_t* eps_in, void* workspace, size_t ws_bytes,
+                               uint8_t* z_out, uint8_t* E_out, uint8_t* fail_out,
+                               int32_t* cleared_out, laim_stream stream);
+
 /* ----------------------------------------------------------- batched form
  * One persistent launch over shots of several codes and sizes (each item a
  * contiguous range of shot ids of one code with its own parameters and

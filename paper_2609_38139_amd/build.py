@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblaim.so")
 SOURCES = ["laim_kernels.hip", "laim_stream.hip", "laim_ctm.hip", "laim_bitcentric.hip", "laim_host.cpp",
-           "laim_batch.cpp", "laim_static.hip"]
+           "laim_batch.cpp", "laim_static.hip", "laim_online.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -100,10 +100,14 @@ size_t resident_workspace_bytes();
 // sweeps[i] = iters x (rounds shot i ran), for the forms that run every sweep
 hipError_t launch_sweep_count(const KParams& kp, const int32_t* tclr, int32_t nshots, int32_t* sweeps,
                               hipStream_t st);
+// With s0 (start syndromes [nshots][m]) the shots start from s0 instead of
+// H e0 (e0 may then be null and fail must be null); r0 numbers the first
+// round for the clocks' random words.
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws,
                            uint8_t* z, uint8_t* s, int32_t* tclr, float* L, uint8_t* fail,
-                           int32_t* sweeps, hipStream_t st);
+                           int32_t* sweeps, hipStream_t st, const uint8_t* s0 = nullptr,
+                           int32_t r0 = 0);
 
 // laim_decode_rounds and its variants: validation, form choice and launch
 // (cfg non-null: the resident form with that launch shape).
@@ -116,7 +120,7 @@ laim_status decode_common(const laim_code* code, const laim_decode_params* param
 size_t stream_workspace_bytes(const DevCode& c, int32_t nshots, bool seq);
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
                          int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
-                         hipStream_t st);
+                         hipStream_t st, const uint8_t* s0 = nullptr, int32_t r0 = 0);
 
 // ---- multi-code kernels (batched plans and the serving loop)
 // Block-uniform description of a unit: the launch shape of one code, the

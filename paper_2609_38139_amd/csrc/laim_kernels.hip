@@ -281,6 +281,7 @@ struct GroupJob {
   int32_t r0;            // number of the first round run here (Philox counter)
   uint64_t shot;         // logical shot id
   const uint8_t* e0row;  // [n] initial error
+  const uint8_t* s0row;  // [m] start syndrome, or null: the start syndrome is H e0
   float* st_msg;         // resumable state or null: [m * dcmax] m_{c->v} in ELL order,
   uint8_t* st_z;         //   [n] correction, [m] syndrome,
   uint8_t* st_s;
@@ -320,6 +321,7 @@ __device__ __forceinline__ GroupJob dead_job() {
   j.r0 = 0;
   j.shot = 0;
   j.e0row = nullptr;
+  j.s0row = nullptr;
   j.st_msg = nullptr;
   j.st_z = j.st_s = nullptr;
   j.st_hdr = nullptr;
@@ -445,8 +447,12 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       } else {
         for (int j = 0; j < DC; ++j) msg[msg_word<DC>(ch, j)] = 0.0f;
         if (alive) {
-          const int32_t d = c.chk_deg[ch];
-          for (int32_t j = 0; j < d; ++j) x ^= job.e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
+          if (job.s0row) {
+            x = job.s0row[ch];
+          } else {
+            const int32_t d = c.chk_deg[ch];
+            for (int32_t j = 0; j < d; ++j) x ^= job.e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
+          }
         }
       }
       sb |= (x & 1u) << k;
@@ -992,7 +998,9 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 // ---- the single-code persistent kernel
 struct ResArgs {
   UnitCtx u;
-  const uint8_t* e0;
+  const uint8_t* e0;  // [nshots][n] initial errors, or null when s0 is given
+  const uint8_t* s0;  // [nshots][m] start syndromes, or null: H e0
+  int32_t r0;         // number of the first round (the clocks' Philox counter)
   uint64_t shot0;
   int32_t nshots;
   uint32_t* counter;  // queue head, zeroed before the launch
@@ -1008,6 +1016,8 @@ struct ResJobs {
   // copied by value: taking the address of a kernel argument would force it
   // into scratch memory
   const uint8_t* e0;
+  const uint8_t* s0;
+  int32_t r0;
   uint64_t shot0;
   int32_t nshots, n, m, base;
   uint8_t* z;
@@ -1031,9 +1041,10 @@ struct ResJobs {
     const int32_t idx = base + g;
     if (idx >= nshots) return j;
     j.alive = 1;
-    j.r0 = 0;
+    j.r0 = r0;
     j.shot = shot0 + (uint64_t)idx;
-    j.e0row = e0 + (int64_t)idx * n;
+    j.e0row = e0 ? e0 + (int64_t)idx * n : nullptr;
+    j.s0row = s0 ? s0 + (int64_t)idx * m : nullptr;
     j.z_out = z + (int64_t)idx * n;
     j.s_out = s + (int64_t)idx * m;
     j.t_out = tclr + idx;
@@ -1050,8 +1061,8 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
   // control words after the groups, so that group 0's messages start at
   // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
-  ResJobs jobs{a.e0,   a.shot0, a.nshots, c.n,      c.m,      0,        a.z,
-               a.s,    a.tclr,  a.L,      a.fail,   a.sweeps, a.counter, a.u.spb};
+  ResJobs jobs{a.e0,   a.s0,   a.r0,     a.shot0,  a.nshots, c.n,       c.m,     0,
+               a.z,    a.s,    a.tclr,   a.L,      a.fail,   a.sweeps,  a.counter, a.u.spb};
   run_units<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
 }
 
@@ -1427,7 +1438,8 @@ size_t resident_workspace_bytes() { return 256; }
 hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                            const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
                            uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, int32_t* sweeps,
-                           hipStream_t st) {
+                           hipStream_t st, const uint8_t* s0, int32_t r0) {
+  if (s0 && fail) return hipErrorInvalidValue;  // the failure test needs e0
   if (nshots <= 0) return hipSuccess;
   // the degrees the shape was sized for; the exact qubit-degree-2 min-sum
   // variants skip a clamp, so the shape must have allowed them
@@ -1444,6 +1456,8 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.u.resume = 0;
   a.u.events = 0;
   a.e0 = e0;
+  a.s0 = s0;
+  a.r0 = r0;
   a.shot0 = shot0;
   a.nshots = nshots;
   a.counter = reinterpret_cast<uint32_t*>(ws);

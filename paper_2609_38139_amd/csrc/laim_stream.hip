@@ -127,9 +127,10 @@ __global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w) {
   st4b(w.fl + o, 0u);
 }
 
-// Shot start: s = H e0 and messages 0 (shots beyond nshots get s = 0).
+// Shot start: s = H e0 (or s0 when given) and messages 0 (shots beyond
+// nshots get s = 0).
 __global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, const uint8_t* e0,
-                                                       int32_t nshots) {
+                                                       const uint8_t* s0, int32_t nshots) {
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
@@ -141,7 +142,10 @@ __global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, co
     const int64_t i = tile * kStreamTile + kSV * lane + q;
     if (i >= nshots) continue;
     uint32_t x = 0;
-    for (int32_t j = 0; j < d; ++j) x ^= e0[i * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]];
+    if (s0)
+      x = s0[i * c.m + ch];
+    else
+      for (int32_t j = 0; j < d; ++j) x ^= e0[i * c.n + c.chk_var[(int64_t)ch * c.dcmax + j]];
     x &= 1u;
     x4 |= x << (8 * q);
     if (x) w.anys[i] = 1u;
@@ -677,7 +681,7 @@ static void stream_fns(int dcmax, SweepFn* sw, MovesFn* mv) {
 
 hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0, uint64_t shot0,
                          int32_t nshots, void* ws, uint8_t* z, uint8_t* s, int32_t* tclr, float* L,
-                         hipStream_t st) {
+                         hipStream_t st, const uint8_t* s0, int32_t r0) {
   if (nshots <= 0) return hipSuccess;
   SweepFn sweep_fn;
   MovesFn moves_fn;
@@ -693,7 +697,7 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
   hipLaunchKernelGGL(stream_clear_shots, dim3((unsigned)((ntot + 255) / 256)), blk, 0, st, w, nshots,
                      ntot);
   hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w);
-  hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, nshots);
+  hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, s0, nshots);
   hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, -1, nshots);
   int cur = 0;
   bool fresh = true;
@@ -706,7 +710,7 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
       cur ^= 1;
       fresh = false;
     }
-    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r, fresh ? 1 : 0, shot0);
+    hipLaunchKernelGGL(moves_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], r0 + r, fresh ? 1 : 0, shot0);
     if (seq) hipLaunchKernelGGL(stream_resolve, dim3(ntile), dim3(kStreamTile), 0, st, c, w);
     hipLaunchKernelGGL(stream_syndrome, gchk, blk, 0, st, c, w);
     hipLaunchKernelGGL(stream_apply, gvar, blk, 0, st, c, w);

@@ -30,7 +30,8 @@ SYMBOLS = [
     "laim_logical_failure", "laim_batch_plan_create", "laim_batch_plan_launch",
     "laim_batch_plan_destroy", "laim_server_create", "laim_server_submit", "laim_server_step",
     "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
-    "laim_decode_bitcentric", "laim_decode_rounds_static",
+    "laim_decode_bitcentric", "laim_decode_rounds_static", "laim_online_plan_create",
+    "laim_online_plan_destroy", "laim_online_workspace_bytes", "laim_decode_online",
 ]
 
 STATIC_SCRATCH_BYTES = 32 << 20  # LAIM_STATIC_SCRATCH_BYTES
@@ -136,6 +137,27 @@ class ContinuousParams:
                                  int(self.skip_fixed))
 
 
+class OnlineParamsC(C.Structure):
+    _fields_ = [("rounds_total", C.c_int32), ("window", C.c_int32), ("commit", C.c_int32),
+                ("p", C.c_double), ("p_meas", C.c_double)]
+
+
+@dataclass
+class OnlineParams:
+    """Online decoding: N syndrome rounds (the last one perfect), windows of
+    W rounds of which the first C are committed, data and measurement error
+    rates."""
+
+    rounds_total: int = 8
+    window: int = 4
+    commit: int = 2
+    p: float = 0.01
+    p_meas: float = 0.01
+
+    def c(self) -> OnlineParamsC:
+        return OnlineParamsC(self.rounds_total, self.window, self.commit, self.p, self.p_meas)
+
+
 CONTINUOUS_WORKSPACE_BYTES = 256
 
 _lib = None
@@ -187,6 +209,12 @@ def lib():
         L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
         L.laim_decode_rounds_static.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, vp, vp, vp,
                                                 vp, vp, i32, vp]
+        L.laim_online_plan_create.argtypes = [vp, C.POINTER(OnlineParamsC), C.POINTER(vp)]
+        L.laim_online_plan_destroy.argtypes = [vp]
+        L.laim_online_plan_destroy.restype = None
+        L.laim_online_workspace_bytes.argtypes = [vp, C.POINTER(Params), i32]
+        L.laim_online_workspace_bytes.restype = sz
+        L.laim_decode_online.argtypes = [vp, C.POINTER(Params), u64, i32, vp, vp, vp, sz, vp, vp, vp, vp, vp]
         L.laim_server_destroy.restype = None
         _lib = L
     return _lib
@@ -431,6 +459,58 @@ def logical_failure(code: Code, e0, z, stream=None):
     check(lib().laim_logical_failure(code.handle, _ptr(e0), _ptr(z), ns, _ptr(f), _stream(stream)),
           "laim_logical_failure")
     return f
+
+
+class OnlinePlan:
+    """``laim_online_plan_*``: the window codes of one code for online
+    decoding with these OnlineParams."""
+
+    def __init__(self, code: Code, op: OnlineParams):
+        self.code = code
+        self.op = op
+        O = op.c()
+        h = C.c_void_p()
+        check(lib().laim_online_plan_create(code.handle, C.byref(O), C.byref(h)), "laim_online_plan_create")
+        self.handle = h
+
+    def workspace_bytes(self, params: DecodeParams, nshots: int) -> int:
+        P = params.c()
+        return int(lib().laim_online_workspace_bytes(self.handle, C.byref(P), nshots))
+
+    def decode(self, params: DecodeParams, nshots: int, shot0: int = 0, e_in=None, eps_in=None,
+               workspace=None, want_E: bool = True, want_fail: bool = True, want_cleared: bool = True,
+               stream=None) -> dict:
+        """``laim_decode_online``: device tensors z [nshots, n] and, as asked,
+        E (the final error), fail and cleared (windows that cleared)."""
+        import torch
+        code = self.code
+        dev = f"cuda:{code.device}"
+        N = self.op.rounds_total
+        if (e_in is None) != (eps_in is None):
+            raise ValueError("give both e_in and eps_in or neither")
+        if e_in is not None:
+            _dev(e_in, torch.uint8, (nshots, N, code.n), "e_in")
+            _dev(eps_in, torch.uint8, (nshots, N, code.m), "eps_in")
+        out = {"z": torch.empty((nshots, code.n), dtype=torch.uint8, device=dev),
+               "E": torch.empty((nshots, code.n), dtype=torch.uint8, device=dev) if want_E else None,
+               "fail": torch.empty((nshots,), dtype=torch.uint8, device=dev) if want_fail else None,
+               "cleared": torch.empty((nshots,), dtype=torch.int32, device=dev) if want_cleared else None}
+        need = self.workspace_bytes(params, nshots)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty((max(need, 256),), dtype=torch.uint8, device=dev)
+        P = params.c()
+        check(lib().laim_decode_online(self.handle, C.byref(P), shot0, nshots, _ptr(e_in), _ptr(eps_in),
+                                       _ptr(workspace), workspace.numel(), _ptr(out["z"]), _ptr(out["E"]),
+                                       _ptr(out["fail"]), _ptr(out["cleared"]), _stream(stream)),
+              "laim_decode_online")
+        out["workspace"] = workspace
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.laim_online_plan_destroy(h)
+            self.handle = None
 
 
 class BatchPlan:

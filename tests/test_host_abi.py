@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(laim):
 
 STRUCTS = {"laim_decode_params": "Params", "laim_resident_cfg": "ResidentCfg",
            "laim_continuous_params": "ContinuousParamsC", "laim_batch_item": "BatchItem",
-           "laim_server_event": "ServerEvent"}
+           "laim_server_event": "ServerEvent", "laim_online_params": "OnlineParamsC"}
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):
