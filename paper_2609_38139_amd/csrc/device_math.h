@@ -69,13 +69,16 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 // a head with 16 significant bits, so k*head is exact, and a tail), the
 // degree-7 Taylor polynomial of e^r in Horner form with one fused
 // multiply-add (v_fma_f32, a single rounding) per step, and a 2^k scale
-// built in the exponent field. Arguments above 80 (and +inf) give 0.
+// built in the exponent field. Arguments above 80 (and +inf) give 0. The
+// evaluation has no branch: an argument above 80 is evaluated as 80 and the
+// result then replaced by 0, so every lane runs the same instructions and
+// the results for a <= 80 are those of the plain sequence.
 __device__ __forceinline__ float exp_neg(float a) {
-  if (!(a <= 80.0f)) return 0.0f;
+  const bool big = !(a <= 80.0f);
   const float ln2_hi = __uint_as_float(0x3F317200u);
   const float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
   const float log2e = (float)1.44269504088896340736;
-  const float x = -a;
+  const float x = -(big ? 80.0f : a);
   const float kf = floorf(fmaf(x, log2e, 0.5f));
   const float r = fmaf(-kf, ln2_lo, fmaf(-kf, ln2_hi, x));
   float p = 1.0f / 5040.0f;
@@ -87,7 +90,8 @@ __device__ __forceinline__ float exp_neg(float a) {
   p = fmaf(p, r, 1.0f);
   p = fmaf(p, r, 1.0f);
   const int k = (int)kf;
-  return p * __uint_as_float((uint32_t)(k + 127) << 23);
+  const float v = p * __uint_as_float((uint32_t)(k + 127) << 23);
+  return big ? 0.0f : v;
 }
 
 // log(1 + u) for u in [0, 1] as u Q(u), Q the degree-9 polynomial that
