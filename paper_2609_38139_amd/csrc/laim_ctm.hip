@@ -18,7 +18,7 @@
 // checks t + k nt (k < CPT); it keeps the m_{v->c} and m_{c->v} of its
 // checks' edges in registers and publishes m_{c->v} in LDS, in tiles of 64
 // checks with a 65-word slot stride, for the partner gathers. Events are
-// handled by thread 0 between Euler steps.
+// handled by the first wavefront between Euler steps.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -151,41 +151,58 @@ __device__ __forceinline__ void ctm_check_rule(const CtmParamsDev& P, const floa
   }
 }
 
-// Every event due by time tk, in order (thread 0 of the block). State in
-// the scratch words: |S|, event counter j, pending event time, counts.
+// Every event due by time tk, in order, handled by the first wavefront of
+// the block (nl = min(64, block size) lanes). Every lane keeps the same
+// event state (|S|, event counter, pending time, counts; identical
+// arithmetic in each). The search for the ringing check is spread over the
+// lanes: lane l counts the active checks of syndrome words l, l + nl, ...,
+// and a prefix sum over the lanes finds the word holding it. Lane 0 applies
+// the flip to the LDS bitmaps; the wavefront executes in order, so the next
+// event's search sees it.
 template <int DC, bool REG>
 __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t shot, double tk,
-                           const float* msg, int32_t* gw, uint32_t* zw, uint32_t* sw) {
+                           const float* msg, int32_t* gw, uint32_t* zw, uint32_t* sw, int32_t nl) {
+  const int32_t lane = threadIdx.x;
   int32_t nS = gw[kCwNs];
   uint32_t j = (uint32_t)gw[kCwJ];
   int32_t events = gw[kCwEvents], moves = gw[kCwMoves];
-  double Tev = *reinterpret_cast<double*>(gw + kCwTev);
+  double Tev = *reinterpret_cast<const double*>(gw + kCwTev);
   const int32_t mw = (c.m + 31) >> 5;
   int32_t moved = 0;
   while (nS > 0 && Tev <= tk) {
     const Philox4 w = ctm_words(P, shot, j);
     uint32_t idx = (uint32_t)(((uint64_t)w.w1 * (uint64_t)nS) >> 32);
+    // the idx-th active check in ascending order
     int32_t ch = -1;
-    for (int32_t q = 0; q < mw && ch < 0; ++q) {
-      uint32_t word = sw[q];
+    for (int32_t base = 0; base < mw && ch < 0; base += nl) {
+      const int32_t q = base + lane;
+      const uint32_t word = (q < mw) ? sw[q] : 0u;
       const uint32_t pc = (uint32_t)__popc(word);
-      if (idx >= pc) {
-        idx -= pc;
+      uint32_t incl = pc;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      const uint32_t total = __shfl(incl, nl - 1);
+      if (idx >= total) {
+        idx -= total;
         continue;
       }
-      for (;;) {
-        const int32_t bpos = __builtin_ctz(word);
-        if (idx == 0) {
-          ch = q * 32 + bpos;
-          break;
-        }
-        --idx;
-        word &= word - 1u;
+      const bool mine = idx >= incl - pc && idx < incl;
+      const int32_t src = (int32_t)__builtin_ctzll(__ballot(mine));
+      int32_t bpos = 0;
+      if (mine) {
+        uint32_t wd = word;
+        for (uint32_t r = idx - (incl - pc); r > 0; --r) wd &= wd - 1u;
+        bpos = __builtin_ctz(wd);
       }
+      ch = (base + src) * 32 + __shfl(bpos, src);
     }
     int32_t chosen = -1;
     const int32_t d = (ch >= 0) ? (REG ? DC : c.chk_deg[ch]) : 0;
     if (d > 0) {
+      // the beliefs of the check's qubits (every lane the same)
       const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
       float Lv[DC];
       float Lmax = 0.0f;
@@ -221,31 +238,39 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
       }
     }
     if (chosen >= 0) {
-      zw[chosen >> 5] ^= 1u << (chosen & 31);
-      const int32_t dv = c.var_deg[chosen];
-      for (int32_t q = 0; q < dv; ++q) {
-        const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
-        const uint32_t bit = 1u << (c2 & 31);
-        sw[c2 >> 5] ^= bit;
-        nS += (sw[c2 >> 5] & bit) ? 1 : -1;
+      int32_t nS_new = nS;
+      if (lane == 0) {
+        zw[chosen >> 5] ^= 1u << (chosen & 31);
+        const int32_t dv = c.var_deg[chosen];
+        for (int32_t q = 0; q < dv; ++q) {
+          const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
+          const uint32_t bit = 1u << (c2 & 31);
+          const uint32_t nw2 = sw[c2 >> 5] ^ bit;
+          sw[c2 >> 5] = nw2;
+          nS_new += (nw2 & bit) ? 1 : -1;
+        }
       }
+      __builtin_amdgcn_wave_barrier();
+      nS = __shfl(nS_new, 0);
       ++moves;
       moved = 1;
     }
     ++events;
     ++j;
     if (nS == 0) {
-      *reinterpret_cast<double*>(gw + kCwClear) = Tev;
+      if (lane == 0) *reinterpret_cast<double*>(gw + kCwClear) = Tev;
       break;
     }
     Tev = Tev + ctm_wait(ctm_words(P, shot, j).w0, nS);
   }
-  gw[kCwNs] = nS;
-  gw[kCwJ] = (int32_t)j;
-  gw[kCwEvents] = events;
-  gw[kCwMoves] = moves;
-  gw[kCwMoved] = moved;
-  *reinterpret_cast<double*>(gw + kCwTev) = Tev;
+  if (lane == 0) {
+    gw[kCwNs] = nS;
+    gw[kCwJ] = (int32_t)j;
+    gw[kCwEvents] = events;
+    gw[kCwMoves] = moves;
+    gw[kCwMoved] = moved;
+    *reinterpret_cast<double*>(gw + kCwTev) = Tev;
+  }
 }
 
 }  // namespace
@@ -363,7 +388,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
     int32_t k = 0;
     for (;; ++k) {
       if (nS > 0 && k >= kev) {
-        if (t == 0) ctm_events<DC, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw);
+        if (t < 64) ctm_events<DC, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw, nt < 64 ? nt : 64);
         __syncthreads();
         nS = gw[kCwNs];
         Tev = *reinterpret_cast<const double*>(gw + kCwTev);
