@@ -78,13 +78,19 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
   }
   *out = nullptr;
   const int device = items[0].code ? items[0].code->device : 0;
-  struct PerBp {
-    std::vector<BatchItemDev> items;
-    std::vector<BatchUnitDev> units;
-    std::vector<double> cost;
-    size_t lds = 0;
-    int block = 0;
-  } per[2];
+  // Items that run resident are grouped by code and parameters: each group
+  // is one persistent launch of the resident kernel specialised for that
+  // code (its own launch shape, registers and LDS), walking the shots of all
+  // its items from one queue.
+  struct Group {
+    const laim_code* code;
+    KParams kp;
+    ResidentShape sh;
+    std::vector<GroupItemDev> items;
+    int32_t total = 0;
+    double cost = 0.0;
+  };
+  std::vector<Group> groups;
   std::vector<int> fallback_fail;  // items whose failure test runs in its own kernel
   struct StreamItem {
     int32_t index;
@@ -102,50 +108,49 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
       set_error("batch item %d: every code must live on the same device", i);
       return LAIM_EINVAL;
     }
-    BatchItemDev it;
-    size_t lds = 0;
-    int block = 0;
-    laim_status st = make_item(b.code, &b.params, &it, &lds, &block);
-    if (st == LAIM_EUNSUP) {
+    KParams kp = {};  // zero padding: groups compare the whole struct
+    laim_status st = resolve_params(&b.params, &kp);
+    if (st != LAIM_OK) return st;
+    ResidentShape sh;
+    const laim_resident_cfg* want = b.code->has_cfg[kp.bp] ? &b.code->cfg[kp.bp] : nullptr;
+    const bool resident = !(kp.bp == 0 && kp.alpha > 1.0f) &&
+                          resident_shape(b.code->dev, kp.bp, want, &sh, device,
+                                         kp.conflict == kConflictSequential, reg_dv2_ok(kp));
+    if (!resident) {
       // no resident variant (the shot's state exceeds the LDS, degrees
       // beyond the compiled variants, or min-sum with alpha > 1): the item
       // runs in the stream form, recorded in the same graph
-      KParams kp;
-      if (resolve_params(&b.params, &kp) != LAIM_OK) return LAIM_EINVAL;
       stream_items.push_back({i, kp});
       continue;
     }
-    if (st != LAIM_OK) return st;
+    if (b.nshots == 0) continue;
+    Group* g = nullptr;
+    for (auto& gg : groups)
+      if (gg.code == b.code && memcmp(&gg.kp, &kp, sizeof(KParams)) == 0) g = &gg;
+    if (!g) {
+      groups.push_back(Group{b.code, kp, sh, {}, 0, 0.0});
+      g = &groups.back();
+    }
+    GroupItemDev it;
     it.e0 = b.e0;
     it.shot0 = b.shot0;
+    it.first = g->total;
     it.nshots = b.nshots;
     it.z = b.z_out;
     it.s = b.s_out;
     it.tclr = b.tclr_out;
     it.fail = (b.fail_out && b.code->dev.kw <= 4) ? b.fail_out : nullptr;
     if (b.fail_out && !it.fail) fallback_fail.push_back(i);
-    PerBp& P = per[it.kp.bp];
-    const int32_t idx = (int32_t)P.items.size();
-    P.items.push_back(it);
-    P.lds = std::max(P.lds, lds);
-    P.block = std::max(P.block, block);
-    // cost of a unit ~ the work of one of its threads
-    const double cost = (double)it.kp.rounds * std::max(it.kp.iters, 1) *
-                        ((double)b.code->E / std::max(it.u.nt, 1));
-    for (int32_t base = 0; base < b.nshots; base += it.u.spb) {
-      P.units.push_back(BatchUnitDev{idx, base});
-      P.cost.push_back(cost);
+    g->items.push_back(it);
+    if ((int64_t)g->total + b.nshots > INT32_MAX) {
+      set_error("more than 2^31 - 1 shots of one code in a plan");
+      return LAIM_EINVAL;
     }
+    g->total += b.nshots;
+    g->cost += (double)b.nshots * kp.rounds * std::max(kp.iters, 1) * b.code->E;
   }
-  // longest work first
-  for (auto& P : per) {
-    std::vector<size_t> ord(P.units.size());
-    for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return P.cost[a] > P.cost[b]; });
-    std::vector<BatchUnitDev> u2;
-    for (size_t k : ord) u2.push_back(P.units[k]);
-    P.units.swap(u2);
-  }
+  // the largest groups first
+  std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
   laim_batch_plan* plan = new (std::nothrow) laim_batch_plan();
   if (!plan) {
     set_error("out of host memory");
@@ -153,15 +158,11 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
   }
   plan->device = device;
   DeviceGuard g(device);
-  size_t off[2][3];
+  std::vector<size_t> goff;
   size_t total = 0;
-  for (int bp = 0; bp < 2; ++bp) {
-    off[bp][0] = total;
-    total += al256(per[bp].items.size() * sizeof(BatchItemDev));
-    off[bp][1] = total;
-    total += al256(per[bp].units.size() * sizeof(BatchUnitDev));
-    off[bp][2] = total;
-    total += 256;
+  for (const Group& gr : groups) {
+    goff.push_back(total);
+    total += 256 + al256(gr.items.size() * sizeof(GroupItemDev));  // queue word, then the item table
   }
   std::vector<size_t> stream_off;
   for (const StreamItem& si : stream_items) {
@@ -170,35 +171,22 @@ laim_status laim_batch_plan_create(const laim_batch_item* items, int32_t nitems,
     total += al256(stream_workspace_bytes(b.code->dev, b.nshots,
                                           si.kp.conflict == kConflictSequential));
   }
-  hipError_t e = hipMalloc(&plan->dev_mem, total);
+  hipError_t e = hipMalloc(&plan->dev_mem, std::max<size_t>(total, 256));
   if (e != hipSuccess) {
     delete plan;
     set_error("hipMalloc of %zu bytes for the plan failed", total);
     return LAIM_ENOMEM;
   }
   char* base = (char*)plan->dev_mem;
-  for (int bp = 0; bp < 2 && e == hipSuccess; ++bp) {
-    if (!per[bp].items.empty())
-      e = hipMemcpy(base + off[bp][0], per[bp].items.data(), per[bp].items.size() * sizeof(BatchItemDev),
-                    hipMemcpyHostToDevice);
-    if (e == hipSuccess && !per[bp].units.empty())
-      e = hipMemcpy(base + off[bp][1], per[bp].units.data(), per[bp].units.size() * sizeof(BatchUnitDev),
-                    hipMemcpyHostToDevice);
-  }
+  for (size_t k = 0; k < groups.size() && e == hipSuccess; ++k)
+    e = hipMemcpy(base + goff[k] + 256, groups[k].items.data(), groups[k].items.size() * sizeof(GroupItemDev),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreate(&plan->cap);
   if (e == hipSuccess) e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
-  for (int bp = 0; bp < 2 && e == hipSuccess; ++bp) {
-    PerBp& P = per[bp];
-    if (P.units.empty()) continue;
-    const int per_cu = batch_blocks_per_cu(bp, P.block, P.lds);
-    if (per_cu < 1) {
-      e = hipErrorInvalidConfiguration;
-      break;
-    }
-    const int grid = (int)std::min<size_t>(P.units.size(), (size_t)per_cu * cu_count(device));
-    e = launch_batch(bp, (const BatchItemDev*)(base + off[bp][0]),
-                     (const BatchUnitDev*)(base + off[bp][1]), (int32_t)P.units.size(),
-                     (uint32_t*)(base + off[bp][2]), P.lds, P.block, grid, plan->cap);
+  for (size_t k = 0; k < groups.size() && e == hipSuccess; ++k) {
+    const Group& gr = groups[k];
+    e = launch_resident_group(gr.code->dev, gr.kp, gr.sh, (const GroupItemDev*)(base + goff[k] + 256),
+                              (int32_t)gr.items.size(), gr.total, base + goff[k], plan->cap);
   }
   for (int i : fallback_fail) {
     if (e != hipSuccess) break;

@@ -146,9 +146,17 @@ struct BatchItemDev {
   uint8_t* fail;
 };
 
-struct BatchUnitDev {
-  int32_t item;
-  int32_t base;  // first shot index of the unit within the item
+// One item of a grouped resident launch (several shot ranges of one code
+// and parameters in one persistent launch): shots first .. first + nshots - 1
+// of the launch's shot index are this item's shots 0 .. nshots - 1.
+struct GroupItemDev {
+  const uint8_t* e0;
+  uint64_t shot0;
+  int32_t first, nshots;
+  uint8_t* z;
+  uint8_t* s;
+  int32_t* tclr;
+  uint8_t* fail;  // or null
 };
 
 struct ServerUnitDev {
@@ -174,10 +182,13 @@ struct ServerReqDev {
 
 bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int device, bool seq,
                    bool reg2, UnitCtx* u, int* variant, size_t* lds, int* block);
-hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
-                        int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
-                        hipStream_t st);
-int batch_blocks_per_cu(int bp, int block, size_t lds);
+// One persistent resident launch over the shots of several items of one
+// code and parameters (items [nitems] in device memory, total shots in
+// all); ws holds the shot queue (resident_workspace_bytes). With a fail
+// pointer the code must have at most 128 logicals.
+hipError_t launch_resident_group(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                                 const GroupItemDev* items, int32_t nitems, int32_t total, void* ws,
+                                 hipStream_t st);
 hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev* units,
                          int32_t nunits, const ServerReqDev* reqs, size_t lds, int block,
                          hipStream_t st);

@@ -259,9 +259,10 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // fixed offsets (immediate operands of the LDS writes) and neighbouring
 // checks' messages in different slots fall in different banks. After the
 // messages come a few scratch words -- the first holds -0.0, which padded
-// qubit-side partners point at (x + (-0.0) == x for every x) -- and three
+// qubit-side partners point at (x + (-0.0) == x for every x) -- and four
 // bitmaps: flip requests of the current feedback step (n bits), the
-// correction z (n bits) and the syndrome s (m bits). A shot either
+// correction z (n bits), the syndrome s (m bits) and the initial error
+// (n bits). A shot either
 // starts fresh from its initial error or resumes from state saved in device
 // memory (used by the serving loop, which runs one round per launch).
 // ====================================================================
@@ -365,10 +366,11 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   uint32_t* flw = reinterpret_cast<uint32_t*>(gw + kGroupWords);  // [nw] flip requests
   uint32_t* zw = flw + nw;                                         // [nw] correction
   uint32_t* sw = zw + nw;                                          // [(m + 31) / 32] syndrome
+  uint32_t* e0w = sw + ((c.m + 31) >> 5);                          // [nw] initial error
   // sequential conflict rule only: ring time and request byte per check
   // (bits 0-6 the slot of the requested qubit, kNoRequest if none; bit 7
   // whether the request applies)
-  uint32_t* rkey = sw + ((c.m + 31) >> 5);                         // [m]
+  uint32_t* rkey = e0w + nw;                                       // [m]
   uint8_t* rq = reinterpret_cast<uint8_t*>(rkey + c.m);            // [m]
   const float C = kp.clamp;
   const float pi = kp.pi;
@@ -404,7 +406,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 
   while (src.next(ctrl)) {
   const Src& job_at = src;
-  // The job is read three times (here, at the start and for the results)
+  // The job is read several times (here, at the start and for the results)
   // rather than kept in registers through the rounds: only the shot id and
   // first round live on.
   bool alive;
@@ -427,7 +429,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       for (int w = 1; w < kGroupWords; ++w) gw[w] = 0;
     }
 #pragma unroll 1
-    for (int32_t w = t; w < 2 * nw + ((c.m + 31) >> 5); w += u.nt) flw[w] = 0u;
+    for (int32_t w = t; w < 3 * nw + ((c.m + 31) >> 5); w += u.nt) flw[w] = 0u;
     if (kp.conflict == kConflictSequential) {
 #pragma unroll 1
       for (int32_t ch = t; ch < c.m; ch += u.nt) rq[ch] = kNoRequest;
@@ -435,24 +437,44 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll 1
     for (int k = 0; k < CPT; ++k) {
       const int32_t ch = t + k * u.nt;
-      if (ch >= c.m) {  // a padding check
-        for (int j = 0; j < DC; ++j) msg[msg_word<DC>(ch, j)] = 0.0f;
-        continue;
+      float* mk = msg + msg_word<DC>(ch, 0);
+      if (u.resume && alive && ch < c.m) {
+        for (int j = 0; j < DC; ++j)
+          mk[j * kSlotStride] = (j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
+      } else {  // fresh start, or a padding check
+        for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = 0.0f;
       }
+    }
+  }
+  __syncthreads();
+  // the initial error as an LDS bitmap, read once from HBM (consecutive
+  // threads read consecutive bytes); the syndrome of a fresh start and the
+  // failure test at the end take it from there
+  if (member && alive) {
+    const GroupJob job = job_at(g);
+    if (job.e0row) {
+#pragma unroll 1
+      for (int32_t v = t; v < c.n; v += u.nt)
+        if (job.e0row[v] & 1u) atomicOr(&e0w[v >> 5], 1u << (v & 31));
+    }
+  }
+  __syncthreads();
+  if (member && alive) {
+    const GroupJob job = job_at(g);
+#pragma unroll 1
+    for (int k = 0; k < CPT; ++k) {
+      const int32_t ch = t + k * u.nt;
+      if (ch >= c.m) continue;
       uint32_t x = 0;
       if (u.resume) {
-        for (int j = 0; j < DC; ++j)
-          msg[msg_word<DC>(ch, j)] = (alive && j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
-        if (alive) x = job.st_s[ch] & 1u;
+        x = job.st_s[ch];
+      } else if (job.s0row) {
+        x = job.s0row[ch];
       } else {
-        for (int j = 0; j < DC; ++j) msg[msg_word<DC>(ch, j)] = 0.0f;
-        if (alive) {
-          if (job.s0row) {
-            x = job.s0row[ch];
-          } else {
-            const int32_t d = c.chk_deg[ch];
-            for (int32_t j = 0; j < d; ++j) x ^= job.e0row[c.chk_var[(int64_t)ch * c.dcmax + j]];
-          }
+        const int32_t d = c.chk_deg[ch];
+        for (int32_t j = 0; j < d; ++j) {
+          const int32_t v = c.chk_var[(int64_t)ch * c.dcmax + j];
+          x ^= e0w[v >> 5] >> (v & 31);
         }
       }
       sb |= (x & 1u) << k;
@@ -967,11 +989,15 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     if (job.f_out || job.ev_out) {
       uint32_t lp[kFusedMaxWords] = {0u, 0u, 0u, 0u};
 #pragma unroll 1
-      for (int32_t v = t; v < c.n; v += u.nt) {
-        if (!((job.e0row[v] ^ (zw[v >> 5] >> (v & 31))) & 1u)) continue;
+      for (int32_t wq = t; wq < nw; wq += u.nt) {
+        uint32_t r = e0w[wq] ^ zw[wq];
+        while (r) {
+          const int32_t v = (wq << 5) + __builtin_ctz(r);
+          r &= r - 1u;
 #pragma unroll
-        for (int w = 0; w < kFusedMaxWords; ++w)
-          if (w < c.kw) lp[w] ^= c.lcol[(int64_t)v * c.kw + w];
+          for (int w = 0; w < kFusedMaxWords; ++w)
+            if (w < c.kw) lp[w] ^= c.lcol[(int64_t)v * c.kw + w];
+        }
       }
 #pragma unroll
       for (int w = 0; w < kFusedMaxWords; ++w)
@@ -998,6 +1024,8 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 // ---- the single-code persistent kernel
 struct ResArgs {
   UnitCtx u;
+  const GroupItemDev* items;  // [nitems] or null: a single item given by the fields below
+  int32_t nitems;
   const uint8_t* e0;  // [nshots][n] initial errors, or null when s0 is given
   const uint8_t* s0;  // [nshots][m] start syndromes, or null: H e0
   int32_t r0;         // number of the first round (the clocks' Philox counter)
@@ -1015,6 +1043,8 @@ struct ResArgs {
 struct ResJobs {
   // copied by value: taking the address of a kernel argument would force it
   // into scratch memory
+  const GroupItemDev* items;
+  int32_t nitems;
   const uint8_t* e0;
   const uint8_t* s0;
   int32_t r0;
@@ -1040,6 +1070,22 @@ struct ResJobs {
     GroupJob j = dead_job();
     const int32_t idx = base + g;
     if (idx >= nshots) return j;
+    if (items) {
+      // the item holding launch shot idx (items ascend in `first`)
+      int32_t it = 0;
+      while (it + 1 < nitems && items[it + 1].first <= idx) ++it;
+      const GroupItemDev& I = items[it];
+      const int32_t li = idx - I.first;
+      j.alive = 1;
+      j.r0 = 0;
+      j.shot = I.shot0 + (uint64_t)li;
+      j.e0row = I.e0 + (int64_t)li * n;
+      j.z_out = I.z + (int64_t)li * n;
+      j.s_out = I.s + (int64_t)li * m;
+      j.t_out = I.tclr + li;
+      j.f_out = I.fail ? I.fail + li : nullptr;
+      return j;
+    }
     j.alive = 1;
     j.r0 = r0;
     j.shot = shot0 + (uint64_t)idx;
@@ -1061,8 +1107,8 @@ __global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, R
   // control words after the groups, so that group 0's messages start at
   // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
-  ResJobs jobs{a.e0,   a.s0,   a.r0,     a.shot0,  a.nshots, c.n,       c.m,     0,
-               a.z,    a.s,    a.tclr,   a.L,      a.fail,   a.sweeps,  a.counter, a.u.spb};
+  ResJobs jobs{a.items, a.nitems, a.e0,     a.s0,     a.r0,      a.shot0,   a.nshots, c.n, c.m, 0,
+               a.z,     a.s,      a.tclr,   a.L,      a.fail,    a.sweeps,  a.counter, a.u.spb};
   run_units<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
 }
 
@@ -1070,33 +1116,6 @@ __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) p[i] = 0u;
 }
-
-// ---- multi-code persistent kernel (one launch over many codes' shots)
-struct BatchJobs {
-  const BatchItemDev* I;
-  int32_t base;
-  bool given;
-  __device__ bool next(int32_t*) {  // a single unit
-    const bool first = !given;
-    given = true;
-    return first;
-  }
-  __device__ GroupJob operator()(int32_t g) const {
-    GroupJob j = dead_job();
-    const int32_t idx = base + g;
-    if (idx >= I->nshots) return j;
-    const int32_t n = I->c.n, m = I->c.m;
-    j.alive = 1;
-    j.r0 = 0;
-    j.shot = I->shot0 + (uint64_t)idx;
-    j.e0row = I->e0 + (int64_t)idx * n;
-    j.z_out = I->z + (int64_t)idx * n;
-    j.s_out = I->s + (int64_t)idx * m;
-    j.t_out = I->tclr + idx;
-    j.f_out = I->fail ? I->fail + idx : nullptr;
-    return j;
-  }
-};
 
 // ---- serving: one round for every scheduled request, state in HBM
 struct ServerJobs {
@@ -1147,30 +1166,6 @@ struct ServerJobs {
 static const int kBatchVariants[][4] = {  // dc, dv, cpt, regular
     {2, 2, 1, 1}, {2, 2, 2, 1}, {4, 2, 1, 1}, {4, 2, 2, 1}, {4, 2, 4, 1}, {6, 2, 1, 1},
     {6, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {6, 3, 1, 1}, {6, 3, 2, 1}, {8, 4, 1, 0}};
-
-template <int BP>
-__global__ void __launch_bounds__(1024) batch_kernel(const BatchItemDev* items,
-                                                     const BatchUnitDev* units, int32_t nunits,
-                                                     uint32_t* counter, int32_t ctrl_off) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  int32_t* ctrl = reinterpret_cast<int32_t*>(smem + ctrl_off);  // after the largest unit's groups
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int32_t un = __builtin_amdgcn_readfirstlane(ctrl[0]);
-    if (un >= nunits) break;
-    const BatchUnitDev U = units[un];
-    const BatchItemDev* I = items + U.item;
-    const DevCode c = I->c;
-    const KParams kp = I->kp;
-    const UnitCtx ctx = I->u;
-    BatchJobs jobs{I, U.base, false};
-#define LAIM_CALL(DC, DV, CPT, BPV, REG) run_units<DC, DV, CPT, BPV, REG>(c, kp, ctx, jobs, smem, ctrl)
-    LAIM_BATCH_SWITCH(I->variant, BP, LAIM_CALL)
-#undef LAIM_CALL
-  }
-}
 
 template <int BP>
 __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
@@ -1247,10 +1242,11 @@ static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) 
 }
 
 // msg, scratch words, flip and correction bitmaps (n bits each), syndrome
-// bitmap (m bits); with the sequential conflict rule also a ring time
+// bitmap (m bits), initial-error bitmap (n bits); with the sequential
+// conflict rule also a ring time
 // (m words) and a request byte (m bytes) per check
 static size_t group_bytes_for(int dc, int mpad, int n, int m, bool seq) {
-  size_t b = (size_t)(dc * (mpad / 64) * kSlotStride + kGroupWords + 2 * ((n + 31) / 32) + (m + 31) / 32) * 4;
+  size_t b = (size_t)(dc * (mpad / 64) * kSlotStride + kGroupWords + 3 * ((n + 31) / 32) + (m + 31) / 32) * 4;
   if (seq) b += (size_t)m * 5;
   return (b + 15) / 16 * 16;
 }
@@ -1363,38 +1359,6 @@ bool batch_variant(const DevCode& c, int bp, const laim_resident_cfg* want, int 
   return true;
 }
 
-hipError_t launch_batch(int bp, const BatchItemDev* items, const BatchUnitDev* units,
-                        int32_t nunits, uint32_t* counter, size_t lds, int block, int grid,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, counter, 1);
-  const void* fn = bp ? reinterpret_cast<const void*>(batch_kernel<1>)
-                      : reinterpret_cast<const void*>(batch_kernel<0>);
-  if (lds > 64 * 1024) {
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipGetLastError();
-  }
-  const int32_t ctrl_off = (int32_t)(lds - kCtrlWords * 4);
-  if (bp)
-    hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter,
-                       ctrl_off);
-  else
-    hipLaunchKernelGGL(batch_kernel<0>, dim3(grid), dim3(block), lds, st, items, units, nunits, counter,
-                       ctrl_off);
-  return hipGetLastError();
-}
-
-int batch_blocks_per_cu(int bp, int block, size_t lds) {
-  const void* fn = bp ? reinterpret_cast<const void*>(batch_kernel<1>)
-                      : reinterpret_cast<const void*>(batch_kernel<0>);
-  if (lds > 64 * 1024) {
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipGetLastError();
-  }
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return 0;
-  return per_cu;
-}
-
 hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev* units,
                          int32_t nunits, const ServerReqDev* reqs, size_t lds, int block,
                          hipStream_t st) {
@@ -1435,18 +1399,14 @@ hipError_t launch_sweep_count(const KParams& kp, const int32_t* tclr, int32_t ns
 
 size_t resident_workspace_bytes() { return 256; }
 
-hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
-                           const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
-                           uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, int32_t* sweeps,
-                           hipStream_t st, const uint8_t* s0, int32_t r0) {
-  if (s0 && fail) return hipErrorInvalidValue;  // the failure test needs e0
-  if (nshots <= 0) return hipSuccess;
-  // the degrees the shape was sized for; the exact qubit-degree-2 min-sum
-  // variants skip a clamp, so the shape must have allowed them
+// The persistent launch of a resident kernel variant: as many blocks as fit
+// on the device at once (at most one per group of shots); the shot queue
+// in a.counter is cleared first by a kernel (no memset node in a graph).
+static hipError_t launch_resident_args(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                                       ResArgs& a, int32_t total, hipStream_t st) {
   if (sh.reg && sh.dv == 2 && !reg_dv2_ok(kp)) return hipErrorInvalidValue;
   const ResVariant* var = find_variant(sh.dc, sh.dv, sh.cpt, kp.bp, sh.reg);
   if (!var) return hipErrorInvalidValue;
-  ResArgs a;
   a.u.nt = sh.nt;
   a.u.vpt = sh.vpt;
   a.u.spb = sh.spb;
@@ -1455,18 +1415,6 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   a.u.rounds = kp.rounds;
   a.u.resume = 0;
   a.u.events = 0;
-  a.e0 = e0;
-  a.s0 = s0;
-  a.r0 = r0;
-  a.shot0 = shot0;
-  a.nshots = nshots;
-  a.counter = reinterpret_cast<uint32_t*>(ws);
-  a.z = z;
-  a.s = s;
-  a.tclr = tclr;
-  a.L = L;
-  a.fail = fail;
-  a.sweeps = sweeps;
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, a.counter, 1);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -1484,11 +1432,57 @@ hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentSh
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (cus <= 0) cus = 256;
-  const int64_t groups = ((int64_t)nshots + sh.spb - 1) / sh.spb;
+  const int64_t groups = ((int64_t)total + sh.spb - 1) / sh.spb;
   int64_t blocks = (int64_t)per_cu * cus;
   if (blocks > groups) blocks = groups;
   hipLaunchKernelGGL(var->fn, dim3((unsigned)blocks), dim3(sh.nt * sh.spb), sh.lds, st, c, kp, a);
   return hipGetLastError();
+}
+
+hipError_t launch_resident(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                           const uint8_t* e0, uint64_t shot0, int32_t nshots, void* ws, uint8_t* z,
+                           uint8_t* s, int32_t* tclr, float* L, uint8_t* fail, int32_t* sweeps,
+                           hipStream_t st, const uint8_t* s0, int32_t r0) {
+  if (s0 && fail) return hipErrorInvalidValue;  // the failure test needs e0
+  if (nshots <= 0) return hipSuccess;
+  ResArgs a;
+  a.items = nullptr;
+  a.nitems = 0;
+  a.e0 = e0;
+  a.s0 = s0;
+  a.r0 = r0;
+  a.shot0 = shot0;
+  a.nshots = nshots;
+  a.counter = reinterpret_cast<uint32_t*>(ws);
+  a.z = z;
+  a.s = s;
+  a.tclr = tclr;
+  a.L = L;
+  a.fail = fail;
+  a.sweeps = sweeps;
+  return launch_resident_args(c, kp, sh, a, nshots, st);
+}
+
+hipError_t launch_resident_group(const DevCode& c, const KParams& kp, const ResidentShape& sh,
+                                 const GroupItemDev* items, int32_t nitems, int32_t total, void* ws,
+                                 hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  ResArgs a;
+  a.items = items;
+  a.nitems = nitems;
+  a.e0 = nullptr;
+  a.s0 = nullptr;
+  a.r0 = 0;
+  a.shot0 = 0;
+  a.nshots = total;
+  a.counter = reinterpret_cast<uint32_t*>(ws);
+  a.z = nullptr;
+  a.s = nullptr;
+  a.tclr = nullptr;
+  a.L = nullptr;
+  a.fail = nullptr;
+  a.sweeps = nullptr;
+  return launch_resident_args(c, kp, sh, a, total, st);
 }
 
 }  // namespace laim
