@@ -32,8 +32,16 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 CU_COUNT = 256
 CLOCK_GHZ = 2.4
-LANES_PER_CU = 64  # one VALU instruction per lane per clock per CU (4 SIMD x 16 lanes)
-VALU_PEAK_TOPS = CU_COUNT * LANES_PER_CU * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s
+# VALU issue: a CU issues up to two wave64 VALU instructions per clock (the
+# dual-rate class -- FP32 add, sub, mul, multiply-add with a literal, 32-bit
+# integer add, and, xor -- measured at 1.5-1.65 per clock by the probes;
+# three-source and most other instructions issue at one per clock, measured
+# at 0.88-1.05)
+VALU_ISSUE_PER_CLK = 2
+VALU_SINGLE_TOPS = CU_COUNT * 64 * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s, one instruction per clock
+VALU_PEAK_TOPS = VALU_ISSUE_PER_CLK * VALU_SINGLE_TOPS  # 78.6 T lane-ops/s
+LDS_BYTES_PER_CLK = 128  # per CU
+LDS_PEAK_TBS = CU_COUNT * LDS_BYTES_PER_CLK * CLOCK_GHZ / 1000.0  # 78.6 TB/s
 
 
 RESIDENT_SOURCES = ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38139_amd/csrc/device_math.h",
@@ -63,32 +71,6 @@ def profile_fields(profile: str, sources):
     return fields if fields.get("source_sha256") == h.hexdigest() else None
 
 
-def profiled_traffic(profile: str, shape: str, sources=RESIDENT_SOURCES):
-    """HBM bytes per launch from a committed rocprofv3 summary (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy's counts), or None when the kernel
-    sources (hashed in order) or the launch shape differ from the profiled
-    ones."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", profile)
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if ": " in line:
-            k, v = line.strip().split(": ", 1)
-            fields[k] = v
-    h = hashlib.sha256()
-    for f in sources:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if fields.get("source_sha256") != h.hexdigest() or fields.get("launch_shape") != shape:
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +96,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-plan comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="open-loop time per arrival rate")
+    ap.add_argument("--no-matrix", action="store_true",
+                    help="skip the other benchmark configurations (2D sizes and p sweep, 3D, BB)")
+    ap.add_argument("--probe-only", action="store_true", help="run the VALU and LDS probes and exit")
     return ap.parse_args()
 
 
@@ -354,6 +339,306 @@ def serving(laim, seconds):
     return out
 
 
+def ops_per_check_sweep(bp, dc, dv, P):
+    """VALU operations that one sweep of one check needs on this instruction
+    set, from the definition of the check and qubit rules (not from the
+    kernel): the fewest instructions that evaluate the prescribed FP32
+    operation sequence, three-input minimum, median and xor counting once.
+
+    Min-sum (normalised, R5):
+      d_c (d_v - 1)        qubit-side sums m_{v->c} = pi + sum of the others,
+      + d_c                their clamps -- none on qubits of degree 2 with
+                           alpha < 1 and |pi| / (1 - alpha) < CLAMP, where the
+                           clamp provably cannot bind,
+      + ceil(d_c / 2) + 1  sign parity of the inputs (three-input xors, the
+                           check's sign folded into +-alpha),
+      + d_c ceil((d_c - 2) / 2)  each output's smallest other |m| (three-input
+                           minima),
+      + 2 d_c              scale and sign of each output;
+      = 19 for d_c = 4, d_v = 2.
+    Sum-product (box-plus form, R6): the qubit side as above with its d_c
+    clamps, 2 sign normalisations of the fold ends, 3 (d_c - 2) box-plus
+    steps of 62 operations each (min, |difference|, sum; two softplus terms
+    of 26: exp by range clamp, 2 for the reduction index, 2 reduction
+    multiply-adds, 7 Horner multiply-adds, 2 for the 2^k scale, the result
+    select, and log1p by 9 Horner multiply-adds and a product; the combine
+    (2), its floor at 0 (1) and the sign of a nonzero result (4)), and the
+    sign and clamp of each output (2 d_c); = 390 for d_c = 4, d_v = 2."""
+    if bp == "minsum":
+        pi = abs(np.log(P.q / (1.0 - P.q)))
+        idle_clamp = dv == 2 and P.alpha < 1.0 and pi < 0.99 * P.clamp * (1.0 - P.alpha)
+        return (dc * (dv - 1) + (0 if idle_clamp else dc) + (dc + 1) // 2 + 1
+                + dc * max(0, (dc - 1) // 2) + 2 * dc)
+    return dc * (dv - 1) + dc + 2 + 3 * (dc - 2) * 62 + 2 * dc
+
+
+def roofline(laim, code, P, args, form, run, default_workload, steps=None):
+    """Roofline of the decode launch of a run of timed steps (duration from
+    HIP events on its stream, averaged over the timed launches).
+
+    Resident form: bound by VALU issue, 256 CU x 64 lanes x 2.4 GHz x 2
+    instructions per clock (the dual-rate class; one per clock for the others,
+    reported beside it). The achieved rate counts ops_per_check_sweep() per
+    computed check-sweep. Beside
+    it, the on-chip traffic the method needs -- each check-to-qubit message
+    written once (4 B) and read by the d_v - 1 other checks of its qubit
+    (4 B each) per sweep -- against the LDS peak (128 B per clock per CU), and
+    the HBM bytes the launch must move (e0 in; z, s, t_clr, failure out).
+    Stream form: HBM bytes of the sweeps (each message 4 B in and out, 1 B of
+    syndrome per check) against 8 TB/s."""
+    steps = steps or args.steps
+    E, m, n, S = code.E, code.m, code.n, args.shots
+    dc, dv = code.dc_max, code.dv_max
+    msg_per_launch = 2 * E * run["sweeps_exec"] / steps
+    check_sweeps = m * run["sweeps_exec"] / steps
+    dec_s = run["decode_ms"] / 1000.0
+    if form == "stream":
+        bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
+        gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"stream form decode (2D toric L={args.L}, {P.bp})",
+                "bytes_per_msg_update": bytes_per_update, "decode_ms_per_launch": round(run["decode_ms"], 3)}
+    ops = ops_per_check_sweep(P.bp, dc, dv, P)
+    tops = check_sweeps * ops / dec_s / 1e12
+    lds_b = 4 * dc + 4 * dc * (dv - 1)
+    lds_tbs = check_sweeps * lds_b / dec_s / 1e12
+    hbm_b = S * (2 * n + m + 5)
+    shape = code.resident_cfg(P.bp)
+    prof = None
+    if default_workload:
+        prof = profile_fields(f"resident_kernel_toric2d_L32_{P.bp}.md", RESIDENT_SOURCES)
+        if prof is not None and prof.get("launch_shape") != f"{shape['checks_per_thread']},{shape['shots_per_block']}":
+            prof = None
+    traffic = float(prof["traffic_bytes_per_launch"]) if prof and "traffic_bytes_per_launch" in prof else None
+    out = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
+           "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+           "frac_of_single_issue": round(tops / VALU_SINGLE_TOPS, 4),
+           "kernel": f"resident_kernel (2D toric L={args.L}, {P.bp}, shape {shape['checks_per_thread']} checks "
+                     f"per thread x {shape['shots_per_block']} shots per block)",
+           "ops_per_check_sweep": ops, "ops_per_msg_update": ops / (2.0 * dc),
+           "decode_ms_per_launch": round(run["decode_ms"], 3), "launches_timed": steps,
+           "check_sweeps_computed_per_launch": check_sweeps,
+           "lds": {"bytes_per_check_sweep": lds_b, "achieved_TBs": round(lds_tbs, 2),
+                   "peak_TBs": round(LDS_PEAK_TBS, 1), "frac": round(lds_tbs / LDS_PEAK_TBS, 4)},
+           "hbm": {"algorithmic_bytes_per_launch": hbm_b, "GBs": round(hbm_b / dec_s / 1e9, 1),
+                   "frac": round(hbm_b / dec_s / 1e9 / HBM_PEAK_GBS, 5)}}
+    if prof is not None:
+        out["profile"] = {k: prof[k] for k in ("avg_timed_launch_ns", "executed_valu_per_check_sweep",
+                                               "valu_issue_frac", "source") if k in prof}
+    return out
+
+
+def host_cores():
+    """Threads for the CPU oracle -- every core this process may use: the CPU
+    affinity mask, bounded by the cgroup CPU quota when there is one -- and
+    what the host reports about itself."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(per)
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = aff if quota is None else max(1, min(aff, int(quota)))
+    return threads, {"nproc": aff, "cpu_count": os.cpu_count(), "cgroup_cpu_quota": quota,
+                     "cpu_model": model, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def probes():
+    """Issue rate of one VALU instruction class at a time (eight independent
+    chains per lane, 2048 blocks of 256 threads) and LDS bandwidth of
+    conflict-free 4-, 8- and 16-byte accesses, from the probe library built
+    beside the decoder."""
+    import ctypes as C
+
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2609_38139_amd", "liblaim_probe.so"))
+    lib.laim_probe_valu.restype = C.c_double
+    lib.laim_probe_valu.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+    lib.laim_probe_lds.restype = C.c_double
+    lib.laim_probe_lds.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+    lib.laim_probe_valu_name.restype = C.c_char_p
+    lib.laim_probe_valu_name.argtypes = [C.c_int32]
+    lib.laim_probe_valu_kinds.restype = C.c_int32
+    blocks, iters = 2048, 1024  # LDS probe: 64 KiB per block, 2 blocks per CU
+    out = torch.empty((blocks * 256,), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    valu = {}
+    for k in range(lib.laim_probe_valu_kinds()):
+        ms = lib.laim_probe_valu(k, blocks, iters, C.c_void_p(out.data_ptr()))
+        if ms <= 0:
+            raise RuntimeError(f"VALU probe {k} failed ({ms})")
+        rate = blocks * 256 * iters * 64 / (ms * 1e-3) / 1e12
+        valu[lib.laim_probe_valu_name(k).decode()] = {
+            "T_lane_ops_per_s": round(rate, 2), "per_CU_clock": round(rate / VALU_SINGLE_TOPS, 3)}
+    lds = {}
+    for mode, (what, width) in enumerate((("read", 4), ("read", 8), ("read", 16), ("write", 4), ("write", 8),
+                                           ("write", 16))):
+        ms = lib.laim_probe_lds(mode, blocks, iters, C.c_void_p(out.data_ptr()))
+        if ms <= 0:
+            raise RuntimeError(f"LDS probe {mode} failed ({ms})")
+        tbs = blocks * 256 * iters * 16 * width / (ms * 1e-3) / 1e12
+        lds[f"{what}_b{8 * width}"] = {"TB_per_s": round(tbs, 2), "frac_of_peak": round(tbs / LDS_PEAK_TBS, 3)}
+    return {"valu_peak_T_lane_ops_per_s": round(VALU_PEAK_TOPS, 1),
+            "valu_single_issue_T_lane_ops_per_s": round(VALU_SINGLE_TOPS, 1),
+            "lds_peak_TB_per_s": round(LDS_PEAK_TBS, 1), "valu": valu, "lds": lds}
+
+
+def one_launch(laim, code, P, p, S, seed=0, shot0=0, form="resident", reps=1):
+    """One decode launch of S fresh shots (noise drawn first), timed with HIP
+    events on the stream it runs on; the fastest of reps."""
+    import torch
+    st = torch.cuda.current_stream()
+    e0 = laim.sample_noise(code, p, seed, shot0, S)
+    out = laim.decode_rounds(code, P, e0, shot0=shot0, form=form, want_fail=True, want_sweeps=True)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        laim.decode_rounds(code, P, e0, shot0=shot0, form=form, workspace=out["workspace"], out=out)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    t = out["tclr"]
+    f = out["fail"]
+    return {"ms": round(best, 3), "shots_per_s": round(S / (best / 1000), 1),
+            "logical_error_rate": float(f.float().mean().item()),
+            "stuck": float((t < 0).float().mean().item()),
+            "wrong_class": float(((t >= 0) & (f > 0)).float().mean().item()),
+            "msg_updates_per_s": 2 * code.E * int(out["sweeps"].sum().item()) / (best / 1000)}
+
+
+def matrix_2d(laim, codes, sizes=(16, 32, 64), S=65536):
+    """2D toric L in {16, 32, 64}, p = 0.01 .. 0.10, both BP rules, 65536
+    shots per launch, 4L rounds of 20 sweeps, retiring at clear, in the
+    resident form with its built-in launch shape: one launch each."""
+    rows = []
+    for L in sizes:
+        code = laim.Code(codes.toric_2d(L), 0)
+        for bp in ("minsum", "sumproduct"):
+            P = laim.DecodeParams(bp=bp, rounds=4 * L)
+            for k in range(1, 11):
+                p = k / 100.0
+                r = one_launch(laim, code, P, p, S, shot0=0)
+                rows.append(dict(code=f"toric2d:{L}", bp=bp, p=p, rounds=4 * L, shots=S, **r))
+                print(f"[bench] 2D toric L={L} {bp} p={p}: {r['shots_per_s']:.0f} shots/s, "
+                      f"LER {r['logical_error_rate']:.4f}", flush=True, file=sys.stderr)
+    return rows
+
+
+def plan_leg(laim, codes, spec_list, seed=1, reps=2):
+    """One batched plan over (name, p, q, rounds, shots) items, replayed;
+    per item the logical error rate, for the plan the shots/s of a replay."""
+    import torch
+    items = []
+    for name, p, q, R, S in spec_list:
+        code = laim.Code(codes.by_name(name), 0)
+        P = laim.DecodeParams(q=q, rounds=R)
+        items.append({"code": code, "params": P, "e0": laim.sample_noise(code, p, seed, 0, S), "shot0": 0,
+                      "name": name, "p": p})
+    plan = laim.BatchPlan(items)
+    plan.launch()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        outs = plan.launch()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    S = sum(it["e0"].shape[0] for it in items)
+    per = [{"code": it["name"], "p": it["p"], "shots": it["e0"].shape[0], "rounds": it["params"].rounds,
+            "logical_error_rate": float(o["fail"].float().mean().item()),
+            "stuck": float((o["tclr"] < 0).float().mean().item())} for it, o in zip(items, outs)]
+    return {"ms": round(best, 3), "shots_per_s": round(S / (best / 1000), 1), "items": per}, items, outs
+
+
+def matrix_3d(laim, codes):
+    """Both 3D toric sectors at L = 8, 16, 24 in one batched launch of 16384
+    shots each (4L rounds, min-sum; prior 0.05 for the point sector, 0.125
+    for the membrane sector), at the ends and middle of each sector's noise
+    range: point 0.01, 0.04, 0.08; membrane 0.01, 0.03, 0.05."""
+    out = []
+    for pp, pm in ((0.01, 0.01), (0.04, 0.03), (0.08, 0.05)):
+        spec = [(f"toric3d_point:{n}", pp, 0.05, 4 * n, 16384) for n in (8, 16, 24)]
+        spec += [(f"toric3d_membrane:{n}", pm, 0.125, 4 * n, 16384) for n in (8, 16, 24)]
+        r, _, _ = plan_leg(laim, codes, spec, reps=1)
+        r["p_point"], r["p_membrane"] = pp, pm
+        out.append(r)
+        print(f"[bench] 3D mixed plan p={pp}/{pm}: {r['shots_per_s']:.0f} shots/s", flush=True, file=sys.stderr)
+    return out
+
+
+def matrix_bb(laim, codes):
+    """Bivariate-bicycle (6,6) and (12,6) at 262144 shots per p, p = 0.001 ..
+    0.010, with 2D toric L = 16 and 32 (p = 0.05), all in one batched launch
+    (64 rounds for BB, 4L for toric, min-sum); then the same items as one
+    resident launch per item, to isolate what one plan and one graph buy."""
+    import torch
+    spec = [(f"bb:{lm}", k / 1000.0, 0.05, 64, 262144) for lm in ("6x6", "12x6") for k in range(1, 11)]
+    spec += [("toric2d:16", 0.05, 0.05, 64, 65536), ("toric2d:32", 0.05, 0.05, 128, 65536)]
+    r, items, outs = plan_leg(laim, codes, spec, reps=2)
+    st = torch.cuda.current_stream()
+    singles = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for it in items:  # warm-up and outputs
+        singles.append(laim.decode_rounds(it["code"], it["params"], it["e0"], want_fail=True))
+    torch.cuda.synchronize()
+    a.record(st)
+    for it, o in zip(items, singles):
+        laim.decode_rounds(it["code"], it["params"], it["e0"], workspace=o["workspace"], out=o)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms_single = a.elapsed_time(b)
+    same = all(torch.equal(o[k], s[k]) for o, s in zip(outs, singles) for k in ("z", "s", "tclr", "fail"))
+    S = sum(it["e0"].shape[0] for it in items)
+    r["per_code_resident_launches"] = {"ms": round(ms_single, 3), "shots_per_s": round(S / (ms_single / 1000), 1),
+                                       "identical_outputs": bool(same),
+                                       "what": "one resident decode launch per item, back to back on one stream"}
+    r["batched_over_per_code_resident"] = round(ms_single / r["ms"], 3)
+    print(f"[bench] BB + toric plan: {r['shots_per_s']:.0f} shots/s; per-code resident "
+          f"{r['per_code_resident_launches']['shots_per_s']:.0f}", flush=True, file=sys.stderr)
+    return r
+
+
+def online_leg(laim, codes, bp="sumproduct", S=65536):
+    """Online decoding in overlapping spacetime windows: 2D toric L = 16, 16
+    syndrome rounds (the last perfect), windows of 4 rounds committing 2,
+    data and measurement error rates 0.01, 16 machine rounds per window."""
+    import torch
+    code = laim.Code(codes.toric_2d(16), 0)
+    plan = laim.OnlinePlan(code, laim.OnlineParams(rounds_total=16, window=4, commit=2, p=0.01, p_meas=0.01))
+    P = laim.DecodeParams(bp=bp, rounds=16)
+    out = plan.decode(P, S)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    out = plan.decode(P, S, workspace=out["workspace"])
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    return {"workload": f"2D toric L=16, 16 rounds, windows of 4 committing 2, p = p_meas = 0.01, {bp}, "
+                        f"16 machine rounds per window, {S} shots", "ms": round(ms, 3),
+            "shots_per_s": round(S / (ms / 1000), 1), "windows_per_s": round(7 * S / (ms / 1000), 1),
+            "logical_error_rate": float(out["fail"].float().mean().item()),
+            "all_windows_cleared": float((out["cleared"] == 7).float().mean().item())}
+
+
 def timed_steps(laim, code, P, args, steps, warmup, form, shot_base=0):
     """Runs warmup + steps passes; returns per-step and per-decode times (ms)
     from HIP events on the stream every kernel is launched on, plus the
@@ -413,7 +698,7 @@ def cpu_baseline(args, spec, P_or, seconds, nthreads=None, max_shots=4096):
     until `seconds` of wall time have passed."""
     from oracle import oracle as O
     if nthreads is None:
-        nthreads = min(16, os.cpu_count() or 1)
+        nthreads = host_cores()[0]
     done = 0
     rounds = 0
     t0 = time.perf_counter()
@@ -440,6 +725,9 @@ def main():
 
     from paper_2609_38139_amd import codes, laim
     torch.cuda.set_device(0)
+    if args.probe_only:
+        print(json.dumps({"probes": probes()}), flush=True)
+        return 0
     L = args.L
     R = args.rounds or 4 * L
     spec = codes.toric_2d(L)
@@ -464,94 +752,54 @@ def main():
             t = autotune.tune(code, bp, rounds=R, use_cache=False)
             if bp == args.bp:
                 tuned = t
+    print("[bench] main: timed steps", flush=True, file=sys.stderr)
     main_run = timed_steps(laim, code, P, args, args.steps, args.warmup, form)
     S_total = main_run["shots"]
     sec = main_run["ms_per_step"] * args.steps / 1000.0
     shots_per_s = S_total / sec
-    # message updates of the method (every sweep of every round run) and
-    # those the kernels computed (sweeps at a fixed point are skipped)
-    msg_updates = 2 * E * args.iters * main_run["rounds_exec"]
+    # message updates the kernels computed (sweeps at a fixed point of the
+    # messages are skipped, with identical results)
     msg_computed = 2 * E * main_run["sweeps_exec"]
     msg_per_s = msg_computed / sec
+    msg_method = 2 * E * args.iters * main_run["rounds_exec"]
     dec_s = main_run["decode_ms"] / 1000.0
     msg_per_launch = msg_computed / args.steps
     sweeps_frac = main_run["sweeps_exec"] / max(1, args.iters * main_run["rounds_exec"])
-
-    # Roofline of the dominant kernel. The resident decode launch keeps every
-    # message on chip, so HBM carries only e0 in and z, s, t_clr out; its
-    # bound is VALU issue (256 CU x 64 lanes x 2.4 GHz). Achieved work is the
-    # operation count of the sweeps on this instruction set (three-input min,
-    # median and xor exist), per check and sweep:
-    #   d_c (d_v - 1) qubit-side sums, plus d_c clamps -- except for min-sum
-    #                 on qubits of degree 2 with alpha < 1 and |pi|/(1 - alpha)
-    #                 < CLAMP, where the clamp provably cannot bind and the
-    #                 kernel does not execute it
-    #   ceil(d_c/2)+1 sign parity by three-input xors, folded into +-alpha
-    #   d_c ceil((d_c - 2)/2)  smallest other |m| per output by three-input mins
-    #   2 d_c         scale and sign per output
-    # = 19 for d_c = 4, d_v = 2 (2.375 per message update; 23 with the
-    # clamps). Sum-product has no fixed count: each of its 3 (d_c - 2)
-    # box-plus steps evaluates exp only for arguments up to 80 (a larger one
-    # gives 0 at once), so its work depends on the message magnitudes --
-    # about 66 VALU per step for small ones, little more than half of that
-    # once |m| is large. Its roofline therefore reports no fraction.
-    # Beside it: the rate the stream form's HBM traffic would need for the
-    # same sweeps (each check-to-qubit message written once and read once by
-    # its partner's gather, 4 B each way, i.e. 4 B per message update
-    # counting both directions, plus 1 B of syndrome per check and sweep).
-    # In the stream form the sweeps themselves stream through HBM and the
-    # roofline is that traffic against the 8 TB/s peak.
-    # Only computed sweeps count as work: with the fixed-point skip the
-    # kernel also spends time comparing each new message with the one it
-    # replaces, and the feedback phase is a larger share of the launch.
     dc, dv = code.dc_max, code.dv_max
-    ops_check = None
-    if args.bp == "minsum":
-        pi = abs(np.log(P.q / (1.0 - P.q)))
-        idle_clamp = dv == 2 and P.alpha < 1.0 and pi < 0.99 * P.clamp * (1.0 - P.alpha)
-        ops_check = (dc * (dv - 1) + (0 if idle_clamp else dc) + (dc + 1) // 2 + 1
-                     + dc * max(0, (dc - 1) // 2) + 2 * dc)
-    ops_per_update = ops_check / (2.0 * dc) if ops_check is not None else None
-    bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
-    hbm_equiv_gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
     default_workload = (L == 32 and args.p == 0.05 and args.shots == 65536 and R == 128
-                        and args.iters == 20 and args.bp == "minsum" and not args.no_retire)
-    if form != "stream":
-        shape = code.resident_cfg(args.bp)
-        traffic = None
-        if default_workload:
-            traffic = profiled_traffic("resident_kernel_toric2d_L32_minsum.md",
-                                       f"{shape['checks_per_thread']},{shape['shots_per_block']}")
-        achieved_tops = msg_per_launch * ops_per_update / dec_s / 1e12 if ops_per_update else None
-        rl = {"bound": "alu", "achieved": round(achieved_tops, 3) if achieved_tops else None,
-              "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
-              "frac": round(achieved_tops / VALU_PEAK_TOPS, 4) if achieved_tops else None, "traffic": traffic,
-              "kernel": f"resident_kernel (2D toric L={L}, {args.bp})",
-              "ops_per_msg_update": ops_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
-              "msg_updates_per_launch": msg_per_launch, "sweeps_computed_frac": round(sweeps_frac, 4),
-              "hbm_equivalent_GBs": round(hbm_equiv_gbs, 1),
-              "hbm_equivalent_frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 3)}
-    else:
-        rl = {"bound": "hbm", "achieved": round(hbm_equiv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(hbm_equiv_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-              "kernel": f"stream form decode, sweeps and feedback kernels (2D toric L={L}, {args.bp})",
-              "bytes_per_msg_update": bytes_per_update, "decode_ms_per_launch": round(main_run["decode_ms"], 3),
-              "msg_updates_per_launch": msg_per_launch}
+                        and args.iters == 20 and not args.no_retire)
+    rl = roofline(laim, code, P, args, form, main_run, default_workload)
 
     extras = {}
     small_gpu = None
+    sp_line = None
     if args.no_extras:
-        args.no_batch = args.no_serve = True
+        args.no_batch = args.no_serve = args.no_matrix = True
     if not args.no_extras:
+        print("[bench] probes", flush=True, file=sys.stderr)
+        extras["probes"] = probes()
+        print("[bench] the other BP rule", flush=True, file=sys.stderr)
+        # the paper's BP rule on the same workload: its own timed steps
+        other = "sumproduct" if args.bp == "minsum" else "minsum"
+        P_o = laim.DecodeParams(bp=other, rounds=R, iters=args.iters, retire=not args.no_retire)
+        ro = timed_steps(laim, code, P_o, args, max(2, args.steps // 4), 1, form, shot_base=3 * 10**9)
+        sec_o = ro["ms_per_step"] * max(2, args.steps // 4) / 1000.0
+        sp_line = {"bp": other, "shots_per_s": round(ro["shots"] / sec_o, 1),
+                   "msg_updates_per_s": 2 * E * ro["sweeps_exec"] / sec_o,
+                   "logical_error_rate": ro["failures"] / ro["shots"],
+                   "sweeps_computed_frac": round(ro["sweeps_exec"] / max(1, args.iters * ro["rounds_exec"]), 4),
+                   "ms_per_step": round(ro["ms_per_step"], 3), "decode_ms": round(ro["decode_ms"], 3),
+                   "resident_shape": code.resident_cfg(other) if form != "stream" else None,
+                   "roofline": roofline(laim, code, P_o, args, form, ro, default_workload,
+                                        steps=max(2, args.steps // 4))}
         # stream form (messages in HBM, one launch per sweep): the plain baseline
+        print("[bench] stream form", flush=True, file=sys.stderr)
         rs = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
         sec_s = rs["ms_per_step"] / 1000.0
         upd = 2 * E * args.iters * rs["rounds_exec"]
         # each m_{c->v} read once by the partner gather and written once (4 B
         # each) per check-to-qubit update, plus 1 B of syndrome per check
         sweeps_bytes = upd * (4.0 + 1.0 / (2.0 * code.dc_max))
-        # context for the HBM fraction: what a plain 1 GiB device copy reaches
-        # (bytes read + bytes written over its time)
         src = torch.empty((1 << 30,), dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -563,8 +811,6 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 5 * 2 * (1 << 30) / (ca.elapsed_time(cb) / 1000) / 1e9
         del src, dst
-        # the sweep kernel alone, from its committed rocprofv3 summary (only
-        # while the stream sources are the profiled ones)
         pf = profile_fields("stream_sweep_toric2d_L32_minsum.md", STREAM_SOURCES) if default_workload else None
         sweep_prof = None
         if pf is not None:
@@ -587,36 +833,25 @@ def main():
             rn = timed_steps(laim, code, laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters,
                                                            retire=not args.no_retire, skip_fixed=False),
                              args, 2, 1, form)
-            sec_n = rn["ms_per_step"] * 2 / 1000  # two timed steps
+            sec_n = rn["ms_per_step"] * 2 / 1000
             extras["every_sweep"] = {
                 "shots_per_s": round(rn["shots"] / sec_n, 1),
                 "decode_ms": round(rn["decode_ms"], 3),
                 "msg_updates_per_s": 2 * E * rn["sweeps_exec"] / sec_n,
                 "failures_per_shot": rn["failures"] / rn["shots"],
                 "what": "skip_fixed = 0: every BP sweep computed; same z, s, t_clr as the value"}
-            if ops_per_update and form != "stream":
-                upd_launch = 2 * E * rn["sweeps_exec"] / 2  # two timed launches
-                ach = upd_launch * ops_per_update / (rn["decode_ms"] / 1000) / 1e12
-                extras["every_sweep"]["roofline"] = {"achieved": round(ach, 3), "peak": round(VALU_PEAK_TOPS, 1),
-                                                     "unit": "Tops/s", "frac": round(ach / VALU_PEAK_TOPS, 4)}
+            if form != "stream":
+                rr = roofline(laim, code, laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters,
+                                                            retire=not args.no_retire, skip_fixed=False),
+                              args, form, rn, False, steps=2)
+                extras["every_sweep"]["roofline"] = {k: rr[k] for k in ("achieved", "peak", "unit", "frac")}
         P_fix = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=False)
         rf = timed_steps(laim, code, P_fix, args, 1, 0, form, shot_base=2 * 10**9)
         extras["fixed_rounds"] = {"shots_per_s": round(rf["shots"] / (rf["ms_per_step"] / 1000), 1),
-                                  "msg_updates_per_s": 2 * E * args.iters * rf["rounds_exec"] / (rf["ms_per_step"] / 1000),
+                                  "msg_updates_per_s": 2 * E * rf["sweeps_exec"] / (rf["ms_per_step"] / 1000),
                                   "failures": rf["failures"]}
-        other = "sumproduct" if args.bp == "minsum" else "minsum"
-        P_o = laim.DecodeParams(bp=other, rounds=R, iters=args.iters, retire=not args.no_retire)
-        ro = timed_steps(laim, code, P_o, args, 1, 1, form, shot_base=3 * 10**9)
-        extras[other] = {"shots_per_s": round(ro["shots"] / (ro["ms_per_step"] / 1000), 1),
-                         "msg_updates_per_s": 2 * E * ro["sweeps_exec"] / (ro["ms_per_step"] / 1000),
-                         "sweeps_computed_frac": round(ro["sweeps_exec"] / max(1, args.iters * ro["rounds_exec"]), 4),
-                         "decode_ms": round(ro["decode_ms"], 2), "failures": ro["failures"],
-                         "logical_error_rate": ro["failures"] / ro["shots"],
-                         "resident_shape": code.resident_cfg(other) if form != "stream" else None}
-        # conflict rules for the round's move requests (ablation): same
-        # workload and shots, each rule
         extras["conflict_rules"] = {}
-        for k, rule in enumerate(("or", "xor", "sequential")):
+        for rule in ("or", "xor", "sequential"):
             P_c = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire,
                                     conflict=rule)
             rc_ = timed_steps(laim, code, P_c, args, 1, 0, form, shot_base=5 * 10**9)
@@ -624,31 +859,49 @@ def main():
                 "shots_per_s": round(rc_["shots"] / (rc_["ms_per_step"] / 1000), 1),
                 "failures": rc_["failures"], "logical_error_rate": rc_["failures"] / rc_["shots"],
                 "mean_rounds_run": round(rc_["rounds_exec"] / rc_["shots"], 3)}
+        extras["moves"] = {}
+        for bp in ("minsum", "sumproduct"):
+            for mv in ("single", "multi"):
+                P_m = laim.DecodeParams(bp=bp, rounds=R, iters=args.iters, retire=not args.no_retire, move=mv)
+                rm = timed_steps(laim, code, P_m, args, 1, 0, form, shot_base=6 * 10**9)
+                extras["moves"][f"{bp}/{mv}"] = {
+                    "shots_per_s": round(rm["shots"] / (rm["ms_per_step"] / 1000), 1),
+                    "logical_error_rate": rm["failures"] / rm["shots"],
+                    "mean_rounds_run": round(rm["rounds_exec"] / rm["shots"], 3)}
+        print("[bench] online decoding", flush=True, file=sys.stderr)
+        extras["online"] = {bp: online_leg(laim, codes, bp) for bp in ("minsum", "sumproduct")}
+    if not args.no_matrix:
+        extras["matrix_2d_toric"] = matrix_2d(laim, codes)
+        extras["matrix_3d_toric"] = matrix_3d(laim, codes)
+        extras["matrix_bb_with_toric"] = matrix_bb(laim, codes)
     if not args.no_batch:
-        extras["batched_vs_plain"] = batch_vs_plain(laim, codes)
+        extras["batched_vs_plain_stream"] = batch_vs_plain(laim, codes)
         extras["per_shot_plain"], small_gpu = per_shot_plain(laim, codes)
     if not args.no_serve:
+        print("[bench] serving", flush=True, file=sys.stderr)
         extras["serving"] = serving(laim, args.serve_seconds)
     if not args.no_extras:
+        print("[bench] bit-centric and continuous machines", flush=True, file=sys.stderr)
         extras["bitcentric"] = bitcentric(laim)
         extras["continuous_machine"] = {
             "minsum": continuous_machine(laim, L, args.p, "minsum", 4096, 30.0),
             "sumproduct": continuous_machine(laim, L, args.p, "sumproduct", 2048, 30.0)}
     cpu = None
     if not args.no_cpu_baseline:
+        print("[bench] CPU oracle", flush=True, file=sys.stderr)
         from oracle import oracle as O
+        nth, host = host_cores()
         P_or = O.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire)
-        n_done, el, nth, rounds = cpu_baseline(args, spec, P_or, args.cpu_seconds)
+        n_done, el, nth, rounds = cpu_baseline(args, spec, P_or, args.cpu_seconds, nthreads=nth)
         cpu = {"value": round(n_done / el, 2), "unit": "shots/s", "cores": nth, "kind": "oracle",
+               "host": host,
                "msg_updates_per_s": 2 * E * args.iters * rounds / el,
                "sample": f"shot ids 0..{n_done - 1} of the same workload ({el:.1f} s wall, "
-                         f"{nth} OpenMP threads over shots)"}
+                         f"{nth} OpenMP threads over shots: every core this process may use)"}
         n1, el1, _, _ = cpu_baseline(args, spec, P_or, min(3.0, args.cpu_seconds), nthreads=1, max_shots=256)
         cpu["single_thread"] = {"value": round(n1 / el1, 2), "unit": "shots/s", "cores": 1,
                                 "sample": f"shot ids 0..{n1 - 1} ({el1:.1f} s wall)"}
         if small_gpu is not None:
-            # the small configuration whole (4 x 1000 shots of 2D toric L=8), by
-            # the oracle on the host cores, compared bit for bit with the GPU's
             spec8 = codes.toric_2d(8)
             P8 = O.DecodeParams(rounds=64)
             t0 = time.perf_counter()
@@ -683,8 +936,8 @@ def main():
                    "resident_shape": code.resident_cfg(args.bp) if form != "stream" else None,
                    "autotuned": tuned is not None},
         "msg_updates_per_s": msg_per_s,
-        "msg_updates_of_the_method_per_s": msg_updates / sec,
         "logical_error_rate": main_run["failures"] / S_total,
+        "sumproduct": sp_line,
         "served_latency": (
             {"p50_round_ms": extras["serving"]["open_loop"][1]["p50_round_ms"],
              "p99_round_ms": extras["serving"]["open_loop"][1]["p99_round_ms"],
@@ -693,7 +946,11 @@ def main():
             if "serving" in extras else None),
         "roofline": rl,
         "cpu_baseline": cpu,
-        "extras": extras,
+        "extras": dict(extras, sweeps_not_computed={
+            "msg_updates_of_the_method_per_s": msg_method / sec,
+            "what": "the method's count: every sweep of every round run, including the identity sweeps "
+                    "at a fixed point that the kernel skips (not computed; msg_updates_per_s counts the "
+                    "computed ones)", "sweeps_computed_frac": round(sweeps_frac, 4)}),
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -1,8 +1,8 @@
 """Launch-shape autotuner for the resident decode form.
 
 For one code and BP rule it times every valid resident launch shape
-(checks per thread x shots per block) on a fixed batch of shots with a
-fixed amount of work (no early retirement), checks that all shapes produce
+(checks per thread x shots per block) on a fixed batch of shots decoded as
+a run decodes them (shots retire once clear), checks that all shapes produce
 identical outputs, installs the fastest with ``laim_set_resident_cfg`` and
 caches the choice per device name and code in a JSON file
 (``$LAIM_TUNE_CACHE``, default ``~/.cache/laim/resident_shapes.json``).

@@ -21,8 +21,12 @@ def test_profile_summaries_carry_their_fields():
     sys.path.insert(0, ROOT)
     import bench
     for name, need in (("resident_kernel_toric2d_L32_minsum.md",
-                        ("kernel", "avg_launch_ns", "traffic_bytes_per_launch", "fetch_scale", "write_scale",
-                         "source_sha256")),
+                        ("kernel", "launch_shape", "avg_launch_ns", "avg_timed_launch_ns",
+                         "executed_valu_per_check_sweep", "traffic_bytes_per_launch", "fetch_scale",
+                         "write_scale", "source_sha256")),
+                       ("resident_kernel_toric2d_L32_sumproduct.md",
+                        ("kernel", "launch_shape", "avg_launch_ns", "avg_timed_launch_ns",
+                         "executed_valu_per_check_sweep", "source_sha256")),
                        ("stream_sweep_toric2d_L32_minsum.md",
                         ("kernel", "avg_launch_ns", "traffic_bytes_per_launch", "source_sha256"))):
         path = os.path.join(ROOT, "profiles", name)
@@ -39,3 +43,18 @@ def test_profile_summaries_carry_their_fields():
     assert "rocprofv3 --kernel-trace --stats" in text and "rocprofv3 --pmc FETCH_SIZE" in text
     # a summary taken on other sources reads as absent, never as stale figures
     assert bench.profile_fields("resident_kernel_toric2d_L32_minsum.md", ("bench.py",)) is None
+
+
+def test_method_operation_counts():
+    """The roofline's operation counts per check-sweep: 19 for normalised
+    min-sum on the 2D toric code (its qubit-side clamps cannot bind), 23 with
+    the clamps, and 390 for sum-product (3 (d_c - 2) box-plus steps)."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class P:
+        q, alpha, clamp = 0.05, 0.75, 1000.0
+    assert bench.ops_per_check_sweep("minsum", 4, 2, P) == 19
+    P.clamp = 4.0
+    assert bench.ops_per_check_sweep("minsum", 4, 2, P) == 23
+    assert bench.ops_per_check_sweep("sumproduct", 4, 2, P) == 390
