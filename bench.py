@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--no-matrix", action="store_true",
                     help="skip the other benchmark configurations (2D sizes and p sweep, 3D, BB)")
     ap.add_argument("--probe-only", action="store_true", help="run the VALU and LDS probes and exit")
+    ap.add_argument("--leg", default="", choices=["", "continuous", "matrix_3d", "matrix_bb", "online"],
+                    help="run one secondary measurement alone, print it as JSON and exit (for profiling)")
     return ap.parse_args()
 
 
@@ -267,6 +269,8 @@ def continuous_machine(laim, L, p, bp, nshots, t_max, reps=2):
            "every_step": {"shots_per_s": round(nshots / sec_all, 1), "decode_ms": round(sec_all * 1e3, 3),
                           "what": "skip_fixed = 0: every Euler step computed; identical outputs"},
            "cleared": int((tclr >= 0).sum()), "logical_error_rate": float(out["fail"].float().mean().item()),
+           "uncleared_at_t_max": float((tclr < 0).mean()),
+           "wrong_class": float(((out["tclr"] >= 0) & (out["fail"] > 0)).float().mean().item()),
            "mean_tclr_cleared": float(tclr[tclr >= 0].mean()) if (tclr >= 0).any() else None}
     if ops_check is not None:
         # only the computed steps count as work
@@ -470,7 +474,9 @@ def probes():
     lib.laim_probe_valu_name.restype = C.c_char_p
     lib.laim_probe_valu_name.argtypes = [C.c_int32]
     lib.laim_probe_valu_kinds.restype = C.c_int32
-    blocks, iters = 2048, 1024  # LDS probe: 64 KiB per block, 2 blocks per CU
+    lib.laim_probe_lds_per_step.restype = C.c_int32
+    per_step = lib.laim_probe_lds_per_step()
+    blocks, iters = 2048, 2048  # LDS probe: 32 KiB per block, 5 blocks per CU
     out = torch.empty((blocks * 256,), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     valu = {}
@@ -487,7 +493,7 @@ def probes():
         ms = lib.laim_probe_lds(mode, blocks, iters, C.c_void_p(out.data_ptr()))
         if ms <= 0:
             raise RuntimeError(f"LDS probe {mode} failed ({ms})")
-        tbs = blocks * 256 * iters * 16 * width / (ms * 1e-3) / 1e12
+        tbs = blocks * 256 * iters * per_step * width / (ms * 1e-3) / 1e12
         lds[f"{what}_b{8 * width}"] = {"TB_per_s": round(tbs, 2), "frac_of_peak": round(tbs / LDS_PEAK_TBS, 3)}
     return {"valu_peak_T_lane_ops_per_s": round(VALU_PEAK_TOPS, 1),
             "valu_single_issue_T_lane_ops_per_s": round(VALU_SINGLE_TOPS, 1),
@@ -727,6 +733,14 @@ def main():
     torch.cuda.set_device(0)
     if args.probe_only:
         print(json.dumps({"probes": probes()}), flush=True)
+        return 0
+    if args.leg:
+        legs = {"continuous": lambda: {bp: continuous_machine(laim, args.L, args.p, bp, n, 30.0)
+                                       for bp, n in (("minsum", 4096), ("sumproduct", 2048))},
+                "matrix_3d": lambda: matrix_3d(laim, codes),
+                "matrix_bb": lambda: matrix_bb(laim, codes),
+                "online": lambda: {bp: online_leg(laim, codes, bp) for bp in ("minsum", "sumproduct")}}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
     L = args.L
     R = args.rounds or 4 * L

@@ -293,7 +293,13 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
   uint32_t* zw = reinterpret_cast<uint32_t*>(gw + kCtmWords);
   uint32_t* sw = zw + nw;
   const float C = P.clamp;
-  const float lam = P.lam;
+  // lambda and pi are held in vector registers: the step uses them as
+  // operands of every update, and scalar registers run short in the
+  // skipping instance (the compiler would otherwise spill them to lanes
+  // of a vector register and read them back in every step)
+  float lam = P.lam;
+  float piv = P.pi;
+  asm volatile("" : "+v"(lam), "+v"(piv));
 
   // ---- per-thread graph tables (for the whole launch). Checks t + k nt
   // from m on pad the last tile: their LDS slots exist (mpad >= nt CPT) and
@@ -418,7 +424,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
       for (int kk = 0; kk < CPT; ++kk) {
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
-          float acc = P.pi;
+          float acc = piv;
 #pragma unroll
           for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[kk][j][p]];
           Fv[kk][j] = kNoClamp ? acc : __builtin_amdgcn_fmed3f(acc, -C, C);
