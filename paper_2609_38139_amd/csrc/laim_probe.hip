@@ -7,9 +7,13 @@
 //    has an instruction ready; the rate is lane-instructions per second.
 //  - LDS bandwidth: every lane reads (or writes) consecutive 4-, 8- or
 //    16-byte words of a block-local LDS array, so a wavefront's access
-//    covers consecutive banks without conflicts.
+//    covers consecutive banks without conflicts; the accesses are issued
+//    eight at a time with almost no other instructions, so that neither
+//    latency nor VALU work limits them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace {
 
@@ -65,55 +69,76 @@ __global__ void __launch_bounds__(256) valu_probe(float* out, int32_t iters, uin
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-// LDS: in each step a lane reads (or writes) 16 distinct words of WIDTH
-// bytes of a 64 KiB block-local array, word lane + 256 u (+ a shift that
-// depends on the step, so nothing is hoisted out of the loop, and no two
-// accesses of a step share a word, so none is merged); the 64 lanes of a
-// wavefront touch consecutive words, i.e. consecutive banks.
+// LDS: in each step a wavefront issues kLdsPerStep reads (or writes) of
+// WIDTH bytes per lane to a 32 KiB block-local array, lane l of access u at
+// word base + l + 256 u, base = 64 (step mod 2): the 64 lanes touch
+// consecutive words, i.e. consecutive banks, no two accesses of a step
+// share a word, and every access stays inside the array (base + 63 +
+// 256 (kLdsPerStep - 1) < 2048 words of 16 B). The accesses of a step are
+// one asm block -- the address in one register, the access number in the
+// instruction's offset field, and a wait for all of them at its end -- so
+// the loop spends two VALU instructions per step and the probe measures the
+// LDS, not the address arithmetic; read results are consumed by an empty
+// asm statement after the wait. 32 KiB per block lets five blocks (20
+// wavefronts) share a CU.
+constexpr int kLdsPerStep = 8;
+
+#define LDS_R8(OP)                                                                              \
+  asm volatile(OP " %0, %8\n\t" OP " %1, %8 offset:%9\n\t" OP " %2, %8 offset:%10\n\t" OP    \
+               " %3, %8 offset:%11\n\t" OP " %4, %8 offset:%12\n\t" OP " %5, %8 offset:%13\n\t" \
+               OP " %6, %8 offset:%14\n\t" OP " %7, %8 offset:%15\n\ts_waitcnt lgkmcnt(0)"      \
+               : "=v"(r0), "=v"(r1), "=v"(r2), "=v"(r3), "=v"(r4), "=v"(r5), "=v"(r6), "=v"(r7)   \
+               : "v"(addr), "i"(1 * kStep), "i"(2 * kStep), "i"(3 * kStep), "i"(4 * kStep),       \
+                 "i"(5 * kStep), "i"(6 * kStep), "i"(7 * kStep)                                  \
+               : "memory")
+
+#define LDS_W8(OP)                                                                                  \
+  asm volatile(OP " %0, %1\n\t" OP " %0, %1 offset:%2\n\t" OP " %0, %1 offset:%3\n\t" OP          \
+               " %0, %1 offset:%4\n\t" OP " %0, %1 offset:%5\n\t" OP " %0, %1 offset:%6\n\t" OP     \
+               " %0, %1 offset:%7\n\t" OP " %0, %1 offset:%8\n\ts_waitcnt lgkmcnt(0)"               \
+               :                                                                                   \
+               : "v"(addr), "v"(val), "i"(1 * kStep), "i"(2 * kStep), "i"(3 * kStep),              \
+                 "i"(4 * kStep), "i"(5 * kStep), "i"(6 * kStep), "i"(7 * kStep)                    \
+               : "memory")
+
 template <int WIDTH, bool WRITE>
 __global__ void __launch_bounds__(256) lds_probe(float* out, int32_t iters) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   typedef float f2 __attribute__((ext_vector_type(2)));
-  constexpr int kBytes = 65536;
-  constexpr int kWords = kBytes / WIDTH;  // per block, >= 16 x 256
+  typedef typename std::conditional<WIDTH == 4, float, typename std::conditional<WIDTH == 8, f2, f4>::type>::type
+      T;
+  constexpr int kBytes = 32768;
+  constexpr int kStep = 256 * WIDTH;  // bytes between the accesses of a step
+  static_assert(kLdsPerStep == 8, "the asm blocks issue eight accesses");
+  static_assert((127 + 256 * (kLdsPerStep - 1)) * WIDTH + WIDTH <= kBytes, "every access inside the array");
   __shared__ __align__(16) f4 buf[kBytes / 16];
-  const int32_t lane = threadIdx.x;
-  for (int32_t i = lane; i < kBytes / 16; i += blockDim.x) buf[i] = f4{(float)i, 1.0f, 2.0f, 3.0f};
+  const int32_t lane = threadIdx.x & 63;  // each wavefront covers words base .. base + 63 + 256 u
+  for (int32_t i = threadIdx.x; i < kBytes / 16; i += blockDim.x) buf[i] = f4{(float)i, 1.0f, 2.0f, 3.0f};
   __syncthreads();
-  float acc = 0.0f;
+  const uint32_t buf0 = (uint32_t)(uintptr_t)buf;  // the low half of a generic LDS address is its offset
+  T val;
+  if constexpr (WIDTH == 4)
+    val = (float)lane;
+  else if constexpr (WIDTH == 8)
+    val = f2{(float)lane, 1.0f};
+  else
+    val = f4{(float)lane, 1.0f, 2.0f, 3.0f};
   for (int32_t i = 0; i < iters; ++i) {
-    const int32_t sh = (64 * i) & (kWords - 1);  // repeats only after kWords / 64 steps
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int32_t w = (lane + 256 * u + sh) & (kWords - 1);
-      if (WIDTH == 4) {
-        float* p = reinterpret_cast<float*>(buf) + w;
-        if (WRITE)
-          *p = acc + (float)u;
-        else
-          acc += *p;
-      } else if (WIDTH == 8) {
-        f2* p = reinterpret_cast<f2*>(buf) + w;
-        if (WRITE) {
-          *p = f2{acc, (float)u};
-        } else {
-          const f2 v = *p;
-          acc += v.x + v.y;
-        }
-      } else {
-        f4* p = buf + w;
-        if (WRITE) {
-          *p = f4{acc, (float)u, acc, (float)i};
-        } else {
-          const f4 v = *p;
-          acc += (v.x + v.y) + (v.z + v.w);
-        }
-      }
+    const uint32_t addr = buf0 + (uint32_t)((64 * (i & 1) + lane) * WIDTH);
+    if constexpr (WRITE) {
+      if constexpr (WIDTH == 4) LDS_W8("ds_write_b32");
+      else if constexpr (WIDTH == 8) LDS_W8("ds_write_b64");
+      else LDS_W8("ds_write_b128");
+    } else {
+      T r0, r1, r2, r3, r4, r5, r6, r7;
+      if constexpr (WIDTH == 4) LDS_R8("ds_read_b32");
+      else if constexpr (WIDTH == 8) LDS_R8("ds_read_b64");
+      else LDS_R8("ds_read_b128");
+      asm volatile("" : : "v"(r0), "v"(r1), "v"(r2), "v"(r3), "v"(r4), "v"(r5), "v"(r6), "v"(r7));
     }
-    if (WRITE) acc += 1.0f;
   }
   __syncthreads();
-  out[blockIdx.x * blockDim.x + threadIdx.x] = acc + reinterpret_cast<float*>(buf)[lane];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = reinterpret_cast<float*>(buf)[threadIdx.x];
 }
 
 typedef void (*ProbeFn)(float*, int32_t);
@@ -167,8 +192,12 @@ double laim_probe_valu(int32_t kind, int32_t blocks, int32_t iters, float* out) 
   return hipGetLastError() == hipSuccess ? (double)ms : -4.0;
 }
 
+// Accesses per lane and step of the LDS probe.
+int32_t laim_probe_lds_per_step(void) { return kLdsPerStep; }
+
 // LDS probe: mode 0..2 reads of 4, 8, 16 bytes per lane, 3..5 writes.
-// Bytes moved: blocks * 256 * iters * 16 * width. Returns ms as above.
+// Bytes moved: blocks * 256 * iters * laim_probe_lds_per_step() * width.
+// Returns ms as above.
 double laim_probe_lds(int32_t mode, int32_t blocks, int32_t iters, float* out) {
   if (mode < 0 || mode > 5 || blocks < 1 || iters < 1 || !out) return -1.0;
   hipEvent_t a, b;
