@@ -178,7 +178,12 @@ typedef struct {
  * following rounds without a flip. A shot's first sweep
  * (v->c messages 0) is a different map and never counts. z, s, t_clr and
  * the beliefs are bit-identical to running every sweep; only the sweeps
- * computed (sweeps_out) differ. The stream form always runs every sweep. */
+ * computed (sweeps_out) differ. The stream form compares on the same
+ * sweeps (reading each compared message once more) and skips a 256-shot
+ * tile's sweep when every shot of the tile is retired or at a fixed point.
+ * Both forms also stop a shot whose messages are at a fixed point at the
+ * feedback step while no active check passes Evidence: nothing can change
+ * in any later round, so its outputs are final. */
 
 /* Conflict rules. Algorithm 1 lets one clock ring at a time; a round of the
  * discretised machine gathers the requests of every check that rang, and
@@ -219,7 +224,9 @@ size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* par
  *              shot, the state at retirement)
  *   sweeps_out device [nshots] int32 or NULL: BP sweeps computed for each
  *              shot; iters x (rounds the shot ran) unless skip_fixed skipped
- *              some (saturates at 2^31 - 1)
+ *              some (saturates at 2^31 - 1). The stream form sweeps whole
+ *              tiles and reports the method's count, iters x (rounds until
+ *              the shot cleared, or R when it did not or retire is 0)
  *   fail_out   device [nshots] uint8 or NULL: the decoder failure of each
  *              shot, exactly as laim_logical_failure(e0, z_out) gives it; the
  *              resident form computes it inside the launch (codes with at

@@ -31,8 +31,12 @@ struct StreamWS {
   uint8_t* fl;       // [ntile][n][kStreamTile]
   uint32_t* anys;    // [ntile * kStreamTile]
   int32_t* tclr;     // [ntile * kStreamTile]
-  uint8_t* done;     // [ntile * kStreamTile]: retired shots and the last tile's padding
+  uint8_t* done;     // [ntile * kStreamTile]: retired (or frozen) shots and the last tile's padding
   uint8_t* newdone;  // [ntile * kStreamTile]
+  // exact shortcuts (kp.skip), per shot:
+  uint8_t* conv;     // the messages are a fixed point of the sweep for the current syndrome
+  uint8_t* chg;      // a compared sweep changed a message
+  uint8_t* evid;     // an active check passed Evidence in this round's feedback step
   // sequential conflict rule only (else null)
   uint8_t* rq;       // [ntile][m][kStreamTile]: slot of the requested qubit (bits 0-6,
                      //   kStreamNoRequest if none), bit 7 whether the request applies
@@ -71,6 +75,12 @@ static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t*
   w.done = reinterpret_cast<uint8_t*>(p + off);
   off += sh1;
   w.newdone = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  w.conv = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  w.chg = reinterpret_cast<uint8_t*>(p + off);
+  off += sh1;
+  w.evid = reinterpret_cast<uint8_t*>(p + off);
   off += sh1;
   w.rq = nullptr;
   w.rkey = nullptr;
@@ -233,10 +243,19 @@ __device__ __forceinline__ void stream_gather(const DevCode& c, const float* __r
 // check). `fresh` marks the first sweep of every shot (m_{v->c} = 0). A tile
 // whose shots have all retired is skipped; the other tiles are swept whole,
 // since the messages of retired shots are never read again.
+//
+// Exact shortcuts (kp.skip): a compared sweep (`cmp`) also reads the old
+// messages of its own rows and marks every shot one of whose messages
+// changed (w.chg); stream_conv then records the shots whose messages are a
+// fixed point of the sweep (w.conv). The sweep is a fixed map of the
+// messages while the syndrome does not change, so at a fixed point every
+// later sweep rewrites the same values, and both message buffers already
+// hold them: a tile whose shots are all retired or at a fixed point skips
+// the sweep, and the outputs are those of sweeping it.
 template <int DCT>
 __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ src,
-                                                    float* __restrict__ dst, int32_t fresh) {
+                                                    float* __restrict__ dst, int32_t fresh, int32_t cmp) {
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
@@ -254,7 +273,9 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
   const int32_t mine_raw = pblk[lane < nidx ? lane : 0];  // in bounds for every lane
   const int32_t d_raw = c.chk_deg[ch];
   const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
-  if (!__any(ld4b(w.done + tile * kStreamTile + kSV * lane) != 0x01010101u)) return;
+  uint32_t idle4 = ld4b(w.done + tile * kStreamTile + kSV * lane);
+  if (kp.skip) idle4 |= ld4b(w.conv + tile * kStreamTile + kSV * lane);
+  if (!__any(idle4 != 0x01010101u)) return;
   const int32_t mine = (lane < nidx) ? mine_raw : -1;
   const int32_t d = __builtin_amdgcn_readfirstlane(d_raw);
   float4 acc[DCT];
@@ -291,6 +312,12 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
     x[2][j] = fresh ? 0.0f : clampf(acc[j].z, C);
     x[3][j] = fresh ? 0.0f : clampf(acc[j].w, C);
   }
+  float4 old[DCT];
+  if (cmp) {
+#pragma unroll
+    for (int j = 0; j < DCT; ++j)
+      if (j < d) old[j] = nt_load4(src + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane));
+  }
   float out[kSV][DCT];
 #pragma unroll
   for (int q = 0; q < kSV; ++q)
@@ -302,6 +329,30 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
     nt_store4(dst + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane), out[0][j], out[1][j], out[2][j],
               out[3][j]);
   }
+  if (cmp) {
+    uint32_t dq[kSV] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < DCT; ++j) {
+      if (j >= d) continue;
+      dq[0] |= __float_as_uint(out[0][j]) ^ __float_as_uint(old[j].x);
+      dq[1] |= __float_as_uint(out[1][j]) ^ __float_as_uint(old[j].y);
+      dq[2] |= __float_as_uint(out[2][j]) ^ __float_as_uint(old[j].z);
+      dq[3] |= __float_as_uint(out[3][j]) ^ __float_as_uint(old[j].w);
+    }
+    // every writer stores the same value: plain byte stores suffice
+#pragma unroll
+    for (int q = 0; q < kSV; ++q)
+      if (dq[q]) w.chg[tile * kStreamTile + kSV * lane + q] = 1;
+  }
+}
+
+// After a compared sweep: a live shot none of whose messages changed is at a
+// fixed point (kept until its syndrome changes); the change marks are cleared.
+__global__ void __launch_bounds__(256) stream_conv(StreamWS w, int32_t ntot) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  if (!w.done[i]) w.conv[i] = w.chg[i] ? 0 : 1;
+  w.chg[i] = 0;
 }
 
 // Belief of qubit v for shot column `col` of a tile.
@@ -330,6 +381,7 @@ __device__ __forceinline__ void stream_request(const DevCode& c, const KParams& 
   for (int j = 0; j < DCT; ++j)
     if (j < d && (j == 0 || Lv[j] > Lmax)) Lmax = Lv[j];
   if (kp.evidence && !(Lmax >= c.thr[d])) return;  // Evidence first, then the clock
+  if (kp.skip) w.evid[tile * kStreamTile + col] = 1;
   const Philox4 rw = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)ch,
                                    ((uint32_t)r << 4) | 1u, (uint32_t)kp.seed, (uint32_t)(kp.seed >> 32));
   if (!below(rw.w0, kp.mask_bound)) return;
@@ -545,7 +597,8 @@ __global__ void __launch_bounds__(256) stream_resolve(DevCode c, StreamWS w) {
   }
 }
 
-// s ^= H f for live shots; flags shots with s != 0.
+// s ^= H f for live shots; flags shots with s != 0 and clears the fixed-point
+// mark of shots whose syndrome changed.
 __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
@@ -558,12 +611,16 @@ __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
   for (int32_t j = 0; j < d; ++j)
     x4 ^= ld4b(w.fl + stream_at(tile, c.n, c.chk_var[(int64_t)ch * c.dcmax + j], lane));
   const int64_t so = stream_at(tile, c.m, ch, lane);
-  const uint32_t s4 = ld4b(w.s + so) ^ (x4 & live);
+  const uint32_t flip = x4 & live;
+  const uint32_t s4 = ld4b(w.s + so) ^ flip;
   st4b(w.s + so, s4);
   const uint32_t hit = s4 & live;
 #pragma unroll
-  for (int q = 0; q < kSV; ++q)
+  for (int q = 0; q < kSV; ++q) {
     if ((hit >> (8 * q)) & 1u) w.anys[tile * kStreamTile + kSV * lane + q] = 1u;
+    // a changed syndrome changes the sweep: no longer at a fixed point
+    if ((flip >> (8 * q)) & 1u) w.conv[tile * kStreamTile + kSV * lane + q] = 0;
+  }
 }
 
 // z ^= f and clear the requests (requests exist for live shots only).
@@ -578,7 +635,11 @@ __global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
   st4b(w.fl + o, 0u);
 }
 
-// Per shot: t_clr at the first clear syndrome, retirement.
+// Per shot: t_clr at the first clear syndrome, retirement. With the exact
+// shortcuts a shot also stops (frozen) when its messages were a fixed point
+// at the feedback step and no active check passed Evidence: nothing was
+// requested, so the syndrome is unchanged, the next round repeats this one
+// exactly, and so does every later one -- the outputs are final.
 __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int32_t r,
                                                      int32_t nshots) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -587,9 +648,12 @@ __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int
   if (w.done[i]) return;
   const bool any = w.anys[i] != 0u;
   w.anys[i] = 0u;
+  const bool evid = w.evid[i] != 0;
+  w.evid[i] = 0;
   if (r < 0) w.tclr[i] = any ? -1 : 0;
   else if (!any && w.tclr[i] < 0) w.tclr[i] = r + 1;
-  if (kp.retire && w.tclr[i] >= 0) {
+  const bool frozen = kp.skip && r >= 0 && w.conv[i] && !evid;
+  if ((kp.retire && w.tclr[i] >= 0) || frozen) {
     w.done[i] = 1;
     w.newdone[i] = 1;
   }
@@ -602,6 +666,9 @@ __global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t ns
   w.anys[i] = 0u;
   w.done[i] = (i >= nshots) ? 1 : 0;
   w.newdone[i] = 0;
+  w.conv[i] = 0;
+  w.chg[i] = 0;
+  w.evid[i] = 0;
   w.tclr[i] = -1;
 }
 
@@ -654,7 +721,7 @@ __global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t
   }
 }
 
-typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t);
+typedef void (*SweepFn)(DevCode, KParams, StreamWS, const float*, float*, int32_t, int32_t);
 typedef void (*MovesFn)(DevCode, KParams, StreamWS, const float*, int32_t, int32_t, uint64_t);
 
 static void stream_fns(int dcmax, SweepFn* sw, MovesFn* mv) {
@@ -705,8 +772,12 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
                             nshots);
   for (int32_t r = 0; r < kp.rounds; ++r) {
     for (int32_t it = 0; it < kp.iters; ++it) {
+      // sweeps 7, 15, ... and the last of the round compare (never a shot's
+      // first sweep, which starts from m_{v->c} = 0 and is a different map)
+      const bool cmp = kp.skip && !fresh && ((it & 7) == 7 || it == kp.iters - 1);
       hipLaunchKernelGGL(sweep_fn, gchk, blk, 0, st, c, kp, w, w.msg[cur], w.msg[cur ^ 1],
-                         fresh ? 1 : 0);
+                         fresh ? 1 : 0, cmp ? 1 : 0);
+      if (cmp) hipLaunchKernelGGL(stream_conv, dim3((unsigned)((ntot + 255) / 256)), blk, 0, st, w, ntot);
       cur ^= 1;
       fresh = false;
     }
