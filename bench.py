@@ -398,6 +398,13 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
     dec_s = run["decode_ms"] / 1000.0
     if form == "stream":
         bytes_per_update = 4.0 + 1.0 / (2.0 * dc)
+        if P.skip_fixed:
+            # whole tiles skip sweeps: the sweeps computed are not counted per
+            # shot, so the bytes of the launch are unknown here (the per-sweep
+            # roofline is the plain form's, --no-skip)
+            return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                    "traffic": None, "kernel": f"stream form decode (2D toric L={args.L}, {P.bp}, skip_fixed)",
+                    "decode_ms_per_launch": round(run["decode_ms"], 3)}
         gbs = msg_per_launch * bytes_per_update / dec_s / 1e9
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
@@ -489,12 +496,13 @@ def probes():
             "T_lane_ops_per_s": round(rate, 2), "per_CU_clock": round(rate / VALU_SINGLE_TOPS, 3)}
     lds = {}
     for mode, (what, width) in enumerate((("read", 4), ("read", 8), ("read", 16), ("write", 4), ("write", 8),
-                                           ("write", 16))):
+                                           ("write", 16), ("write2_stride65", 8))):
         ms = lib.laim_probe_lds(mode, blocks, iters, C.c_void_p(out.data_ptr()))
         if ms <= 0:
             raise RuntimeError(f"LDS probe {mode} failed ({ms})")
         tbs = blocks * 256 * iters * per_step * width / (ms * 1e-3) / 1e12
-        lds[f"{what}_b{8 * width}"] = {"TB_per_s": round(tbs, 2), "frac_of_peak": round(tbs / LDS_PEAK_TBS, 3)}
+        lds[f"{what}_b{8 * width}"] = {"TB_per_s": round(tbs, 2), "frac_of_peak": round(tbs / LDS_PEAK_TBS, 3),
+                                       "bytes_per_CU_clock": round(tbs * 1e12 / (CU_COUNT * CLOCK_GHZ * 1e9), 1)}
     return {"valu_peak_T_lane_ops_per_s": round(VALU_PEAK_TOPS, 1),
             "valu_single_issue_T_lane_ops_per_s": round(VALU_SINGLE_TOPS, 1),
             "lds_peak_TB_per_s": round(LDS_PEAK_TBS, 1), "valu": valu, "lds": lds}
@@ -808,7 +816,11 @@ def main():
                                         steps=max(2, args.steps // 4))}
         # stream form (messages in HBM, one launch per sweep): the plain baseline
         print("[bench] stream form", flush=True, file=sys.stderr)
-        rs = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
+        P_plain = laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters, retire=not args.no_retire,
+                                    skip_fixed=False)
+        rs = timed_steps(laim, code, P_plain, args, 1, 0, "stream", shot_base=10**9)
+        # the same launch with the exact shortcuts (identical outputs)
+        rk = timed_steps(laim, code, P, args, 1, 0, "stream", shot_base=10**9)
         sec_s = rs["ms_per_step"] / 1000.0
         upd = 2 * E * args.iters * rs["rounds_exec"]
         # each m_{c->v} read once by the partner gather and written once (4 B
@@ -841,7 +853,14 @@ def main():
                                  "msg_updates_per_s": upd / sec_s,
                                  "decode_ms": round(rs["decode_ms"], 2),
                                  "algorithmic_hbm_GBs": round(sweeps_bytes / (rs["decode_ms"] / 1000) / 1e9, 1),
-                                 "failures": rs["failures"]}
+                                 "failures": rs["failures"],
+                                 "what": "every sweep of every round (skip_fixed = 0)",
+                                 "with_shortcuts": {
+                                     "shots_per_s": round(rk["shots"] / (rk["ms_per_step"] / 1000), 1),
+                                     "decode_ms": round(rk["decode_ms"], 2), "failures": rk["failures"],
+                                     "identical_failures": rk["failures"] == rs["failures"],
+                                     "what": "skip_fixed = 1: tiles of 256 shots all retired or at a fixed "
+                                             "point skip the sweep; stuck shots stop (identical outputs)"}}
         if skip:
             # the same launch running every sweep: identical results
             rn = timed_steps(laim, code, laim.DecodeParams(bp=args.bp, rounds=R, iters=args.iters,
@@ -946,7 +965,7 @@ def main():
                                f"{form} form",
                    "code": f"toric2d:{L}", "p": args.p, "shots_per_step": args.shots, "rounds": R,
                    "iters": args.iters, "bp": args.bp, "form": form, "retire": not args.no_retire,
-                   "skip_fixed": skip and form != "stream",
+                   "skip_fixed": skip,
                    "resident_shape": code.resident_cfg(args.bp) if form != "stream" else None,
                    "autotuned": tuned is not None},
         "msg_updates_per_s": msg_per_s,

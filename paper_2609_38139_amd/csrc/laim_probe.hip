@@ -141,6 +141,40 @@ __global__ void __launch_bounds__(256) lds_probe(float* out, int32_t iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = reinterpret_cast<float*>(buf)[threadIdx.x];
 }
 
+// ds_write2_b32 with the two dwords 65 words apart (the resident decode
+// kernels' message writes): per step eight such writes per lane, each to
+// its own address register (word base + lane + 256 u), every word inside
+// the 32 KiB array (base + 63 + 256 * 7 + 65 < 8192 words).
+__global__ void __launch_bounds__(256) lds_write2_probe(float* out, int32_t iters) {
+  constexpr int kBytes = 32768;
+  static_assert((127 + 256 * 7 + 65) * 4 + 4 <= kBytes, "every access inside the array");
+  __shared__ __align__(16) float buf[kBytes / 4];
+  const int32_t lane = threadIdx.x & 63;
+  for (int32_t i = threadIdx.x; i < kBytes / 4; i += blockDim.x) buf[i] = (float)i;
+  __syncthreads();
+  const uint32_t buf0 = (uint32_t)(uintptr_t)buf;
+  const float va = (float)lane, vb = 1.0f;
+  for (int32_t i = 0; i < iters; ++i) {
+    const uint32_t a0 = buf0 + (uint32_t)((64 * (i & 1) + lane) * 4);
+    asm volatile(
+        "ds_write2_b32 %0, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %1, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %2, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %3, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %4, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %5, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %6, %8, %9 offset1:65\n\t"
+        "ds_write2_b32 %7, %8, %9 offset1:65\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        :
+        : "v"(a0), "v"(a0 + 1024u), "v"(a0 + 2048u), "v"(a0 + 3072u), "v"(a0 + 4096u), "v"(a0 + 5120u),
+          "v"(a0 + 6144u), "v"(a0 + 7168u), "v"(va), "v"(vb)
+        : "memory");
+  }
+  __syncthreads();
+  out[blockIdx.x * blockDim.x + threadIdx.x] = buf[threadIdx.x];
+}
+
 typedef void (*ProbeFn)(float*, int32_t);
 typedef void (*ValuFn)(float*, int32_t, uint64_t);
 
@@ -151,7 +185,8 @@ const ValuFn kValu[] = {valu_probe<0>,  valu_probe<1>,  valu_probe<2>,  valu_pro
                          valu_probe<16>, valu_probe<17>, valu_probe<18>, valu_probe<19>,
                          valu_probe<20>, valu_probe<21>, valu_probe<22>};
 const ProbeFn kLds[] = {lds_probe<4, false>, lds_probe<8, false>, lds_probe<16, false>,
-                        lds_probe<4, true>,  lds_probe<8, true>,  lds_probe<16, true>};
+                        lds_probe<4, true>,  lds_probe<8, true>,  lds_probe<16, true>,
+                        lds_write2_probe};
 
 }  // namespace
 
@@ -195,11 +230,12 @@ double laim_probe_valu(int32_t kind, int32_t blocks, int32_t iters, float* out) 
 // Accesses per lane and step of the LDS probe.
 int32_t laim_probe_lds_per_step(void) { return kLdsPerStep; }
 
-// LDS probe: mode 0..2 reads of 4, 8, 16 bytes per lane, 3..5 writes.
+// LDS probe: mode 0..2 reads of 4, 8, 16 bytes per lane, 3..5 writes, 6
+// ds_write2_b32 (8 bytes per lane, two dwords 65 words apart).
 // Bytes moved: blocks * 256 * iters * laim_probe_lds_per_step() * width.
 // Returns ms as above.
 double laim_probe_lds(int32_t mode, int32_t blocks, int32_t iters, float* out) {
-  if (mode < 0 || mode > 5 || blocks < 1 || iters < 1 || !out) return -1.0;
+  if (mode < 0 || mode > 6 || blocks < 1 || iters < 1 || !out) return -1.0;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
   hipLaunchKernelGGL(kLds[mode], dim3(blocks), dim3(256), 0, 0, out, iters);
