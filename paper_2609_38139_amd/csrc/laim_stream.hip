@@ -213,7 +213,7 @@ __device__ __forceinline__ void stream_check_rule(const KParams& kp, const float
 template <int DCT, int PW>
 __device__ __forceinline__ void stream_gather(const DevCode& c, const float* __restrict__ src, int64_t tile,
                                               int32_t erows, int32_t lane, int32_t mine, int32_t d,
-                                              int32_t pstride, float4* acc) {
+                                              int32_t pstride, bool live, float4* acc) {
   int32_t eix[PW][DCT];
   float4 v[PW][DCT];
 #pragma unroll
@@ -222,8 +222,18 @@ __device__ __forceinline__ void stream_gather(const DevCode& c, const float* __r
     for (int j = 0; j < DCT; ++j) {
       const int32_t e = __builtin_amdgcn_readlane(mine, j * pstride + p);
       eix[p][j] = (j < d) ? e : -1;
-      const int64_t row = (eix[p][j] >= 0) ? (int64_t)edge_check(e) * c.dcmax + edge_slot(e) : 0;
-      v[p][j] = nt_load4(src + stream_at(tile, erows, row, lane));
+      v[p][j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+  if (live) {  // a lane whose shots are all idle requests no memory
+#pragma unroll
+    for (int p = 0; p < PW; ++p) {
+#pragma unroll
+      for (int j = 0; j < DCT; ++j) {
+        const int32_t e = eix[p][j];
+        const int64_t row = (e >= 0) ? (int64_t)edge_check(e) * c.dcmax + edge_slot(e) : 0;
+        v[p][j] = nt_load4(src + stream_at(tile, erows, row, lane));
+      }
     }
   }
 #pragma unroll
@@ -251,7 +261,10 @@ __device__ __forceinline__ void stream_gather(const DevCode& c, const float* __r
 // messages while the syndrome does not change, so at a fixed point every
 // later sweep rewrites the same values, and both message buffers already
 // hold them: a tile whose shots are all retired or at a fixed point skips
-// the sweep, and the outputs are those of sweeping it.
+// the sweep, and within a swept tile a lane whose four shots are all idle
+// (retired, or with the shortcuts at a fixed point) neither reads nor
+// writes; the outputs are those of sweeping everything. (Retired shots'
+// messages are never read again.)
 template <int DCT>
 __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ src,
@@ -276,18 +289,19 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
   uint32_t idle4 = ld4b(w.done + tile * kStreamTile + kSV * lane);
   if (kp.skip) idle4 |= ld4b(w.conv + tile * kStreamTile + kSV * lane);
   if (!__any(idle4 != 0x01010101u)) return;
+  const bool live = idle4 != 0x01010101u;
   const int32_t mine = (lane < nidx) ? mine_raw : -1;
   const int32_t d = __builtin_amdgcn_readfirstlane(d_raw);
   float4 acc[DCT];
 #pragma unroll
   for (int j = 0; j < DCT; ++j) acc[j] = make_float4(kp.pi, kp.pi, kp.pi, kp.pi);
   if (DCT <= 8 && nidx <= 64 && pw == 1)
-    stream_gather<DCT, 1>(c, src, tile, erows, lane, mine, d, pstride, acc);
+    stream_gather<DCT, 1>(c, src, tile, erows, lane, mine, d, pstride, live, acc);
   else if (DCT <= 8 && nidx <= 64 && pw == 2)
-    stream_gather<DCT, 2>(c, src, tile, erows, lane, mine, d, pstride, acc);
+    stream_gather<DCT, 2>(c, src, tile, erows, lane, mine, d, pstride, live, acc);
   else if (DCT <= 8 && nidx <= 64 && pw == 3)
-    stream_gather<DCT, 3>(c, src, tile, erows, lane, mine, d, pstride, acc);
-  else {
+    stream_gather<DCT, 3>(c, src, tile, erows, lane, mine, d, pstride, live, acc);
+  else if (live) {
 #pragma unroll
     for (int j = 0; j < DCT; ++j) {
       if (j >= d) continue;
@@ -313,7 +327,7 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
     x[3][j] = fresh ? 0.0f : clampf(acc[j].w, C);
   }
   float4 old[DCT];
-  if (cmp) {
+  if (cmp && live) {
 #pragma unroll
     for (int j = 0; j < DCT; ++j)
       if (j < d) old[j] = nt_load4(src + stream_at(tile, erows, (int64_t)ch * c.dcmax + j, lane));
@@ -322,6 +336,7 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
 #pragma unroll
   for (int q = 0; q < kSV; ++q)
     stream_check_rule<DCT>(kp, x[q], d, ((s4 >> (8 * q)) ^ (uint32_t)d) & 1u, out[q]);
+  if (!live) return;
 #pragma unroll
   for (int j = 0; j < DCT; ++j) {
     if (j >= d) continue;
