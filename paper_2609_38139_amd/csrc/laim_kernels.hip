@@ -336,9 +336,9 @@ __device__ __forceinline__ GroupJob dead_job() {
 }
 
 // Applies a flip of qubit v to the correction and syndrome bitmaps.
+// s ^= H e_v: toggles the syndrome bits of qubit v's checks.
 template <int DV, bool REG>
-__device__ __forceinline__ void flip_qubit(const DevCode& c, int32_t v, uint32_t* zw, uint32_t* sw) {
-  atomicXor(&zw[v >> 5], 1u << (v & 31));
+__device__ __forceinline__ void toggle_checks(const DevCode& c, int32_t v, uint32_t* sw) {
   const int32_t dv = REG ? DV : c.var_deg[v];
 #pragma unroll
   for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
@@ -346,6 +346,16 @@ __device__ __forceinline__ void flip_qubit(const DevCode& c, int32_t v, uint32_t
     atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
   }
 }
+
+template <int DV, bool REG>
+__device__ __forceinline__ void flip_qubit(const DevCode& c, int32_t v, uint32_t* zw, uint32_t* sw) {
+  atomicXor(&zw[v >> 5], 1u << (v & 31));
+  toggle_checks<DV, REG>(c, v, sw);
+}
+
+// Bits 0..3 of `nib` to bit 0 of bytes 0..3: the four shifted copies
+// nib 2^(7i) occupy disjoint bits, so the product has no carries.
+__device__ __forceinline__ uint32_t spread4(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
 
 // Runs the units `src` hands out, one after another, all with the same
 // code and launch shape: the per-thread graph tables are built once and
@@ -447,53 +457,76 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     }
   }
   __syncthreads();
-  // the initial error as an LDS bitmap, read once from HBM (consecutive
-  // threads read consecutive bytes); the syndrome of a fresh start and the
-  // failure test at the end take it from there
+  // the initial error as an LDS bitmap, read once from HBM; the syndrome
+  // of a fresh start and the failure test at the end take it from there.
+  // A row of a multiple of 16 bytes at a 16-byte aligned address is read
+  // 16 bytes per thread (independent loads, bits packed by multiplies);
+  // other rows a byte per thread.
   if (member && alive) {
     const GroupJob job = job_at(g);
     if (job.e0row) {
-#pragma unroll 1
-      for (int32_t v = t; v < c.n; v += u.nt)
-        if (job.e0row[v] & 1u) atomicOr(&e0w[v >> 5], 1u << (v & 31));
+      const uint8_t* row = job.e0row;
+      if ((c.n & 15) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+#pragma unroll 4
+        for (int32_t q = t; q < (c.n >> 4); q += u.nt) {
+          const uint32_t b = pack_bit0(*reinterpret_cast<const uint4*>(row + 16 * q));  // qubits 16q ..
+          if (b) atomicOr(&e0w[q >> 1], b << ((q & 1) * 16));
+        }
+      } else {
+#pragma unroll 4
+        for (int32_t v = t; v < c.n; v += u.nt)
+          if (row[v] & 1u) atomicOr(&e0w[v >> 5], 1u << (v & 31));
+      }
     }
   }
   __syncthreads();
+  // the start syndrome: from a fresh start s = H e0, accumulated from the
+  // qubits of e0 (few) toggling the bits of their checks; on resume or from
+  // a given syndrome, each thread reads its checks' bits
+  bool from_e0 = false;
   if (member && alive) {
     const GroupJob job = job_at(g);
+    if (!u.resume && !job.s0row) {
+      from_e0 = true;
 #pragma unroll 1
-    for (int k = 0; k < CPT; ++k) {
-      const int32_t ch = t + k * u.nt;
-      if (ch >= c.m) continue;
-      uint32_t x = 0;
-      if (u.resume) {
-        x = job.st_s[ch];
-      } else if (job.s0row) {
-        x = job.s0row[ch];
-      } else {
-        const int32_t d = c.chk_deg[ch];
-        for (int32_t j = 0; j < d; ++j) {
-          const int32_t v = c.chk_var[(int64_t)ch * c.dcmax + j];
-          x ^= e0w[v >> 5] >> (v & 31);
+      for (int32_t wq = t; wq < nw; wq += u.nt) {
+        uint32_t r = e0w[wq];
+        while (r) {
+          const int32_t v = (wq << 5) + __builtin_ctz(r);
+          r &= r - 1u;
+          toggle_checks<DV, REG>(c, v, sw);
         }
       }
-      sb |= (x & 1u) << k;
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k) {
+        const int32_t ch = t + k * u.nt;
+        if (ch >= c.m) continue;
+        const uint32_t x = u.resume ? job.st_s[ch] : job.s0row[ch];
+        sb |= (x & 1u) << k;
+      }
     }
   }
   __syncthreads();
   if (member && alive) {
-    if (u.resume) {
-      const GroupJob job = job_at(g);
+    if (from_e0) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        if ((vmask >> k) & 1u) sb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+    } else {
+      if (u.resume) {
+        const GroupJob job = job_at(g);
 #pragma unroll 1
-      for (int32_t v = t; v < c.n; v += u.nt)
-        if (job.st_z[v] & 1u) atomicOr(&zw[v >> 5], 1u << (v & 31));
-    }
-#pragma unroll 1
-    for (int k = 0; k < CPT; ++k)
-      if ((sb >> k) & 1u) {
-        const int32_t ch = t + k * u.nt;
-        atomicOr(&sw[ch >> 5], 1u << (ch & 31));
+        for (int32_t v = t; v < c.n; v += u.nt)
+          if (job.st_z[v] & 1u) atomicOr(&zw[v >> 5], 1u << (v & 31));
       }
+#pragma unroll 1
+      for (int k = 0; k < CPT; ++k)
+        if ((sb >> k) & 1u) {
+          const int32_t ch = t + k * u.nt;
+          atomicOr(&sw[ch >> 5], 1u << (ch & 31));
+        }
+    }
   }
   if (member && sb) gw[kGwInit] = 1;
   __syncthreads();
@@ -726,6 +759,9 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
         float Lmax = -__builtin_inff();
+        // regular codes with qubits of degree 2: the check's qubits and the
+        // other check of each, read together up front (one round trip)
+        int32_t pe[DC], nbv[DC];
         if (REG && DV == 2) {
           // Qubit j has two messages: the check's own and the one of the
           // other check of the qubit (one read of the partner table for
@@ -733,9 +769,11 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           // (a regular variant runs only on codes whose every check has degree
           // DC and every qubit degree DV, so a row holds DC entries)
           const int32_t* prow = c.partner + (int64_t)ch * DC;
-          int32_t pe[DC];
 #pragma unroll
-          for (int j = 0; j < DC; ++j) pe[j] = prow[j];
+          for (int j = 0; j < DC; ++j) {
+            pe[j] = prow[j];
+            nbv[j] = nb[j];
+          }
 #pragma unroll
           for (int j = 0; j < DC; ++j) {
             const int32_t c2 = edge_check(pe[j]);
@@ -813,7 +851,19 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         while (fmask) {
           const int32_t jj = __builtin_ctz(fmask);
           fmask &= fmask - 1u;
-          const int32_t chosen = nb[jj];
+          int32_t chosen, c2 = 0;
+          if (REG && DV == 2) {  // from registers: the qubit and its other check
+            chosen = nbv[0];
+            c2 = edge_check(pe[0]);
+#pragma unroll
+            for (int j = 1; j < DC; ++j)
+              if (jj == j) {
+                chosen = nbv[j];
+                c2 = edge_check(pe[j]);
+              }
+          } else {
+            chosen = nb[jj];
+          }
           const uint32_t bit = 1u << (chosen & 31);
           uint32_t had;
           if (kp.conflict == kConflictOr) {
@@ -822,7 +872,13 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           } else {
             had = atomicXor(&flw[chosen >> 5], bit) & bit;
           }
-          flip_qubit<DV, REG>(c, chosen, zw, sw);
+          if (REG && DV == 2) {  // z ^= e_v; s ^= H e_v over the qubit's two checks
+            atomicXor(&zw[chosen >> 5], bit);
+            atomicXor(&sw[ch >> 5], 1u << (ch & 31));
+            atomicXor(&sw[c2 >> 5], 1u << (c2 & 31));
+          } else {
+            flip_qubit<DV, REG>(c, chosen, zw, sw);
+          }
           nflip += had ? -1 : 1;
         }
       }
@@ -945,8 +1001,19 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   if (alive) {
     const GroupJob job = job_at(g_res);
     if (job.z_out) {
+      uint8_t* zrow = job.z_out;
+      if ((c.n & 15) == 0 && (reinterpret_cast<uintptr_t>(zrow) & 15) == 0) {
+        // 16 bytes per thread from 16 bits of the bitmap
 #pragma unroll 1
-      for (int32_t v = t; v < c.n; v += u.nt) job.z_out[v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
+        for (int32_t q = t; q < (c.n >> 4); q += u.nt) {
+          const uint32_t b = zw[q >> 1] >> ((q & 1) * 16);
+          *reinterpret_cast<uint4*>(zrow + 16 * q) =
+              make_uint4(spread4(b & 15u), spread4((b >> 4) & 15u), spread4((b >> 8) & 15u), spread4((b >> 12) & 15u));
+        }
+      } else {
+#pragma unroll 1
+        for (int32_t v = t; v < c.n; v += u.nt) zrow[v] = (uint8_t)((zw[v >> 5] >> (v & 31)) & 1u);
+      }
     }
     if (job.s_out) {
 #pragma unroll 1
