@@ -40,8 +40,12 @@ CLOCK_GHZ = 2.4
 VALU_ISSUE_PER_CLK = 2
 VALU_SINGLE_TOPS = CU_COUNT * 64 * CLOCK_GHZ / 1000.0  # 39.3 T lane-ops/s, one instruction per clock
 VALU_PEAK_TOPS = VALU_ISSUE_PER_CLK * VALU_SINGLE_TOPS  # 78.6 T lane-ops/s
-LDS_BYTES_PER_CLK = 128  # per CU
-LDS_PEAK_TBS = CU_COUNT * LDS_BYTES_PER_CLK * CLOCK_GHZ / 1000.0  # 78.6 TB/s
+# LDS reads: 256 B per clock per CU (conflict-free 16-byte reads reach 97% of
+# it in the probe); narrower reads and every write form run slower (the
+# probe's table). The resident kernels' LDS side is priced by the measured
+# rates of the two access forms their sweeps use.
+LDS_BYTES_PER_CLK = 256  # per CU, reads
+LDS_PEAK_TBS = CU_COUNT * LDS_BYTES_PER_CLK * CLOCK_GHZ / 1000.0  # 157.3 TB/s
 
 
 RESIDENT_SOURCES = ("paper_2609_38139_amd/csrc/laim_kernels.hip", "paper_2609_38139_amd/csrc/device_math.h",
@@ -386,7 +390,8 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
     computed check-sweep. Beside
     it, the on-chip traffic the method needs -- each check-to-qubit message
     written once (4 B) and read by the d_v - 1 other checks of its qubit
-    (4 B each) per sweep -- against the LDS peak (128 B per clock per CU), and
+    (4 B each) per sweep -- as the time the LDS needs at the probe's measured
+    rates for the same access forms, a fraction of the launch, and
     the HBM bytes the launch must move (e0 in; z, s, t_clr, failure out).
     Stream form: HBM bytes of the sweeps (each message 4 B in and out, 1 B of
     syndrome per check) against 8 TB/s."""
@@ -412,8 +417,12 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
                 "bytes_per_msg_update": bytes_per_update, "decode_ms_per_launch": round(run["decode_ms"], 3)}
     ops = ops_per_check_sweep(P.bp, dc, dv, P)
     tops = check_sweeps * ops / dec_s / 1e12
-    lds_b = 4 * dc + 4 * dc * (dv - 1)
-    lds_tbs = check_sweeps * lds_b / dec_s / 1e12
+    # LDS: each message written once (4 B) and read by the d_v - 1 other
+    # checks of its qubit (4 B each) per sweep; busy time at the measured
+    # rates of the two access forms
+    rd_b, wr_b = 4 * dc * (dv - 1), 4 * dc
+    rates = lds_rates()
+    lds_busy = check_sweeps * (rd_b / rates["read_b32"] + wr_b / rates["write2_stride65"]) / 1e12 / dec_s
     hbm_b = S * (2 * n + m + 5)
     shape = code.resident_cfg(P.bp)
     prof = None
@@ -430,8 +439,14 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
            "ops_per_check_sweep": ops, "ops_per_msg_update": ops / (2.0 * dc),
            "decode_ms_per_launch": round(run["decode_ms"], 3), "launches_timed": steps,
            "check_sweeps_computed_per_launch": check_sweeps,
-           "lds": {"bytes_per_check_sweep": lds_b, "achieved_TBs": round(lds_tbs, 2),
-                   "peak_TBs": round(LDS_PEAK_TBS, 1), "frac": round(lds_tbs / LDS_PEAK_TBS, 4)},
+           "lds": {"read_bytes_per_check_sweep": rd_b, "write_bytes_per_check_sweep": wr_b,
+                   "read_TBs": round(check_sweeps * rd_b / dec_s / 1e12, 2),
+                   "write_TBs": round(check_sweeps * wr_b / dec_s / 1e12, 2),
+                   "probe_read_b32_TBs": round(rates["read_b32"], 2),
+                   "probe_write2_TBs": round(rates["write2_stride65"], 2),
+                   "busy_frac": round(lds_busy, 4),
+                   "what": "time the LDS needs for the sweeps' reads and writes at the probe's rates "
+                           "for the same access forms, as a fraction of the launch"},
            "hbm": {"algorithmic_bytes_per_launch": hbm_b, "GBs": round(hbm_b / dec_s / 1e9, 1),
                    "frac": round(hbm_b / dec_s / 1e9 / HBM_PEAK_GBS, 5)}}
     if prof is not None:
@@ -465,14 +480,8 @@ def host_cores():
                      "cpu_model": model, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
-def probes():
-    """Issue rate of one VALU instruction class at a time (eight independent
-    chains per lane, 2048 blocks of 256 threads) and LDS bandwidth of
-    conflict-free 4-, 8- and 16-byte accesses, from the probe library built
-    beside the decoder."""
+def _probe_lib():
     import ctypes as C
-
-    import torch
     lib = C.CDLL(os.path.join(ROOT, "paper_2609_38139_amd", "liblaim_probe.so"))
     lib.laim_probe_valu.restype = C.c_double
     lib.laim_probe_valu.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
@@ -482,8 +491,50 @@ def probes():
     lib.laim_probe_valu_name.argtypes = [C.c_int32]
     lib.laim_probe_valu_kinds.restype = C.c_int32
     lib.laim_probe_lds_per_step.restype = C.c_int32
-    per_step = lib.laim_probe_lds_per_step()
-    blocks, iters = 2048, 2048  # LDS probe: 32 KiB per block, 5 blocks per CU
+    return lib
+
+
+LDS_MODES = (("read", 4), ("read", 8), ("read", 16), ("write", 4), ("write", 8), ("write", 16),
+             ("write2_stride65", 8))
+
+
+def lds_probe_tbs(lib, mode, out, blocks=2048, iters=2048):
+    """Device-wide TB/s of LDS probe `mode` (32 KiB per block, 5 blocks per CU)."""
+    import ctypes as C
+    ms = lib.laim_probe_lds(mode, blocks, iters, C.c_void_p(out.data_ptr()))
+    if ms <= 0:
+        raise RuntimeError(f"LDS probe {mode} failed ({ms})")
+    return blocks * 256 * iters * lib.laim_probe_lds_per_step() * LDS_MODES[mode][1] / (ms * 1e-3) / 1e12
+
+
+_LDS_RATES = {}
+
+
+def lds_rates():
+    """Measured LDS rates (TB/s, whole device) of the access forms the
+    resident sweeps use: conflict-free ds_read_b32 (the partner gathers) and
+    ds_write2_b32 with the dwords 65 words apart (the message writes). Once
+    per process."""
+    import torch
+    if not _LDS_RATES:
+        lib = _probe_lib()
+        out = torch.empty((2048 * 256,), dtype=torch.float32, device="cuda")
+        _LDS_RATES["read_b32"] = lds_probe_tbs(lib, 0, out)
+        _LDS_RATES["write2_stride65"] = lds_probe_tbs(lib, 6, out)
+        del out
+    return _LDS_RATES
+
+
+def probes():
+    """Issue rate of one VALU instruction class at a time (eight independent
+    chains per lane, 2048 blocks of 256 threads) and LDS bandwidth of
+    conflict-free 4-, 8- and 16-byte accesses, from the probe library built
+    beside the decoder."""
+    import ctypes as C
+
+    import torch
+    lib = _probe_lib()
+    blocks, iters = 2048, 2048
     out = torch.empty((blocks * 256,), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     valu = {}
@@ -495,12 +546,8 @@ def probes():
         valu[lib.laim_probe_valu_name(k).decode()] = {
             "T_lane_ops_per_s": round(rate, 2), "per_CU_clock": round(rate / VALU_SINGLE_TOPS, 3)}
     lds = {}
-    for mode, (what, width) in enumerate((("read", 4), ("read", 8), ("read", 16), ("write", 4), ("write", 8),
-                                           ("write", 16), ("write2_stride65", 8))):
-        ms = lib.laim_probe_lds(mode, blocks, iters, C.c_void_p(out.data_ptr()))
-        if ms <= 0:
-            raise RuntimeError(f"LDS probe {mode} failed ({ms})")
-        tbs = blocks * 256 * iters * per_step * width / (ms * 1e-3) / 1e12
+    for mode, (what, width) in enumerate(LDS_MODES):
+        tbs = lds_probe_tbs(lib, mode, out, blocks, iters)
         lds[f"{what}_b{8 * width}"] = {"TB_per_s": round(tbs, 2), "frac_of_peak": round(tbs / LDS_PEAK_TBS, 3),
                                        "bytes_per_CU_clock": round(tbs * 1e12 / (CU_COUNT * CLOCK_GHZ * 1e9), 1)}
     return {"valu_peak_T_lane_ops_per_s": round(VALU_PEAK_TOPS, 1),
