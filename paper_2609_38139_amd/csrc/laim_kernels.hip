@@ -1227,12 +1227,13 @@ struct ServerJobs {
     case 8: CALL(4, 4, 2, BP, true); break;           \
     case 9: CALL(6, 3, 1, BP, true); break;           \
     case 10: CALL(6, 3, 2, BP, true); break;          \
+    case 11: CALL(6, 2, 1, BP, false); break;         \
     default: CALL(8, 4, 1, BP, false); break;         \
   }
 
 static const int kBatchVariants[][4] = {  // dc, dv, cpt, regular
     {2, 2, 1, 1}, {2, 2, 2, 1}, {4, 2, 1, 1}, {4, 2, 2, 1}, {4, 2, 4, 1}, {6, 2, 1, 1},
-    {6, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {6, 3, 1, 1}, {6, 3, 2, 1}, {8, 4, 1, 0}};
+    {6, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {6, 3, 1, 1}, {6, 3, 2, 1}, {6, 2, 1, 0}, {8, 4, 1, 0}};
 
 template <int BP>
 __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
@@ -1275,13 +1276,15 @@ static const ResVariant kResVariants[] = {
     LAIM_RES(6, 2, 1), LAIM_RES(6, 2, 2), LAIM_RES(6, 2, 4), LAIM_RES(6, 2, 8),
     LAIM_RES(4, 4, 1), LAIM_RES(4, 4, 2), LAIM_RES(4, 4, 4),
     LAIM_RES(6, 3, 1), LAIM_RES(6, 3, 2), LAIM_RES(6, 3, 4),
+    LAIM_RES_IRR(6, 2, 1), LAIM_RES_IRR(6, 2, 2), LAIM_RES_IRR(6, 2, 4), LAIM_RES_IRR(6, 2, 8),
     LAIM_RES_IRR(8, 4, 1), LAIM_RES_IRR(8, 4, 2), LAIM_RES_IRR(8, 4, 4),
 };
 
-// Template degrees for a code: exact ones for the regular families, the
-// padded (8, 4) variant otherwise -- and for qubit degree 2 when reg2 is
-// false (min-sum whose qubit-side clamp could bind; the exact variant skips
-// it).
+// Template degrees for a code: exact ones for the regular families, a
+// padded variant otherwise -- (6, 2) for checks of degree <= 6 on qubits of
+// degree <= 2 (the spacetime window codes of online decoding among them),
+// else (8, 4) -- and for qubit degree 2 when reg2 is false (min-sum whose
+// qubit-side clamp could bind; the exact variant skips it).
 static bool pick_degrees(const DevCode& c, bool reg2, int* dc, int* dv, int* reg) {
   static const int exact[][2] = {{2, 2}, {4, 2}, {6, 2}, {4, 4}, {6, 3}};
   if (c.regular) {
@@ -1292,6 +1295,12 @@ static bool pick_degrees(const DevCode& c, bool reg2, int* dc, int* dv, int* reg
         *reg = 1;
         return true;
       }
+  }
+  if (c.dcmax <= 6 && c.dvmax <= 2) {
+    *dc = 6;
+    *dv = 2;
+    *reg = 0;
+    return true;
   }
   if (c.dcmax <= 8 && c.dvmax <= 4) {
     *dc = 8;

@@ -273,6 +273,39 @@ def test_decode_irregular_graphs(L, orc, bp, form):
         compare_decode(L, orc, key, P, e0, form=form)
 
 
+@pytest.mark.parametrize("bp", ["minsum", "sumproduct"])
+def test_padded_degree2_variant(L, orc, bp):
+    """Codes with checks of degree <= 6 and qubits of degree <= 2 that are not
+    regular run the padded (6, 2) resident variant, in every launch shape: a
+    random graph with check degrees 1..6 and qubit degrees 1..2, and the 2D
+    toric code with alpha = 1 (its qubit-side clamp could bind, so the exact
+    degree-2 kernel is not used)."""
+    rng = np.random.default_rng(17)
+    m, n = 48, 90
+    H = np.zeros((m, n), dtype=np.uint8)
+    deg = np.zeros(m, dtype=int)
+    for v in range(n):
+        for _ in range(int(rng.integers(1, 3))):
+            free = np.nonzero((deg < 6) & (H[:, v] == 0))[0]
+            r = int(rng.choice(free))
+            H[r, v] = 1
+            deg[r] += 1
+    H = H[H.sum(1) > 0]
+    assert H.sum(0).max() <= 2 and H.sum(1).max() <= 6 and H.sum(1).min() >= 1 and H.sum(0).min() >= 1
+    graph = codes.from_dense(H, name="deg2-padded")
+    _code_cache[graph.name] = (graph, L.Code(graph, 0))
+    e0 = orc.sample_noise(graph, 0.1, 5, 0, 131)
+    for cfg in (None, {"checks_per_thread": 1}, {"checks_per_thread": 2, "shots_per_block": 2},
+                {"checks_per_thread": 4}, {"checks_per_thread": 8, "shots_per_block": 3}):
+        compare_decode(L, orc, graph.name, L.DecodeParams(bp=bp, q=0.1, rounds=16), e0, cfg=cfg,
+                       tag="padded (6, 2)")
+    code, dc = dcode(L, "toric2d:8")
+    e0 = orc.sample_noise(code, 0.06, 6, 0, 150)
+    for cfg in (None, {"checks_per_thread": 8}):
+        compare_decode(L, orc, "toric2d:8", L.DecodeParams(bp=bp, alpha=1.0, rounds=24), e0, cfg=cfg,
+                       form="resident", tag="alpha 1")
+
+
 def test_resident_launch_shapes_agree(L, orc):
     """Results do not depend on the resident launch shape."""
     code, dc = dcode(L, "toric2d:16")
