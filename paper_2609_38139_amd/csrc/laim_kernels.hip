@@ -750,6 +750,22 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       if (!same_state) noev = 0u;
       uint32_t act = sb & ~noev;
       int32_t nflip = 0;
+      // regular codes with qubits of degree 2: the qubits of an active check
+      // and the other check of each are read together (one round trip), and
+      // those of the next active check are requested before this one is
+      // evaluated, so that the round trip overlaps the evaluation
+      int32_t pe_n[DC], nb_n[DC];
+      auto fetch_rows = [&](int32_t kk) {
+        const int32_t chn = t + kk * u.nt;
+        const int32_t* prow = c.partner + (int64_t)chn * DC;
+        const int32_t* nrow = c.chk_var + (int64_t)chn * c.dcmax;
+#pragma unroll
+        for (int j = 0; j < DC; ++j) {
+          pe_n[j] = prow[j];
+          nb_n[j] = nrow[j];
+        }
+      };
+      if (REG && DV == 2 && act) fetch_rows(__builtin_ctz(act));
 #pragma unroll 1
       while (act) {
         const int32_t k = __builtin_ctz(act);
@@ -759,21 +775,19 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
         float Lmax = -__builtin_inff();
-        // regular codes with qubits of degree 2: the check's qubits and the
-        // other check of each, read together up front (one round trip)
         int32_t pe[DC], nbv[DC];
         if (REG && DV == 2) {
           // Qubit j has two messages: the check's own and the one of the
-          // other check of the qubit (one read of the partner table for
-          // all j), added to pi in ascending check order as everywhere.
-          // (a regular variant runs only on codes whose every check has degree
-          // DC and every qubit degree DV, so a row holds DC entries)
-          const int32_t* prow = c.partner + (int64_t)ch * DC;
+          // other check of the qubit, added to pi in ascending check order
+          // as everywhere. (A regular variant runs only on codes whose every
+          // check has degree DC and every qubit degree DV, so a row holds DC
+          // entries.)
 #pragma unroll
           for (int j = 0; j < DC; ++j) {
-            pe[j] = prow[j];
-            nbv[j] = nb[j];
+            pe[j] = pe_n[j];
+            nbv[j] = nb_n[j];
           }
+          if (act) fetch_rows(__builtin_ctz(act));
 #pragma unroll
           for (int j = 0; j < DC; ++j) {
             const int32_t c2 = edge_check(pe[j]);
