@@ -37,6 +37,12 @@ struct StreamWS {
   uint8_t* conv;     // the messages are a fixed point of the sweep for the current syndrome
   uint8_t* chg;      // a compared sweep changed a message
   uint8_t* evid;     // an active check passed Evidence in this round's feedback step
+  // live-shot compaction (with the exact shortcuts):
+  int32_t* sid;      // [ntile * kStreamTile]: the shot (0 .. nshots - 1) in each slot, -1 for none
+  int32_t* sid2;     // [ntile * kStreamTile]: scratch
+  int32_t* inv;      // [ntile * kStreamTile]: new slot -> old slot of a compaction
+  int32_t* ctl;      // [4]: tiles in use, compaction pending, live shots, tiles after it
+  uint8_t* s2;       // [ntile][m][kStreamTile]: scratch
   // sequential conflict rule only (else null)
   uint8_t* rq;       // [ntile][m][kStreamTile]: slot of the requested qubit (bits 0-6,
                      //   kStreamNoRequest if none), bit 7 whether the request applies
@@ -82,6 +88,16 @@ static StreamWS stream_carve(const DevCode& c, int32_t nshots, void* ws, size_t*
   off += sh1;
   w.evid = reinterpret_cast<uint8_t*>(p + off);
   off += sh1;
+  w.sid = reinterpret_cast<int32_t*>(p + off);
+  off += sh4;
+  w.sid2 = reinterpret_cast<int32_t*>(p + off);
+  off += sh4;
+  w.inv = reinterpret_cast<int32_t*>(p + off);
+  off += sh4;
+  w.ctl = reinterpret_cast<int32_t*>(p + off);
+  off += 256;
+  w.s2 = reinterpret_cast<uint8_t*>(p + off);
+  off += s_b;
   w.rq = nullptr;
   w.rkey = nullptr;
   if (seq) {
@@ -272,7 +288,7 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  if (ch >= c.m) return;
+  if (ch >= c.m || tile >= w.ctl[0]) return;
   const float C = kp.clamp;
   const int32_t pw = c.dvmax - 1;           // partners per edge
   const int32_t pstride = pw > 0 ? pw : 1;  // the partner table's row length
@@ -390,7 +406,7 @@ __device__ __forceinline__ void stream_request(const DevCode& c, const KParams& 
                                                int32_t d, const int32_t* nb, const float* Lv, int64_t tile,
                                                int32_t lane, int32_t q, int32_t r, uint64_t shot0) {
   const int32_t col = kSV * lane + q;
-  const uint64_t shot = shot0 + (uint64_t)(tile * kStreamTile + col);
+  const uint64_t shot = shot0 + (uint64_t)w.sid[tile * kStreamTile + col];
   float Lmax = 0.0f;
 #pragma unroll
   for (int j = 0; j < DCT; ++j)
@@ -491,7 +507,7 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  if (ch >= c.m) return;
+  if (ch >= c.m || tile >= w.ctl[0]) return;
   const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
   const uint32_t dn = ld4b(w.done + tile * kStreamTile + kSV * lane);
   const uint32_t act = s4 & ~dn & 0x01010101u;
@@ -569,7 +585,7 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
 __global__ void __launch_bounds__(256) stream_resolve(DevCode c, StreamWS w) {
   const int32_t col = threadIdx.x;
   const int64_t tile = blockIdx.x;
-  if (w.done[tile * kStreamTile + col]) return;
+  if (tile >= w.ctl[0] || w.done[tile * kStreamTile + col]) return;
   uint8_t* rq = w.rq + tile * c.m * kStreamTile + col;
   const uint32_t* rk = w.rkey + tile * c.m * kStreamTile + col;
 #pragma unroll 1
@@ -618,7 +634,7 @@ __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
   const int32_t lane = threadIdx.x & 63;
   const int32_t ch = stream_row();
   const int64_t tile = blockIdx.y;
-  if (ch >= c.m) return;
+  if (ch >= c.m || tile >= w.ctl[0]) return;
   const uint32_t live = ~ld4b(w.done + tile * kStreamTile + kSV * lane) & 0x01010101u;
   if (!live) return;
   const int32_t d = c.chk_deg[ch];
@@ -642,7 +658,7 @@ __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
 __global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
   const int32_t lane = threadIdx.x & 63;
   const int32_t v = stream_row();
-  if (v >= c.n) return;
+  if (v >= c.n || (int32_t)blockIdx.y >= w.ctl[0]) return;
   const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
   const uint32_t f4 = ld4b(w.fl + o);
   if (!f4) return;
@@ -677,7 +693,14 @@ __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int
 // Every shot slot of the tiles: shots beyond nshots start retired.
 __global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots, int32_t ntot) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    w.ctl[0] = ntot / kStreamTile;
+    w.ctl[1] = 0;
+    w.ctl[2] = 0;
+    w.ctl[3] = 0;
+  }
   if (i >= ntot) return;
+  w.sid[i] = (i < nshots) ? i : -1;
   w.anys[i] = 0u;
   w.done[i] = (i >= nshots) ? 1 : 0;
   w.newdone[i] = 0;
@@ -696,7 +719,7 @@ __global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp,
   const int32_t lane = threadIdx.x & 63;
   const int32_t v = stream_row();
   const int64_t tile = blockIdx.y;
-  if (v >= c.n) return;
+  if (v >= c.n || tile >= w.ctl[0]) return;
 #pragma unroll 1
   for (int q = 0; q < kSV; ++q) {
     const int32_t col = kSV * lane + q;
@@ -711,7 +734,7 @@ __global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp,
     } else {
       val = stream_belief(c, msg, tile, col, v, kp.pi, kp.clamp);
     }
-    L[i * c.n + v] = val;
+    L[(int64_t)w.sid[i] * c.n + v] = val;
   }
 }
 
@@ -733,6 +756,190 @@ __global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t
   } else if (idx < tz + ts + nshots) {
     const int64_t i = idx - tz - ts;
     tclr[i] = w.tclr[i];
+  }
+}
+
+// ---- live-shot compaction (with the exact shortcuts, over more than one
+// tile). A tile sweeps while any of its shots runs, so after most shots have
+// stopped the few still running are moved to the first tiles, in slot
+// order, and the per-tile kernels skip every tile past them: the number of
+// tiles in use is read on the device (w.ctl[0]), so the launch sequence and
+// its grids stay the same and a HIP graph may hold it. w.sid maps a slot to
+// its shot (the clocks' Philox words and the outputs go by shot). A shot's
+// outputs are written when it stops, since its slot may then be reused, and
+// those of the shots still running at the end.
+
+// z (rows 0 .. n) and s (rows n .. n + m) of the slots that just stopped
+// (only_new) or of every slot still running (!only_new) to the caller's
+// row-major outputs.
+__global__ void __launch_bounds__(256) stream_out_rows(DevCode c, StreamWS w, int32_t only_new, uint8_t* z,
+                                                       uint8_t* s) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t row = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (row >= c.n + c.m || tile >= w.ctl[0]) return;
+  const int64_t b = tile * kStreamTile + kSV * lane;
+  const uint32_t sel = only_new ? ld4b(w.newdone + b) : (~ld4b(w.done + b) & 0x01010101u);
+  if (!sel) return;
+  const bool isz = row < c.n;
+  const uint32_t v4 = isz ? ld4b(w.z + stream_at(tile, c.n, row, lane)) : ld4b(w.s + stream_at(tile, c.m, row - c.n, lane));
+#pragma unroll
+  for (int q = 0; q < kSV; ++q) {
+    if (!((sel >> (8 * q)) & 1u)) continue;
+    const int64_t sh = w.sid[b + q];
+    if (sh < 0) continue;
+    const uint8_t x = (uint8_t)((v4 >> (8 * q)) & 0xFFu);
+    if (isz)
+      z[sh * c.n + row] = x;
+    else
+      s[sh * c.m + (row - c.n)] = x;
+  }
+}
+
+// t_clr of the slots that just stopped (only_new) or of every slot still
+// running (!only_new).
+__global__ void __launch_bounds__(256) stream_out_tclr(StreamWS w, int32_t only_new, int32_t* tclr, int32_t ntot) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot || i >= w.ctl[0] * kStreamTile) return;
+  const bool sel = only_new ? (w.newdone[i] != 0) : (w.done[i] == 0);
+  const int32_t sh = w.sid[i];
+  if (sel && sh >= 0) tclr[sh] = w.tclr[i];
+}
+
+// The compaction's plan, in one block: the running slots of the tiles in use
+// in slot order (w.inv: new slot -> old slot), their number, the tiles they
+// need, and whether to move them -- when that frees at least a quarter of
+// the tiles in use, or all of them.
+__global__ void __launch_bounds__(1024) stream_compact_plan(StreamWS w) {
+  __shared__ int32_t part[1024];
+  const int32_t ntl = w.ctl[0];
+  const int32_t N = ntl * kStreamTile;
+  const int32_t per = (N + 1023) / 1024;
+  const int32_t b = (int32_t)threadIdx.x * per;
+  const int32_t e = min(b + per, N);
+  int32_t cnt = 0;
+  for (int32_t i = b; i < e; ++i) cnt += w.done[i] ? 0 : 1;
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int32_t off = 1; off < 1024; off <<= 1) {  // inclusive scan
+    const int32_t v = (int32_t)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const int32_t total = part[1023];
+  const int32_t nt = (total + kStreamTile - 1) / kStreamTile;
+  const bool go = nt < ntl && (nt == 0 || 4 * nt <= 3 * ntl);
+  if (go) {
+    int32_t pos = part[threadIdx.x] - cnt;
+    for (int32_t i = b; i < e; ++i)
+      if (!w.done[i]) w.inv[pos++] = i;
+  }
+  if (threadIdx.x == 0) {
+    w.ctl[1] = go ? 1 : 0;
+    w.ctl[2] = total;
+    w.ctl[3] = nt;
+  }
+}
+
+// Row `row` of an array of `rows` rows per tile: new slot j (< the number of
+// running shots) of the tiles after the compaction takes old slot inv[j],
+// from src to dst (4-byte elements: messages).
+__global__ void __launch_bounds__(256) stream_compact_f32(StreamWS w, int32_t rows, const float* __restrict__ src,
+                                                          float* __restrict__ dst) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t row = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
+  const int32_t nlive = w.ctl[2];
+  float v[kSV];
+#pragma unroll
+  for (int q = 0; q < kSV; ++q) {
+    const int64_t j = tile * kStreamTile + kSV * lane + q;
+    v[q] = 0.0f;
+    if (j < nlive) {
+      const int64_t i = w.inv[j];
+      v[q] = src[((i / kStreamTile) * rows + row) * kStreamTile + (i % kStreamTile)];
+    }
+  }
+  *reinterpret_cast<float4*>(dst + stream_at(tile, rows, row, lane)) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// The same for 1-byte elements (syndrome, correction).
+__global__ void __launch_bounds__(256) stream_compact_u8(StreamWS w, int32_t rows, const uint8_t* __restrict__ src,
+                                                         uint8_t* __restrict__ dst) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t row = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
+  const int32_t nlive = w.ctl[2];
+  uint32_t x = 0u;
+#pragma unroll
+  for (int q = 0; q < kSV; ++q) {
+    const int64_t j = tile * kStreamTile + kSV * lane + q;
+    if (j < nlive) {
+      const int64_t i = w.inv[j];
+      x |= (uint32_t)src[((i / kStreamTile) * rows + row) * kStreamTile + (i % kStreamTile)] << (8 * q);
+    }
+  }
+  st4b(dst + stream_at(tile, rows, row, lane), x);
+}
+
+// Copies rows of the tiles after the compaction back (from -> to), and
+// clears `from` when asked (the flip requests used as scratch). 16 bytes
+// per lane: 4 elements of 4 bytes or 16 of 1 byte (then rows cover 4
+// lanes' worth per 16 bytes: `ebytes` is the element size).
+__global__ void __launch_bounds__(256) stream_compact_back(StreamWS w, int32_t rows, int32_t ebytes,
+                                                           unsigned char* from, unsigned char* to, int32_t clear) {
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t row = stream_row();
+  const int64_t tile = blockIdx.y;
+  if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
+  const int64_t o = ((tile * rows + row) * kStreamTile + kSV * lane) * ebytes;
+  if (ebytes == 4) {
+    *reinterpret_cast<uint4*>(to + o) = *reinterpret_cast<const uint4*>(from + o);
+    if (clear) *reinterpret_cast<uint4*>(from + o) = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    *reinterpret_cast<uint32_t*>(to + o) = *reinterpret_cast<const uint32_t*>(from + o);
+    if (clear) *reinterpret_cast<uint32_t*>(from + o) = 0u;
+  }
+}
+
+// Per slot, gathered into scratch (anys holds t_clr, sid2 the shot, newdone
+// the fixed-point mark: all three are free at the end of a round) ...
+__global__ void __launch_bounds__(256) stream_compact_slots(StreamWS w, int32_t ntot) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!w.ctl[1] || j >= ntot) return;
+  if (j < w.ctl[2]) {
+    const int32_t i = w.inv[j];
+    w.anys[j] = (uint32_t)w.tclr[i];
+    w.sid2[j] = w.sid[i];
+    w.newdone[j] = w.conv[i];
+  } else {
+    w.anys[j] = 0xFFFFFFFFu;
+    w.sid2[j] = -1;
+    w.newdone[j] = 0;
+  }
+}
+
+// ... and put in place; the slots past the running shots are stopped.
+__global__ void __launch_bounds__(256) stream_compact_slots_back(StreamWS w, int32_t ntot) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!w.ctl[1] || j >= ntot) return;
+  w.tclr[j] = (int32_t)w.anys[j];
+  w.anys[j] = 0u;
+  w.sid[j] = w.sid2[j];
+  w.conv[j] = w.newdone[j];
+  w.newdone[j] = 0;
+  w.done[j] = (j < w.ctl[2]) ? 0 : 1;
+  w.chg[j] = 0;
+  w.evid[j] = 0;
+}
+
+__global__ void stream_compact_commit(StreamWS w) {
+  if (threadIdx.x == 0 && w.ctl[1]) {
+    w.ctl[0] = w.ctl[3];
+    w.ctl[1] = 0;
   }
 }
 
@@ -781,7 +988,31 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
   hipLaunchKernelGGL(stream_init_var, gvar, blk, 0, st, c, w);
   hipLaunchKernelGGL(stream_init_chk, gchk, blk, 0, st, c, w, e0, s0, nshots);
   hipLaunchKernelGGL(stream_status, dim3(gshot), blk, 0, st, kp, w, -1, nshots);
+  // live-shot compaction: with the exact shortcuts, over more than one tile
+  const bool compact = kp.skip && ntile > 1;
+  const dim3 gout((unsigned)((c.n + c.m + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const dim3 gmsg((unsigned)((c.m * c.dcmax + kStreamRowsPerBlock - 1) / kStreamRowsPerBlock), ntile);
+  const unsigned gslot = (unsigned)((ntot + 255) / 256);
+  auto out_new = [&]() {
+    hipLaunchKernelGGL(stream_out_rows, gout, blk, 0, st, c, w, 1, z, s);
+    hipLaunchKernelGGL(stream_out_tclr, dim3(gslot), blk, 0, st, w, 1, tclr, ntot);
+  };
   int cur = 0;
+  auto compaction = [&]() {
+    hipLaunchKernelGGL(stream_compact_plan, dim3(1), dim3(1024), 0, st, w);
+    hipLaunchKernelGGL(stream_compact_f32, gmsg, blk, 0, st, w, c.m * c.dcmax, w.msg[cur], w.msg[cur ^ 1]);
+    hipLaunchKernelGGL(stream_compact_back, gmsg, blk, 0, st, w, c.m * c.dcmax, 4,
+                       reinterpret_cast<unsigned char*>(w.msg[cur ^ 1]), reinterpret_cast<unsigned char*>(w.msg[cur]),
+                       0);
+    hipLaunchKernelGGL(stream_compact_u8, gchk, blk, 0, st, w, c.m, w.s, w.s2);
+    hipLaunchKernelGGL(stream_compact_back, gchk, blk, 0, st, w, c.m, 1, w.s2, w.s, 0);
+    hipLaunchKernelGGL(stream_compact_u8, gvar, blk, 0, st, w, c.n, w.z, w.fl);
+    hipLaunchKernelGGL(stream_compact_back, gvar, blk, 0, st, w, c.n, 1, w.fl, w.z, 1);
+    hipLaunchKernelGGL(stream_compact_slots, dim3(gslot), blk, 0, st, w, ntot);
+    hipLaunchKernelGGL(stream_compact_slots_back, dim3(gslot), blk, 0, st, w, ntot);
+    hipLaunchKernelGGL(stream_compact_commit, dim3(1), dim3(64), 0, st, w);
+  };
+  if (compact) out_new();
   bool fresh = true;
   if (L) hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1, 1, L,
                             nshots);
@@ -804,13 +1035,22 @@ hipError_t launch_stream(const DevCode& c, const KParams& kp, const uint8_t* e0,
     if (L)
       hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 1,
                          fresh ? 1 : 0, L, nshots);
+    if (compact) {
+      out_new();
+      if (r + 1 < kp.rounds) compaction();
+    }
   }
   if (L)
     hipLaunchKernelGGL(stream_beliefs_out, gvar, blk, 0, st, c, kp, w, w.msg[cur], 0, fresh ? 1 : 0,
                        L, nshots);
-  const int64_t tot = (int64_t)nshots * (c.n + c.m + 1);
-  hipLaunchKernelGGL(stream_out, dim3((unsigned)((tot + 255) / 256)), blk, 0, st, c, w, z, s, tclr,
-                     nshots);
+  if (compact) {  // the shots still running (the others were written when they stopped)
+    hipLaunchKernelGGL(stream_out_rows, gout, blk, 0, st, c, w, 0, z, s);
+    hipLaunchKernelGGL(stream_out_tclr, dim3(gslot), blk, 0, st, w, 0, tclr, ntot);
+  } else {
+    const int64_t tot = (int64_t)nshots * (c.n + c.m + 1);
+    hipLaunchKernelGGL(stream_out, dim3((unsigned)((tot + 255) / 256)), blk, 0, st, c, w, z, s, tclr,
+                       nshots);
+  }
   return hipGetLastError();
 }
 

@@ -3,12 +3,15 @@
 With skip_fixed the stream form compares sweeps 7, 15, ... and the last of
 each round against the messages they replace, marks the shots whose
 messages are a fixed point of the sweep, skips the sweep of a 256-shot tile
-whose shots are all retired or at a fixed point, and stops a shot at a
-fixed point whose active checks all fail Evidence (its later rounds would
-repeat the last one exactly). These tests check that z, s, t_clr, the
+whose shots are all retired or at a fixed point, stops a shot at a fixed
+point whose active checks all fail Evidence (its later rounds would repeat
+the last one exactly), and moves the shots still running to the first
+tiles once most have stopped. These tests check that z, s, t_clr, the
 beliefs and the failure flags are bit-identical with and without the
 shortcuts, and equal to the oracle (which runs every sweep of every round),
-on workloads where many shots get stuck, so that whole tiles stop."""
+on workloads where many shots get stuck, so that whole tiles stop, and on
+many tiles whose shots mostly stop early, so that the running shots are
+moved to the first tiles."""
 import numpy as np
 import pytest
 
@@ -52,6 +55,10 @@ CASES = [
     ("bb:6x6", dict(rounds=32), 0.05, 300),
     ("toric3d_point:6", dict(rounds=24), 0.05, 520),
     ("toric3d_membrane:4", dict(rounds=24, q=0.125), 0.06, 300),
+    # many tiles, most shots stopping early: the running shots are compacted
+    ("toric2d:12", dict(rounds=40), 0.03, 2000),
+    ("toric2d:12", dict(rounds=40, conflict="sequential", retire=False), 0.04, 1100),
+    ("toric2d:12", dict(bp="sumproduct", rounds=30, move="multi", conflict="xor"), 0.05, 1300),
 ]
 
 
