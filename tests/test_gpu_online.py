@@ -77,6 +77,17 @@ def test_online_stream_form_and_multi_moves(L, orc):
                                                  conflict="xor"), op_kw, 100, tag="multi xor")
 
 
+def test_online_stream_form_many_tiles(L, orc):
+    """Window decodes in the stream form over several 256-shot tiles, where
+    the shots still running after most have stopped are moved to the first
+    tiles (start syndromes, round offsets and per-window outputs included)."""
+    op_kw = dict(rounds_total=8, window=3, commit=2, p=0.015, p_meas=0.015)
+    run_both(L, orc, "toric2d:6", L.DecodeParams(alpha=1.25, rounds=12, iters=8), op_kw, 900, shot0=3,
+             tag="stream tiles")
+    run_both(L, orc, "toric2d:6", L.DecodeParams(alpha=1.25, rounds=12, iters=8, conflict="sequential"),
+             op_kw, 600, tag="stream tiles sequential")
+
+
 def test_online_given_errors(L, orc):
     """Given errors instead of sampled ones: a single measurement error, a
     single data error, and random histories (the last round's measurement
