@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--no-matrix", action="store_true",
                     help="skip the other benchmark configurations (2D sizes and p sweep, 3D, BB)")
     ap.add_argument("--probe-only", action="store_true", help="run the VALU and LDS probes and exit")
-    ap.add_argument("--leg", default="", choices=["", "continuous", "matrix_3d", "matrix_bb", "online"],
+    ap.add_argument("--leg", default="", choices=["", "continuous", "matrix_3d", "matrix_bb", "online", "bitcentric"],
                     help="run one secondary measurement alone, print it as JSON and exit (for profiling)")
     return ap.parse_args()
 
@@ -308,10 +308,23 @@ def bitcentric(laim, d=101, p=0.3, nshots=262144, q=0.1):
     sec = ev0.elapsed_time(ev1) / 1000.0
     fail = (e0 ^ out["z"]).any(dim=1).float().mean().item()
     ic = out["iclr"]
+    # Work per bit and iteration (checks of degree 2, bits of degree 2, one
+    # check per bit): the belief pi + m1 + m2 (2 double adds) and its sign
+    # test (1); per edge the check-to-bit message, the other edge's message
+    # with the check's syndrome sign (1), the bit-to-check sum pi + the other
+    # message (1) and the LLR switch of both (2); the prior's switch (1); the
+    # check's syndrome update s ^= f_v ^ f_w (1): 13 operations, every one a
+    # single VALU instruction, against one instruction per CU per clock (FP64
+    # and the sign and bit operations on 64-bit values are not dual-rate).
+    ops = 13
+    ach = nshots * d * d * ops / sec / 1e12
     return {"workload": f"periodic repetition d={d}, p={p}, q={q}, {d} iterations, {nshots} shots",
             "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
             "logical_error_rate": fail, "binomial_tail": float(binom.sf(d // 2, d, p)),
-            "mean_iclr_cleared": float(ic[ic > 0].float().mean().item()) if bool((ic > 0).any()) else None}
+            "mean_iclr_cleared": float(ic[ic > 0].float().mean().item()) if bool((ic > 0).any()) else None,
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_SINGLE_TOPS, 1),
+                         "unit": "Tops/s", "frac": round(ach / VALU_SINGLE_TOPS, 4),
+                         "ops_per_bit_iteration": ops}}
 
 
 def serving(laim, seconds):
@@ -795,7 +808,8 @@ def main():
                                        for bp, n in (("minsum", 4096), ("sumproduct", 2048))},
                 "matrix_3d": lambda: matrix_3d(laim, codes),
                 "matrix_bb": lambda: matrix_bb(laim, codes),
-                "online": lambda: {bp: online_leg(laim, codes, bp) for bp in ("minsum", "sumproduct")}}
+                "online": lambda: {bp: online_leg(laim, codes, bp) for bp in ("minsum", "sumproduct")},
+                "bitcentric": lambda: bitcentric(laim)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
     L = args.L
