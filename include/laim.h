@@ -389,6 +389,26 @@ laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_
                                    int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
                                    double* L_out, laim_stream stream);
 
+/* Forms of the bit-centric machine; both give the same results bit for bit.
+ * The chain form takes chains (checks {v, v + 1}, plus {0, n - 1} when
+ * periodic) of 2 to 1008 bits (3 to 1024 periodic) in which no bit other than
+ * bit 0 has its left check at the larger index: one wavefront per shot with
+ * each bit's messages in its lane's registers, run in the frame of the
+ * current error e0 ^ z (where the syndrome signs and the LLR switch cancel
+ * and each iteration shifts the messages one bit along the chain and adds
+ * the prior). The block form takes any code the call above accepts: one
+ * workgroup per shot with the messages in LDS. */
+#define LAIM_BC_AUTO 0  /* the chain form where it applies, else the block form */
+#define LAIM_BC_CHAIN 1
+#define LAIM_BC_BLOCK 2
+
+/* laim_decode_bitcentric_form -- laim_decode_bitcentric in `form`.
+ * Errors: as laim_decode_bitcentric; LAIM_EUNSUP for form = LAIM_BC_CHAIN
+ * on a code the chain form does not take; LAIM_EINVAL for an unknown form. */
+laim_status laim_decode_bitcentric_form(const laim_code* code, double q, const uint8_t* e0,
+                                        int32_t nshots, int32_t iters, int32_t form, uint8_t* z_out,
+                                        int32_t* iclr_out, double* L_out, laim_stream stream);
+
 /* -------------------------------------------------------- online decoding
  * Online decoding (Discussion: faults and syndrome rounds keep arriving; the
  * Tanner graph is promoted to a spacetime decoding graph and the local

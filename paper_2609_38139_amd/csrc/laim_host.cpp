@@ -733,27 +733,81 @@ laim_status laim_decode_continuous(const laim_code* code, const laim_continuous_
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "continuous-machine kernel");
 }
 
-laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_t* e0,
-                                   int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
-                                   double* L_out, laim_stream stream) {
+// Whether H is a chain over bits 0..n-1 in index order: each check is {v, v + 1}
+// for one v < n - 1, or {0, n - 1} when periodic (m = n), and each appears once.
+// swap0: bit 0 sums its right check's message first (its left check has the
+// larger index); a chain where another bit does so is not taken.
+static bool bit_chain(const laim_code* code, bool* periodic, int32_t* swap0) {
+  const int32_t n = code->n, m = code->m;
+  if (m != n - 1 && m != n) return false;
+  const bool per = (m == n);
+  if (n < (per ? 3 : 2)) return false;
+  std::vector<int32_t> left((size_t)n, -1), right((size_t)n, -1);
+  for (int32_t c = 0; c < m; ++c) {
+    const int32_t b0 = code->h_rowptr[c];
+    if (code->h_rowptr[c + 1] - b0 != 2) return false;
+    int32_t a = code->h_col[b0], b = code->h_col[b0 + 1];
+    if (a > b) std::swap(a, b);
+    if (b == a + 1) {
+      if (right[a] >= 0 || left[b] >= 0) return false;
+      right[a] = left[b] = c;
+    } else if (per && a == 0 && b == n - 1) {
+      if (left[0] >= 0 || right[n - 1] >= 0) return false;
+      left[0] = right[n - 1] = c;
+    } else {
+      return false;
+    }
+  }
+  *swap0 = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (left[v] >= 0 && right[v] >= 0 && left[v] > right[v]) {
+      if (v != 0) return false;
+      *swap0 = 1;
+    }
+  *periodic = per;
+  return true;
+}
+
+laim_status laim_decode_bitcentric_form(const laim_code* code, double q, const uint8_t* e0,
+                                        int32_t nshots, int32_t iters, int32_t form, uint8_t* z_out,
+                                        int32_t* iclr_out, double* L_out, laim_stream stream) {
   if (!code || nshots < 0 || iters < 0 || !(q > 0.0 && q < 1.0) ||
+      (form != LAIM_BC_AUTO && form != LAIM_BC_CHAIN && form != LAIM_BC_BLOCK) ||
       (nshots > 0 && (!e0 || !z_out || !iclr_out))) {
     set_error("laim_decode_bitcentric: bad arguments");
     return LAIM_EINVAL;
   }
-  if (nshots == 0) return LAIM_OK;
   for (int32_t c = 0; c < code->m; ++c)
     if (code->h_rowptr[c + 1] - code->h_rowptr[c] != 2) {
       set_error("the bit-centric machine needs every check of degree 2");
       return LAIM_EUNSUP;
     }
+  bool periodic = false;
+  int32_t swap0 = 0, K = 0, nl = 0;
+  const bool chain = form != LAIM_BC_BLOCK && bit_chain(code, &periodic, &swap0) &&
+                     bitchain_shape(code->n, periodic, &K, &nl);
+  if (form == LAIM_BC_CHAIN && !chain) {
+    set_error("the chain form needs a chain of 2..1008 bits (3..1024 periodic) whose bits "
+              "other than bit 0 list their left check first");
+    return LAIM_EUNSUP;
+  }
+  if (nshots == 0) return LAIM_OK;
   int32_t nt = 0;
   size_t lds = 0;
-  if (!bitcentric_shape(code->dev, code->device, &nt, &lds)) return LAIM_EUNSUP;
+  if (!chain && !bitcentric_shape(code->dev, code->device, &nt, &lds)) return LAIM_EUNSUP;
   DeviceGuard g(code->device);
-  hipError_t er = launch_bitcentric(code->dev, q, e0, nshots, iters, nt, lds, z_out, iclr_out, L_out,
-                                    (hipStream_t)stream);
+  hipError_t er = chain ? launch_bitchain(code->n, periodic, swap0, K, nl, q, e0, nshots, iters,
+                                          z_out, iclr_out, L_out, (hipStream_t)stream)
+                        : launch_bitcentric(code->dev, q, e0, nshots, iters, nt, lds, z_out,
+                                            iclr_out, L_out, (hipStream_t)stream);
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "bit-centric kernel");
+}
+
+laim_status laim_decode_bitcentric(const laim_code* code, double q, const uint8_t* e0,
+                                   int32_t nshots, int32_t iters, uint8_t* z_out, int32_t* iclr_out,
+                                   double* L_out, laim_stream stream) {
+  return laim_decode_bitcentric_form(code, q, e0, nshots, iters, LAIM_BC_AUTO, z_out, iclr_out,
+                                     L_out, stream);
 }
 
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg) {

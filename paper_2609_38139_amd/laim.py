@@ -32,6 +32,7 @@ SYMBOLS = [
     "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
     "laim_decode_bitcentric", "laim_decode_rounds_static", "laim_online_plan_create",
     "laim_online_plan_destroy", "laim_online_workspace_bytes", "laim_decode_online",
+    "laim_decode_bitcentric_form",
 ]
 
 STATIC_SCRATCH_BYTES = 32 << 20  # LAIM_STATIC_SCRATCH_BYTES
@@ -207,6 +208,7 @@ def lib():
         L.laim_decode_continuous.argtypes = [vp, C.POINTER(ContinuousParamsC), vp, u64, i32, vp, sz,
                                              vp, vp, vp, vp, vp, vp, i32, vp]
         L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
+        L.laim_decode_bitcentric_form.argtypes = [vp, C.c_double, vp, i32, i32, i32, vp, vp, vp, vp]
         L.laim_decode_rounds_static.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, vp, vp, vp,
                                                 vp, vp, i32, vp]
         L.laim_online_plan_create.argtypes = [vp, C.POINTER(OnlineParamsC), C.POINTER(vp)]
@@ -433,10 +435,14 @@ def decode_continuous(code: Code, params: ContinuousParams, e0, shot0: int = 0,
     return out
 
 
+BITCENTRIC_FORMS = {"auto": 0, "chain": 1, "block": 2}
+
+
 def decode_bitcentric(code: Code, q: float, e0, iters: int, want_beliefs: bool = False,
-                      stream=None) -> dict:
-    """``laim_decode_bitcentric``: returns device tensors z, iclr and (with
-    want_beliefs) L, the float64 beliefs of the last iteration."""
+                      stream=None, form: str = "auto") -> dict:
+    """``laim_decode_bitcentric_form``: returns device tensors z, iclr and
+    (with want_beliefs) L, the float64 beliefs of the last iteration. form:
+    "auto", "chain" (one wavefront per shot, chains only) or "block"."""
     import torch
     ns = e0.shape[0]
     _dev(e0, torch.uint8, (ns, code.n), "e0")
@@ -444,9 +450,12 @@ def decode_bitcentric(code: Code, q: float, e0, iters: int, want_beliefs: bool =
     out = {"z": torch.empty((ns, code.n), dtype=torch.uint8, device=dev),
            "iclr": torch.empty((ns,), dtype=torch.int32, device=dev),
            "L": torch.empty((ns, code.n), dtype=torch.float64, device=dev) if want_beliefs else None}
-    check(lib().laim_decode_bitcentric(code.handle, q, _ptr(e0), ns, iters, _ptr(out["z"]),
-                                       _ptr(out["iclr"]), _ptr(out["L"]), _stream(stream)),
-          "laim_decode_bitcentric")
+    if form not in BITCENTRIC_FORMS:
+        raise ValueError(f"unknown bit-centric form {form!r}")
+    check(lib().laim_decode_bitcentric_form(code.handle, q, _ptr(e0), ns, iters, BITCENTRIC_FORMS[form],
+                                            _ptr(out["z"]), _ptr(out["iclr"]), _ptr(out["L"]),
+                                            _stream(stream)),
+          "laim_decode_bitcentric_form")
     return out
 
 

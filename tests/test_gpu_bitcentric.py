@@ -1,9 +1,11 @@
 """Parity of the bit-centric machine on the GPU with the oracle (SM "Setup
 and algorithm"): corrections and clearing iterations bit for bit and the
 double-precision beliefs of the last iteration equal, on periodic and open
-repetition codes up to thousands of bits; and the paper's statement, on the
-GPU at scale, that the machine fails exactly when more than half of the bits
-are in error."""
+repetition codes up to thousands of bits, in both forms (the chain form, one
+wavefront per shot in the frame of the current error, and the block form,
+one workgroup per shot with its messages in LDS), which also agree with each
+other bit for bit; and the paper's statement, on the GPU at scale, that the
+machine fails exactly when more than half of the bits are in error."""
 import numpy as np
 import pytest
 
@@ -22,12 +24,13 @@ def L():
     return laim
 
 
-def compare(L, orc, code, q, p, nshots, iters, seed=0):
+def compare(L, orc, code, q, p, nshots, iters, seed=0, form="auto"):
     import torch
-    print(f"[bitcentric] n={code.H.cols} q={q} p={p} shots={nshots} iters={iters}", flush=True)
+    print(f"[bitcentric] n={code.H.cols} q={q} p={p} shots={nshots} iters={iters} form={form}",
+          flush=True)
     dc = L.Code(code, 0)
     e0 = orc.sample_noise(code, p, seed, 0, nshots)
-    g = L.decode_bitcentric(dc, q, torch.from_numpy(e0).cuda(), iters, want_beliefs=True)
+    g = L.decode_bitcentric(dc, q, torch.from_numpy(e0).cuda(), iters, want_beliefs=True, form=form)
     torch.cuda.synchronize()
     z, ic, Lg = g["z"].cpu().numpy(), g["iclr"].cpu().numpy(), g["L"].cpu().numpy()
     for i in range(nshots):
@@ -36,45 +39,119 @@ def compare(L, orc, code, q, p, nshots, iters, seed=0):
         assert np.array_equal(e0[i] ^ z[i], e_last), f"shot {i}: final error differs"
         assert ic[i] == icl, f"shot {i}: i_clr {ic[i]} vs {icl}"
         if iters > 0:
-            assert np.array_equal(Lg[i], Lt[-1]), f"shot {i}: beliefs differ"
+            # the machine's beliefs are never -0, so equal bits are required
+            assert np.array_equal(Lg[i].view(np.uint64), Lt[-1].view(np.uint64)), \
+                f"shot {i}: beliefs differ"
     return e0, z, ic
 
 
+@pytest.mark.parametrize("form", ["chain", "block"])
 @pytest.mark.parametrize("d", [5, 11, 21, 101])
 @pytest.mark.parametrize("p", [0.05, 0.25, 0.45])
-def test_periodic_repetition(L, orc, d, p):
-    compare(L, orc, codes.repetition(d, periodic=True), 0.1, p, 64, d + 3)
+def test_periodic_repetition(L, orc, d, p, form):
+    compare(L, orc, codes.repetition(d, periodic=True), 0.1, p, 64, d + 3, form=form)
 
 
-def test_open_chain_and_other_priors(L, orc):
-    """Bits of degree 1 at the ends; several priors."""
-    for q in (0.02, 0.3):
-        compare(L, orc, codes.repetition(16, periodic=False), q, 0.2, 48, 20)
+# chain lengths for every bits-per-lane variant of the chain form (1, 2, 4, 8
+# and 16 bits per lane), with the last lane full and partly filled, odd and
+# even iteration counts
+CHAIN_CASES = [(3, True, 4), (2, False, 3), (63, False, 64), (64, True, 65), (64, False, 31),
+               (65, True, 70), (128, True, 129), (127, False, 40), (200, True, 201),
+               (256, False, 99), (300, True, 120), (511, True, 80), (700, False, 90),
+               (1024, True, 60), (1008, False, 41)]
+
+
+@pytest.mark.parametrize("d,periodic,iters", CHAIN_CASES)
+def test_chain_form_every_lane_shape(L, orc, d, periodic, iters):
+    compare(L, orc, codes.repetition(d, periodic=periodic), 0.15, 0.3, 12, iters, seed=d,
+            form="chain")
+
+
+def test_chain_and_block_forms_agree_at_scale(L):
+    """65,536 shots of d = 101 at p = 0.3 (the measured workload's code and
+    noise): the two forms give the same corrections, clearing iterations and
+    belief bits on every shot."""
+    import torch
+    code = codes.repetition(101, periodic=True)
+    dc = L.Code(code, 0)
+    e0 = L.sample_noise(dc, 0.3, 9, 0, 65536)
+    a = L.decode_bitcentric(dc, 0.1, e0, 101, want_beliefs=True, form="chain")
+    b = L.decode_bitcentric(dc, 0.1, e0, 101, want_beliefs=True, form="block")
+    torch.cuda.synchronize()
+    assert torch.equal(a["z"], b["z"])
+    assert torch.equal(a["iclr"], b["iclr"])
+    assert torch.equal(a["L"].view(torch.int64), b["L"].view(torch.int64))
+
+
+def test_forms_on_other_graphs(L, orc):
+    """Codes the chain form does not take run in the block form under
+    "auto" and are refused under "chain": a chain whose checks are listed so
+    that bits other than bit 0 sum their right message first, and a graph of
+    degree-2 checks that is not a chain (a cycle with chords, bits of degree
+    up to 4)."""
+    import torch
+    rng = np.random.default_rng(3)
+    base = codes.repetition(24, periodic=True)
+    perm = rng.permutation(base.H.rows)
+    rows = [list(base.H.col[base.H.rowptr[c]:base.H.rowptr[c + 1]]) for c in perm]
+    relabelled = codes.Code("rep24_relabelled", codes.CSR.from_rows(base.H.rows, 24, rows), base.G, {})
+    n = 30
+    edges = [[v, (v + 1) % n] for v in range(n)] + [[v, (v + 7) % n] for v in range(0, n, 3)]
+    chords = codes.Code("cycle_chords", codes.CSR.from_rows(len(edges), n, edges),
+                        codes.CSR.from_rows(0, n, []), {})
+    for code in (relabelled, chords):
+        compare(L, orc, code, 0.2, 0.3, 32, 40, form="auto")
+        compare(L, orc, code, 0.2, 0.3, 32, 40, form="block")
+        dc = L.Code(code, 0)
+        with pytest.raises(L.LaimError):
+            L.decode_bitcentric(dc, 0.2, torch.zeros((2, code.H.cols), dtype=torch.uint8, device="cuda"),
+                                4, form="chain")
+
+
+@pytest.mark.parametrize("form", ["chain", "block"])
+def test_open_chain_and_other_priors(L, orc, form):
+    """Bits of degree 1 at the ends; several priors, including q = 1/2
+    (prior 0: nothing ever flips)."""
+    for q in (0.02, 0.3, 0.5):
+        compare(L, orc, codes.repetition(16, periodic=False), q, 0.2, 48, 20, form=form)
 
 
 def test_long_chains_several_bits_per_thread(L, orc):
-    """1001 bits (one per thread) and 2001 bits (two per thread, 148 KB of
-    LDS); 2501 bits do not fit in LDS and are refused."""
+    """Block form: 1001 bits (one per thread) and 2001 bits (two per thread,
+    148 KB of LDS; too long for the chain form, so "auto" takes the block
+    form); 2501 bits do not fit in LDS and are refused."""
     import torch
-    compare(L, orc, codes.repetition(1001, periodic=True), 0.1, 0.3, 6, 60)
+    compare(L, orc, codes.repetition(1001, periodic=True), 0.1, 0.3, 6, 60, form="block")
     compare(L, orc, codes.repetition(2001, periodic=True), 0.1, 0.45, 3, 40)
+    with pytest.raises(L.LaimError):
+        L.decode_bitcentric(L.Code(codes.repetition(2001, periodic=True), 0), 0.1,
+                            torch.zeros((1, 2001), dtype=torch.uint8, device="cuda"), 4, form="chain")
     dc = L.Code(codes.repetition(2501, periodic=True), 0)
     with pytest.raises(L.LaimError):
         L.decode_bitcentric(dc, 0.1, torch.zeros((1, 2501), dtype=torch.uint8, device="cuda"), 4)
 
 
-def test_no_iterations_and_clear_start(L, orc):
+@pytest.mark.parametrize("form", ["chain", "block"])
+def test_no_iterations_and_clear_start(L, orc, form):
+    """No iterations; a clear start (also the all-ones error, whose syndrome
+    is zero); and a launch of zero shots."""
     import torch
     code = codes.repetition(9)
     dc = L.Code(code, 0)
-    e0 = np.zeros((2, 9), dtype=np.uint8)
+    e0 = np.zeros((3, 9), dtype=np.uint8)
     e0[1, 3] = 1
-    g = L.decode_bitcentric(dc, 0.1, torch.from_numpy(e0).cuda(), 0)
-    assert g["iclr"].cpu().tolist() == [0, -1]
+    e0[2, :] = 1
+    g = L.decode_bitcentric(dc, 0.1, torch.from_numpy(e0).cuda(), 0, form=form)
+    assert g["iclr"].cpu().tolist() == [0, -1, 0]
     assert not g["z"].cpu().numpy().any()
+    g = L.decode_bitcentric(dc, 0.1, torch.from_numpy(e0).cuda(), 5, form=form)
+    assert g["iclr"].cpu().tolist()[::2] == [0, 0]
+    g = L.decode_bitcentric(dc, 0.1, torch.zeros((0, 9), dtype=torch.uint8, device="cuda"), 5, form=form)
+    assert g["z"].shape == (0, 9)
 
 
-def test_fails_exactly_above_half(L, orc):
+@pytest.mark.parametrize("form", ["chain", "block"])
+def test_fails_exactly_above_half(L, orc, form):
     """The SM's theorem: after d iterations on the periodic repetition code
     the machine has not returned to the zero error exactly when |E| > d/2;
     checked on every shot of a large GPU run (so the logical error rate is
@@ -84,7 +161,7 @@ def test_fails_exactly_above_half(L, orc):
         code = codes.repetition(d, periodic=True)
         dc = L.Code(code, 0)
         e0 = orc.sample_noise(code, p, 3, 0, 20000)
-        g = L.decode_bitcentric(dc, 0.1, torch.from_numpy(e0).cuda(), d)
+        g = L.decode_bitcentric(dc, 0.1, torch.from_numpy(e0).cuda(), d, form=form)
         e_fin = e0 ^ g["z"].cpu().numpy()
         ok = ~e_fin.any(axis=1)
         assert np.array_equal(ok, e0.sum(axis=1) < d / 2)
