@@ -155,153 +155,6 @@ __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0,
   if (t == 0) iclr_out[shot] = iclr;
 }
 
-// ---- chain form
-// On a chain (checks (v, v + 1), and (d - 1, 0) when periodic) the machine can
-// be carried in the frame of its current error x = e0 ^ z. With
-// M_{c->v} = (-1)^{x_v} m_{c->v} and Y_{v->c} = (-1)^{x_v} m_{v->c}, the
-// syndrome sign of a check of degree 2 (s_c = x_v ^ x_w) and the LLR switch
-// cancel, and one iteration is a shift and an add:
-//   Y^i_{v->c} = P_v + M^{i-1}_{c'->v},  P_v = (-1)^{e0_v} pi0, c' the other check;
-//   M^i_{c->v} = Y^{i-1}_{w->c},         w the other bit of c;
-//   L^i_v = (-1)^{x^{i-1}_v} (P_v + sum over c of M^{i-1}_{c->v}) (ascending c),
-// and x^i_v is 1 where the bracket is positive, 0 where it is negative, and
-// x^{i-1}_v where it is zero. Negation commutes with round-to-nearest, so the
-// doubles are the machine's up to the sign of a zero, which no decision reads
-// (a zero belief is written as +0, the sign the machine gives it). The
-// syndrome is zero exactly when x is constant along the chain.
-//
-// Messages of iteration i come from iteration i - 2 only, so the even and odd
-// iterations are two independent recursions; a neighbour's message is
-// exchanged across lanes one iteration before it is needed.
-//
-// One wavefront per shot: lane l holds bits K l + k, k < K (lane nl - 1 up to
-// bit d - 1, in slot kl); lanes from nl on are idle (prior 0, messages 0,
-// their own neighbours), and an open chain's ends take their missing message
-// from lane 63, which is idle. x is held as a 64-lane mask per slot.
-__device__ inline double bperm_f64(int32_t addr, double x) {
-  const int32_t lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
-  const int32_t hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
-  return __hiloint2double(hi, lo);
-}
-
-template <int K, bool PERIODIC>
-__global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, int32_t swap0, double pi0,
-                                                       const uint8_t* __restrict__ e0, int32_t nshots,
-                                                       int32_t iters, uint8_t* __restrict__ z_out,
-                                                       int32_t* __restrict__ iclr_out,
-                                                       double* __restrict__ L_out) {
-  const int32_t lane = threadIdx.x & 63;
-  const int64_t shot = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (shot >= nshots) return;  // whole wavefronts
-  const int32_t kl = d - 1 - K * (nl - 1);
-  const bool act = lane < nl;
-  const bool last = lane == nl - 1;
-  const uint8_t* er = e0 + shot * d;
-
-  double P[K];
-  uint64_t X[K], V[K];
-  uint32_t ebits = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int32_t v = K * lane + k;
-    const bool ok = act && v < d;
-    const uint32_t e = ok ? (uint32_t)(er[v] & 1u) : 0u;
-    ebits |= e << k;
-    P[k] = ok ? (e ? -pi0 : pi0) : 0.0;
-    X[k] = __builtin_amdgcn_ballot_w64(e != 0);
-    V[k] = __builtin_amdgcn_ballot_w64(ok);
-  }
-  const int32_t srcl = act ? (lane > 0 ? lane - 1 : (PERIODIC ? nl - 1 : 63)) : lane;
-  const int32_t srcr = act ? (lane < nl - 1 ? lane + 1 : (PERIODIC ? 0 : 63)) : lane;
-  const int32_t al = srcl * 4, ar = srcr * 4;
-  const bool first_swapped = PERIODIC && swap0 && lane == 0;
-
-  // [parity][slot]: Y towards the right and the left check; r*: the
-  // neighbours' boundary Y of the same parity
-  double YR[2][K], YL[2][K], rR[2], rL[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) YR[p][k] = YL[p][k] = 0.0;
-    rR[p] = rL[p] = 0.0;
-  }
-  auto count = [&]() {
-    int32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) c += __builtin_popcountll(X[k]);
-    return c;
-  };
-  int32_t c0 = count();
-  int32_t iclr = (c0 == 0 || c0 == d) ? 0 : -1;
-
-  auto step = [&](double (&yr)[K], double (&yl)[K], double& rr, double& rl, int32_t it) {
-    double ML[K], MR[K], Lg[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ML[k] = k ? yr[k - 1] : rr;
-      MR[k] = (k < K - 1) ? yl[k + 1] : rl;
-    }
-    if (K > 1 && kl < K - 1) {
-#pragma unroll
-      for (int k = 0; k < K - 1; ++k)
-        if (k == kl) MR[k] = last ? rl : MR[k];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      yr[k] = P[k] + ML[k];
-      yl[k] = P[k] + MR[k];
-      Lg[k] = yr[k] + MR[k];
-    }
-    if (PERIODIC && swap0) {
-      const double alt = yl[0] + ML[0];
-      Lg[0] = first_swapped ? alt : Lg[0];
-    }
-    double sr = yr[K - 1];
-    if (PERIODIC && K > 1 && kl < K - 1) {
-#pragma unroll
-      for (int k = 0; k < K - 1; ++k)
-        if (k == kl) sr = last ? yr[k] : sr;
-    }
-    rr = bperm_f64(al, sr);
-    rl = bperm_f64(ar, yl[0]);
-    if (L_out && it == iters) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int32_t v = K * lane + k;
-        if (act && v < d) {
-          const double Lo = ((X[k] >> lane) & 1u) ? -Lg[k] : Lg[k];
-          L_out[shot * d + v] = Lo + 0.0;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint64_t gt = __builtin_amdgcn_ballot_w64(Lg[k] > 0.0);
-      const uint64_t lt = __builtin_amdgcn_ballot_w64(Lg[k] < 0.0);
-      X[k] = (gt | (X[k] & ~lt)) & V[k];
-    }
-    if (iclr < 0) {
-      const int32_t c = count();
-      if (c == 0 || c == d) iclr = it;
-    }
-  };
-
-  int32_t it = 1;
-  for (; it + 1 <= iters; it += 2) {
-    step(YR[1], YL[1], rR[1], rL[1], it);
-    step(YR[0], YL[0], rR[0], rL[0], it + 1);
-  }
-  if (it <= iters) step(YR[1], YL[1], rR[1], rL[1], it);
-
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int32_t v = K * lane + k;
-    if (act && v < d)
-      z_out[shot * d + v] = (uint8_t)(((uint32_t)(X[k] >> lane) & 1u) ^ ((ebits >> k) & 1u));
-  }
-  if (lane == 0) iclr_out[shot] = iclr;
-}
-
 bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds) {
   if (c.dcmax != 2 || c.dvmax > 4) {
     set_error("the bit-centric machine needs checks of degree 2 and qubit degree <= 4");
@@ -339,37 +192,219 @@ hipError_t launch_bitcentric(const DevCode& c, double q, const uint8_t* e0, int3
   return hipGetLastError();
 }
 
-bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl) {
+// ---- chain form
+// On a chain (checks (v, v + 1), and (d - 1, 0) when periodic) the machine can
+// be carried in the frame of its current error x = e0 ^ z. With
+// M_{c->v} = (-1)^{x_v} m_{c->v} and Y_{v->c} = (-1)^{x_v} m_{v->c}, the
+// syndrome sign of a check of degree 2 (s_c = x_v ^ x_w) and the LLR switch
+// cancel, and one iteration is a shift and an add:
+//   Y^i_{v->c} = P_v + M^{i-1}_{c'->v},  P_v = (-1)^{e0_v} pi0, c' the other check;
+//   M^i_{c->v} = Y^{i-1}_{w->c},         w the other bit of c;
+//   L^i_v = (-1)^{x^{i-1}_v} (P_v + sum over c of M^{i-1}_{c->v}) (ascending c),
+// and x^i_v is 1 where the bracket is positive, 0 where it is negative, and
+// x^{i-1}_v where it is zero. Negation commutes with round-to-nearest, so the
+// doubles are the machine's up to the sign of a zero, which no decision reads
+// (a zero belief is written as +0, the sign the machine gives it). The
+// syndrome is zero exactly when x is constant along the chain.
+//
+// Messages of iteration i come from iteration i - 2 only, so the even and odd
+// iterations are two independent recursions; a neighbour's message is
+// exchanged across lanes one iteration before it is needed.
+//
+// A wavefront holds S shots, each on a segment of nl lanes. The first nl - r
+// lanes of a segment hold K bits and the last r (r = nl K - d <= nl) hold
+// K - 1, in order along the chain, so a lane's last bit is in slot K - 1 or
+// K - 2 whatever d is. Lanes outside the segments, and segments past the
+// last shot, are idle (prior 0, messages 0, their own neighbours); an open
+// chain's ends take their missing message from lane 63, which is idle. x is
+// held as a 64-lane mask per slot.
+__device__ inline double bperm_f64(int32_t addr, double x) {
+  const int32_t lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int32_t hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+template <int K, bool PERIODIC>
+__global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, int32_t S, double pi0,
+                                                       const uint8_t* __restrict__ e0, int32_t nshots,
+                                                       int32_t iters, uint8_t* __restrict__ z_out,
+                                                       int32_t* __restrict__ iclr_out,
+                                                       double* __restrict__ L_out) {
+  const int32_t lane = threadIdx.x & 63;
+  const int64_t shot0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * S;
+  if (shot0 >= nshots) return;  // whole wavefronts
+  const int32_t seg = lane / nl;
+  const int32_t lam = lane - seg * nl;  // lane within the segment
+  const int64_t shot = shot0 + seg;
+  const bool act = seg < S && shot < nshots;
+  const int32_t full = nl - (nl * K - d);  // lanes with K bits
+  const bool part = K > 1 && lam >= full;  // K - 1 bits: slot K - 1 unused
+  const int32_t b0 = lam * K - (lam > full ? lam - full : 0);  // the lane's first bit
+  const int32_t nb = act ? (part ? K - 1 : K) : 0;
+  const uint8_t* er = e0 + (act ? shot : 0) * d;
+
+  double P[K];
+  uint64_t X[K], V[K];
+  uint32_t ebits = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool ok = k < nb;
+    const uint32_t e = ok ? (uint32_t)(er[b0 + k] & 1u) : 0u;
+    ebits |= e << k;
+    P[k] = ok ? (e ? -pi0 : pi0) : 0.0;
+    X[k] = __builtin_amdgcn_ballot_w64(e != 0);
+    V[k] = __builtin_amdgcn_ballot_w64(ok);
+  }
+  const int32_t srcl = !act ? lane : lam > 0 ? lane - 1 : PERIODIC ? lane + nl - 1 : 63;
+  const int32_t srcr = !act ? lane : lam < nl - 1 ? lane + 1 : PERIODIC ? lane - nl + 1 : 63;
+  const int32_t al = srcl * 4, ar = srcr * 4;
+  // bit 0 of a periodic chain lists its right check (0, 1) before the wrap
+  // check, so it sums its right message first
+  const bool first_swapped = PERIODIC && act && lam == 0;
+  const uint64_t seg0 = (nl >= 64) ? ~0ull : ((1ull << nl) - 1ull);
+
+  // [parity][slot]: Y towards the right and the left check; r*: the
+  // neighbours' boundary Y of the same parity
+  double YR[2][K], YL[2][K], rR[2], rL[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) YR[p][k] = YL[p][k] = 0.0;
+    rR[p] = rL[p] = 0.0;
+  }
+  // lanes of the segments whose syndrome is zero: x constant over the
+  // segment's bits
+  auto cleared = [&]() {
+    uint64_t any1 = 0, all1 = ~0ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      any1 |= X[k] & V[k];
+      all1 &= X[k] | ~V[k];
+    }
+    uint64_t cl = 0;
+    for (int32_t j = 0; j < S; ++j) {
+      const uint64_t m = seg0 << (j * nl);
+      if ((any1 & m) == 0 || (all1 & m) == m) cl |= m;
+    }
+    return cl;
+  };
+  int32_t iclr = ((cleared() >> lane) & 1ull) ? 0 : -1;
+  bool pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
+
+  // One iteration of one parity, in place: Y^i from Y^{i-2} (the lane's own
+  // and the neighbours' boundary ones), the beliefs, new x.
+  auto step = [&](double (&yr)[K], double (&yl)[K], double& rr, double& rl, int32_t it) {
+    const double ml0 = rr;
+    // towards the right check: from the left neighbour's, highest slot first
+    // so each old value is read before it is replaced
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) yr[k] = P[k] + (k ? yr[k - 1] : ml0);
+    // towards the left check: from the right neighbour's, lowest slot first
+    double Lg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double mr = (k < K - 1) ? yl[k + 1] : rl;
+      if (k == K - 2) mr = part ? rl : mr;  // a K - 1 bit lane's last bit
+      yl[k] = P[k] + mr;
+      Lg[k] = yr[k] + mr;
+    }
+    if (PERIODIC) {
+      const double alt = yl[0] + ml0;
+      Lg[0] = first_swapped ? alt : Lg[0];
+    }
+    const double sr = (K > 1 && part) ? yr[K > 1 ? K - 2 : 0] : yr[K - 1];
+    rr = bperm_f64(al, sr);
+    rl = bperm_f64(ar, yl[0]);
+    if (L_out && it == iters) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < nb) {
+          const double Lo = ((X[k] >> lane) & 1u) ? -Lg[k] : Lg[k];
+          L_out[shot * d + b0 + k] = Lo + 0.0;
+        }
+      }
+    }
+    // x <- 1 where the belief bracket is positive, 0 where negative (lanes
+    // outside a chain may change; every use masks them)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t gt = __builtin_amdgcn_ballot_w64(Lg[k] > 0.0);
+      const uint64_t lt = __builtin_amdgcn_ballot_w64(Lg[k] < 0.0);
+      X[k] = gt | (X[k] & ~lt);
+    }
+    if (pending) {
+      const uint64_t cl = cleared();
+      if (iclr < 0 && ((cl >> lane) & 1ull)) iclr = it;
+      pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
+    }
+  };
+
+  int32_t it = 1;
+  for (; it + 1 <= iters; it += 2) {
+    step(YR[1], YL[1], rR[1], rL[1], it);
+    step(YR[0], YL[0], rR[0], rL[0], it + 1);
+  }
+  if (it <= iters) step(YR[1], YL[1], rR[1], rL[1], it);
+
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (k < nb)
+      z_out[shot * d + b0 + k] = (uint8_t)(((uint32_t)(X[k] >> lane) & 1u) ^ ((ebits >> k) & 1u));
+  }
+  if (act && lam == 0) iclr_out[shot] = iclr;
+}
+
+bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl, int32_t* S) {
   // an open chain keeps lane 63 idle: its ends read their missing message there
   const int32_t cap = periodic ? 64 : 63;
   if (d < (periodic ? 3 : 2)) return false;
-  const int32_t need = (d + cap - 1) / cap;
-  int32_t k = 1;
-  while (k < need) k *= 2;
-  if (k > kBcChainMaxK) return false;
-  *K = k;
-  *nl = (d + k - 1) / k;
+  // bits per lane: the fewest VALU instructions per shot and iteration,
+  // about 5 per slot plus 7 per lane (the wrap bit's sum order and the
+  // selects of a lane with K - 1 bits), shared by the S shots of a
+  // wavefront; more than 8 bits per lane only where the chain needs it
+  // (their registers halve occupancy)
+  int32_t best = 0;
+  double best_cost = 0.0;
+  // (one bit per lane is never the cheapest: 12 instructions per lane)
+  for (int32_t k = 2; k <= kBcChainMaxK; k *= 2) {
+    const int32_t n_l = (d + k - 1) / k;
+    // lanes hold K or K - 1 bits: at most one unused slot per lane
+    if (n_l > cap || n_l * k - d > n_l) continue;
+    if (k > 8 && best) break;
+    const int32_t s = cap / n_l;
+    const double cost = (5.0 * k + 7.0) / s;
+    if (!best || cost < best_cost) {
+      best = k;
+      best_cost = cost;
+    }
+  }
+  if (!best) return false;
+  *K = best;
+  *nl = (d + best - 1) / best;
+  *S = cap / *nl;
   return true;
 }
 
-#define LAIM_BCHAIN_CASE(KK)                                                                       \
-  case KK:                                                                                      \
-    if (periodic)                                                                               \
-      hipLaunchKernelGGL((bitchain_kernel<KK, true>), grid, dim3(256), 0, st, d, nl, swap0, pi0, \
-                         e0, nshots, iters, z, iclr, L);                                        \
-    else                                                                                        \
-      hipLaunchKernelGGL((bitchain_kernel<KK, false>), grid, dim3(256), 0, st, d, nl, swap0,    \
-                         pi0, e0, nshots, iters, z, iclr, L);                                   \
+#define LAIM_BCHAIN_CASE(KK)                                                                  \
+  case KK:                                                                                     \
+    if (periodic)                                                                              \
+      hipLaunchKernelGGL((bitchain_kernel<KK, true>), grid, dim3(256), 0, st, d, nl, S, pi0,    \
+                         e0, nshots, iters, z, iclr, L);                                       \
+    else                                                                                       \
+      hipLaunchKernelGGL((bitchain_kernel<KK, false>), grid, dim3(256), 0, st, d, nl, S, pi0,   \
+                         e0, nshots, iters, z, iclr, L);                                       \
     break;
 
-hipError_t launch_bitchain(int32_t d, bool periodic, int32_t swap0, int32_t K, int32_t nl, double q,
+hipError_t launch_bitchain(int32_t d, bool periodic, int32_t K, int32_t nl, int32_t S, double q,
                            const uint8_t* e0, int32_t nshots, int32_t iters, uint8_t* z,
                            int32_t* iclr, double* L, hipStream_t st) {
   if (nshots <= 0) return hipSuccess;
+  if (S < 1 || nl < 1 || nl * S > 64) return hipErrorInvalidValue;
   const double pi0 = log(q / (1.0 - q));
-  const dim3 grid((unsigned)((nshots + 3) / 4));
+  // four wavefronts of S shots per workgroup
+  const int64_t per_block = 4 * (int64_t)S;
+  const dim3 grid((unsigned)((nshots + per_block - 1) / per_block));
   switch (K) {
-    LAIM_BCHAIN_CASE(1)
     LAIM_BCHAIN_CASE(2)
     LAIM_BCHAIN_CASE(4)
     LAIM_BCHAIN_CASE(8)

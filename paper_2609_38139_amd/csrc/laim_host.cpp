@@ -783,9 +783,11 @@ laim_status laim_decode_bitcentric_form(const laim_code* code, double q, const u
       return LAIM_EUNSUP;
     }
   bool periodic = false;
-  int32_t swap0 = 0, K = 0, nl = 0;
+  int32_t swap0 = 0, K = 0, nl = 0, S = 0;
+  // on a cycle some bit has its left check at the larger index; the chain
+  // form takes the cycles where that bit is bit 0 (and only bit 0)
   const bool chain = form != LAIM_BC_BLOCK && bit_chain(code, &periodic, &swap0) &&
-                     bitchain_shape(code->n, periodic, &K, &nl);
+                     swap0 == (periodic ? 1 : 0) && bitchain_shape(code->n, periodic, &K, &nl, &S);
   if (form == LAIM_BC_CHAIN && !chain) {
     set_error("the chain form needs a chain of 2..1008 bits (3..1024 periodic) whose bits "
               "other than bit 0 list their left check first");
@@ -796,8 +798,8 @@ laim_status laim_decode_bitcentric_form(const laim_code* code, double q, const u
   size_t lds = 0;
   if (!chain && !bitcentric_shape(code->dev, code->device, &nt, &lds)) return LAIM_EUNSUP;
   DeviceGuard g(code->device);
-  hipError_t er = chain ? launch_bitchain(code->n, periodic, swap0, K, nl, q, e0, nshots, iters,
-                                          z_out, iclr_out, L_out, (hipStream_t)stream)
+  hipError_t er = chain ? launch_bitchain(code->n, periodic, K, nl, S, q, e0, nshots, iters, z_out,
+                                          iclr_out, L_out, (hipStream_t)stream)
                         : launch_bitcentric(code->dev, q, e0, nshots, iters, nt, lds, z_out,
                                             iclr_out, L_out, (hipStream_t)stream);
   return er == hipSuccess ? LAIM_OK : hip_fail(er, "bit-centric kernel");

@@ -250,10 +250,10 @@ bool bitcentric_shape(const DevCode& c, int device, int32_t* nt, size_t* lds);
 hipError_t launch_bitcentric(const DevCode& c, double q, const uint8_t* e0, int32_t nshots,
                              int32_t iters, int32_t nt, size_t lds, uint8_t* z, int32_t* iclr,
                              double* L, hipStream_t st);
-// chain form: bits per lane K and lanes nl for a chain of d bits (false if
-// the chain is too short or too long for it)
-bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl);
-hipError_t launch_bitchain(int32_t d, bool periodic, int32_t swap0, int32_t K, int32_t nl, double q,
+// chain form: bits per lane K, lanes per shot nl and shots per wavefront S
+// for a chain of d bits (false if the chain is too short or too long for it)
+bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl, int32_t* S);
+hipError_t launch_bitchain(int32_t d, bool periodic, int32_t K, int32_t nl, int32_t S, double q,
                            const uint8_t* e0, int32_t nshots, int32_t iters, uint8_t* z,
                            int32_t* iclr, double* L, hipStream_t st);
 

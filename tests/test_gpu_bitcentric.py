@@ -52,13 +52,15 @@ def test_periodic_repetition(L, orc, d, p, form):
     compare(L, orc, codes.repetition(d, periodic=True), 0.1, p, 64, d + 3, form=form)
 
 
-# chain lengths for every bits-per-lane variant of the chain form (1, 2, 4, 8
-# and 16 bits per lane), with the last lane full and partly filled, odd and
-# even iteration counts
-CHAIN_CASES = [(3, True, 4), (2, False, 3), (63, False, 64), (64, True, 65), (64, False, 31),
-               (65, True, 70), (128, True, 129), (127, False, 40), (200, True, 201),
-               (256, False, 99), (300, True, 120), (511, True, 80), (700, False, 90),
-               (1024, True, 60), (1008, False, 41)]
+# chain lengths for every shape of the chain form: 2, 4, 8 and 16 bits per
+# lane, one to 64 shots per wavefront, lanes all full or some holding one bit
+# less, odd and even iteration counts; 12 shots, so the last wavefront is
+# partly empty
+CHAIN_CASES = [(2, False, 3), (3, True, 4), (5, True, 9), (6, False, 8), (9, True, 12),
+               (63, False, 64), (64, True, 65), (64, False, 31), (65, True, 70), (84, True, 85),
+               (101, True, 101), (128, True, 129), (127, False, 40), (200, True, 201),
+               (250, False, 99), (300, True, 120), (511, True, 80), (600, True, 70),
+               (700, False, 90), (1024, True, 60), (1008, False, 41)]
 
 
 @pytest.mark.parametrize("d,periodic,iters", CHAIN_CASES)
