@@ -272,23 +272,22 @@ __global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, in
     for (int k = 0; k < K; ++k) YR[p][k] = YL[p][k] = 0.0;
     rR[p] = rL[p] = 0.0;
   }
-  // lanes of the segments whose syndrome is zero: x constant over the
-  // segment's bits
-  auto cleared = [&]() {
-    uint64_t any1 = 0, all1 = ~0ull;
+  // The syndrome of a shot is zero when no two neighbouring bits of its
+  // segment differ in x (a ring's wrap check then agrees too). walls(): the
+  // lanes holding the left bit of such a pair, the wrap excepted.
+  const uint64_t v_full = __builtin_amdgcn_ballot_w64(act && !part);
+  const uint64_t v_part = __builtin_amdgcn_ballot_w64(act && part);
+  const uint64_t v_inner = __builtin_amdgcn_ballot_w64(act && lam < nl - 1);
+  auto walls = [&]() {
+    uint64_t w = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      any1 |= X[k] & V[k];
-      all1 &= X[k] | ~V[k];
-    }
-    uint64_t cl = 0;
-    for (int32_t j = 0; j < S; ++j) {
-      const uint64_t m = seg0 << (j * nl);
-      if ((any1 & m) == 0 || (all1 & m) == m) cl |= m;
-    }
-    return cl;
+    for (int k = 0; k + 1 < K; ++k) w |= (X[k] ^ X[k + 1]) & V[k + 1];
+    const uint64_t lastx = (X[K - 1] & v_full) | (X[K > 1 ? K - 2 : 0] & v_part);
+    return w | ((lastx ^ (X[0] >> 1)) & v_inner);
   };
-  int32_t iclr = ((cleared() >> lane) & 1ull) ? 0 : -1;
+  // this lane's segment, as a lane mask
+  const uint64_t myseg = act ? (seg0 << (seg * nl)) : 0ull;
+  int32_t iclr = ((walls() & myseg) == 0) ? 0 : -1;
   bool pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
 
   // One iteration of one parity, in place: Y^i from Y^{i-2} (the lane's own
@@ -333,8 +332,7 @@ __global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, in
       X[k] = gt | (X[k] & ~lt);
     }
     if (pending) {
-      const uint64_t cl = cleared();
-      if (iclr < 0 && ((cl >> lane) & 1ull)) iclr = it;
+      if (iclr < 0 && (walls() & myseg) == 0) iclr = it;
       pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
     }
   };
