@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_math.h"
 #include "laim_internal.h"
 
@@ -356,21 +358,24 @@ bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl, int32_t* 
   // an open chain keeps lane 63 idle: its ends read their missing message there
   const int32_t cap = periodic ? 64 : 63;
   if (d < (periodic ? 3 : 2)) return false;
-  // bits per lane: the fewest VALU instructions per shot and iteration,
-  // about 5 per slot plus 7 per lane (the wrap bit's sum order and the
-  // selects of a lane with K - 1 bits), shared by the S shots of a
-  // wavefront; more than 8 bits per lane only where the chain needs it
-  // (their registers halve occupancy)
+  // Bits per lane: the fewest VALU instructions per shot and iteration --
+  // about 5 per slot and 7 per lane (the wrap bit's sum order and the
+  // selects of a lane with K - 1 bits), shared by the S shots of a wavefront
+  // -- weighed by occupancy: the kernel takes about 13 K + 20 VGPRs, and
+  // below four wavefronts per SIMD the measured time per instruction grows
+  // (by about 10% at three and 40% at two). One bit per lane is never the
+  // cheapest.
   int32_t best = 0;
   double best_cost = 0.0;
-  // (one bit per lane is never the cheapest: 12 instructions per lane)
-  for (int32_t k = 2; k <= kBcChainMaxK; k *= 2) {
+  for (int32_t k = 2; k <= kBcChainMaxK; ++k) {
     const int32_t n_l = (d + k - 1) / k;
     // lanes hold K or K - 1 bits: at most one unused slot per lane
     if (n_l > cap || n_l * k - d > n_l) continue;
-    if (k > 8 && best) break;
     const int32_t s = cap / n_l;
-    const double cost = (5.0 * k + 7.0) / s;
+    const int32_t vgpr = (13 * k + 20 + 7) / 8 * 8;
+    const int32_t waves = std::min(8, 512 / vgpr);
+    const double slow = waves >= 4 ? 1.0 : waves == 3 ? 1.1 : waves == 2 ? 1.4 : 2.0;
+    const double cost = (5.0 * k + 7.0) / s * slow;
     if (!best || cost < best_cost) {
       best = k;
       best_cost = cost;
@@ -404,8 +409,19 @@ hipError_t launch_bitchain(int32_t d, bool periodic, int32_t K, int32_t nl, int3
   const dim3 grid((unsigned)((nshots + per_block - 1) / per_block));
   switch (K) {
     LAIM_BCHAIN_CASE(2)
+    LAIM_BCHAIN_CASE(3)
     LAIM_BCHAIN_CASE(4)
+    LAIM_BCHAIN_CASE(5)
+    LAIM_BCHAIN_CASE(6)
+    LAIM_BCHAIN_CASE(7)
     LAIM_BCHAIN_CASE(8)
+    LAIM_BCHAIN_CASE(9)
+    LAIM_BCHAIN_CASE(10)
+    LAIM_BCHAIN_CASE(11)
+    LAIM_BCHAIN_CASE(12)
+    LAIM_BCHAIN_CASE(13)
+    LAIM_BCHAIN_CASE(14)
+    LAIM_BCHAIN_CASE(15)
     LAIM_BCHAIN_CASE(16)
     default:
       return hipErrorInvalidValue;

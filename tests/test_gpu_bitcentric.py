@@ -52,15 +52,18 @@ def test_periodic_repetition(L, orc, d, p, form):
     compare(L, orc, codes.repetition(d, periodic=True), 0.1, p, 64, d + 3, form=form)
 
 
-# chain lengths for every shape of the chain form: 2, 4, 8 and 16 bits per
-# lane, one to 64 shots per wavefront, lanes all full or some holding one bit
-# less, odd and even iteration counts; 12 shots, so the last wavefront is
-# partly empty
-CHAIN_CASES = [(2, False, 3), (3, True, 4), (5, True, 9), (6, False, 8), (9, True, 12),
-               (63, False, 64), (64, True, 65), (64, False, 31), (65, True, 70), (84, True, 85),
-               (101, True, 101), (128, True, 129), (127, False, 40), (200, True, 201),
-               (250, False, 99), (300, True, 120), (511, True, 80), (600, True, 70),
-               (700, False, 90), (1024, True, 60), (1008, False, 41)]
+# chain lengths for every shape of the chain form: 2 to 16 bits per lane,
+# one to 64 shots per wavefront, lanes all full or some holding one bit
+# less, open and periodic, odd and even iteration counts; 12 shots, so the
+# last wavefront is partly empty
+CHAIN_CASES = [(2, False, 3), (3, True, 4), (3, False, 5), (4, True, 6), (250, False, 99),
+               (5, True, 9), (45, True, 46), (315, False, 40), (12, True, 13), (383, True, 50),
+               (101, True, 101), (84, True, 85), (63, False, 64), (64, True, 65), (64, False, 31),
+               (65, True, 70), (128, True, 129), (511, True, 80), (16, False, 20), (31, True, 31),
+               (9, True, 12), (26, False, 27), (575, True, 44), (200, True, 201), (300, True, 120),
+               (600, True, 70), (11, True, 14), (127, False, 40), (703, True, 33), (700, False, 90),
+               (760, False, 35), (831, True, 36), (850, True, 37), (900, True, 38), (1024, True, 60),
+               (1008, False, 41)]
 
 
 @pytest.mark.parametrize("d,periodic,iters", CHAIN_CASES)
