@@ -56,6 +56,10 @@ STREAM_SOURCES = ("paper_2609_38139_amd/csrc/laim_stream.hip", "paper_2609_38139
                   "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py")
 
 
+BITCENTRIC_SOURCES = ("paper_2609_38139_amd/csrc/laim_bitcentric.hip", "paper_2609_38139_amd/csrc/device_math.h",
+                      "paper_2609_38139_amd/csrc/laim_internal.h", "paper_2609_38139_amd/build.py")
+
+
 def profile_fields(profile: str, sources):
     """The machine-readable fields of a committed rocprofv3 summary, or None
     when the kernel sources (hashed in order) differ from the profiled ones."""
@@ -327,6 +331,14 @@ def bitcentric(laim, d=101, p=0.3, nshots=262144, q=0.1):
     # 8 of them exactly.
     ops = 5
     ach = nshots * d * d * ops / sec / 1e12
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_SINGLE_TOPS, 1), "unit": "Tops/s",
+            "frac": round(ach / VALU_SINGLE_TOPS, 4), "ops_per_bit_iteration": ops,
+            "kernel": "bitchain_kernel (chain form)", "decode_ms_per_launch": round(sec * 1e3, 4), "launches_timed": 10}
+    prof = profile_fields("bitchain_kernel_rep_d101.md", BITCENTRIC_SOURCES) \
+        if (d, p, nshots, q) == (101, 0.3, 262144, 0.1) else None
+    if prof is not None:
+        roof["profile"] = {k: prof[k] for k in ("avg_timed_launch_ns", "executed_valu_per_bit_iteration",
+                                                "valu_issue_frac", "source") if k in prof}
     return {"workload": f"periodic repetition d={d}, p={p}, q={q}, {d} iterations, {nshots} shots",
             "form": "chain", "shots_per_s": round(nshots / sec, 1), "decode_ms": round(sec * 1e3, 3),
             "logical_error_rate": fail, "binomial_tail": float(binom.sf(d // 2, d, p)),
@@ -334,9 +346,7 @@ def bitcentric(laim, d=101, p=0.3, nshots=262144, q=0.1):
             "block_form": {"shots_per_s": round(nshots / sec_b, 1), "decode_ms": round(sec_b * 1e3, 3),
                            "same_results": bool(torch.equal(out["z"], out_b["z"]) and
                                                 torch.equal(out["iclr"], out_b["iclr"]))},
-            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(VALU_SINGLE_TOPS, 1),
-                         "unit": "Tops/s", "frac": round(ach / VALU_SINGLE_TOPS, 4),
-                         "ops_per_bit_iteration": ops}}
+            "roofline": roof}
 
 
 def serving(laim, seconds):
