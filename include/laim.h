@@ -286,6 +286,21 @@ laim_status laim_decode_rounds_static(const laim_code* code, const laim_decode_p
                                       float* L_out, int32_t* sweeps_out, uint8_t* fail_out,
                                       int32_t form, laim_stream stream);
 
+/* laim_resident_variant -- the resident kernel laim_decode_rounds (or, with
+ * cfg, laim_decode_rounds_cfg) would run for these parameters: its template
+ * degrees, checks per thread, and whether it is the tiled variant. The tiled
+ * variant runs min-sum on the 2D toric layout (checks i L + j, L a multiple
+ * of 4, each sharing one qubit with each lattice neighbour) with 8 checks per
+ * thread and m / 8 threads per shot: each thread's checks form a 2 x 4 tile,
+ * and the messages on the 10 qubits inside a tile stay in the thread's
+ * registers through a round's sweeps. Results never depend on the variant.
+ * Any output pointer may be NULL. Errors: LAIM_EUNSUP when the code or the
+ * parameters cannot run in the resident form; LAIM_EINVAL for bad
+ * arguments. */
+laim_status laim_resident_variant(const laim_code* code, const laim_decode_params* params,
+                                  const laim_resident_cfg* cfg, int32_t* dc, int32_t* dv,
+                                  int32_t* checks_per_thread, int32_t* tiled);
+
 /* Sets the resident launch shape used from now on for this code and BP
  * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg);

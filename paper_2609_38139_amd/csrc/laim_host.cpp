@@ -293,6 +293,60 @@ laim_status laim_host_logicals(int32_t m, int32_t n, const int32_t* h_rowptr, co
   return LAIM_OK;
 }
 
+// The 2D toric layout (DevCode::tile_*): m = L^2 checks of degree 4 on
+// n = 2 m qubits of degree 2, L a multiple of 4, where check i L + j shares
+// exactly one qubit with each of (i, j -/+ 1) and (i -/+ 1, j) (indices mod L)
+// and those four qubits are its row. Fills the tiled variant's tables.
+static bool toric_tiles(int32_t m, int32_t n, int32_t dcmax, const std::vector<int32_t>& chk_deg,
+                        const std::vector<int32_t>& chk_var, const std::vector<int32_t>& vdeg,
+                        std::vector<int32_t>* tchk, std::vector<int32_t>* tjo,
+                        std::vector<int32_t>* tword) {
+  const int32_t L = (int32_t)lround(sqrt((double)m));
+  if (dcmax != 4 || L < 4 || L % 4 != 0 || L * L != m || n != 2 * m) return false;
+  for (int32_t c = 0; c < m; ++c)
+    if (chk_deg[c] != 4) return false;
+  for (int32_t v = 0; v < n; ++v)
+    if (vdeg[v] != 2) return false;
+  // jo[4 c + g]: the row slot of the qubit check c shares with its neighbour
+  // in direction g (0 left, 1 right, 2 up, 3 down)
+  std::vector<int32_t> jo((size_t)m * 4);
+  for (int32_t i = 0; i < L; ++i)
+    for (int32_t j = 0; j < L; ++j) {
+      const int32_t c = i * L + j;
+      const int32_t nb[4] = {i * L + (j + L - 1) % L, i * L + (j + 1) % L, ((i + L - 1) % L) * L + j,
+                             ((i + 1) % L) * L + j};
+      uint32_t used = 0u;
+      for (int g = 0; g < 4; ++g) {
+        int32_t slot = -1, count = 0;
+        for (int s = 0; s < 4; ++s)
+          for (int s2 = 0; s2 < 4; ++s2)
+            if (chk_var[(size_t)c * 4 + s] == chk_var[(size_t)nb[g] * 4 + s2]) {
+              ++count;
+              slot = s;
+            }
+        if (count != 1 || (used >> slot) & 1u) return false;
+        used |= 1u << slot;
+        jo[(size_t)c * 4 + g] = slot;
+      }
+    }
+  const int32_t nt = m / 8, tw = L / 4;
+  tchk->assign((size_t)m, 0);
+  tjo->assign((size_t)m * 4, 0);
+  tword->assign((size_t)m * 4, 0);
+  for (int32_t t = 0; t < nt; ++t)
+    for (int32_t k = 0; k < 8; ++k) {
+      const int32_t c = (2 * (t / tw) + (k >> 2)) * L + 4 * (t % tw) + (k & 3);
+      const int32_t vc = t + k * nt;
+      (*tchk)[vc] = c;
+      for (int g = 0; g < 4; ++g) {
+        const int32_t s = jo[(size_t)c * 4 + g];
+        (*tjo)[(size_t)vc * 4 + g] = s;
+        (*tword)[(size_t)c * 4 + s] = resident_msg_word(4, vc, g);
+      }
+    }
+  return true;
+}
+
 laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr,
                                  const int32_t* h_col, int32_t mg, const int32_t* g_rowptr,
                                  const int32_t* g_col, int32_t kl, const int32_t* l_rowptr,
@@ -383,12 +437,17 @@ laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr,
   std::vector<float> thr(dcmax + 1);
   for (int32_t d = 0; d <= dcmax; ++d) thr[d] = (d <= 1) ? INFINITY : (float)(-log((double)(d - 1)));
 
+  std::vector<int32_t> tile_chk, tile_jo, tile_word;
+  const bool tiled = toric_tiles(m, n, dcmax, chk_deg, chk_var, vdeg, &tile_chk, &tile_jo, &tile_word);
+
   // ---- one device allocation
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t b_cv = al(chk_var.size() * 4), b_cd = al((size_t)m * 4), b_vd = al((size_t)n * 4),
                b_ve = al(var_edge.size() * 4), b_pa = al(partner.size() * 4),
-               b_lc = al(lcol.size() * 4), b_th = al(thr.size() * 4);
-  const size_t total = b_cv + b_cd + b_vd + b_ve + b_pa + b_lc + b_th;
+               b_lc = al(lcol.size() * 4), b_th = al(thr.size() * 4),
+               b_tc = al(tile_chk.size() * 4), b_tj = al(tile_jo.size() * 4),
+               b_tw = al(tile_word.size() * 4);
+  const size_t total = b_cv + b_cd + b_vd + b_ve + b_pa + b_lc + b_th + b_tc + b_tj + b_tw;
   int prev = 0;
   (void)hipGetDevice(&prev);
   hipError_t he = hipSetDevice(device);
@@ -432,6 +491,9 @@ laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr,
   d.partner = (const int32_t*)up(partner.data(), partner.size() * 4, b_pa);
   d.lcol = (const uint32_t*)up(lcol.data(), lcol.size() * 4, b_lc);
   d.thr = (const float*)up(thr.data(), thr.size() * 4, b_th);
+  d.tile_chk = tiled ? (const int32_t*)up(tile_chk.data(), tile_chk.size() * 4, b_tc) : nullptr;
+  d.tile_jo = tiled ? (const int32_t*)up(tile_jo.data(), tile_jo.size() * 4, b_tj) : nullptr;
+  d.tile_word = tiled ? (const int32_t*)up(tile_word.data(), tile_word.size() * 4, b_tw) : nullptr;
   (void)hipSetDevice(prev);
   if (he != hipSuccess) {
     (void)hipFree(dmem);
@@ -555,6 +617,31 @@ static int resolve_form(const laim_code* code, int bp, bool seq, bool reg2, int 
   const bool ok = resident_shape(code->dev, bp, want, sh, code->device, seq, reg2);
   if (form == LAIM_FORM_RESIDENT) return ok ? LAIM_FORM_RESIDENT : -1;
   return ok ? LAIM_FORM_RESIDENT : LAIM_FORM_STREAM;
+}
+
+laim_status laim_resident_variant(const laim_code* code, const laim_decode_params* params,
+                                  const laim_resident_cfg* cfg, int32_t* dc, int32_t* dv,
+                                  int32_t* checks_per_thread, int32_t* tiled) {
+  if (!code || !params) {
+    set_error("laim_resident_variant: bad arguments");
+    return LAIM_EINVAL;
+  }
+  KParams kp;
+  laim_status st = resolve_params(params, &kp);
+  if (st != LAIM_OK) return st;
+  if (kp.bp == 0 && kp.alpha > 1.0f) {
+    set_error("the resident min-sum form needs alpha <= 1");
+    return LAIM_EUNSUP;
+  }
+  const bool seq = kp.conflict == kConflictSequential;
+  const laim_resident_cfg* want = cfg ? cfg : (code->has_cfg[kp.bp] ? &code->cfg[kp.bp] : nullptr);
+  ResidentShape sh;
+  if (!resident_shape(code->dev, kp.bp, want, &sh, code->device, seq, reg_dv2_ok(kp))) return LAIM_EUNSUP;
+  if (dc) *dc = sh.dc;
+  if (dv) *dv = sh.dv;
+  if (checks_per_thread) *checks_per_thread = sh.cpt;
+  if (tiled) *tiled = sh.tile;
+  return LAIM_OK;
 }
 
 size_t laim_workspace_bytes(const laim_code* code, const laim_decode_params* params,

@@ -33,7 +33,25 @@ struct DevCode {
                             // other than (c, j), ascending check
   const uint32_t* lcol;     // [n][kw] bit i of word w: qubit v in logical 32w + i
   const float* thr;         // [dcmax + 1] Evidence bound per check degree
+  // 2D toric layout (null otherwise): checks i L + j, L a multiple of 4, each
+  // sharing one qubit with each of its four lattice neighbours. Thread t of
+  // the tiled resident variant (8 checks per thread, m / 8 threads) owns the
+  // 2 x 4 tile of checks (2I + r, 4J + q), t = I L / 4 + J, as its checks
+  // k = 4 r + q; in LDS check k of thread t sits at virtual index t + k m / 8
+  // with its messages in lattice order (left, right, up, down neighbour).
+  const int32_t* tile_chk;   // [m] check at virtual index
+  const int32_t* tile_jo;    // [m][4] row slot of lattice direction g, by virtual index
+  const int32_t* tile_word;  // [m][4] LDS word of message (check, row slot)
 };
+
+// LDS word of message (check c, slot j) in the resident layout of checks of
+// degree dc: a slot of a group of 64 checks spans kResSlotStride words (64
+// used), so that messages of neighbouring checks in different slots fall in
+// different LDS banks.
+constexpr int kResSlotStride = 65;
+__host__ __device__ inline int32_t resident_msg_word(int32_t dc, int32_t c, int32_t j) {
+  return ((c >> 6) * dc + j) * kResSlotStride + (c & 63);
+}
 
 void set_error(const char* fmt, ...);
 laim_status hip_fail(hipError_t e, const char* what);
@@ -79,6 +97,7 @@ struct ResidentShape {
   int32_t group_bytes;  // LDS bytes of one shot's group
   size_t lds;    // dynamic LDS bytes per block
   int32_t dc, dv, reg;  // kernel variant degrees (reg: exact regular variant)
+  int32_t tile = 0;     // the tiled variant (2D toric layout, min-sum, 8 checks per thread)
 };
 
 // Whether the exact-degree kernels for qubit degree 2 may run: they skip the

@@ -270,10 +270,24 @@ hipError_t launch_failure(const DevCode& c, const uint8_t* e0, const uint8_t* z,
 // LDS word of message (check c, slot j) in the resident layout. A slot of
 // a tile spans kSlotStride words (64 used), so that messages of
 // neighbouring checks in different slots fall in different LDS banks.
-constexpr int kSlotStride = 65;
+constexpr int kSlotStride = kResSlotStride;
 template <int DC>
 __device__ __forceinline__ int32_t msg_word(int32_t c, int32_t j) {
-  return ((c >> 6) * DC + j) * kSlotStride + (c & 63);
+  return resident_msg_word(DC, c, j);
+}
+
+// Tiled variant (DevCode::tile_*): a thread's 8 checks form a 2 x 4 tile, so
+// 10 of the qubits they touch lie inside the tile. The message a check needs
+// on such a qubit is the other tile check's output of the previous sweep,
+// kept in a register; only the 12 messages on the tile's boundary go through
+// LDS during the sweeps. tile_partner(k, g) is the (check, direction) whose
+// output check k's input in direction g (0 left, 1 right, 2 up, 3 down)
+// reads, or -1 on the boundary.
+__host__ __device__ constexpr int tile_partner(int k, int g) {
+  return g == 0 ? ((k & 3) > 0 ? 4 * (k - 1) + 1 : -1)
+       : g == 1 ? ((k & 3) < 3 ? 4 * (k + 1) + 0 : -1)
+       : g == 2 ? ((k >> 2) == 1 ? 4 * (k - 4) + 3 : -1)
+                : ((k >> 2) == 0 ? 4 * (k + 4) + 2 : -1);
 }
 
 // What one group of a unit works on.
@@ -361,9 +375,11 @@ __device__ __forceinline__ uint32_t spread4(uint32_t nib) { return (nib * 0x0020
 // code and launch shape: the per-thread graph tables are built once and
 // stay in registers. Every thread of the block calls it (threads beyond
 // spb * nt only take part in the barriers).
-template <int DC, int DV, int CPT, int BP, bool REG, class Src>
+template <int DC, int DV, int CPT, int BP, bool REG, class Src, bool TILE = false>
 __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u, Src& src,
                           unsigned char* smem, int32_t* ctrl) {
+  static_assert(!TILE || (DC == 4 && DV == 2 && CPT == 8 && BP == 0 && REG),
+                "the tiled variant is min-sum on the 2D toric layout");
   const int32_t spb = u.spb;
   const int32_t tid = threadIdx.x;
   const int32_t g = tid / u.nt;
@@ -385,34 +401,48 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   const float C = kp.clamp;
   const float pi = kp.pi;
   const float thr_reg = REG ? c.thr[DC] : 0.0f;  // Evidence bound of the one check degree
+  // this thread's check k: its index in the code, and its index in the LDS
+  // layout (the same except in the tiled variant); the LDS word of message
+  // (check, row slot) of any check
+  auto own_ch = [&](int32_t k) -> int32_t { return TILE ? c.tile_chk[t + k * u.nt] : t + k * u.nt; };
+  auto mword = [&](int32_t ch, int32_t j) -> int32_t {
+    return TILE ? c.tile_word[ch * DC + j] : msg_word<DC>(ch, j);
+  };
 
   // ---- per-thread graph tables
   // A member owns checks t + k nt, k < CPT; those from m on pad the last
   // tile. Their LDS slots exist (mpad >= nt CPT) and they are swept like
   // the others -- inputs from the zero word, syndrome 0 -- so that the
   // sweep needs no per-check condition; nothing reads what they write.
+  // In the tiled variant slot j of a check's LDS messages is lattice
+  // direction j, whose row slot is tile_jo; pidx of an input inside the tile
+  // is not used.
   int32_t cidx[CPT];
   int32_t deg[CPT];
   int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
   uint32_t vmask = 0u;  // bit k: check k of this thread is one of the code's checks
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
-    const int32_t ch = t + k * u.nt;
-    const bool valid = member && ch < c.m;
+    const int32_t vk = t + k * u.nt;
+    const bool valid = member && vk < c.m;
+    const int32_t ch = (TILE && valid) ? c.tile_chk[vk] : vk;
     cidx[k] = member ? ch : -1;
     vmask |= (valid ? 1u : 0u) << k;
     deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
+      const int32_t jr = (TILE && valid) ? c.tile_jo[vk * DC + j] : j;
 #pragma unroll
       for (int p = 0; p < DV - 1; ++p) {
         int32_t e = -1;
-        if (valid && j < c.dcmax && p < c.dvmax - 1)
-          e = c.partner[((int64_t)ch * c.dcmax + j) * (c.dvmax - 1) + p];
-        pidx[k][j][p] = (e >= 0) ? msg_word<DC>(edge_check(e), edge_slot(e)) : zslot;
+        if (valid && jr < c.dcmax && p < c.dvmax - 1)
+          e = c.partner[((int64_t)ch * c.dcmax + jr) * (c.dvmax - 1) + p];
+        pidx[k][j][p] = (e >= 0) ? mword(edge_check(e), edge_slot(e)) : zslot;
       }
     }
   }
+  // the tile's inner outputs of the last sweep (tiled variant)
+  float io[TILE ? CPT : 1][DC];
 
   while (src.next(ctrl)) {
   const Src& job_at = src;
@@ -446,9 +476,9 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     }
 #pragma unroll 1
     for (int k = 0; k < CPT; ++k) {
-      const int32_t ch = t + k * u.nt;
+      const int32_t ch = t + k * u.nt;  // no resume in the tiled variant: its LDS index
       float* mk = msg + msg_word<DC>(ch, 0);
-      if (u.resume && alive && ch < c.m) {
+      if (!TILE && u.resume && alive && ch < c.m) {
         for (int j = 0; j < DC; ++j)
           mk[j * kSlotStride] = (j < c.dcmax) ? job.st_msg[(int64_t)ch * c.dcmax + j] : 0.0f;
       } else {  // fresh start, or a padding check
@@ -500,8 +530,8 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     } else {
 #pragma unroll 1
       for (int k = 0; k < CPT; ++k) {
-        const int32_t ch = t + k * u.nt;
-        if (ch >= c.m) continue;
+        if (t + k * u.nt >= c.m) continue;
+        const int32_t ch = own_ch(k);
         const uint32_t x = u.resume ? job.st_s[ch] : job.s0row[ch];
         sb |= (x & 1u) << k;
       }
@@ -512,7 +542,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     if (from_e0) {
 #pragma unroll
       for (int k = 0; k < CPT; ++k)
-        if ((vmask >> k) & 1u) sb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+        if ((vmask >> k) & 1u) {
+          const int32_t ch = TILE ? own_ch(k) : cidx[k];
+          sb |= ((sw[ch >> 5] >> (ch & 31)) & 1u) << k;
+        }
     } else {
       if (u.resume) {
         const GroupJob job = job_at(g);
@@ -523,7 +556,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll 1
       for (int k = 0; k < CPT; ++k)
         if ((sb >> k) & 1u) {
-          const int32_t ch = t + k * u.nt;
+          const int32_t ch = own_ch(k);
           atomicOr(&sw[ch >> 5], 1u << (ch & 31));
         }
     }
@@ -575,6 +608,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     // ---- BP sweeps, only while some working group is not at a fixed point
     const bool same_state = conv;  // nothing changed since the last feedback
     bool sweep = working && !conv;
+    bool swept = false;  // this group computed a sweep in this round
     if (anyw & 2) {
       int32_t it0 = 0;
       if (fresh && REG && kp.iters > 0) {
@@ -584,15 +618,28 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
             const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
-            float* mk = msg + msg_word<DC>(cidx[k], 0);
+            float* mk = msg + msg_word<DC>(TILE ? t + k * u.nt : cidx[k], 0);
 #pragma unroll
-            for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = z0;
+            for (int j = 0; j < DC; ++j) {
+              mk[j * kSlotStride] = z0;
+              if (TILE) io[TILE ? k : 0][j] = z0;
+            }
           }
         }
         fresh = false;
         it0 = 1;
         nsweeps += (sweep && nsweeps != 0x7fffffff) ? 1 : 0;  // saturating
         __syncthreads();
+      }
+      if (TILE && sweep && it0 == 0) {
+        // the tile's inner messages from LDS (written there by the flush of
+        // the last round that swept, or by the start): registers hold them
+        // only while the sweeps run
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+#pragma unroll
+          for (int j = 0; j < DC; ++j)
+            if (tile_partner(k, j) >= 0) io[TILE ? k : 0][j] = msg[msg_word<DC>(t + k * u.nt, j)];
       }
       // With CMP, a sweep may also compare each new message with the one
       // it replaces; comparing costs half a sweep's worth of extra VALU per
@@ -622,6 +669,9 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
               for (int k = 0; k < CPT; ++k) {
 #pragma unroll
                 for (int j = 0; j < DC; ++j) {
+                  // (inside a tile the input is formed after the barrier,
+                  // from a register)
+                  if (TILE && tile_partner(k, j) >= 0) continue;
                   float acc = pi;
 #pragma unroll
                   for (int p = 0; p < DV - 1; ++p) acc = acc + msg[pidx[k][j][p]];
@@ -642,8 +692,16 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           }
           uint32_t diff = 0u;
           if (sweep) {
+            float ion[TILE ? CPT : 1][DC];  // this sweep's inner outputs
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
+              if (TILE) {
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                  const int tp = tile_partner(k, j);
+                  if (tp >= 0) x[k][j] = pi + io[TILE ? tp >> 2 : 0][tp & 3];
+                }
+              }
               const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
               float out[DC];
               if (BP == 0) {
@@ -699,18 +757,33 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
                 for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
               }
-              float* mk = msg + msg_word<DC>(cidx[k], 0);
+              float* mk = msg + msg_word<DC>(TILE ? t + k * u.nt : cidx[k], 0);
               if (CMP) {  // padding checks and the padding slots of irregular checks are never read
                 uint32_t dk = 0u;
 #pragma unroll
-                for (int j = 0; j < DC; ++j)
-                  if (REG || j < deg[k]) dk |= __float_as_uint(mk[j * kSlotStride]) ^ __float_as_uint(out[j]);
+                for (int j = 0; j < DC; ++j) {
+                  const float old = (TILE && tile_partner(k, j) >= 0) ? io[TILE ? k : 0][j] : mk[j * kSlotStride];
+                  if (REG || j < deg[k]) dk |= __float_as_uint(old) ^ __float_as_uint(out[j]);
+                }
                 diff |= ((vmask >> k) & 1u) ? dk : 0u;
               }
 #pragma unroll
-              for (int j = 0; j < DC; ++j) mk[j * kSlotStride] = out[j];
+              for (int j = 0; j < DC; ++j) {
+                if (TILE && tile_partner(k, j) >= 0)
+                  ion[TILE ? k : 0][j] = out[j];  // read from a register within the tile
+                else
+                  mk[j * kSlotStride] = out[j];
+              }
+            }
+            if (TILE) {
+#pragma unroll
+              for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                for (int j = 0; j < DC; ++j)
+                  if (tile_partner(k, j) >= 0) io[TILE ? k : 0][j] = ion[TILE ? k : 0][j];
             }
           }
+          swept = swept || sweep;
           if (CMP && sweep && (diff || first)) {
             gw[f ? kGwChg1 : kGwChg0] = 1;
             ctrl[f ? kCtrlChg1 : kCtrlChg0] = 1;
@@ -732,6 +805,18 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         sweeps(BoolTag<true>());
       else
         sweeps(BoolTag<false>());
+      if (TILE) {
+        // the tile's inner messages back to LDS, for the feedback and the
+        // next round's sweeps (anyw is the same in every thread of the block)
+        if (swept) {
+#pragma unroll
+          for (int k = 0; k < CPT; ++k)
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+              if (tile_partner(k, j) >= 0) msg[msg_word<DC>(t + k * u.nt, j)] = io[TILE ? k : 0][j];
+        }
+        __syncthreads();
+      }
     }
 
     // ---- feedback: every active check whose clock rang tests Evidence
@@ -754,15 +839,19 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       // and the other check of each are read together (one round trip), and
       // those of the next active check are requested before this one is
       // evaluated, so that the round trip overlaps the evaluation
-      int32_t pe_n[DC], nb_n[DC];
+      int32_t pe_n[DC], nb_n[DC], ow_n[DC], pw_n[DC];
       auto fetch_rows = [&](int32_t kk) {
-        const int32_t chn = t + kk * u.nt;
+        const int32_t chn = own_ch(kk);
         const int32_t* prow = c.partner + (int64_t)chn * DC;
         const int32_t* nrow = c.chk_var + (int64_t)chn * c.dcmax;
 #pragma unroll
         for (int j = 0; j < DC; ++j) {
           pe_n[j] = prow[j];
           nb_n[j] = nrow[j];
+          if (TILE) {  // the LDS words of the check's messages and of the other check's
+            ow_n[j] = c.tile_word[chn * DC + j];
+            pw_n[j] = c.tile_word[edge_check(pe_n[j]) * DC + edge_slot(pe_n[j])];
+          }
         }
       };
       if (REG && DV == 2 && act) fetch_rows(__builtin_ctz(act));
@@ -770,12 +859,12 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
       while (act) {
         const int32_t k = __builtin_ctz(act);
         act &= act - 1u;
-        const int32_t ch = t + k * u.nt;
+        const int32_t ch = own_ch(k);
         const int32_t d = REG ? DC : c.chk_deg[ch];
         const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
         float Lv[DC];
         float Lmax = -__builtin_inff();
-        int32_t pe[DC], nbv[DC];
+        int32_t pe[DC], nbv[DC], ow[DC], pw[DC];
         if (REG && DV == 2) {
           // Qubit j has two messages: the check's own and the one of the
           // other check of the qubit, added to pi in ascending check order
@@ -786,13 +875,15 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           for (int j = 0; j < DC; ++j) {
             pe[j] = pe_n[j];
             nbv[j] = nb_n[j];
+            ow[j] = ow_n[j];
+            pw[j] = pw_n[j];
           }
           if (act) fetch_rows(__builtin_ctz(act));
 #pragma unroll
           for (int j = 0; j < DC; ++j) {
             const int32_t c2 = edge_check(pe[j]);
-            const float own = msg[msg_word<DC>(ch, j)];
-            const float oth = msg[msg_word<DC>(c2, edge_slot(pe[j]))];
+            const float own = msg[TILE ? ow[j] : msg_word<DC>(ch, j)];
+            const float oth = msg[TILE ? pw[j] : msg_word<DC>(c2, edge_slot(pe[j]))];
             const float acc = clampf(c2 < ch ? (pi + oth) + own : (pi + own) + oth, C);
             Lv[j] = acc;
             if (j == 0 || acc > Lmax) Lmax = acc;
@@ -807,7 +898,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
             for (int32_t q = 0; q < (REG ? DV : dv); ++q) {
               const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-              acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
+              acc = acc + msg[mword(edge_check(e), edge_slot(e))];
             }
             acc = clampf(acc, C);
             Lv[j] = acc;
@@ -920,7 +1011,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         while (pend) {
           const int32_t k = __builtin_ctz(pend);
           pend &= pend - 1u;
-          const int32_t ch = t + k * u.nt;
+          const int32_t ch = own_ch(k);
           const uint32_t key = rkey[ch];
           const int32_t d = REG ? DC : c.chk_deg[ch];
           const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
@@ -957,7 +1048,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         while (pend) {
           const int32_t k = __builtin_ctz(pend);
           pend &= pend - 1u;
-          const int32_t ch = t + k * u.nt;
+          const int32_t ch = own_ch(k);
           const uint32_t cur = rq[ch];
           rq[ch] = kNoRequest;
           if (!(cur >> 7)) continue;
@@ -979,7 +1070,12 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         uint32_t nsb = 0;
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-          if ((vmask >> k) & 1u) nsb |= ((sw[cidx[k] >> 5] >> (cidx[k] & 31)) & 1u) << k;
+          if ((vmask >> k) & 1u) {
+            // (the tiled variant reads its checks' indices again: registers
+            // are short there)
+            const int32_t ch = TILE ? own_ch(k) : cidx[k];
+            nsb |= ((sw[ch >> 5] >> (ch & 31)) & 1u) << k;
+          }
         sb = nsb;
       }
       if (sb) gw[(rr & 1) ? kGwAct1 : kGwAct0] = 1;
@@ -1031,10 +1127,8 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     }
     if (job.s_out) {
 #pragma unroll 1
-      for (int k = 0; k < CPT; ++k) {
-        const int32_t ch = t + k * u.nt;
-        if (ch < c.m) job.s_out[ch] = (uint8_t)((sb >> k) & 1u);
-      }
+      for (int k = 0; k < CPT; ++k)
+        if (t + k * u.nt < c.m) job.s_out[own_ch(k)] = (uint8_t)((sb >> k) & 1u);
     }
     if (job.t_out && t == 0) job.t_out[0] = tclr;
     if (job.sw_out && t == 0) job.sw_out[0] = nsweeps;
@@ -1045,7 +1139,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
         float acc = pi;
         for (int32_t q = 0; q < dv; ++q) {
           const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-          acc = acc + msg[msg_word<DC>(edge_check(e), edge_slot(e))];
+          acc = acc + msg[mword(edge_check(e), edge_slot(e))];
         }
         job.L_out[v] = clampf(acc, C);
       }
@@ -1053,10 +1147,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     if (job.st_msg) {
 #pragma unroll 1
       for (int k = 0; k < CPT; ++k) {
-        const int32_t ch = t + k * u.nt;
-        if (ch >= c.m) continue;
+        if (t + k * u.nt >= c.m) continue;
+        const int32_t ch = own_ch(k);
         for (int j = 0; j < c.dcmax && j < DC; ++j)
-          job.st_msg[(int64_t)ch * c.dcmax + j] = msg[msg_word<DC>(ch, j)];
+          job.st_msg[(int64_t)ch * c.dcmax + j] = msg[mword(ch, j)];
         job.st_s[ch] = (uint8_t)((sb >> k) & 1u);
       }
 #pragma unroll 1
@@ -1182,15 +1276,32 @@ struct ResJobs {
   }
 };
 
-template <int DC, int DV, int CPT, int BP, bool REG>
-__global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, ResArgs a) {
+template <int DC, int DV, int CPT, int BP, bool REG, bool TILE>
+__device__ __forceinline__ void resident_body(const DevCode& c, const KParams& kp, const ResArgs& a) {
   extern __shared__ __align__(16) unsigned char smem[];
   // control words after the groups, so that group 0's messages start at
   // LDS address 0 and the slot offsets fit the LDS instructions' offset fields
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + (size_t)a.u.spb * a.u.group_bytes);
   ResJobs jobs{a.items, a.nitems, a.e0,     a.s0,     a.r0,      a.shot0,   a.nshots, c.n, c.m, 0,
                a.z,     a.s,      a.tclr,   a.L,      a.fail,    a.sweeps,  a.counter, a.u.spb};
-  run_units<DC, DV, CPT, BP, REG>(c, kp, a.u, jobs, smem, ctrl);
+  run_units<DC, DV, CPT, BP, REG, ResJobs, TILE>(c, kp, a.u, jobs, smem, ctrl);
+}
+
+template <int DC, int DV, int CPT, int BP, bool REG>
+__global__ void __launch_bounds__(1024) resident_kernel(DevCode c, KParams kp, ResArgs a) {
+  resident_body<DC, DV, CPT, BP, REG, false>(c, kp, a);
+}
+
+// The tiled variant runs blocks of at most kTileMaxThreads threads with at
+// least kTileWavesPerSimd wavefronts per SIMD (128 VGPRs), as the plain
+// variant: measured on 2D toric L = 32, two and three wavefronts per SIMD
+// (no spills) ran 57% and 13% slower than four (a few spills outside the
+// sweeps).
+constexpr int kTileMaxThreads = 512;
+constexpr int kTileWavesPerSimd = 4;
+__global__ void __launch_bounds__(kTileMaxThreads, kTileWavesPerSimd)
+    resident_tile_kernel(DevCode c, KParams kp, ResArgs a) {
+  resident_body<4, 2, 8, 0, true, true>(c, kp, a);
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
@@ -1273,16 +1384,16 @@ __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
 typedef void (*ResKernel)(DevCode, KParams, ResArgs);
 
 struct ResVariant {
-  int dc, dv, cpt, bp, reg;
+  int dc, dv, cpt, bp, reg, tile;
   ResKernel fn;
 };
 
 #define LAIM_RES(DC, DV, CPT)                                                     \
-  {DC, DV, CPT, 0, 1, resident_kernel<DC, DV, CPT, 0, true>},                    \
-      {DC, DV, CPT, 1, 1, resident_kernel<DC, DV, CPT, 1, true>}
+  {DC, DV, CPT, 0, 1, 0, resident_kernel<DC, DV, CPT, 0, true>},                 \
+      {DC, DV, CPT, 1, 1, 0, resident_kernel<DC, DV, CPT, 1, true>}
 #define LAIM_RES_IRR(DC, DV, CPT)                                                 \
-  {DC, DV, CPT, 0, 0, resident_kernel<DC, DV, CPT, 0, false>},                   \
-      {DC, DV, CPT, 1, 0, resident_kernel<DC, DV, CPT, 1, false>}
+  {DC, DV, CPT, 0, 0, 0, resident_kernel<DC, DV, CPT, 0, false>},                \
+      {DC, DV, CPT, 1, 0, 0, resident_kernel<DC, DV, CPT, 1, false>}
 
 static const ResVariant kResVariants[] = {
     LAIM_RES(2, 2, 1), LAIM_RES(2, 2, 2), LAIM_RES(2, 2, 4), LAIM_RES(2, 2, 8),
@@ -1292,6 +1403,7 @@ static const ResVariant kResVariants[] = {
     LAIM_RES(6, 3, 1), LAIM_RES(6, 3, 2), LAIM_RES(6, 3, 4),
     LAIM_RES_IRR(6, 2, 1), LAIM_RES_IRR(6, 2, 2), LAIM_RES_IRR(6, 2, 4), LAIM_RES_IRR(6, 2, 8),
     LAIM_RES_IRR(8, 4, 1), LAIM_RES_IRR(8, 4, 2), LAIM_RES_IRR(8, 4, 4),
+    {4, 2, 8, 0, 1, 1, resident_tile_kernel},
 };
 
 // Template degrees for a code: exact ones for the regular families, a
@@ -1325,9 +1437,9 @@ static bool pick_degrees(const DevCode& c, bool reg2, int* dc, int* dv, int* reg
   return false;
 }
 
-static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg) {
+static const ResVariant* find_variant(int dc, int dv, int cpt, int bp, int reg, int tile = 0) {
   for (const auto& v : kResVariants)
-    if (v.dc == dc && v.dv == dv && v.cpt == cpt && v.bp == bp && v.reg == reg) return &v;
+    if (v.dc == dc && v.dv == dv && v.cpt == cpt && v.bp == bp && v.reg == reg && v.tile == tile) return &v;
   return nullptr;
 }
 
@@ -1410,6 +1522,11 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
   out->dc = dc;
   out->dv = dv;
   out->reg = reg;
+  // the tiled variant: min-sum on the 2D toric layout with its shape (8
+  // checks per thread, m / 8 threads per shot); the sequential rule keeps
+  // the plain variant
+  out->tile = (c.tile_chk && bp == 0 && dc == 4 && dv == 2 && reg && cpt == 8 && nt * 8 == c.m && !seq &&
+               nt * spb <= kTileMaxThreads) ? 1 : 0;
   return true;
 }
 
@@ -1495,7 +1612,7 @@ size_t resident_workspace_bytes() { return 256; }
 static hipError_t launch_resident_args(const DevCode& c, const KParams& kp, const ResidentShape& sh,
                                        ResArgs& a, int32_t total, hipStream_t st) {
   if (sh.reg && sh.dv == 2 && !reg_dv2_ok(kp)) return hipErrorInvalidValue;
-  const ResVariant* var = find_variant(sh.dc, sh.dv, sh.cpt, kp.bp, sh.reg);
+  const ResVariant* var = find_variant(sh.dc, sh.dv, sh.cpt, kp.bp, sh.reg, sh.tile);
   if (!var) return hipErrorInvalidValue;
   a.u.nt = sh.nt;
   a.u.vpt = sh.vpt;

@@ -32,7 +32,7 @@ SYMBOLS = [
     "laim_server_result", "laim_server_stats", "laim_server_destroy", "laim_decode_continuous",
     "laim_decode_bitcentric", "laim_decode_rounds_static", "laim_online_plan_create",
     "laim_online_plan_destroy", "laim_online_workspace_bytes", "laim_decode_online",
-    "laim_decode_bitcentric_form",
+    "laim_decode_bitcentric_form", "laim_resident_variant",
 ]
 
 STATIC_SCRATCH_BYTES = 32 << 20  # LAIM_STATIC_SCRATCH_BYTES
@@ -209,6 +209,7 @@ def lib():
                                              vp, vp, vp, vp, vp, vp, i32, vp]
         L.laim_decode_bitcentric.argtypes = [vp, C.c_double, vp, i32, i32, vp, vp, vp, vp]
         L.laim_decode_bitcentric_form.argtypes = [vp, C.c_double, vp, i32, i32, i32, vp, vp, vp, vp]
+        L.laim_resident_variant.argtypes = [vp, C.POINTER(Params), vp, i32p, i32p, i32p, i32p]
         L.laim_decode_rounds_static.argtypes = [vp, C.POINTER(Params), vp, u64, i32, vp, vp, vp, vp,
                                                 vp, vp, i32, vp]
         L.laim_online_plan_create.argtypes = [vp, C.POINTER(OnlineParamsC), C.POINTER(vp)]
@@ -295,6 +296,20 @@ class Code:
               "laim_get_resident_cfg")
         return {"threads_per_shot": cfg.threads_per_shot, "checks_per_thread": cfg.checks_per_thread,
                 "shots_per_block": cfg.shots_per_block}
+
+    def resident_variant(self, params: "DecodeParams", cfg: dict | None = None) -> dict:
+        """``laim_resident_variant``: the resident kernel a decode with these
+        parameters (and launch shape) would run."""
+        c = None
+        if cfg is not None:
+            c = ResidentCfg(cfg.get("threads_per_shot", 0), cfg.get("checks_per_thread", 0),
+                            cfg.get("shots_per_block", 0))
+        P = params.c()
+        out = [C.c_int32() for _ in range(4)]
+        check(lib().laim_resident_variant(self.handle, C.byref(P), C.byref(c) if c is not None else None,
+                                          *[C.byref(o) for o in out]), "laim_resident_variant")
+        return {"dc": out[0].value, "dv": out[1].value, "checks_per_thread": out[2].value,
+                "tiled": bool(out[3].value)}
 
     def set_resident_cfg(self, bp: str, cfg: dict | None):
         c = None
