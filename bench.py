@@ -451,11 +451,17 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
                 "kernel": f"stream form decode (2D toric L={args.L}, {P.bp})",
                 "bytes_per_msg_update": bytes_per_update, "decode_ms_per_launch": round(run["decode_ms"], 3)}
     ops = ops_per_check_sweep(P.bp, dc, dv, P)
+    tiled = code.resident_variant(P)["tiled"]
     tops = check_sweeps * ops / dec_s / 1e12
     # LDS: each message written once (4 B) and read by the d_v - 1 other
     # checks of its qubit (4 B each) per sweep; busy time at the measured
-    # rates of the two access forms
+    # rates of the two access forms. In the tiled variant only the 12
+    # messages on a tile's boundary (of 32 per 8 checks) go through LDS in a
+    # sweep (the inner 20 are written and read back once per round that
+    # swept, not counted here).
     rd_b, wr_b = 4 * dc * (dv - 1), 4 * dc
+    if tiled:
+        rd_b = wr_b = 4 * 12 / 8
     rates = lds_rates()
     lds_busy = check_sweeps * (rd_b / rates["read_b32"] + wr_b / rates["write2_stride65"]) / 1e12 / dec_s
     hbm_b = S * (2 * n + m + 5)
@@ -469,8 +475,9 @@ def roofline(laim, code, P, args, form, run, default_workload, steps=None):
     out = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 1), "unit": "Tops/s",
            "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
            "frac_of_single_issue": round(tops / VALU_SINGLE_TOPS, 4),
-           "kernel": f"resident_kernel (2D toric L={args.L}, {P.bp}, shape {shape['checks_per_thread']} checks "
-                     f"per thread x {shape['shots_per_block']} shots per block)",
+           "kernel": f"{'resident_tile_kernel' if tiled else 'resident_kernel'} (2D toric L={args.L}, {P.bp}, "
+                     f"shape {shape['checks_per_thread']} checks per thread x {shape['shots_per_block']} shots "
+                     f"per block{', 2x4 check tiles with inner messages in registers' if tiled else ''})",
            "ops_per_check_sweep": ops, "ops_per_msg_update": ops / (2.0 * dc),
            "decode_ms_per_launch": round(run["decode_ms"], 3), "launches_timed": steps,
            "check_sweeps_computed_per_launch": check_sweeps,
