@@ -300,8 +300,9 @@ laim_status laim_host_logicals(int32_t m, int32_t n, const int32_t* h_rowptr, co
 static bool toric_tiles(int32_t m, int32_t n, int32_t dcmax, const std::vector<int32_t>& chk_deg,
                         const std::vector<int32_t>& chk_var, const std::vector<int32_t>& vdeg,
                         std::vector<int32_t>* tchk, std::vector<int32_t>* tjo,
-                        std::vector<int32_t>* tword) {
+                        std::vector<int32_t>* tword, int32_t* Lout) {
   const int32_t L = (int32_t)lround(sqrt((double)m));
+  *Lout = L;
   if (dcmax != 4 || L < 4 || L % 4 != 0 || L * L != m || n != 2 * m) return false;
   for (int32_t c = 0; c < m; ++c)
     if (chk_deg[c] != 4) return false;
@@ -438,7 +439,9 @@ laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr,
   for (int32_t d = 0; d <= dcmax; ++d) thr[d] = (d <= 1) ? INFINITY : (float)(-log((double)(d - 1)));
 
   std::vector<int32_t> tile_chk, tile_jo, tile_word;
-  const bool tiled = toric_tiles(m, n, dcmax, chk_deg, chk_var, vdeg, &tile_chk, &tile_jo, &tile_word);
+  int32_t tile_L = 0;
+  const bool tiled =
+      toric_tiles(m, n, dcmax, chk_deg, chk_var, vdeg, &tile_chk, &tile_jo, &tile_word, &tile_L);
 
   // ---- one device allocation
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -494,6 +497,7 @@ laim_status laim_build_tanner_ex(int32_t m, int32_t n, const int32_t* h_rowptr,
   d.tile_chk = tiled ? (const int32_t*)up(tile_chk.data(), tile_chk.size() * 4, b_tc) : nullptr;
   d.tile_jo = tiled ? (const int32_t*)up(tile_jo.data(), tile_jo.size() * 4, b_tj) : nullptr;
   d.tile_word = tiled ? (const int32_t*)up(tile_word.data(), tile_word.size() * 4, b_tw) : nullptr;
+  d.tile_L = tiled ? tile_L : 0;
   (void)hipSetDevice(prev);
   if (he != hipSuccess) {
     (void)hipFree(dmem);

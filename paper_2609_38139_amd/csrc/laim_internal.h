@@ -42,6 +42,7 @@ struct DevCode {
   const int32_t* tile_chk;   // [m] check at virtual index
   const int32_t* tile_jo;    // [m][4] row slot of lattice direction g, by virtual index
   const int32_t* tile_word;  // [m][4] LDS word of message (check, row slot)
+  int32_t tile_L;            // L of the 2D toric layout (0 without one)
 };
 
 // LDS word of message (check c, slot j) in the resident layout of checks of

@@ -404,7 +404,16 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   // this thread's check k: its index in the code, and its index in the LDS
   // layout (the same except in the tiled variant); the LDS word of message
   // (check, row slot) of any check
-  auto own_ch = [&](int32_t k) -> int32_t { return TILE ? c.tile_chk[t + k * u.nt] : t + k * u.nt; };
+  // (a tile's checks are (2I + r) L + 4J + q: its first check plus an offset)
+  const int32_t tile0 = (TILE && member) ? c.tile_chk[t] : 0;
+  auto own_ch = [&](int32_t k) -> int32_t {
+    if (!TILE) return t + k * u.nt;
+    // recomputed where used (two instructions) rather than kept for all k:
+    // registers are the tiled variant's limit
+    int32_t b = tile0;
+    asm volatile("" : "+v"(b));
+    return b + (k >> 2) * c.tile_L + (k & 3);
+  };
   auto mword = [&](int32_t ch, int32_t j) -> int32_t {
     return TILE ? c.tile_word[ch * DC + j] : msg_word<DC>(ch, j);
   };
@@ -425,7 +434,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   for (int k = 0; k < CPT; ++k) {
     const int32_t vk = t + k * u.nt;
     const bool valid = member && vk < c.m;
-    const int32_t ch = (TILE && valid) ? c.tile_chk[vk] : vk;
+    const int32_t ch = (TILE && valid) ? own_ch(k) : vk;
     cidx[k] = member ? ch : -1;
     vmask |= (valid ? 1u : 0u) << k;
     deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
