@@ -406,14 +406,14 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   // (check, row slot) of any check
   // (a tile's checks are (2I + r) L + 4J + q: its first check plus an offset)
   const int32_t tile0 = (TILE && member) ? c.tile_chk[t] : 0;
+  // Recomputed where used (one or two instructions) rather than kept for
+  // every k: registers are the resident kernels' limit.
   auto own_ch = [&](int32_t k) -> int32_t {
-    if (!TILE) return t + k * u.nt;
-    // recomputed where used (two instructions) rather than kept for all k:
-    // registers are the tiled variant's limit
-    int32_t b = tile0;
+    int32_t b = TILE ? tile0 : t;
     asm volatile("" : "+v"(b));
-    return b + (k >> 2) * c.tile_L + (k & 3);
+    return TILE ? b + (k >> 2) * c.tile_L + (k & 3) : b + k * u.nt;
   };
+
   auto mword = [&](int32_t ch, int32_t j) -> int32_t {
     return TILE ? c.tile_word[ch * DC + j] : msg_word<DC>(ch, j);
   };
@@ -426,7 +426,6 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   // In the tiled variant slot j of a check's LDS messages is lattice
   // direction j, whose row slot is tile_jo; pidx of an input inside the tile
   // is not used.
-  int32_t cidx[CPT];
   int32_t deg[CPT];
   int32_t pidx[CPT][DC][DV > 1 ? DV - 1 : 1];
   uint32_t vmask = 0u;  // bit k: check k of this thread is one of the code's checks
@@ -435,7 +434,6 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
     const int32_t vk = t + k * u.nt;
     const bool valid = member && vk < c.m;
     const int32_t ch = (TILE && valid) ? own_ch(k) : vk;
-    cidx[k] = member ? ch : -1;
     vmask |= (valid ? 1u : 0u) << k;
     deg[k] = (valid && !REG) ? c.chk_deg[ch] : DC;
 #pragma unroll
@@ -552,7 +550,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
       for (int k = 0; k < CPT; ++k)
         if ((vmask >> k) & 1u) {
-          const int32_t ch = TILE ? own_ch(k) : cidx[k];
+          const int32_t ch = own_ch(k);
           sb |= ((sw[ch >> 5] >> (ch & 31)) & 1u) << k;
         }
     } else {
@@ -627,7 +625,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
           for (int k = 0; k < CPT; ++k) {
             const float z0 = (((sb >> k) ^ (uint32_t)DC) & 1u) ? -0.0f : 0.0f;
-            float* mk = msg + msg_word<DC>(TILE ? t + k * u.nt : cidx[k], 0);
+            float* mk = msg + msg_word<DC>(t + k * u.nt, 0);  // LDS index of check k
 #pragma unroll
             for (int j = 0; j < DC; ++j) {
               mk[j * kSlotStride] = z0;
@@ -766,7 +764,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
                 for (int j = 0; j < DC; ++j) out[j] = __builtin_amdgcn_fmed3f(sigma_neg ? -acc[j] : acc[j], -C, C);
               }
-              float* mk = msg + msg_word<DC>(TILE ? t + k * u.nt : cidx[k], 0);
+              float* mk = msg + msg_word<DC>(t + k * u.nt, 0);
               if (CMP) {  // padding checks and the padding slots of irregular checks are never read
                 uint32_t dk = 0u;
 #pragma unroll
@@ -1080,9 +1078,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
           if ((vmask >> k) & 1u) {
-            // (the tiled variant reads its checks' indices again: registers
-            // are short there)
-            const int32_t ch = TILE ? own_ch(k) : cidx[k];
+            const int32_t ch = own_ch(k);
             nsb |= ((sw[ch >> 5] >> (ch & 31)) & 1u) << k;
           }
         sb = nsb;
