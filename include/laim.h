@@ -302,7 +302,12 @@ laim_status laim_resident_variant(const laim_code* code, const laim_decode_param
                                   int32_t* checks_per_thread, int32_t* tiled);
 
 /* Sets the resident launch shape used from now on for this code and BP
- * rule (the autotuner's choice); cfg = NULL restores the built-in rule. */
+ * rule (the autotuner's choice); cfg = NULL restores the built-in rule:
+ * min-sum on the 2D toric layout takes the tiled variant (8 checks per
+ * thread, m / 8 threads per shot, blocks near 128 threads with wavefronts at
+ * least 80% full); otherwise 1, 2, 4 or 8 checks per thread for m up to 256,
+ * 512, 1024 and beyond, and 256-thread blocks. A field given as 0 in cfg is
+ * chosen by the same rule. */
 laim_status laim_set_resident_cfg(laim_code* code, int32_t bp, const laim_resident_cfg* cfg);
 /* The launch shape that would be used (after the built-in rule). */
 laim_status laim_get_resident_cfg(const laim_code* code, int32_t bp, laim_resident_cfg* cfg);

@@ -1474,6 +1474,10 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
   int cpt = want ? want->checks_per_thread : 0;
   int nt = want ? want->threads_per_shot : 0;
   int spb = want ? want->shots_per_block : 0;
+  // min-sum on the 2D toric layout: the tiled variant, faster than the
+  // other shapes at every L measured (8 to 64)
+  const bool tile_ok = c.tile_chk && bp == 0 && dc == 4 && dv == 2 && reg && !seq;
+  if (cpt <= 0 && nt <= 0 && tile_ok) cpt = 8;
   if (cpt <= 0) {
     if (nt > 0)
       cpt = (c.m + nt - 1) / nt;
@@ -1504,6 +1508,21 @@ bool resident_shape(const DevCode& c, int bp, const laim_resident_cfg* want, Res
     return false;
   }
   const int vpt = (c.n + nt - 1) / nt;
+  if (spb <= 0 && tile_ok && cpt == 8 && nt * 8 == c.m) {
+    // blocks near 128 threads with wavefronts at least 80% full (measured:
+    // 128 threads best at L = 8 and 32, 216 at L = 24, 64-128 at L = 16)
+    int best = 0, gap = 0;
+    for (int s = 1; nt * s <= kTileMaxThreads; ++s) {
+      const int th = nt * s, waves = (th + 63) / 64;
+      if (5 * th < 4 * 64 * waves) continue;
+      const int d = th > 128 ? th - 128 : 128 - th;
+      if (!best || d < gap) {
+        best = s;
+        gap = d;
+      }
+    }
+    spb = best > 0 ? best : 1;
+  }
   if (spb <= 0) spb = (nt >= 256) ? 1 : 256 / nt;
   if (spb > kMaxShotsPerBlock) spb = kMaxShotsPerBlock;
   if (nt * spb > 1024) {
