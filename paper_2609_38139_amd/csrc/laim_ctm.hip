@@ -159,9 +159,15 @@ __device__ __forceinline__ void ctm_check_rule(const CtmParamsDev& P, const floa
 // and a prefix sum over the lanes finds the word holding it. Lane 0 applies
 // the flip to the LDS bitmaps; the wavefront executes in order, so the next
 // event's search sees it.
-template <int DC, bool REG>
+// With qubits of degree 2 (regular codes) a qubit's two messages are the
+// check's own and the one named by the partner table, and a flip toggles
+// those two checks: one table read per qubit instead of the qubit's degree
+// and edge list read one after the other, on the path every other wavefront
+// of the block waits for.
+template <int DC, int DV, bool REG>
 __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t shot, double tk,
                            const float* msg, int32_t* gw, uint32_t* zw, uint32_t* sw, int32_t nl) {
+  constexpr bool PAIR = REG && DV == 2;
   const int32_t lane = threadIdx.x;
   int32_t nS = gw[kCwNs];
   uint32_t j = (uint32_t)gw[kCwJ];
@@ -199,22 +205,33 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
       }
       ch = (base + src) * 32 + __shfl(bpos, src);
     }
-    int32_t chosen = -1;
+    int32_t chosen = -1, chosen_c2 = -1;
     const int32_t d = (ch >= 0) ? (REG ? DC : c.chk_deg[ch]) : 0;
     if (d > 0) {
-      // the beliefs of the check's qubits (every lane the same)
+      // the beliefs of the check's qubits (every lane the same), their two
+      // messages added to pi in ascending check order as everywhere
       const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
       float Lv[DC];
+      int32_t c2v[DC];
       float Lmax = 0.0f;
 #pragma unroll
       for (int jj = 0; jj < DC; ++jj) {
         if (jj >= d) continue;
-        const int32_t v = nb[jj];
-        const int32_t dv = c.var_deg[v];
         float acc = P.pi;
-        for (int32_t q = 0; q < dv; ++q) {
-          const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
-          acc = acc + msg[ctm_word<DC>(edge_check(e), edge_slot(e))];
+        if (PAIR) {
+          const int32_t pe = c.partner[(int64_t)ch * DC + jj];
+          const int32_t c2 = edge_check(pe);
+          const float own = msg[ctm_word<DC>(ch, jj)];
+          const float oth = msg[ctm_word<DC>(c2, edge_slot(pe))];
+          acc = c2 < ch ? (acc + oth) + own : (acc + own) + oth;
+          c2v[jj] = c2;
+        } else {
+          const int32_t v = nb[jj];
+          const int32_t dv = c.var_deg[v];
+          for (int32_t q = 0; q < dv; ++q) {
+            const int32_t e = c.var_edge[(int64_t)v * c.dvmax + q];
+            acc = acc + msg[ctm_word<DC>(edge_check(e), edge_slot(e))];
+          }
         }
         acc = clampf(acc, P.clamp);
         Lv[jj] = acc;
@@ -229,10 +246,12 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
 #pragma unroll
         for (int jj = 0; jj < DC; ++jj) {
           if (jj < d && Lv[jj] == Lmax && chosen < 0) {
-            if (pick == 0)
+            if (pick == 0) {
               chosen = nb[jj];
-            else
+              if (PAIR) chosen_c2 = c2v[jj];
+            } else {
               --pick;
+            }
           }
         }
       }
@@ -241,13 +260,18 @@ __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t sho
       int32_t nS_new = nS;
       if (lane == 0) {
         zw[chosen >> 5] ^= 1u << (chosen & 31);
-        const int32_t dv = c.var_deg[chosen];
-        for (int32_t q = 0; q < dv; ++q) {
-          const int32_t c2 = edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]);
+        auto toggle = [&](int32_t c2) {
           const uint32_t bit = 1u << (c2 & 31);
           const uint32_t nw2 = sw[c2 >> 5] ^ bit;
           sw[c2 >> 5] = nw2;
           nS_new += (nw2 & bit) ? 1 : -1;
+        };
+        if (PAIR) {  // the qubit's two checks: this one and its partner
+          toggle(ch);
+          toggle(chosen_c2);
+        } else {
+          const int32_t dv = c.var_deg[chosen];
+          for (int32_t q = 0; q < dv; ++q) toggle(edge_check(c.var_edge[(int64_t)chosen * c.dvmax + q]));
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -394,7 +418,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
     int32_t k = 0;
     for (;; ++k) {
       if (nS > 0 && k >= kev) {
-        if (t < 64) ctm_events<DC, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw, nt < 64 ? nt : 64);
+        if (t < 64) ctm_events<DC, DV, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw, nt < 64 ? nt : 64);
         __syncthreads();
         nS = gw[kCwNs];
         Tev = *reinterpret_cast<const double*>(gw + kCwTev);
