@@ -350,8 +350,10 @@ typedef struct {
   uint64_t seed;    /* Philox key for the clocks and tie-breaks */
   int32_t skip_fixed; /* 1: skip Euler steps that cannot change the messages. Between
                          moves the step is a fixed map of the messages; once one
-                         leaves every message bit for bit as it was (tested on steps
-                         7, 15, 23, ...), the steps up to the next event are skipped.
+                         leaves every message bit for bit as it was (tested 7 steps
+                         after the start and after each move, then at intervals that
+                         double from 8 to 256 while the messages keep changing), the
+                         steps up to the next event are skipped.
                          Events are still handled one by one: all outputs, counts
                          included, equal those of every step. 0: run every step. */
 } laim_continuous_params;

@@ -409,13 +409,20 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
     // is a fixed map of (messages, syndrome), so every step up to the next
     // move is the identity and the loop goes straight to the next event
     // step (thread 0 adds the skipped steps to kCwSkipped); events are still
-    // handled one by one. Steps 7, 15, 23, ... compare (with P.skip) and
-    // raise kCwChg if a message changed; the step before each of them
-    // clears it, after every thread has read the last one. A jump happens
-    // only on a clear flag, and nothing raises it until the next compared
-    // step, so the steps after a jump find it clear as well.
+    // handled one by one. With P.skip, compared steps raise kCwChg if a
+    // message changed; every other step clears it, after every thread has
+    // read the last one. A jump happens only on a clear flag, and nothing
+    // raises it until the next compared step, so the steps after a jump find
+    // it clear as well. The compared steps: the 7th after the start and
+    // after every move, then at intervals that double (8, 16, ... 256 steps)
+    // while compares find a changed message -- sum-product, for one, drifts
+    // in its last bits without reaching a fixed point, and a compare costs
+    // extra instructions on every message. Which steps compare changes no
+    // result: a step is skipped only after a compare found the messages
+    // fixed.
     bool conv = false;
     int32_t k = 0;
+    int32_t cmp_gap = 8, next_cmp = 7;
     for (;; ++k) {
       if (nS > 0 && k >= kev) {
         if (t < 64) ctm_events<DC, DV, REG>(c, P, shot, (double)k * P.dt, msg, gw, zw, sw, nt < 64 ? nt : 64);
@@ -431,6 +438,8 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
             if ((vmask >> kk) & 1u) nsb |= ((sw[cidx[kk] >> 5] >> (cidx[kk] & 31)) & 1u) << kk;
           sb = nsb;
           conv = false;
+          cmp_gap = 8;
+          next_cmp = k + 7;
         }
       }
       if (nS == 0 || k >= P.max_steps) break;
@@ -440,7 +449,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         k = next - 1;
         continue;
       }
-      const bool cmp = SKIP && (k & 7) == 7;
+      const bool cmp = SKIP && k == next_cmp;
 
       // ---- one Euler step: both directions from the state before it
       float Fv[CPT][DC], Fc[CPT][DC];
@@ -493,7 +502,11 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
         update(BoolTag<false>());
       if (cmp && diff) gw[kCwChg] = 1;
       __syncthreads();
-      if (cmp) conv = gw[kCwChg] == 0;
+      if (cmp) {
+        conv = gw[kCwChg] == 0;
+        if (!conv && cmp_gap < 256) cmp_gap *= 2;
+        next_cmp = k + cmp_gap;
+      }
     }
 
     // ---- results
