@@ -219,7 +219,9 @@ hipError_t launch_bitcentric(const DevCode& c, double q, const uint8_t* e0, int3
 // K - 2 whatever d is. Lanes outside the segments, and segments past the
 // last shot, are idle (prior 0, messages 0, their own neighbours); an open
 // chain's ends take their missing message from lane 63, which is idle. x is
-// held as a 64-lane mask per slot.
+// held as a 64-lane mask per slot, and so are the shots not yet cleared.
+// Up to 8 bits per lane the launch bounds hold the kernel to 128 VGPRs,
+// four wavefronts per SIMD.
 __device__ inline double bperm_f64(int32_t addr, double x) {
   const int32_t lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
   const int32_t hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
@@ -227,7 +229,7 @@ __device__ inline double bperm_f64(int32_t addr, double x) {
 }
 
 template <int K, bool PERIODIC>
-__global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, int32_t S, double pi0,
+__global__ void __launch_bounds__(256, K <= 8 ? 4 : 1) bitchain_kernel(int32_t d, int32_t nl, int32_t S, double pi0,
                                                        const uint8_t* __restrict__ e0, int32_t nshots,
                                                        int32_t iters, uint8_t* __restrict__ z_out,
                                                        int32_t* __restrict__ iclr_out,
@@ -290,7 +292,8 @@ __global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, in
   // this lane's segment, as a lane mask
   const uint64_t myseg = act ? (seg0 << (seg * nl)) : 0ull;
   int32_t iclr = ((walls() & myseg) == 0) ? 0 : -1;
-  bool pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
+  // lanes of the shots whose syndrome has not been zero yet
+  uint64_t pend = __builtin_amdgcn_ballot_w64(act && iclr < 0);
 
   // One iteration of one parity, in place: Y^i from Y^{i-2} (the lane's own
   // and the neighbours' boundary ones), the beliefs, new x.
@@ -333,18 +336,30 @@ __global__ void __launch_bounds__(256) bitchain_kernel(int32_t d, int32_t nl, in
       const uint64_t lt = __builtin_amdgcn_ballot_w64(Lg[k] < 0.0);
       X[k] = gt | (X[k] & ~lt);
     }
-    if (pending) {
-      if (iclr < 0 && (walls() & myseg) == 0) iclr = it;
-      pending = __builtin_amdgcn_ballot_w64(act && iclr < 0) != 0;
+    if (pend) {
+      const uint64_t w = walls();
+      const uint64_t clr = __builtin_amdgcn_ballot_w64((w & myseg) == 0);
+      const uint64_t first = clr & pend;  // shots whose syndrome is zero for the first time
+      if (first) {
+        if ((first >> lane) & 1ull) iclr = it;
+        pend &= ~clr;
+      }
     }
   };
 
+  // four iterations per trip, so that the two parities' neighbour values
+  // stay in their registers from one trip to the next
   int32_t it = 1;
-  for (; it + 1 <= iters; it += 2) {
+  for (; it + 3 <= iters; it += 4) {
     step(YR[1], YL[1], rR[1], rL[1], it);
     step(YR[0], YL[0], rR[0], rL[0], it + 1);
+    step(YR[1], YL[1], rR[1], rL[1], it + 2);
+    step(YR[0], YL[0], rR[0], rL[0], it + 3);
   }
-  if (it <= iters) step(YR[1], YL[1], rR[1], rL[1], it);
+  for (; it <= iters; it += 2) {
+    step(YR[1], YL[1], rR[1], rL[1], it);
+    if (it + 1 <= iters) step(YR[0], YL[0], rR[0], rL[0], it + 1);
+  }
 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -361,10 +376,11 @@ bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl, int32_t* 
   // Bits per lane: the fewest VALU instructions per shot and iteration --
   // about 5 per slot and 7 per lane (the wrap bit's sum order and the
   // selects of a lane with K - 1 bits), shared by the S shots of a wavefront
-  // -- weighed by occupancy: the kernel takes about 13 K + 20 VGPRs, and
-  // below four wavefronts per SIMD the measured time per instruction grows
-  // (by about 10% at three and 40% at two). One bit per lane is never the
-  // cheapest.
+  // -- weighed by occupancy: the kernel takes about 13 K + 25 VGPRs (at
+  // most 128 up to K = 8, whose launch bounds ask for four wavefronts per
+  // SIMD), and below four wavefronts per SIMD the measured time per
+  // instruction grows (by about 10% at three and 40% at two). One bit per
+  // lane is never the cheapest.
   int32_t best = 0;
   double best_cost = 0.0;
   for (int32_t k = 2; k <= kBcChainMaxK; ++k) {
@@ -372,7 +388,7 @@ bool bitchain_shape(int32_t d, bool periodic, int32_t* K, int32_t* nl, int32_t* 
     // lanes hold K or K - 1 bits: at most one unused slot per lane
     if (n_l > cap || n_l * k - d > n_l) continue;
     const int32_t s = cap / n_l;
-    const int32_t vgpr = (13 * k + 20 + 7) / 8 * 8;
+    const int32_t vgpr = k <= 8 ? 128 : (13 * k + 25 + 7) / 8 * 8;
     const int32_t waves = std::min(8, 512 / vgpr);
     const double slow = waves >= 4 ? 1.0 : waves == 3 ? 1.1 : waves == 2 ? 1.4 : 2.0;
     const double cost = (5.0 * k + 7.0) / s * slow;
