@@ -699,14 +699,24 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
           }
           uint32_t diff = 0u;
           if (sweep) {
-            float ion[TILE ? CPT : 1][DC];  // this sweep's inner outputs
+            // Inside a tile the checks' outputs replace the last sweep's in
+            // place: when check k runs, the inputs that its outputs feed in
+            // a later check are formed first (xpre), from the old outputs;
+            // the inputs it takes from an earlier check were formed there.
+            float xpre[TILE ? CPT : 1][DC];
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
               if (TILE) {
 #pragma unroll
                 for (int j = 0; j < DC; ++j) {
                   const int tp = tile_partner(k, j);
-                  if (tp >= 0) x[k][j] = pi + io[TILE ? tp >> 2 : 0][tp & 3];
+                  if (tp < 0) continue;
+                  x[k][j] = (tp >> 2) < k ? xpre[TILE ? k : 0][j] : pi + io[TILE ? tp >> 2 : 0][tp & 3];
+                }
+#pragma unroll
+                for (int j = 0; j < DC; ++j) {
+                  const int tp = tile_partner(k, j);
+                  if (tp >= 0 && (tp >> 2) > k) xpre[TILE ? tp >> 2 : 0][tp & 3] = pi + io[TILE ? k : 0][j];
                 }
               }
               const uint32_t sigma_neg = ((sb >> k) ^ (uint32_t)(REG ? DC : deg[k])) & 1u;
@@ -777,17 +787,10 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
 #pragma unroll
               for (int j = 0; j < DC; ++j) {
                 if (TILE && tile_partner(k, j) >= 0)
-                  ion[TILE ? k : 0][j] = out[j];  // read from a register within the tile
+                  io[TILE ? k : 0][j] = out[j];  // read from a register within the tile
                 else
                   mk[j * kSlotStride] = out[j];
               }
-            }
-            if (TILE) {
-#pragma unroll
-              for (int k = 0; k < CPT; ++k)
-#pragma unroll
-                for (int j = 0; j < DC; ++j)
-                  if (tile_partner(k, j) >= 0) io[TILE ? k : 0][j] = ion[TILE ? k : 0][j];
             }
           }
           swept = swept || sweep;
