@@ -11,6 +11,20 @@
 
 namespace laim {
 
+// Work-item and work-group indices, the work-group size, and the high half
+// of a 32-bit product, from the compiler's builtins. The kernels are built
+// with IEEE mode off (-mno-amdgpu-ieee); the device library behind
+// threadIdx, blockIdx, blockDim and __umulhi is not, so its accessors would
+// not be inlined (their floating-point modes differ) and every use would be
+// a function call.
+__device__ __forceinline__ uint32_t tid_x() { return __builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ uint32_t bid_x() { return __builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ uint32_t bid_y() { return __builtin_amdgcn_workgroup_id_y(); }
+__device__ __forceinline__ uint32_t bdim_x() { return __builtin_amdgcn_workgroup_size_x(); }
+__device__ __forceinline__ uint32_t mulhi_u32(uint32_t a, uint32_t b) {
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as
 // easy as 1, 2, 3", SC'11). Ten rounds of the 4x32 S-box: the products of
 // words 0 and 2 with the two round multipliers are split into halves; the
@@ -25,9 +39,9 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint32_t a = 0xD2511F53u * c0;                  // low half of M0 * c0
-    const uint32_t ah = __umulhi(0xD2511F53u, c0);        // high half
+    const uint32_t ah = mulhi_u32(0xD2511F53u, c0);        // high half
     const uint32_t b = 0xCD9E8D57u * c2;
-    const uint32_t bh = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t bh = mulhi_u32(0xCD9E8D57u, c2);
     const uint32_t n0 = bh ^ c1 ^ k0;
     const uint32_t n2 = ah ^ c3 ^ k1;
     c0 = n0;

@@ -37,9 +37,9 @@ __global__ void __launch_bounds__(1024) bitcentric_kernel(DevCode c, double pi0,
                                                           int32_t iters, uint8_t* z_out,
                                                           int32_t* iclr_out, double* L_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int32_t t = threadIdx.x;
-  const int32_t nt = blockDim.x;
-  const int64_t shot = blockIdx.x;
+  const int32_t t = tid_x();
+  const int32_t nt = bdim_x();
+  const int64_t shot = bid_x();
   const int32_t E = c.E;
   // messages by edge (check-major: edge 2 ch + j), two buffers each
   double* cv[2] = {reinterpret_cast<double*>(smem), reinterpret_cast<double*>(smem) + E};
@@ -234,8 +234,8 @@ __global__ void __launch_bounds__(256, K <= 8 ? 4 : 1) bitchain_kernel(int32_t d
                                                        int32_t iters, uint8_t* __restrict__ z_out,
                                                        int32_t* __restrict__ iclr_out,
                                                        double* __restrict__ L_out) {
-  const int32_t lane = threadIdx.x & 63;
-  const int64_t shot0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * S;
+  const int32_t lane = tid_x() & 63;
+  const int64_t shot0 = ((int64_t)bid_x() * (bdim_x() >> 6) + (tid_x() >> 6)) * S;
   if (shot0 >= nshots) return;  // whole wavefronts
   const int32_t seg = lane / nl;
   const int32_t lam = lane - seg * nl;  // lane within the segment

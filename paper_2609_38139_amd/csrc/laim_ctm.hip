@@ -56,7 +56,7 @@ __host__ __device__ __forceinline__ int32_t ctm_zslot(int32_t dc, int32_t mpad) 
 }
 
 __global__ void ctm_zero_counter(uint32_t* p) {
-  if (threadIdx.x == 0) p[0] = 0u;
+  if (tid_x() == 0) p[0] = 0u;
 }
 
 // ln(u) for 0 < u <= 1 in double: u = f 2^e with f in [sqrt(1/2), sqrt(2)),
@@ -168,7 +168,7 @@ template <int DC, int DV, bool REG>
 __device__ void ctm_events(const DevCode& c, const CtmParamsDev& P, uint64_t shot, double tk,
                            const float* msg, int32_t* gw, uint32_t* zw, uint32_t* sw, int32_t nl) {
   constexpr bool PAIR = REG && DV == 2;
-  const int32_t lane = threadIdx.x;
+  const int32_t lane = tid_x();
   int32_t nS = gw[kCwNs];
   uint32_t j = (uint32_t)gw[kCwJ];
   int32_t events = gw[kCwEvents], moves = gw[kCwMoves];
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(1024) ctm_kernel(DevCode c, CtmParamsDev P, Ct
   // ctm_reg_dv2_ok holds): no clamp can bind
   constexpr bool kNoClamp = (BP == 0 && REG && DV == 2);
   extern __shared__ __align__(16) unsigned char smem[];
-  const int32_t t = threadIdx.x;
+  const int32_t t = tid_x();
   const int32_t nt = a.nt;
   float* msg = reinterpret_cast<float*>(smem);
   const int32_t zslot = ctm_zslot(DC, a.mpad);

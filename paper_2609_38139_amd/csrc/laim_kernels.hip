@@ -26,8 +26,8 @@ namespace laim {
 __global__ void __launch_bounds__(256) noise_kernel(int32_t n, int32_t nb4, uint64_t bound,
                                                     uint64_t seed, uint64_t shot0, int32_t word_rows,
                                                     uint8_t* __restrict__ e) {
-  const int64_t i = blockIdx.x;
-  const int32_t b = (int32_t)blockIdx.y * 256 + (int32_t)threadIdx.x;
+  const int64_t i = bid_x();
+  const int32_t b = (int32_t)bid_y() * 256 + (int32_t)tid_x();
   if (b >= nb4) return;
   const uint64_t shot = shot0 + (uint64_t)i;
   const Philox4 w = philox4x32_10((uint32_t)shot, (uint32_t)(shot >> 32), (uint32_t)b, 0u,
@@ -60,7 +60,7 @@ hipError_t launch_noise(const DevCode& c, uint64_t bound, uint64_t seed, uint64_
 // ------------------------------------------------------------- syndrome
 __global__ void __launch_bounds__(256) syndrome_kernel(DevCode c, const uint8_t* __restrict__ e,
                                                        int64_t total, uint8_t* __restrict__ s) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bid_x() * bdim_x() + tid_x();
   if (idx >= total) return;
   const int64_t i = idx / c.m;
   const int32_t ch = (int32_t)(idx - i * c.m);
@@ -90,14 +90,14 @@ __global__ void __launch_bounds__(256) failure_kernel(DevCode c, const uint8_t* 
                                                       uint8_t* __restrict__ fail) {
   __shared__ uint32_t par[kFailMaxWords];
   __shared__ int32_t anys;
-  const int64_t i = blockIdx.x;
+  const int64_t i = bid_x();
   const uint8_t* a = e0 + i * (int64_t)c.n;
   const uint8_t* b = z + i * (int64_t)c.n;
-  for (int w = threadIdx.x; w < kFailMaxWords; w += blockDim.x) par[w] = 0u;
-  if (threadIdx.x == 0) anys = 0;
+  for (int w = tid_x(); w < kFailMaxWords; w += bdim_x()) par[w] = 0u;
+  if (tid_x() == 0) anys = 0;
   __syncthreads();
   uint32_t local[4] = {0u, 0u, 0u, 0u};
-  for (int32_t v = threadIdx.x; v < c.n; v += blockDim.x) {
+  for (int32_t v = tid_x(); v < c.n; v += bdim_x()) {
     if ((a[v] ^ b[v]) & 1u) {
       for (int32_t w = 0; w < c.kw; ++w) {
         const uint32_t bits = c.lcol[(int64_t)v * c.kw + w];
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) failure_kernel(DevCode c, const uint8_t* 
   for (int32_t w = 0; w < c.kw && w < 4; ++w)
     if (local[w]) atomicXor(&par[w], local[w]);
   int32_t mine = 0;
-  for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+  for (int32_t ch = tid_x(); ch < c.m; ch += bdim_x()) {
     const int32_t d = c.chk_deg[ch];
     uint32_t x = 0;
     for (int32_t j = 0; j < d; ++j) {
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) failure_kernel(DevCode c, const uint8_t* 
   }
   if (mine) anys = 1;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     uint32_t f = (uint32_t)anys;
     for (int32_t w = 0; w < c.kw; ++w) f |= par[w];
     fail[i] = f ? 1 : 0;
@@ -151,12 +151,12 @@ __global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const ui
   __shared__ int32_t anys;
   const int32_t nw = c.n >> 5;
   uint32_t* par = rb + nw;
-  const int64_t i = blockIdx.x;
+  const int64_t i = bid_x();
   const uint4* a = reinterpret_cast<const uint4*>(e0 + i * (int64_t)c.n);
   const uint4* b = reinterpret_cast<const uint4*>(z + i * (int64_t)c.n);
-  for (int32_t w = threadIdx.x; w < c.kw; w += blockDim.x) par[w] = 0u;
-  if (threadIdx.x == 0) anys = 0;
-  for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+  for (int32_t w = tid_x(); w < c.kw; w += bdim_x()) par[w] = 0u;
+  if (tid_x() == 0) anys = 0;
+  for (int32_t w = tid_x(); w < nw; w += bdim_x()) {
     const uint4 a0 = a[2 * w], a1 = a[2 * w + 1], b0 = b[2 * w], b1 = b[2 * w + 1];
     const uint4 r0 = make_uint4(a0.x ^ b0.x, a0.y ^ b0.y, a0.z ^ b0.z, a0.w ^ b0.w);
     const uint4 r1 = make_uint4(a1.x ^ b1.x, a1.y ^ b1.y, a1.z ^ b1.z, a1.w ^ b1.w);
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const ui
   // per qubit (at most 32 logicals) a lane reads the rows of its 32 qubits
   // as eight independent 16-byte loads and keeps those whose bit is set.
   uint32_t local[4] = {0u, 0u, 0u, 0u};
-  for (int32_t w = threadIdx.x; w < nw; w += blockDim.x) {
+  for (int32_t w = tid_x(); w < nw; w += bdim_x()) {
     uint32_t bits = rb[w];
     if (!bits) continue;
     if (c.kw == 1) {
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const ui
   int32_t mine = 0;
   if (c.dcmax <= 8) {
 #pragma unroll 2
-    for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+    for (int32_t ch = tid_x(); ch < c.m; ch += bdim_x()) {
       const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
       int32_t vv[8];
 #pragma unroll
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const ui
       mine |= (int32_t)(x & 1u);
     }
   } else {
-    for (int32_t ch = threadIdx.x; ch < c.m; ch += blockDim.x) {
+    for (int32_t ch = tid_x(); ch < c.m; ch += bdim_x()) {
       const int32_t d = c.chk_deg[ch];
       const int32_t* nb = c.chk_var + (int64_t)ch * c.dcmax;
       uint32_t x = 0u;
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) failure_packed_kernel(DevCode c, const ui
   }
   if (mine) anys = 1;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     uint32_t f = (uint32_t)anys;
     for (int32_t q = 0; q < c.kw; ++q) f |= par[q];
     fail[i] = f ? 1 : 0;
@@ -381,7 +381,7 @@ __device__ void run_units(const DevCode& c, const KParams& kp, const UnitCtx& u,
   static_assert(!TILE || (DC == 4 && DV == 2 && CPT == 8 && BP == 0 && REG),
                 "the tiled variant is min-sum on the 2D toric layout");
   const int32_t spb = u.spb;
-  const int32_t tid = threadIdx.x;
+  const int32_t tid = tid_x();
   const int32_t g = tid / u.nt;
   const bool member = g < spb;
   const int32_t t = member ? tid - g * u.nt : 0;
@@ -1244,7 +1244,7 @@ struct ResJobs {
   // Takes the next spb shots from the launch's queue; false once it is empty.
   __device__ bool next(int32_t* ctrl) {
     __syncthreads();
-    if (threadIdx.x == 0) ctrl[0] = (int32_t)atomicAdd(counter, (uint32_t)spb);
+    if (tid_x() == 0) ctrl[0] = (int32_t)atomicAdd(counter, (uint32_t)spb);
     __syncthreads();
     base = ctrl[0];
     return base < nshots;
@@ -1313,7 +1313,7 @@ __global__ void __launch_bounds__(kTileMaxThreads, kTileWavesPerSimd)
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int32_t k) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i < k) p[i] = 0u;
 }
 
@@ -1374,7 +1374,7 @@ __global__ void __launch_bounds__(1024) server_kernel(const BatchItemDev* items,
                                                       const ServerReqDev* reqs, int32_t ctrl_off) {
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t* ctrl = reinterpret_cast<int32_t*>(smem + ctrl_off);
-  const ServerUnitDev U = units[blockIdx.x];
+  const ServerUnitDev U = units[bid_x()];
   const BatchItemDev* I = items + U.item;
   const DevCode c = I->c;
   const KParams kp = I->kp;
@@ -1616,7 +1616,7 @@ hipError_t launch_server(int bp, const BatchItemDev* items, const ServerUnitDev*
 __global__ void __launch_bounds__(256) sweep_count_kernel(int32_t iters, int32_t rounds, int32_t retire,
                                                           const int32_t* __restrict__ tclr,
                                                           int32_t nshots, int32_t* __restrict__ sweeps) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i >= nshots) return;
   const int32_t t = tclr[i];
   const int64_t k = (int64_t)iters * ((retire && t >= 0) ? t : rounds);

@@ -53,31 +53,31 @@ __global__ void __launch_bounds__(256) online_noise_kernel(DevCode c, int32_t N,
   uint8_t* et = sm;
   uint8_t* Ea = sm + n;
   uint8_t* ep[2] = {sm + 2 * n, sm + 2 * n + m};
-  const int64_t i = blockIdx.x;
+  const int64_t i = bid_x();
   const uint64_t shot = shot0 + (uint64_t)i;
   const uint32_t s_lo = (uint32_t)shot, s_hi = (uint32_t)(shot >> 32);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  for (int32_t v = threadIdx.x; v < n; v += blockDim.x) Ea[v] = 0;
+  for (int32_t v = tid_x(); v < n; v += bdim_x()) Ea[v] = 0;
   // round t writes its measurement errors to ep[t & 1] and reads eps_{t-1}
   // from the other buffer: eps_0 = 0 goes to ep[0]
-  for (int32_t ch = threadIdx.x; ch < m; ch += blockDim.x) ep[0][ch] = 0;
+  for (int32_t ch = tid_x(); ch < m; ch += bdim_x()) ep[0][ch] = 0;
   for (int32_t t = 1; t <= N; ++t) {
     uint8_t* ec = ep[t & 1];
     const uint8_t* eq = ep[(t & 1) ^ 1];
     if (e_in) {
       const uint8_t* row = e_in + (i * N + (t - 1)) * (int64_t)n;
-      for (int32_t v = threadIdx.x; v < n; v += blockDim.x) et[v] = row[v] & 1u;
+      for (int32_t v = tid_x(); v < n; v += bdim_x()) et[v] = row[v] & 1u;
       const uint8_t* mrow = eps_in + (i * N + (t - 1)) * (int64_t)m;
-      for (int32_t ch = threadIdx.x; ch < m; ch += blockDim.x) ec[ch] = (t < N) ? (mrow[ch] & 1u) : 0;
+      for (int32_t ch = tid_x(); ch < m; ch += bdim_x()) ec[ch] = (t < N) ? (mrow[ch] & 1u) : 0;
     } else {
-      for (int32_t b = threadIdx.x; 4 * b < n; b += blockDim.x) {
+      for (int32_t b = tid_x(); 4 * b < n; b += bdim_x()) {
         const Philox4 w = philox4x32_10(s_lo, s_hi, (uint32_t)b, ((uint32_t)t << 4) | 3u, k0, k1);
         const uint32_t ww[4] = {w.w0, w.w1, w.w2, w.w3};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (4 * b + q < n) et[4 * b + q] = below(ww[q], bd) ? 1 : 0;
       }
-      for (int32_t b = threadIdx.x; 4 * b < m; b += blockDim.x) {
+      for (int32_t b = tid_x(); 4 * b < m; b += bdim_x()) {
         uint32_t ww[4] = {0u, 0u, 0u, 0u};
         if (t < N) {
           const Philox4 w = philox4x32_10(s_lo, s_hi, (uint32_t)b, ((uint32_t)t << 4) | 4u, k0, k1);
@@ -92,9 +92,9 @@ __global__ void __launch_bounds__(256) online_noise_kernel(DevCode c, int32_t N,
       }
     }
     __syncthreads();
-    for (int32_t v = threadIdx.x; v < n; v += blockDim.x) Ea[v] ^= et[v];
+    for (int32_t v = tid_x(); v < n; v += bdim_x()) Ea[v] ^= et[v];
     uint8_t* Drow = D + (i * N + (t - 1)) * (int64_t)m;
-    for (int32_t ch = threadIdx.x; ch < m; ch += blockDim.x) {
+    for (int32_t ch = tid_x(); ch < m; ch += bdim_x()) {
       const int32_t d = c.chk_deg[ch];
       uint32_t x = ec[ch] ^ eq[ch];
       for (int32_t j = 0; j < d; ++j) x ^= et[c.chk_var[(int64_t)ch * c.dcmax + j]];
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) online_noise_kernel(DevCode c, int32_t N,
     }
     __syncthreads();
   }
-  for (int32_t v = threadIdx.x; v < n; v += blockDim.x) E[i * (int64_t)n + v] = Ea[v];
+  for (int32_t v = tid_x(); v < n; v += bdim_x()) E[i * (int64_t)n + v] = Ea[v];
 }
 
 // Syndrome of window k for every shot: rows a .. a + w - 1 of the
@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(256) online_window_syndrome(int32_t m, int32_t
                                                               const uint8_t* __restrict__ D,
                                                               const uint8_t* __restrict__ bnd,
                                                               uint8_t* __restrict__ sw) {
-  const int64_t i = blockIdx.y;
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = bid_y();
+  const int32_t j = bid_x() * bdim_x() + tid_x();
   if (j >= w * m) return;
   uint8_t x = D[(i * N + a) * (int64_t)m + j];
   if (j < m) x ^= bnd[i * (int64_t)m + j];
@@ -127,8 +127,8 @@ __global__ void __launch_bounds__(256) online_commit(int32_t n, int32_t m, int32
                                                      const int32_t* __restrict__ tclr_w,
                                                      uint8_t* __restrict__ z, uint8_t* __restrict__ bnd,
                                                      int32_t* __restrict__ cleared) {
-  const int64_t i = blockIdx.y;
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = bid_y();
+  const int32_t j = bid_x() * bdim_x() + tid_x();
   const uint8_t* row = zw + i * (int64_t)nvw;
   if (j < n) {
     uint8_t x = z[i * (int64_t)n + j];
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) online_commit(int32_t n, int32_t m, int32
 
 __global__ void __launch_bounds__(256) online_clear(uint8_t* __restrict__ a, int64_t na, int32_t* __restrict__ b,
                                                     int64_t nb) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)bid_x() * bdim_x() + tid_x();
   if (j < na) a[j] = 0;
   if (j < nb) b[j] = 0;
 }

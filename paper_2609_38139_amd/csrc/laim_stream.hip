@@ -120,7 +120,7 @@ constexpr int kStreamRowsPerBlock = 4;  // 256 threads: one row per wavefront
 
 // Row handled by this wavefront (uniform, so table reads become scalar loads).
 __device__ __forceinline__ int32_t stream_row() {
-  return (int32_t)blockIdx.x * kStreamRowsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  return (int32_t)bid_x() * kStreamRowsPerBlock + __builtin_amdgcn_readfirstlane(tid_x() >> 6);
 }
 
 // Offset of this lane's first shot in row `row` of tile `tile` of an array of rows.
@@ -145,10 +145,10 @@ __device__ __forceinline__ void st4b(uint8_t* p, uint32_t v) { *reinterpret_cast
 
 // Shot start: z = 0, no flip requests.
 __global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t v = stream_row();
   if (v >= c.n) return;
-  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  const int64_t o = stream_at(bid_y(), c.n, v, lane);
   st4b(w.z + o, 0u);
   st4b(w.fl + o, 0u);
 }
@@ -157,9 +157,9 @@ __global__ void __launch_bounds__(256) stream_init_var(DevCode c, StreamWS w) {
 // nshots get s = 0).
 __global__ void __launch_bounds__(256) stream_init_chk(DevCode c, StreamWS w, const uint8_t* e0,
                                                        const uint8_t* s0, int32_t nshots) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t ch = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (ch >= c.m) return;
   const int32_t d = c.chk_deg[ch];
   uint32_t x4 = 0;
@@ -285,9 +285,9 @@ template <int DCT>
 __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ src,
                                                     float* __restrict__ dst, int32_t fresh, int32_t cmp) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t ch = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (ch >= c.m || tile >= w.ctl[0]) return;
   const float C = kp.clamp;
   const int32_t pw = c.dvmax - 1;           // partners per edge
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(256) stream_sweep(DevCode c, KParams kp, Strea
 // After a compared sweep: a live shot none of whose messages changed is at a
 // fixed point (kept until its syndrome changes); the change marks are cleared.
 __global__ void __launch_bounds__(256) stream_conv(StreamWS w, int32_t ntot) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i >= ntot) return;
   if (!w.done[i]) w.conv[i] = w.chg[i] ? 0 : 1;
   w.chg[i] = 0;
@@ -504,9 +504,9 @@ template <int DCT>
 __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, StreamWS w,
                                                     const float* __restrict__ msg, int32_t r,
                                                     int32_t fresh, uint64_t shot0) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t ch = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (ch >= c.m || tile >= w.ctl[0]) return;
   const uint32_t s4 = ld4b(w.s + stream_at(tile, c.m, ch, lane));
   const uint32_t dn = ld4b(w.done + tile * kStreamTile + kSV * lane);
@@ -583,8 +583,8 @@ __global__ void __launch_bounds__(256) stream_moves(DevCode c, KParams kp, Strea
 // chain + 2) passes. Then the applied requests become flip requests
 // (f ^= e_v) and the records are cleared.
 __global__ void __launch_bounds__(256) stream_resolve(DevCode c, StreamWS w) {
-  const int32_t col = threadIdx.x;
-  const int64_t tile = blockIdx.x;
+  const int32_t col = tid_x();
+  const int64_t tile = bid_x();
   if (tile >= w.ctl[0] || w.done[tile * kStreamTile + col]) return;
   uint8_t* rq = w.rq + tile * c.m * kStreamTile + col;
   const uint32_t* rk = w.rkey + tile * c.m * kStreamTile + col;
@@ -631,9 +631,9 @@ __global__ void __launch_bounds__(256) stream_resolve(DevCode c, StreamWS w) {
 // s ^= H f for live shots; flags shots with s != 0 and clears the fixed-point
 // mark of shots whose syndrome changed.
 __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t ch = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (ch >= c.m || tile >= w.ctl[0]) return;
   const uint32_t live = ~ld4b(w.done + tile * kStreamTile + kSV * lane) & 0x01010101u;
   if (!live) return;
@@ -656,10 +656,10 @@ __global__ void __launch_bounds__(256) stream_syndrome(DevCode c, StreamWS w) {
 
 // z ^= f and clear the requests (requests exist for live shots only).
 __global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t v = stream_row();
-  if (v >= c.n || (int32_t)blockIdx.y >= w.ctl[0]) return;
-  const int64_t o = stream_at(blockIdx.y, c.n, v, lane);
+  if (v >= c.n || (int32_t)bid_y() >= w.ctl[0]) return;
+  const int64_t o = stream_at(bid_y(), c.n, v, lane);
   const uint32_t f4 = ld4b(w.fl + o);
   if (!f4) return;
   st4b(w.z + o, ld4b(w.z + o) ^ f4);
@@ -673,7 +673,7 @@ __global__ void __launch_bounds__(256) stream_apply(DevCode c, StreamWS w) {
 // exactly, and so does every later one -- the outputs are final.
 __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int32_t r,
                                                      int32_t nshots) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i >= nshots) return;
   w.newdone[i] = 0;
   if (w.done[i]) return;
@@ -692,7 +692,7 @@ __global__ void __launch_bounds__(256) stream_status(KParams kp, StreamWS w, int
 
 // Every shot slot of the tiles: shots beyond nshots start retired.
 __global__ void __launch_bounds__(256) stream_clear_shots(StreamWS w, int32_t nshots, int32_t ntot) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i == 0) {
     w.ctl[0] = ntot / kStreamTile;
     w.ctl[1] = 0;
@@ -716,9 +716,9 @@ __global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp,
                                                           const float* __restrict__ msg,
                                                           int32_t only_new, int32_t fresh,
                                                           float* __restrict__ L, int32_t nshots) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t v = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (v >= c.n || tile >= w.ctl[0]) return;
 #pragma unroll 1
   for (int q = 0; q < kSV; ++q) {
@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(256) stream_beliefs_out(DevCode c, KParams kp,
 // Interleaved state -> caller's row-major outputs.
 __global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t* z, uint8_t* s,
                                                   int32_t* tclr, int32_t nshots) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bid_x() * bdim_x() + tid_x();
   const int64_t tz = (int64_t)nshots * c.n;
   const int64_t ts = (int64_t)nshots * c.m;
   if (idx < tz) {
@@ -774,9 +774,9 @@ __global__ void __launch_bounds__(256) stream_out(DevCode c, StreamWS w, uint8_t
 // row-major outputs.
 __global__ void __launch_bounds__(256) stream_out_rows(DevCode c, StreamWS w, int32_t only_new, uint8_t* z,
                                                        uint8_t* s) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t row = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (row >= c.n + c.m || tile >= w.ctl[0]) return;
   const int64_t b = tile * kStreamTile + kSV * lane;
   const uint32_t sel = only_new ? ld4b(w.newdone + b) : (~ld4b(w.done + b) & 0x01010101u);
@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(256) stream_out_rows(DevCode c, StreamWS w, in
 // t_clr of the slots that just stopped (only_new) or of every slot still
 // running (!only_new).
 __global__ void __launch_bounds__(256) stream_out_tclr(StreamWS w, int32_t only_new, int32_t* tclr, int32_t ntot) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t i = bid_x() * bdim_x() + tid_x();
   if (i >= ntot || i >= w.ctl[0] * kStreamTile) return;
   const bool sel = only_new ? (w.newdone[i] != 0) : (w.done[i] == 0);
   const int32_t sh = w.sid[i];
@@ -815,27 +815,27 @@ __global__ void __launch_bounds__(1024) stream_compact_plan(StreamWS w) {
   const int32_t ntl = w.ctl[0];
   const int32_t N = ntl * kStreamTile;
   const int32_t per = (N + 1023) / 1024;
-  const int32_t b = (int32_t)threadIdx.x * per;
+  const int32_t b = (int32_t)tid_x() * per;
   const int32_t e = min(b + per, N);
   int32_t cnt = 0;
   for (int32_t i = b; i < e; ++i) cnt += w.done[i] ? 0 : 1;
-  part[threadIdx.x] = cnt;
+  part[tid_x()] = cnt;
   __syncthreads();
   for (int32_t off = 1; off < 1024; off <<= 1) {  // inclusive scan
-    const int32_t v = (int32_t)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    const int32_t v = (int32_t)tid_x() >= off ? part[tid_x() - off] : 0;
     __syncthreads();
-    part[threadIdx.x] += v;
+    part[tid_x()] += v;
     __syncthreads();
   }
   const int32_t total = part[1023];
   const int32_t nt = (total + kStreamTile - 1) / kStreamTile;
   const bool go = nt < ntl && (nt == 0 || 4 * nt <= 3 * ntl);
   if (go) {
-    int32_t pos = part[threadIdx.x] - cnt;
+    int32_t pos = part[tid_x()] - cnt;
     for (int32_t i = b; i < e; ++i)
       if (!w.done[i]) w.inv[pos++] = i;
   }
-  if (threadIdx.x == 0) {
+  if (tid_x() == 0) {
     w.ctl[1] = go ? 1 : 0;
     w.ctl[2] = total;
     w.ctl[3] = nt;
@@ -847,9 +847,9 @@ __global__ void __launch_bounds__(1024) stream_compact_plan(StreamWS w) {
 // from src to dst (4-byte elements: messages).
 __global__ void __launch_bounds__(256) stream_compact_f32(StreamWS w, int32_t rows, const float* __restrict__ src,
                                                           float* __restrict__ dst) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t row = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
   const int32_t nlive = w.ctl[2];
   float v[kSV];
@@ -868,9 +868,9 @@ __global__ void __launch_bounds__(256) stream_compact_f32(StreamWS w, int32_t ro
 // The same for 1-byte elements (syndrome, correction).
 __global__ void __launch_bounds__(256) stream_compact_u8(StreamWS w, int32_t rows, const uint8_t* __restrict__ src,
                                                          uint8_t* __restrict__ dst) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t row = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
   const int32_t nlive = w.ctl[2];
   uint32_t x = 0u;
@@ -891,9 +891,9 @@ __global__ void __launch_bounds__(256) stream_compact_u8(StreamWS w, int32_t row
 // lanes' worth per 16 bytes: `ebytes` is the element size).
 __global__ void __launch_bounds__(256) stream_compact_back(StreamWS w, int32_t rows, int32_t ebytes,
                                                            unsigned char* from, unsigned char* to, int32_t clear) {
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = tid_x() & 63;
   const int32_t row = stream_row();
-  const int64_t tile = blockIdx.y;
+  const int64_t tile = bid_y();
   if (!w.ctl[1] || row >= rows || tile >= w.ctl[3]) return;
   const int64_t o = ((tile * rows + row) * kStreamTile + kSV * lane) * ebytes;
   if (ebytes == 4) {
@@ -908,7 +908,7 @@ __global__ void __launch_bounds__(256) stream_compact_back(StreamWS w, int32_t r
 // Per slot, gathered into scratch (anys holds t_clr, sid2 the shot, newdone
 // the fixed-point mark: all three are free at the end of a round) ...
 __global__ void __launch_bounds__(256) stream_compact_slots(StreamWS w, int32_t ntot) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t j = bid_x() * bdim_x() + tid_x();
   if (!w.ctl[1] || j >= ntot) return;
   if (j < w.ctl[2]) {
     const int32_t i = w.inv[j];
@@ -924,7 +924,7 @@ __global__ void __launch_bounds__(256) stream_compact_slots(StreamWS w, int32_t 
 
 // ... and put in place; the slots past the running shots are stopped.
 __global__ void __launch_bounds__(256) stream_compact_slots_back(StreamWS w, int32_t ntot) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t j = bid_x() * bdim_x() + tid_x();
   if (!w.ctl[1] || j >= ntot) return;
   w.tclr[j] = (int32_t)w.anys[j];
   w.anys[j] = 0u;
@@ -937,7 +937,7 @@ __global__ void __launch_bounds__(256) stream_compact_slots_back(StreamWS w, int
 }
 
 __global__ void stream_compact_commit(StreamWS w) {
-  if (threadIdx.x == 0 && w.ctl[1]) {
+  if (tid_x() == 0 && w.ctl[1]) {
     w.ctl[0] = w.ctl[3];
     w.ctl[1] = 0;
   }
